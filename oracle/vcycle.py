@@ -1,0 +1,134 @@
+"""ORACLE (test infrastructure only): Galerkin multigrid V-cycle in FP64.
+
+Follows Alg. "V-cycle" and Alg. "Galerkin Surface Multigrid Solver" (Sec. 5):
+
+  Vcycle(l, x, b):
+    l == H (coarsest): solve A_H x = b directly (dense Cholesky, FP64)
+    otherwise:
+      x' = relax(A_l, x, b, mu_pre)                 pre-relaxation
+      r  = P_l^T (b - A_l x')                       restrict residual
+      c  = Vcycle(l + 1, 0, r)                      coarse-grid correction
+      x  = x' + P_l c                               prolong and update
+      x  = relax(A_l, x, b, mu_post)                post-relaxation
+
+  Solve: x = 0; while max_c ||b_c - A x_c|| / ||b_c|| > eps: x = Vcycle(0, x, b)
+
+Readings (the paper is silent or inconsistent):
+  * the correction is added to the pre-relaxed iterate x' (the update line of
+    the listing names the un-relaxed iterate; the residual was taken at x');
+  * relaxation is multicolor Gauss-Seidel (App. A), colors in ascending
+    creation order in both pre- and post-relaxation.  Rows of one color share
+    no matrix entry, so updating them together equals updating them one after
+    another: the sweep is serial Gauss-Seidel in color-major order;
+  * the error measure is the relative residual in the 2-norm per right-hand
+    side column, evaluated in FP64 before every cycle; x0 = 0.
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from . import hierarchy as H
+
+
+class Level:
+    def __init__(self, A, colors=None, ncolors=0):
+        self.A = A.tocsr()
+        self.n = A.shape[0]
+        self.diag = self.A.diagonal().copy()
+        self.colors = colors
+        self.ncolors = ncolors
+        self._split()
+
+    def _split(self):
+        A = self.A
+        off = A.copy()
+        off.setdiag(0.0)          # keeps the off-diagonal structure, diag value 0
+        self.off = off
+        self.rows = []
+        self.off_rows = []
+        if self.colors is not None:
+            for c in range(self.ncolors):
+                rows = np.flatnonzero(self.colors == c)
+                self.rows.append(rows)
+                self.off_rows.append(off[rows])
+
+
+class Solver:
+    """Hierarchy (P_l, coloring) fixed at construction; values via set_values."""
+
+    def __init__(self, Ps, A0, mu_pre=2, mu_post=2):
+        self.P = [P.tocsr() for P in Ps]
+        self.mu_pre, self.mu_post = mu_pre, mu_post
+        self.nlev = len(Ps) + 1
+        self.colors = []
+        self.set_values(A0, recolor=True)
+
+    def set_values(self, A0, recolor=False):
+        As = [A0.tocsr()]
+        for P in self.P:
+            As.append(H.galerkin(As[-1], P))
+        if recolor:
+            self.colors = [H.coloring(A) for A in As[:-1]]
+        self.levels = [Level(A, *self.colors[l]) for l, A in enumerate(As[:-1])]
+        self.levels.append(Level(As[-1]))
+        dense = As[-1].toarray()
+        self.G = np.linalg.cholesky(dense)          # lower, A_H = G G^T
+        self.A = As
+
+    # --- building blocks -------------------------------------------------
+    def relax(self, l, x, b, sweeps):
+        """Multicolor Gauss-Seidel: for each color in ascending order, every
+        row i of that color becomes (b_i - sum_{j != i} A_ij x_j) / A_ii."""
+        lv = self.levels[l]
+        for _ in range(sweeps):
+            for rows, offr in zip(lv.rows, lv.off_rows):
+                x[rows] = (b[rows] - offr @ x) / lv.diag[rows, None]
+        return x
+
+    def residual(self, l, x, b):
+        return b - self.A[l] @ x
+
+    def restrict(self, l, r):
+        return self.P[l].T @ r
+
+    def prolong(self, l, e):
+        return self.P[l] @ e
+
+    def coarse_solve(self, b):
+        y = sla.solve_triangular(self.G, b, lower=True)
+        return sla.solve_triangular(self.G.T, y, lower=False)
+
+    def vcycle(self, l, x, b):
+        if l == self.nlev - 1:
+            return self.coarse_solve(b)
+        x = self.relax(l, x, b, self.mu_pre)
+        r = self.restrict(l, self.residual(l, x, b))
+        c = self.vcycle(l + 1, np.zeros_like(r), r)
+        x = x + self.prolong(l, c)
+        return self.relax(l, x, b, self.mu_post)
+
+    def solve(self, b, rtol, max_cycles=100, x0=None, fixed_cycles=None):
+        """Returns (x, cycles, history of per-column relative residuals)."""
+        b = np.asarray(b, dtype=np.float64)
+        if b.ndim == 1:
+            b = b[:, None]
+        x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).reshape(b.shape)
+        bn = np.linalg.norm(b, axis=0)
+        scale = np.where(bn > 0, bn, 1.0)
+        hist = []
+        cycles = 0
+        while True:
+            rho = np.linalg.norm(self.residual(0, x, b), axis=0) / scale
+            hist.append(rho)
+            if fixed_cycles is not None:
+                if cycles == fixed_cycles:
+                    break
+            elif rho.max() <= rtol or cycles >= max_cycles:
+                break
+            x = self.vcycle(0, x, b)
+            cycles += 1
+        return x, cycles, np.array(hist)
+
+
+def build(V, F, A0, n_levels=0, mu_pre=2, mu_post=2, min_coarse=500):
+    Ps, meshes, stats = H.prolongations(V, F, n_levels, min_coarse)
+    return Solver(Ps, A0, mu_pre, mu_post), meshes, stats
