@@ -1,0 +1,239 @@
+/*
+ * smg.h -- C ABI of the MI355X surface-multigrid library (libsmg.so).
+ *
+ * Solves A x = b on a triangle mesh with the Galerkin multigrid V-cycle of
+ * Liu, Zhang, Ben-Chen, Jacobson, "Surface Multigrid via Intrinsic
+ * Prolongation" (ACM TOG 40(4), 2021): Alg. "Galerkin Surface Multigrid
+ * Solver" (outer loop) and Alg. "V-cycle" (pre-relaxation, restriction P^T r,
+ * coarse-grid correction with A_{l+1} = P_l^T A_l P_l (Eq. gca), prolongation
+ * P c, post-relaxation, direct coarsest solve), with the intrinsic
+ * prolongations P_l of Sec. 4 (successive self-parameterization, at most three
+ * barycentric weights per row, Sec. 4.5) and multicolor Gauss-Seidel
+ * relaxation (App. A, Alg. "Graph Coloring").
+ *
+ * Conventions for every entry point:
+ *  - Returns SMG_OK (0) or a negative smg_status; nothing is thrown across the
+ *    ABI.  smg_last_error() gives a thread-local message for the last failure.
+ *  - Indices are 0-based int32.  Vectors with k right-hand sides are n x k,
+ *    row-major (the k values of one vertex are adjacent), 1 <= k <= 4.
+ *  - Pointers named d_* are device pointers on the solver's device; h_* and
+ *    unprefixed arrays are host pointers.  The caller owns every pointer it
+ *    passes; the library never frees them and keeps none after returning,
+ *    except where stated.  The library owns its internal device buffers
+ *    (allocated with hipMalloc in smg_solver_create / smg_batch_create and
+ *    released by the matching destroy call).
+ *  - stream is a hipStream_t (NULL = default stream).  Work is enqueued on it;
+ *    calls that return values to the host synchronize that stream.
+ *  - Vectors of level l are in that level's natural vertex numbering (level 0:
+ *    the caller's vertex order; level l > 0: the coarse numbering of the
+ *    hierarchy).  The library's internal color-major permutation is never
+ *    visible at the ABI.
+ */
+#ifndef SMG_H
+#define SMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smg_status;
+enum {
+    SMG_OK = 0,
+    SMG_ERR_INVALID_ARG = -1,    /* bad size, null pointer, out-of-range index */
+    SMG_ERR_OOM = -2,            /* device or host allocation failed */
+    SMG_ERR_HIP = -3,            /* a HIP runtime call failed */
+    SMG_ERR_NOT_SPD = -4,        /* coarsest Cholesky met a pivot <= 0 */
+    SMG_ERR_NO_CONVERGENCE = -5, /* cycle cap reached; x holds the last iterate */
+    SMG_ERR_NONFINITE = -6,      /* NaN/Inf in b or in the matrix values */
+    SMG_ERR_STATE = -7,          /* call out of order (e.g. solve before set_values) */
+    SMG_ERR_PRECOMPUTE = -8      /* hierarchy construction failed */
+};
+
+enum { SMG_FP64 = 0, SMG_FP32_IR = 1 };   /* precision of smg_solve / smg_vcycle */
+
+typedef struct smg_hier_s *smg_hier;       /* host-side hierarchy (prolongations) */
+typedef struct smg_solver_s *smg_solver;   /* device-resident solver of one mesh */
+typedef struct smg_batch_s *smg_batch;     /* many solvers in one launch schedule */
+typedef void *smg_stream;                  /* hipStream_t */
+
+/* ------------------------------------------------------------------------ */
+/* Host precompute (CPU, geometry only; paper Alg. "Galerkin Surface Multigrid
+ * Solver", second line, and Sec. 5 "Successive Self-Parameterization").     */
+
+typedef struct {
+    int32_t n_levels;      /* total levels incl. the finest; 0 = rule below      */
+    int32_t min_coarse;    /* rule: decimate while floor(n/4 + 1/2) >= min_coarse
+                              (Sec. 5 defaults: ratio 0.25, coarsest >= 500)     */
+    int32_t interior_only; /* 1: only collapse edges with both ends interior     */
+} smg_pre_opts;
+
+/* Build P_1..P_H by mid-point edge collapse with joint LSCM flattening
+ * (Sec. 4.1-4.4) and the barycentric query (App. C, Fig. baryQuery).
+ * V: n x 3 double, F: m x 3 int32, a consistently oriented manifold mesh with
+ * or without boundary.  opts may be NULL (n_levels 0, min_coarse 500).
+ * *out is owned by the caller and released with smg_hier_free.
+ * Errors: INVALID_ARG (bad sizes/indices), PRECOMPUTE (non-manifold input). */
+smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F, int32_t m,
+                         const smg_pre_opts *opts, smg_hier *out);
+
+/* Wrap externally computed prolongations: level l has sizes[l] vertices,
+ * P_l is sizes[l] x 3 in ELL form (p_cols[l], p_w[l]); a slot with weight 0
+ * or column < 0 is unused.  Weights must be >= 0.  Data are copied. */
+smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_t *sizes,
+                                       const int32_t *const *p_cols,
+                                       const double *const *p_w, smg_hier *out);
+
+int32_t smg_hier_num_levels(smg_hier h);
+int32_t smg_hier_level_size(smg_hier h, int32_t level);
+/* Copy P_level (n_level x 3 ELL, unused slots: col -1, weight 0). */
+smg_status smg_hier_get_prolongation(smg_hier h, int32_t level, int32_t *cols, double *w);
+/* Per-level decimation statistics: collapses, failed tests, interior,
+ * one-boundary, boundary case 1/2/3 counts, largest clamped barycentric. */
+smg_status smg_hier_stats(smg_hier h, int32_t level, double *stats8);
+void smg_hier_free(smg_hier h);
+
+/* Greedy coloring of the off-diagonal graph of a CSR pattern (App. A, Alg.
+ * "Graph Coloring": descending degree, ties by ascending index; first palette
+ * color free among painted neighbours, moved to the palette's back; else a
+ * new color).  color: n ids (host).  Returns the number of colors, or a
+ * negative smg_status. */
+int32_t smg_color_pattern(int32_t n, const int32_t *rowptr, const int32_t *cols, int32_t *color);
+
+/* CSR pattern {diagonal} U {mesh edges}, columns ascending.  Call with
+ * cols == NULL to get *nnz; then with cols of capacity *nnz. */
+smg_status smg_mesh_pattern(int32_t n, const int32_t *F, int32_t m, int32_t *rowptr,
+                            int32_t *cols, int32_t *nnz);
+
+/* ------------------------------------------------------------------------ */
+/* Device solver.                                                           */
+
+typedef struct {
+    int32_t mu_pre;        /* pre-relaxation sweeps (Sec. 5 default 2)  */
+    int32_t mu_post;       /* post-relaxation sweeps (Sec. 5 default 2) */
+} smg_opts;
+
+/* Upload a hierarchy for the level-0 pattern (a0_rowptr, a0_cols: host CSR,
+ * n0 = hierarchy level-0 size rows, diagonal present, columns ascending).
+ * Builds on the host: R_l = P_l^T, the symbolic Galerkin patterns and their
+ * numeric plans, the coloring of every smoothed level (App. A) and the
+ * color-major layout; then copies everything to device `device`.
+ * opts may be NULL (2/2).  Errors: INVALID_ARG, OOM, HIP. */
+smg_status smg_solver_create(int32_t device, smg_hier h, const int32_t *a0_rowptr,
+                             const int32_t *a0_cols, const smg_opts *opts, smg_solver *out);
+void smg_solver_destroy(smg_solver s);
+
+/* Enable on-device assembly for the mesh faces F (m x 3, host). The level-0
+ * pattern must be smg_mesh_pattern(F). */
+smg_status smg_solver_attach_mesh(smg_solver s, const int32_t *F, int32_t m);
+
+/* On-device A_0 = diag(s .* m) + t L_w (cotan Laplacian with optional per-edge
+ * weights, lumped mass; the system of the paper's Sec. 6 examples):
+ *   d_V: n x 3 positions; d_mass_scale: n (NULL = 1); d_edge_w: one weight per
+ *   edge of the canonical sorted edge list (i < j, lexicographic) (NULL = 1).
+ * Writes d_a0_vals (nnz, CSR order) and, if non-NULL, d_l_vals (L_w in CSR
+ * order) and d_mass (n, unscaled lumped mass).  Requires attach_mesh. */
+smg_status smg_assemble(smg_solver s, const double *d_V, double t, const double *d_mass_scale,
+                        const float *d_edge_w, double *d_a0_vals, double *d_l_vals,
+                        double *d_mass, smg_stream stream);
+
+/* Set A_0 (d_a0_vals in the CSR order given at create) and refresh the whole
+ * hierarchy on the device: Galerkin A_{l+1} = P_l^T A_l P_l for every level
+ * (Eq. gca; "store the system matrix hierarchy", Sec. 5), FP32 copies, and the
+ * dense FP64 Cholesky factor of the coarsest A_H.  Errors: NOT_SPD, HIP. */
+smg_status smg_set_values(smg_solver s, const double *d_a0_vals, smg_stream stream);
+
+int32_t smg_num_levels(smg_solver s);
+int32_t smg_level_size(smg_solver s, int32_t level);
+int64_t smg_level_nnz(smg_solver s, int32_t level);
+/* Colors of level `level` (host array of n_level ids, may be NULL); returns
+ * the number of colors (0 for the coarsest level). */
+int32_t smg_level_colors(smg_solver s, int32_t level, int32_t *color);
+/* Host copy of A_level in CSR (natural numbering, ascending columns,
+ * structural pattern incl. explicit zeros).  Sizes from smg_level_nnz. */
+smg_status smg_get_level_matrix(smg_solver s, int32_t level, int32_t *rowptr, int32_t *cols,
+                                double *vals);
+/* Host copy of the coarsest factor G (A_H = G G^T), n_H x n_H column-major,
+ * upper part zero. */
+smg_status smg_get_coarse_factor(smg_solver s, double *G);
+
+/* --- one step of the V-cycle on level l (FP64; for parity checks) --- */
+/* r = b - A_l x  (Alg. "V-cycle", restriction line, inner term) */
+smg_status smg_residual(smg_solver s, int32_t level, const double *d_b, const double *d_x,
+                        double *d_r, int32_t k, smg_stream stream);
+/* `sweeps` multicolor Gauss-Seidel sweeps in place on x (App. A) */
+smg_status smg_smooth(smg_solver s, int32_t level, const double *d_b, double *d_x, int32_t k,
+                      int32_t sweeps, smg_stream stream);
+/* rc = P_l^T r  (restriction, R = P^T, Eq. gca) */
+smg_status smg_restrict(smg_solver s, int32_t level, const double *d_r, double *d_rc,
+                        int32_t k, smg_stream stream);
+/* x += P_l e  (prolong correction and update) */
+smg_status smg_prolong_add(smg_solver s, int32_t level, const double *d_e, double *d_x,
+                           int32_t k, smg_stream stream);
+/* x = A_H^{-1} b by the Cholesky factor (coarsest direct solve) */
+smg_status smg_coarse_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                            smg_stream stream);
+/* One V-cycle at level 0 in place on x (precision SMG_FP64 only). */
+smg_status smg_vcycle(smg_solver s, const double *d_b, double *d_x, int32_t k, smg_stream stream);
+
+/* --- the solve (Alg. "Galerkin Surface Multigrid Solver") --- */
+typedef struct {
+    double rtol;           /* stop when max_c ||b_c - A x_c|| / ||b_c|| <= rtol */
+    int32_t max_cycles;    /* cap (SMG_ERR_NO_CONVERGENCE when reached)         */
+    int32_t precision;     /* SMG_FP64 or SMG_FP32_IR                            */
+    int32_t fixed_cycles;  /* > 0: run exactly this many cycles, no stop test   */
+    int32_t use_graph;     /* 1: replay each cycle from a captured hipGraph     */
+} smg_solve_params;
+
+typedef struct {
+    int32_t cycles;        /* V-cycles run (outer refinement steps for FP32_IR) */
+    int32_t k;
+    double rel_res[4];     /* final FP64 relative residual per column           */
+    double ms;             /* wall time of the solve on the stream              */
+} smg_solve_info;
+
+/* x = A^{-1} b from x0 = 0.  SMG_FP32_IR runs relaxation, residual and
+ * transfers of every cycle in FP32 (FP32 accumulation) inside an FP64
+ * iterative-refinement loop: FP64 outer residual, FP64 coarsest Cholesky,
+ * FP64 update.  info may be NULL.  Errors: STATE, NONFINITE, NO_CONVERGENCE. */
+smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                     const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
+
+/* --- adjoint helpers for A = diag(s.*m) + t L (differentiation) --- */
+/* *h_out = lambda^T L u over the level-0 pattern (d_l_vals in CSR order), k = 1 */
+smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const double *d_lambda,
+                        const double *d_u, double *h_out, smg_stream stream);
+/* d_out[i] = -lambda_i * m_i * u_i */
+smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const double *d_m,
+                         const double *d_u, double *d_out, smg_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batching: many solvers in one persistent launch.                          */
+
+typedef struct {
+    int32_t wg_per_mesh_min;  /* autotuned if 0 */
+    int32_t block_rows;       /* rows per workgroup chunk, autotuned if 0 */
+} smg_batch_opts;
+
+smg_status smg_batch_create(const smg_solver *solvers, int32_t count, const smg_batch_opts *o,
+                            smg_batch *out);
+void smg_batch_destroy(smg_batch b);
+/* Solve mesh i: x_i = A_i^{-1} b_i with k[i] columns, FP32 bulk with FP64
+ * refinement, all meshes in one persistent kernel captured in a hipGraph
+ * (captured on the first call, replayed afterwards).  infos may be NULL. */
+smg_status smg_batch_solve(smg_batch b, const double *const *d_b, double *const *d_x,
+                           const int32_t *k, const smg_solve_params *p, smg_solve_info *infos,
+                           smg_stream stream);
+/* Time candidate launch shapes and keep the fastest (never changes mu, the
+ * levels, the coloring or the color order). budget_ms bounds the search. */
+smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_stream stream);
+
+const char *smg_status_string(smg_status st);
+const char *smg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMG_H */

@@ -1,0 +1,873 @@
+// C ABI of libsmg (see include/smg.h): host precompute entry points, device
+// solver construction, hierarchy refresh (Galerkin + coarsest Cholesky), the
+// V-cycle driver and the FP64 / FP32-in-FP64-refinement solve loops.
+#include "smg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hier.h"
+#include "kernels.h"
+#include "runtime.h"
+
+using namespace smg;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+namespace smg {
+smg_status fail(smg_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+}  // namespace smg
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *smg_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *smg_status_string(smg_status st) {
+    switch (st) {
+    case SMG_OK: return "ok";
+    case SMG_ERR_INVALID_ARG: return "invalid argument";
+    case SMG_ERR_OOM: return "out of memory";
+    case SMG_ERR_HIP: return "HIP runtime error";
+    case SMG_ERR_NOT_SPD: return "coarsest matrix not positive definite";
+    case SMG_ERR_NO_CONVERGENCE: return "no convergence within the cycle cap";
+    case SMG_ERR_NONFINITE: return "non-finite value";
+    case SMG_ERR_STATE: return "call out of order";
+    case SMG_ERR_PRECOMPUTE: return "hierarchy precompute failed";
+    default: return "unknown status";
+    }
+}
+
+// ------------------------------------------------------- host precompute
+struct smg_hier_s {
+    HierHost H;
+};
+
+extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F, int32_t m,
+                                    const smg_pre_opts *opts, smg_hier *out) {
+    if (!V || !F || !out || n < 3 || m < 1) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: bad arguments");
+    for (int64_t i = 0; i < 3 * (int64_t)m; ++i)
+        if (F[i] < 0 || F[i] >= n) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: face index out of range");
+    const int min_coarse = (opts && opts->min_coarse > 0) ? opts->min_coarse : 500;
+    const bool interior_only = opts && opts->interior_only;
+    int nlev = opts ? opts->n_levels : 0;
+    auto target = [](int nn) { return (int)std::floor(nn / 4.0 + 0.5); };
+    if (nlev <= 0) {
+        nlev = 1;
+        for (int nn = n; target(nn) >= min_coarse; nn = target(nn)) ++nlev;
+    }
+    auto h = std::make_unique<smg_hier_s>();
+    h->H.nlev = nlev;
+    h->H.sizes.push_back(n);
+    std::vector<double> X(V, V + 3 * (size_t)n);
+    std::vector<int32_t> Fv(F, F + 3 * (size_t)m);
+    for (int l = 0; l + 1 < nlev; ++l) {
+        LevelOut lo;
+        const int rc = ssp_decimate_level(X, Fv, target((int)(X.size() / 3)), interior_only, lo);
+        if (rc != 0) return fail(SMG_ERR_PRECOMPUTE, "successive self-parameterization failed at level " + std::to_string(l));
+        h->H.pcols.push_back(std::move(lo.pcols));
+        h->H.pw.push_back(std::move(lo.pw));
+        std::array<double, 8> st;
+        std::copy(lo.stats, lo.stats + 8, st.begin());
+        h->H.stats.push_back(st);
+        X = std::move(lo.X);
+        Fv = std::move(lo.F);
+        h->H.sizes.push_back((int)(X.size() / 3));
+    }
+    // zero-column removal (App. B): drop coarse vertices that receive no
+    // weight, and the matching rows of the next prolongation.
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const int nc = h->H.sizes[l + 1];
+        std::vector<char> used(nc, 0);
+        for (size_t e = 0; e < h->H.pcols[l].size(); ++e)
+            if (h->H.pcols[l][e] >= 0 && h->H.pw[l][e] > 0.0) used[h->H.pcols[l][e]] = 1;
+        std::vector<int32_t> newid(nc, -1);
+        int cnt = 0;
+        for (int a = 0; a < nc; ++a) if (used[a]) newid[a] = cnt++;
+        if (cnt == nc) continue;
+        for (auto &c : h->H.pcols[l]) if (c >= 0) c = newid[c];
+        if (l + 2 < nlev) {
+            std::vector<int32_t> pc2;
+            std::vector<double> pw2;
+            for (int a = 0; a < nc; ++a)
+                if (used[a])
+                    for (int q = 0; q < 3; ++q) { pc2.push_back(h->H.pcols[l + 1][3 * a + q]); pw2.push_back(h->H.pw[l + 1][3 * a + q]); }
+            h->H.pcols[l + 1] = std::move(pc2);
+            h->H.pw[l + 1] = std::move(pw2);
+        }
+        h->H.sizes[l + 1] = cnt;
+    }
+    *out = h.release();
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_t *sizes,
+                                                  const int32_t *const *p_cols,
+                                                  const double *const *p_w, smg_hier *out) {
+    if (n_levels < 1 || !sizes || !out || (n_levels > 1 && (!p_cols || !p_w)))
+        return fail(SMG_ERR_INVALID_ARG, "smg_hier_from_prolongations: bad arguments");
+    auto h = std::make_unique<smg_hier_s>();
+    h->H.nlev = n_levels;
+    h->H.sizes.assign(sizes, sizes + n_levels);
+    for (int l = 0; l + 1 < n_levels; ++l) {
+        const int n = sizes[l], nc = sizes[l + 1];
+        if (n < 1 || nc < 1) return fail(SMG_ERR_INVALID_ARG, "empty level");
+        std::vector<int32_t> pc(p_cols[l], p_cols[l] + 3 * (size_t)n);
+        std::vector<double> pw(p_w[l], p_w[l] + 3 * (size_t)n);
+        for (size_t e = 0; e < pc.size(); ++e) {
+            if (pc[e] >= nc || pw[e] < 0.0 || !std::isfinite(pw[e]))
+                return fail(SMG_ERR_INVALID_ARG, "prolongation entry out of range");
+            if (pc[e] < 0 || pw[e] == 0.0) { pc[e] = -1; pw[e] = 0.0; }
+        }
+        h->H.pcols.push_back(std::move(pc));
+        h->H.pw.push_back(std::move(pw));
+        h->H.stats.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+    }
+    if (n_levels > 1 && sizes[0] < 1) return fail(SMG_ERR_INVALID_ARG, "empty level");
+    *out = h.release();
+    return SMG_OK;
+}
+
+extern "C" int32_t smg_hier_num_levels(smg_hier h) { return h ? h->H.nlev : 0; }
+extern "C" int32_t smg_hier_level_size(smg_hier h, int32_t l) {
+    return (h && l >= 0 && l < h->H.nlev) ? h->H.sizes[l] : -1;
+}
+extern "C" smg_status smg_hier_get_prolongation(smg_hier h, int32_t l, int32_t *cols, double *w) {
+    if (!h || l < 0 || l + 1 >= h->H.nlev || !cols || !w) return fail(SMG_ERR_INVALID_ARG, "bad level");
+    std::copy(h->H.pcols[l].begin(), h->H.pcols[l].end(), cols);
+    std::copy(h->H.pw[l].begin(), h->H.pw[l].end(), w);
+    return SMG_OK;
+}
+extern "C" smg_status smg_hier_stats(smg_hier h, int32_t l, double *s8) {
+    if (!h || l < 0 || l + 1 >= h->H.nlev || !s8) return fail(SMG_ERR_INVALID_ARG, "bad level");
+    std::copy(h->H.stats[l].begin(), h->H.stats[l].end(), s8);
+    return SMG_OK;
+}
+extern "C" void smg_hier_free(smg_hier h) { delete h; }
+
+extern "C" int32_t smg_color_pattern(int32_t n, const int32_t *rowptr, const int32_t *cols,
+                                     int32_t *color) {
+    if (n < 0 || !rowptr || !cols || !color) return fail(SMG_ERR_INVALID_ARG, "smg_color_pattern: bad arguments");
+    for (int i = 0; i < n; ++i)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            if (cols[p] < 0 || cols[p] >= n) return fail(SMG_ERR_INVALID_ARG, "column out of range");
+    std::vector<int32_t> c;
+    const int nc = greedy_coloring(n, rowptr, cols, c);
+    std::copy(c.begin(), c.end(), color);
+    return nc;
+}
+
+extern "C" smg_status smg_mesh_pattern(int32_t n, const int32_t *F, int32_t m, int32_t *rowptr,
+                                       int32_t *cols, int32_t *nnz) {
+    if (n < 1 || !F || m < 1 || !rowptr || !nnz) return fail(SMG_ERR_INVALID_ARG, "smg_mesh_pattern: bad arguments");
+    std::vector<std::vector<int32_t>> adj(n);
+    for (int f = 0; f < m; ++f)
+        for (int c = 0; c < 3; ++c) {
+            const int a = F[3 * f + c], b = F[3 * f + (c + 1) % 3];
+            if (a < 0 || a >= n || b < 0 || b >= n) return fail(SMG_ERR_INVALID_ARG, "face index out of range");
+            adj[a].push_back(b);
+            adj[b].push_back(a);
+        }
+    int64_t total = 0;
+    rowptr[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        adj[i].push_back(i);
+        std::sort(adj[i].begin(), adj[i].end());
+        adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
+        total += (int64_t)adj[i].size();
+        if (total > INT32_MAX) return fail(SMG_ERR_INVALID_ARG, "pattern too large");
+        rowptr[i + 1] = (int32_t)total;
+    }
+    if (cols) {
+        if (*nnz < total) return fail(SMG_ERR_INVALID_ARG, "cols capacity too small");
+        for (int i = 0; i < n; ++i) std::copy(adj[i].begin(), adj[i].end(), cols + rowptr[i]);
+    }
+    *nnz = (int32_t)total;
+    return SMG_OK;
+}
+
+// ---------------------------------------------------------- device memory
+namespace smg {
+
+template <typename T>
+static smg_status dalloc(T **p, size_t count, std::vector<void *> &owned) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) return fail(SMG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    owned.push_back(*p);
+    return SMG_OK;
+}
+template <typename T>
+static smg_status dupload(T **p, const std::vector<T> &h, std::vector<void *> &owned) {
+    smg_status st = dalloc(p, h.size(), owned);
+    if (st) return st;
+    if (!h.empty()) {
+        hipError_t e = hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(SMG_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+#define CHK(call)                           \
+    do {                                    \
+        smg_status s_ = (call);             \
+        if (s_ != SMG_OK) return s_;        \
+    } while (0)
+
+extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_t *a0_rowptr,
+                                        const int32_t *a0_cols, const smg_opts *opts,
+                                        smg_solver *out) {
+    if (!h || !a0_rowptr || !a0_cols || !out) return fail(SMG_ERR_INVALID_ARG, "smg_solver_create: null argument");
+    const int n0 = h->H.sizes[0];
+    Csr A0;
+    A0.n = A0.m = n0;
+    A0.ptr.assign(a0_rowptr, a0_rowptr + n0 + 1);
+    if (A0.ptr[0] != 0) return fail(SMG_ERR_INVALID_ARG, "rowptr[0] != 0");
+    for (int i = 0; i < n0; ++i) if (A0.ptr[i + 1] < A0.ptr[i]) return fail(SMG_ERR_INVALID_ARG, "rowptr not monotone");
+    A0.idx.assign(a0_cols, a0_cols + A0.ptr[n0]);
+    for (int i = 0; i < n0; ++i)
+        for (int p = A0.ptr[i]; p < A0.ptr[i + 1]; ++p) {
+            if (A0.idx[p] < 0 || A0.idx[p] >= n0) return fail(SMG_ERR_INVALID_ARG, "column out of range");
+            if (p > A0.ptr[i] && A0.idx[p] <= A0.idx[p - 1]) return fail(SMG_ERR_INVALID_ARG, "columns not strictly ascending");
+        }
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SMG_ERR_INVALID_ARG, "bad device");
+    HIPCHK(hipSetDevice(device));
+    auto S = std::make_unique<smg_solver_s>();
+    S->device = device;
+    S->mu_pre = opts && opts->mu_pre >= 0 ? opts->mu_pre : 2;
+    S->mu_post = opts && opts->mu_post >= 0 ? opts->mu_post : 2;
+    if (!opts) S->mu_pre = S->mu_post = 2;
+    std::vector<LevelHost> levels;
+    std::string err;
+    if (build_levels(h->H, A0, levels, err) != 0) return fail(SMG_ERR_INVALID_ARG, "hierarchy setup: " + err);
+    S->nlev = h->H.nlev;
+    S->lev.resize(S->nlev);
+    int64_t tmax = 1;
+    int nmax = 1;
+    for (int l = 0; l < S->nlev; ++l) {
+        LevelHost &L = levels[l];
+        DevLevel &D = S->lev[l];
+        D.n = L.n;
+        D.coarsest = L.coarsest;
+        D.ncolors = L.ncolors;
+        D.nnz_nat = (int64_t)L.pat.idx.size();
+        D.pat_ptr = L.pat.ptr;
+        D.pat_idx = L.pat.idx;
+        D.store_h = L.store;
+        D.color_h = L.color;
+        nmax = std::max(nmax, L.n);
+        CHK(dupload(&D.perm, L.perm, S->owned));
+        CHK(dupload(&D.store, L.store, S->owned));
+        if (L.coarsest) {
+            CHK(dalloc(&D.dense, (size_t)L.n * L.n, S->owned));
+            CHK(dalloc(&D.dense_a, (size_t)L.n * L.n, S->owned));
+        } else {
+            const SellLayout &Sl = L.sell;
+            D.nslices = Sl.nslices;
+            D.color_slice = Sl.color_slice;
+            D.slots = Sl.slots();
+            std::vector<int32_t> row0 = Sl.slice_row0;
+            row0.push_back(L.n);
+            CHK(dupload(&D.slice_row0, row0, S->owned));
+            CHK(dupload(&D.slice_off, Sl.slice_off, S->owned));
+            CHK(dupload(&D.cols, Sl.cols, S->owned));
+            CHK(dupload(&D.rowlen, Sl.rowlen, S->owned));
+            CHK(dupload(&D.row_slice, Sl.row_slice, S->owned));
+            CHK(dalloc(&D.vals, (size_t)D.slots, S->owned));
+            CHK(dalloc(&D.diag, (size_t)L.n, S->owned));
+            CHK(dalloc(&D.vals32, (size_t)D.slots, S->owned));
+            CHK(dalloc(&D.diag32, (size_t)L.n, S->owned));
+            // transfer to the next level
+            CHK(dupload(&D.pc, L.pc, S->owned));
+            CHK(dupload(&D.pw, L.pw, S->owned));
+            std::vector<float> pw32(L.pw.begin(), L.pw.end()), rw32(L.rw.begin(), L.rw.end());
+            CHK(dupload(&D.pw32, pw32, S->owned));
+            CHK(dupload(&D.rptr, L.rptr, S->owned));
+            CHK(dupload(&D.ridx, L.ridx, S->owned));
+            CHK(dupload(&D.rw, L.rw, S->owned));
+            CHK(dupload(&D.rw32, rw32, S->owned));
+            CHK(dupload(&D.tptr, L.tptr, S->owned));
+            CHK(dupload(&D.plan1ptr, L.plan1ptr, S->owned));
+            CHK(dupload(&D.plan1, L.plan1, S->owned));
+            CHK(dupload(&D.plan2ptr, L.plan2ptr, S->owned));
+            CHK(dupload(&D.plan2, L.plan2, S->owned));
+            tmax = std::max<int64_t>(tmax, L.tptr.back());
+        }
+        const size_t nk = (size_t)L.n * 4;
+        CHK(dalloc(&D.x, nk, S->owned));
+        CHK(dalloc(&D.b, nk, S->owned));
+        CHK(dalloc(&D.r, nk, S->owned));
+        CHK(dalloc(&D.x32, nk, S->owned));
+        CHK(dalloc(&D.b32, nk, S->owned));
+        CHK(dalloc(&D.r32, nk, S->owned));
+        // release host-only setup data of this level
+        L = LevelHost();
+    }
+    CHK(dalloc(&S->tbuf, (size_t)tmax, S->owned));
+    int64_t maxblk = (nmax + 255) / 256 + 1;
+    for (const DevLevel &D : S->lev) maxblk = std::max<int64_t>(maxblk, (D.nslices + 3) / 4 + 1);
+    S->npartial = 2 * 4 * maxblk;
+    CHK(dalloc(&S->partial, (size_t)S->npartial, S->owned));
+    CHK(dalloc(&S->norms, 16, S->owned));
+    CHK(dalloc(&S->flag, 4, S->owned));
+    HIPCHK(hipHostMalloc((void **)&S->h_norms, 16 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S->h_flag, 4 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
+    *out = S.release();
+    return SMG_OK;
+}
+
+smg_solver_s::~smg_solver_s() {
+    (void)hipSetDevice(device);
+    for (auto &g : graphs) if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (void *p : owned) (void)hipFree(p);
+    if (h_norms) (void)hipHostFree(h_norms);
+    if (h_flag) (void)hipHostFree(h_flag);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
+}
+
+extern "C" void smg_solver_destroy(smg_solver s) { delete s; }
+
+extern "C" int32_t smg_num_levels(smg_solver s) { return s ? s->nlev : 0; }
+extern "C" int32_t smg_level_size(smg_solver s, int32_t l) {
+    return (s && l >= 0 && l < s->nlev) ? s->lev[l].n : -1;
+}
+extern "C" int64_t smg_level_nnz(smg_solver s, int32_t l) {
+    return (s && l >= 0 && l < s->nlev) ? s->lev[l].nnz_nat : -1;
+}
+extern "C" int32_t smg_level_colors(smg_solver s, int32_t l, int32_t *color) {
+    if (!s || l < 0 || l >= s->nlev) return -1;
+    const DevLevel &D = s->lev[l];
+    if (color && !D.coarsest) std::copy(D.color_h.begin(), D.color_h.end(), color);
+    return D.coarsest ? 0 : D.ncolors;
+}
+
+// ---------------------------------------------------------- mesh assembly
+extern "C" smg_status smg_solver_attach_mesh(smg_solver s, const int32_t *F, int32_t m) {
+    if (!s || !F || m < 1) return fail(SMG_ERR_INVALID_ARG, "smg_solver_attach_mesh: bad arguments");
+    HIPCHK(hipSetDevice(s->device));
+    const DevLevel &D = s->lev[0];
+    const int n = D.n;
+    auto find = [&](int i, int j) -> int {
+        auto b = D.pat_idx.begin() + D.pat_ptr[i], e = D.pat_idx.begin() + D.pat_ptr[i + 1];
+        auto it = std::lower_bound(b, e, j);
+        return (it != e && *it == j) ? (int)(it - D.pat_idx.begin()) : -1;
+    };
+    std::vector<int32_t> vf_ptr(n + 1, 0), vf_face, slot_a, slot_b, diag_pos(n), eoe(D.pat_idx.size(), -1);
+    for (int f = 0; f < m; ++f)
+        for (int c = 0; c < 3; ++c) {
+            const int v = F[3 * f + c];
+            if (v < 0 || v >= n) return fail(SMG_ERR_INVALID_ARG, "face index out of range");
+            vf_ptr[v + 1]++;
+        }
+    for (int v = 0; v < n; ++v) vf_ptr[v + 1] += vf_ptr[v];
+    vf_face.resize(vf_ptr[n]);
+    slot_a.resize(vf_ptr[n]);
+    slot_b.resize(vf_ptr[n]);
+    std::vector<int32_t> fill(vf_ptr.begin(), vf_ptr.end() - 1);
+    for (int f = 0; f < m; ++f)
+        for (int c = 0; c < 3; ++c) {
+            const int v = F[3 * f + c], a = F[3 * f + (c + 1) % 3], b = F[3 * f + (c + 2) % 3];
+            const int q = fill[v]++;
+            vf_face[q] = f;
+            slot_a[q] = find(v, a);
+            slot_b[q] = find(v, b);
+            if (slot_a[q] < 0 || slot_b[q] < 0) return fail(SMG_ERR_INVALID_ARG, "mesh edge missing from the level-0 pattern");
+        }
+    int32_t eid = 0;
+    for (int i = 0; i < n; ++i) {
+        diag_pos[i] = find(i, i);
+        for (int p = D.pat_ptr[i]; p < D.pat_ptr[i + 1]; ++p)
+            if (D.pat_idx[p] > i) eoe[p] = eid++;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int p = D.pat_ptr[i]; p < D.pat_ptr[i + 1]; ++p)
+            if (D.pat_idx[p] < i) eoe[p] = eoe[find(D.pat_idx[p], i)];
+    MeshDev &M = s->mesh;
+    M.n = n;
+    M.m = m;
+    M.nedges = eid;
+    std::vector<int32_t> Fv(F, F + 3 * (size_t)m);
+    CHK(dupload(&M.faces, Fv, s->owned));
+    CHK(dupload(&M.vf_ptr, vf_ptr, s->owned));
+    CHK(dupload(&M.vf_face, vf_face, s->owned));
+    CHK(dupload(&M.slot_a, slot_a, s->owned));
+    CHK(dupload(&M.slot_b, slot_b, s->owned));
+    CHK(dupload(&M.eoe, eoe, s->owned));
+    CHK(dupload(&M.diag_pos, diag_pos, s->owned));
+    CHK(dupload(&M.rowptr, D.pat_ptr, s->owned));
+    CHK(dupload(&M.cols, D.pat_idx, s->owned));
+    M.attached = true;
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_assemble(smg_solver s, const double *d_V, double t,
+                                   const double *d_mass_scale, const float *d_edge_w,
+                                   double *d_a0_vals, double *d_l_vals, double *d_mass,
+                                   smg_stream stream) {
+    if (!s || !d_V || !d_a0_vals) return fail(SMG_ERR_INVALID_ARG, "smg_assemble: null argument");
+    if (!s->mesh.attached) return fail(SMG_ERR_STATE, "smg_assemble: no mesh attached");
+    HIPCHK(hipSetDevice(s->device));
+    const MeshDev &M = s->mesh;
+    MeshView mv{M.n, M.vf_ptr, M.vf_face, M.faces, M.slot_a, M.slot_b, M.eoe, M.diag_pos, M.rowptr};
+    HIPCHK(launch_assemble(mv, d_V, t, d_mass_scale, d_edge_w, d_a0_vals, d_l_vals, d_mass,
+                           (hipStream_t)stream));
+    return SMG_OK;
+}
+
+// -------------------------------------------------------- hierarchy values
+extern "C" smg_status smg_set_values(smg_solver s, const double *d_a0_vals, smg_stream stream) {
+    if (!s || !d_a0_vals) return fail(SMG_ERR_INVALID_ARG, "smg_set_values: null argument");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    CHK(refresh_values(s, d_a0_vals, st));
+    HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (s->h_flag[0]) { s->values_set = false; return fail(SMG_ERR_NONFINITE, "non-finite matrix value"); }
+    if (s->h_flag[1]) { s->values_set = false; return fail(SMG_ERR_NOT_SPD, "coarsest Cholesky: non-positive pivot"); }
+    s->values_set = true;
+    return SMG_OK;
+}
+
+namespace smg {
+
+smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st) {
+    HIPCHK(launch_fill<int>(s->flag, 0, 2, st));
+    for (int l = 0; l < s->nlev; ++l) {
+        DevLevel &D = s->lev[l];
+        if (D.coarsest) HIPCHK(launch_fill<double>(D.dense_a, 0.0, (int64_t)D.n * D.n, st));
+        else {
+            HIPCHK(launch_fill<double>(D.vals, 0.0, D.slots, st));
+            HIPCHK(launch_fill<double>(D.diag, 0.0, D.n, st));
+        }
+    }
+    DevLevel &L0 = s->lev[0];
+    HIPCHK(launch_scatter_values(d_a0_vals, L0.store, L0.nnz_nat, L0.coarsest ? L0.dense_a : L0.vals,
+                                 L0.coarsest ? nullptr : L0.diag, s->flag, st));
+    for (int l = 0; l + 1 < s->nlev; ++l) {
+        DevLevel &D = s->lev[l];
+        DevLevel &C = s->lev[l + 1];
+        HIPCHK(launch_galerkin_t(D.n, D.tptr, D.plan1ptr, D.plan1, D.row_slice, D.slice_row0,
+                                 D.slice_off, D.rowlen, D.cols, D.vals, D.diag, D.pc, D.pw,
+                                 s->tbuf, st));
+        HIPCHK(launch_galerkin_c(C.n, D.plan2ptr, D.plan2, D.rptr, D.ridx, D.rw, D.tptr, s->tbuf,
+                                 C.coarsest ? C.dense_a : C.vals, C.coarsest ? nullptr : C.diag, st));
+    }
+    for (int l = 0; l < s->nlev; ++l) {
+        DevLevel &D = s->lev[l];
+        if (D.coarsest) continue;
+        HIPCHK(launch_to_f32(D.vals, D.vals32, D.slots, st));
+        HIPCHK(launch_to_f32(D.diag, D.diag32, D.n, st));
+    }
+    DevLevel &Lc = s->lev[s->nlev - 1];
+    HIPCHK(hipMemcpyAsync(Lc.dense, Lc.dense_a, (size_t)Lc.n * Lc.n * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_cholesky(Lc.dense, Lc.n, s->flag + 1, st));
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+extern "C" smg_status smg_get_level_matrix(smg_solver s, int32_t l, int32_t *rowptr, int32_t *cols,
+                                           double *vals) {
+    if (!s || l < 0 || l >= s->nlev || !rowptr || !cols || !vals) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    if (!s->values_set) return fail(SMG_ERR_STATE, "values not set");
+    HIPCHK(hipSetDevice(s->device));
+    const DevLevel &D = s->lev[l];
+    std::copy(D.pat_ptr.begin(), D.pat_ptr.end(), rowptr);
+    std::copy(D.pat_idx.begin(), D.pat_idx.end(), cols);
+    if (D.coarsest) {
+        std::vector<double> dense((size_t)D.n * D.n);
+        HIPCHK(hipMemcpy(dense.data(), D.dense_a, dense.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t p = 0; p < D.store_h.size(); ++p) vals[p] = dense[D.store_h[p]];
+    } else {
+        std::vector<double> sv((size_t)D.slots), dg(D.n);
+        HIPCHK(hipMemcpy(sv.data(), D.vals, sv.size() * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(dg.data(), D.diag, dg.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t p = 0; p < D.store_h.size(); ++p) {
+            const int32_t sp = D.store_h[p];
+            vals[p] = sp >= 0 ? sv[sp] : dg[-1 - sp];
+        }
+    }
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_get_coarse_factor(smg_solver s, double *G) {
+    if (!s || !G) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    if (!s->values_set) return fail(SMG_ERR_STATE, "values not set");
+    HIPCHK(hipSetDevice(s->device));
+    const DevLevel &D = s->lev[s->nlev - 1];
+    HIPCHK(hipMemcpy(G, D.dense, (size_t)D.n * D.n * sizeof(double), hipMemcpyDeviceToHost));
+    return SMG_OK;
+}
+
+// ----------------------------------------------------------- V-cycle core
+namespace smg {
+
+template <typename T>
+static SellView<T> sell_view(const DevLevel &D);
+template <>
+SellView<double> sell_view<double>(const DevLevel &D) {
+    return {D.n, D.slice_row0, D.slice_off, D.cols, D.vals, D.diag};
+}
+template <>
+SellView<float> sell_view<float>(const DevLevel &D) {
+    return {D.n, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32};
+}
+static TransferView transfer_view(const DevLevel &D, const DevLevel &C) {
+    return {D.n, C.n, D.pc, D.rptr, D.ridx};
+}
+template <typename T> static T *xbuf(DevLevel &D);
+template <> double *xbuf<double>(DevLevel &D) { return D.x; }
+template <> float *xbuf<float>(DevLevel &D) { return D.x32; }
+template <typename T> static T *bbuf(DevLevel &D);
+template <> double *bbuf<double>(DevLevel &D) { return D.b; }
+template <> float *bbuf<float>(DevLevel &D) { return D.b32; }
+template <typename T> static T *rbuf(DevLevel &D);
+template <> double *rbuf<double>(DevLevel &D) { return D.r; }
+template <> float *rbuf<float>(DevLevel &D) { return D.r32; }
+template <typename T> static const T *pwbuf(const DevLevel &D);
+template <> const double *pwbuf<double>(const DevLevel &D) { return D.pw; }
+template <> const float *pwbuf<float>(const DevLevel &D) { return D.pw32; }
+template <typename T> static const T *rwbuf(const DevLevel &D);
+template <> const double *rwbuf<double>(const DevLevel &D) { return D.rw; }
+template <> const float *rwbuf<float>(const DevLevel &D) { return D.rw32; }
+
+template <typename T>
+smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    const SellView<T> A = sell_view<T>(D);
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int c = 0; c < D.ncolors; ++c)
+            HIPCHK(launch_gs_color<T>(A, D.color_slice[c], D.color_slice[c + 1], bbuf<T>(D), xbuf<T>(D), k, st));
+    return SMG_OK;
+}
+
+template <typename T>
+smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    int nblk = 0;
+    HIPCHK(launch_residual<T>(sell_view<T>(D), D.nslices, bbuf<T>(D), xbuf<T>(D), rbuf<T>(D), k,
+                              norms ? s->partial : nullptr, &nblk, st));
+    if (norms) HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st));
+    return SMG_OK;
+}
+
+// Alg. "V-cycle" from level l with b_l, x_l in the level buffers (x_l in/out).
+template <typename T>
+smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    if (D.coarsest) {
+        HIPCHK((launch_coarse_solve<T, T>(D.dense, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
+        return SMG_OK;
+    }
+    DevLevel &C = s->lev[l + 1];
+    const TransferView P = transfer_view(D, C);
+    CHK(smooth_level<T>(s, l, k, s->mu_pre, st));                  // pre-relaxation
+    CHK(residual_level<T>(s, l, k, false, st));                    // r = b - A x'
+    HIPCHK(launch_restrict<T>(P, rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st));   // P^T r
+    if (!C.coarsest) HIPCHK(launch_fill<T>(xbuf<T>(C), T(0), (int64_t)C.n * k, st));
+    CHK(vcycle_from<T>(s, l + 1, k, st));                           // coarse correction
+    HIPCHK(launch_prolong_add<T>(P, pwbuf<T>(D), xbuf<T>(C), xbuf<T>(D), k, st));  // x' + P c
+    CHK(smooth_level<T>(s, l, k, s->mu_post, st));                 // post-relaxation
+    return SMG_OK;
+}
+
+template smg_status vcycle_from<double>(smg_solver_s *, int, int, hipStream_t);
+template smg_status vcycle_from<float>(smg_solver_s *, int, int, hipStream_t);
+template smg_status residual_level<double>(smg_solver_s *, int, int, bool, hipStream_t);
+template smg_status residual_level<float>(smg_solver_s *, int, int, bool, hipStream_t);
+
+}  // namespace smg
+
+// ----------------------------------------------------- per-step entry points
+static smg_status check_level(smg_solver s, int l, int k) {
+    if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
+    if (l < 0 || l >= s->nlev) return fail(SMG_ERR_INVALID_ARG, "level out of range");
+    if (k < 1 || k > 4) return fail(SMG_ERR_INVALID_ARG, "k must be 1..4");
+    if (!s->values_set) return fail(SMG_ERR_STATE, "values not set");
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_residual(smg_solver s, int32_t l, const double *d_b, const double *d_x,
+                                   double *d_r, int32_t k, smg_stream stream) {
+    CHK(check_level(s, l, k));
+    if (!d_b || !d_x || !d_r) return fail(SMG_ERR_INVALID_ARG, "null vector");
+    if (s->lev[l].coarsest) return fail(SMG_ERR_INVALID_ARG, "residual on the coarsest level is not part of the cycle");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[l];
+    HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
+    CHK(residual_level<double>(s, l, k, false, st));
+    HIPCHK(launch_scatter_rows(D.perm, D.r, d_r, D.n, k, st));
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_smooth(smg_solver s, int32_t l, const double *d_b, double *d_x,
+                                 int32_t k, int32_t sweeps, smg_stream stream) {
+    CHK(check_level(s, l, k));
+    if (!d_b || !d_x || sweeps < 0) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    if (s->lev[l].coarsest) return fail(SMG_ERR_INVALID_ARG, "the coarsest level is not smoothed");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[l];
+    HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
+    CHK(smooth_level<double>(s, l, k, sweeps, st));
+    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_restrict(smg_solver s, int32_t l, const double *d_r, double *d_rc,
+                                   int32_t k, smg_stream stream) {
+    CHK(check_level(s, l, k));
+    if (l + 1 >= s->nlev || !d_r || !d_rc) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[l], &C = s->lev[l + 1];
+    HIPCHK(launch_gather_rows(D.perm, d_r, D.r, D.n, k, st));
+    HIPCHK(launch_restrict<double>(transfer_view(D, C), D.rw, D.r, C.b, k, st));
+    HIPCHK(launch_scatter_rows(C.perm, C.b, d_rc, C.n, k, st));
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_prolong_add(smg_solver s, int32_t l, const double *d_e, double *d_x,
+                                      int32_t k, smg_stream stream) {
+    CHK(check_level(s, l, k));
+    if (l + 1 >= s->nlev || !d_e || !d_x) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[l], &C = s->lev[l + 1];
+    HIPCHK(launch_gather_rows(C.perm, d_e, C.x, C.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
+    HIPCHK(launch_prolong_add<double>(transfer_view(D, C), D.pw, C.x, D.x, k, st));
+    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_coarse_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                                       smg_stream stream) {
+    if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
+    CHK(check_level(s, s->nlev - 1, k));
+    if (!d_b || !d_x) return fail(SMG_ERR_INVALID_ARG, "null vector");
+    HIPCHK(hipSetDevice(s->device));
+    const DevLevel &D = s->lev[s->nlev - 1];
+    HIPCHK((launch_coarse_solve<double, double>(D.dense, D.n, d_b, d_x, k, (hipStream_t)stream)));
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_vcycle(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                                 smg_stream stream) {
+    CHK(check_level(s, 0, k));
+    if (!d_b || !d_x) return fail(SMG_ERR_INVALID_ARG, "null vector");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[0];
+    HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
+    CHK(vcycle_from<double>(s, 0, k, st));
+    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
+    return SMG_OK;
+}
+
+// ------------------------------------------------------------------ solve
+namespace smg {
+
+// read back the column norms (sum of squares, max) reduced into s->norms
+static smg_status fetch_norms(smg_solver_s *s, int k, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(s->h_norms, s->norms, 2 * k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SMG_OK;
+}
+
+// one refinement or plain cycle, enqueued; ends with the FP64 level-0
+// residual and its column norms in s->norms
+smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st) {
+    DevLevel &D = s->lev[0];
+    if (precision == SMG_FP64) {
+        CHK(vcycle_from<double>(s, 0, k, st));
+    } else {
+        HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
+        HIPCHK(launch_fill<float>(D.x32, 0.0f, (int64_t)D.n * k, st));
+        CHK(vcycle_from<float>(s, 0, k, st));
+        HIPCHK(launch_ir_up(D.x32, s->norms, D.x, D.n, k, st));
+    }
+    if (D.coarsest) {
+        // single-level hierarchy: the residual is not smoothed-level work
+        return SMG_OK;
+    }
+    CHK(residual_level<double>(s, 0, k, true, st));
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                                const smg_solve_params *p, smg_solve_info *info,
+                                smg_stream stream) {
+    CHK(check_level(s, 0, k));
+    if (!d_b || !d_x || !p) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    if (p->precision != SMG_FP64 && p->precision != SMG_FP32_IR) return fail(SMG_ERR_INVALID_ARG, "bad precision");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t caller = (hipStream_t)stream;
+    DevLevel &D = s->lev[0];
+    if (D.coarsest) return smg_solve_single_level(s, d_b, d_x, k, p, info, caller);
+    const auto t0 = std::chrono::steady_clock::now();
+    // graph capture needs a capturable stream: the cycles then run on the
+    // solver's own stream, ordered after and before the caller's work
+    hipStream_t st = caller;
+    if (p->use_graph) {
+        st = s->gstream;
+        HIPCHK(hipEventRecord(s->ev_in, caller));
+        HIPCHK(hipStreamWaitEvent(st, s->ev_in, 0));
+    }
+    HIPCHK(launch_fill<int>(s->flag, 0, 1, st));
+    HIPCHK(launch_check_finite(d_b, (int64_t)D.n * k, s->flag, st));
+    HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
+    HIPCHK(launch_fill<double>(D.x, 0.0, (int64_t)D.n * k, st));
+    // r = b for x0 = 0 (FP32_IR needs r and its max-norm in s->norms)
+    int nblk = 0;
+    HIPCHK(hipMemcpyAsync(D.r, D.b, (size_t)D.n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_colnorm_partial(D.b, D.n, k, s->partial, &nblk, st));
+    HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st));
+    HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(fetch_norms(s, k, st));
+    if (s->h_flag[0]) return fail(SMG_ERR_NONFINITE, "non-finite right-hand side");
+    double bn[4], rho[4];
+    for (int q = 0; q < k; ++q) {
+        bn[q] = std::sqrt(s->h_norms[q]);
+        rho[q] = bn[q] > 0.0 ? 1.0 : 0.0;
+    }
+    int cycles = 0;
+    smg_status status = SMG_OK;
+    hipGraphExec_t gexec = nullptr;
+    if (p->use_graph) CHK(get_cycle_graph(s, k, p->precision, st, &gexec));
+    for (;;) {
+        double worst = 0.0;
+        for (int q = 0; q < k; ++q) worst = std::max(worst, rho[q]);
+        if (p->fixed_cycles > 0) {
+            if (cycles >= p->fixed_cycles) break;
+        } else if (worst <= p->rtol) {
+            break;
+        } else if (cycles >= p->max_cycles) {
+            status = SMG_ERR_NO_CONVERGENCE;
+            break;
+        }
+        if (gexec) HIPCHK(hipGraphLaunch(gexec, st));
+        else CHK(cycle_enqueue(s, k, p->precision, st));
+        ++cycles;
+        if (p->fixed_cycles > 0 && cycles < p->fixed_cycles) continue;
+        CHK(fetch_norms(s, k, st));
+        for (int q = 0; q < k; ++q) {
+            const double rn = std::sqrt(s->h_norms[q]);
+            rho[q] = bn[q] > 0.0 ? rn / bn[q] : rn;
+            if (!std::isfinite(rho[q])) status = SMG_ERR_NONFINITE;
+        }
+        if (status == SMG_ERR_NONFINITE) break;
+    }
+    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
+    if (st != caller) {
+        HIPCHK(hipEventRecord(s->ev_out, st));
+        HIPCHK(hipStreamWaitEvent(caller, s->ev_out, 0));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) {
+        info->cycles = cycles;
+        info->k = k;
+        for (int q = 0; q < 4; ++q) info->rel_res[q] = q < k ? rho[q] : 0.0;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status == SMG_ERR_NO_CONVERGENCE) return fail(status, "cycle cap reached");
+    if (status == SMG_ERR_NONFINITE) return fail(status, "non-finite residual");
+    return SMG_OK;
+}
+
+namespace smg {
+
+// a one-level hierarchy: the V-cycle is the direct solve
+smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_x, int k,
+                                  const smg_solve_params *p, smg_solve_info *info, hipStream_t st) {
+    (void)p;
+    const DevLevel &D = s->lev[0];
+    HIPCHK((launch_coarse_solve<double, double>(D.dense, D.n, d_b, d_x, k, st)));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) {
+        info->cycles = 1;
+        info->k = k;
+        for (int q = 0; q < 4; ++q) info->rel_res[q] = 0.0;
+        info->ms = 0.0;
+    }
+    return SMG_OK;
+}
+
+// Capture one cycle (V-cycle + FP64 residual with norms) into a hipGraph.
+// No memset nodes are recorded: buffers are cleared by fill kernels.
+smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st,
+                           hipGraphExec_t *out) {
+    for (auto &g : s->graphs)
+        if (g.k == k && g.precision == precision && g.stream == st) { *out = g.exec; return SMG_OK; }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    smg_status rc = cycle_enqueue(s, k, precision, st);
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc != SMG_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+    if (e != hipSuccess) return fail(SMG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    s->graphs.push_back({k, precision, st, exec});
+    *out = exec;
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+// ------------------------------------------------- adjoint helper kernels
+extern "C" smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const double *d_lambda,
+                                   const double *d_u, double *h_out, smg_stream stream) {
+    if (!s || !d_l_vals || !d_lambda || !d_u || !h_out) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    if (!s->mesh.attached) return fail(SMG_ERR_STATE, "no mesh attached (level-0 pattern on device)");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    int nblk = 0;
+    HIPCHK(launch_spmv_dot(s->mesh.rowptr, s->mesh.cols, d_l_vals, d_lambda, d_u, s->lev[0].n,
+                           s->partial, &nblk, st));
+    HIPCHK(launch_reduce_partial(s->partial, nblk, 1, s->norms, st));
+    CHK(fetch_norms(s, 1, st));
+    *h_out = s->h_norms[0];
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const double *d_m,
+                                    const double *d_u, double *d_out, smg_stream stream) {
+    if (!s || !d_lambda || !d_m || !d_u || !d_out) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(launch_mass_grad(d_lambda, d_m, d_u, d_out, s->lev[0].n, (hipStream_t)stream));
+    return SMG_OK;
+}

@@ -1,0 +1,271 @@
+// Host setup of the device hierarchy: coloring (App. A, Alg. "Graph
+// Coloring"), color-major permutation, sliced-ELL layout, restriction
+// R = P^T, and the symbolic Galerkin products A_{l+1} = P_l^T A_l P_l (Eq. gca)
+// with the plans that let the device recompute their values for any A_0.
+#include "hier.h"
+
+#include <algorithm>
+#include <numeric>
+
+namespace smg {
+
+// Alg. "Graph Coloring": descending degree (ties ascending index); first
+// palette color absent among painted neighbours, moved to the palette's back;
+// otherwise a new color appended.  Colors are numbered by creation.
+int greedy_coloring(int n, const int32_t *rowptr, const int32_t *cols, std::vector<int32_t> &color) {
+    std::vector<int32_t> degree(n);
+    for (int i = 0; i < n; ++i) {
+        int d = 0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) d += cols[p] != i;
+        degree[i] = d;
+    }
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degree[a] > degree[b]; });
+    color.assign(n, -1);
+    std::vector<int32_t> palette;
+    std::vector<int32_t> taken;   // taken[c] == node + 1 marks color c as used around node
+    for (int node : order) {
+        for (int p = rowptr[node]; p < rowptr[node + 1]; ++p) {
+            const int nb = cols[p];
+            if (nb != node && color[nb] >= 0) taken[color[nb]] = node + 1;
+        }
+        auto it = std::find_if(palette.begin(), palette.end(), [&](int c) { return taken[c] != node + 1; });
+        int c;
+        if (it == palette.end()) {
+            c = (int)taken.size();
+            taken.push_back(0);
+            palette.push_back(c);
+        } else {
+            c = *it;
+            palette.erase(it);
+            palette.push_back(c);
+        }
+        color[node] = c;
+    }
+    return (int)taken.size();
+}
+
+Csr galerkin_pattern(const Csr &A, int nc, const std::vector<int32_t> &pcols) {
+    const int n = A.n;
+    // R = P^T structure
+    std::vector<int32_t> rptr(nc + 1, 0);
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < 3; ++m) if (pcols[3 * i + m] >= 0) rptr[pcols[3 * i + m] + 1]++;
+    for (int a = 0; a < nc; ++a) rptr[a + 1] += rptr[a];
+    std::vector<int32_t> ridx(rptr[nc]);
+    std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < 3; ++m) if (pcols[3 * i + m] >= 0) ridx[fill[pcols[3 * i + m]]++] = i;
+    Csr C;
+    C.n = C.m = nc;
+    C.ptr.assign(nc + 1, 0);
+    std::vector<int32_t> mark(nc, -1), row;
+    for (int a = 0; a < nc; ++a) {
+        row.clear();
+        for (int q = rptr[a]; q < rptr[a + 1]; ++q) {
+            const int i = ridx[q];
+            for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+                const int j = A.idx[p];
+                for (int m = 0; m < 3; ++m) {
+                    const int b = pcols[3 * j + m];
+                    if (b >= 0 && mark[b] != a) { mark[b] = a; row.push_back(b); }
+                }
+            }
+        }
+        std::sort(row.begin(), row.end());
+        C.idx.insert(C.idx.end(), row.begin(), row.end());
+        C.ptr[a + 1] = (int32_t)C.idx.size();
+    }
+    return C;
+}
+
+static void build_sell(LevelHost &L) {
+    SellLayout &S = L.sell;
+    const int n = L.n;
+    S.n = n;
+    // permuted off-diagonal pattern, ascending permuted columns
+    S.pptr.assign(n + 1, 0);
+    S.rowlen.assign(n, 0);
+    for (int r = 0; r < n; ++r) {
+        const int i = L.perm[r];
+        S.rowlen[r] = (L.pat.ptr[i + 1] - L.pat.ptr[i]) - 1;
+        S.pptr[r + 1] = S.pptr[r] + S.rowlen[r];
+    }
+    S.pidx.resize(S.pptr[n]);
+    for (int r = 0; r < n; ++r) {
+        const int i = L.perm[r];
+        int o = S.pptr[r];
+        for (int p = L.pat.ptr[i]; p < L.pat.ptr[i + 1]; ++p)
+            if (L.pat.idx[p] != i) S.pidx[o++] = L.iperm[L.pat.idx[p]];
+        std::sort(S.pidx.begin() + S.pptr[r], S.pidx.begin() + S.pptr[r + 1]);
+    }
+    // slices of 64 rows that never straddle two colors
+    S.slice_row0.clear();
+    S.slice_off.assign(1, 0);
+    S.color_slice.assign(1, 0);
+    S.row_slice.assign(n, 0);
+    for (int c = 0; c < L.ncolors; ++c) {
+        for (int r0 = S.color_row[c]; r0 < S.color_row[c + 1]; r0 += 64) {
+            const int r1 = std::min(r0 + 64, S.color_row[c + 1]);
+            int w = 0;
+            for (int r = r0; r < r1; ++r) { w = std::max(w, S.rowlen[r]); S.row_slice[r] = (int)S.slice_row0.size(); }
+            S.slice_row0.push_back(r0);
+            S.slice_off.push_back(S.slice_off.back() + 64 * w);
+        }
+        S.color_slice.push_back((int)S.slice_row0.size());
+    }
+    S.nslices = (int)S.slice_row0.size();
+    S.cols.assign(S.slots(), 0);
+    for (int s = 0; s < S.nslices; ++s) {
+        const int w = (S.slice_off[s + 1] - S.slice_off[s]) / 64;
+        for (int t = 0; t < 64; ++t) {
+            const int r = S.slice_row0[s] + t;
+            const bool valid = r < n && S.row_slice[r] == s;
+            for (int e = 0; e < w; ++e) {
+                const int slot = S.slice_off[s] + e * 64 + t;
+                if (valid && e < S.rowlen[r]) S.cols[slot] = S.pidx[S.pptr[r] + e];
+                else S.cols[slot] = valid ? r : S.slice_row0[s];   // padding: weight 0
+            }
+        }
+    }
+}
+
+// storage position of entry (r, c) of level L (permuted indices)
+static int32_t store_pos(const LevelHost &L, int r, int c) {
+    if (L.coarsest) return r + c * L.n;
+    if (r == c) return -1 - r;
+    const SellLayout &S = L.sell;
+    const int32_t *b = S.pidx.data() + S.pptr[r], *e = S.pidx.data() + S.pptr[r + 1];
+    const int32_t *it = std::lower_bound(b, e, c);
+    if (it == e || *it != c) return INT32_MIN;
+    return S.slot(r, (int)(it - b));
+}
+
+int build_levels(const HierHost &H, const Csr &A0, std::vector<LevelHost> &levels, std::string &err) {
+    const int nlev = H.nlev;
+    levels.assign(nlev, LevelHost());
+    Csr pat = A0;
+    for (int l = 0; l < nlev; ++l) {
+        LevelHost &L = levels[l];
+        L.n = H.sizes[l];
+        L.pat = pat;
+        L.coarsest = l == nlev - 1;
+        if (pat.n != L.n) { err = "pattern size mismatch at level " + std::to_string(l); return -1; }
+        for (int i = 0; i < L.n; ++i) {   // diagonal must be present
+            bool d = false;
+            for (int p = pat.ptr[i]; p < pat.ptr[i + 1]; ++p) d |= pat.idx[p] == i;
+            if (!d) { err = "missing diagonal entry"; return -1; }
+        }
+        L.perm.resize(L.n);
+        L.iperm.resize(L.n);
+        if (!L.coarsest) {
+            L.ncolors = greedy_coloring(L.n, pat.ptr.data(), pat.idx.data(), L.color);
+            std::vector<int32_t> cnt(L.ncolors + 1, 0);
+            for (int i = 0; i < L.n; ++i) cnt[L.color[i] + 1]++;
+            for (int c = 0; c < L.ncolors; ++c) cnt[c + 1] += cnt[c];
+            L.sell.color_row = cnt;
+            for (int i = 0; i < L.n; ++i) L.perm[cnt[L.color[i]]++] = i;
+        } else {
+            std::iota(L.perm.begin(), L.perm.end(), 0);
+        }
+        for (int r = 0; r < L.n; ++r) L.iperm[L.perm[r]] = r;
+        if (!L.coarsest) build_sell(L);
+        if (l + 1 < nlev) pat = galerkin_pattern(pat, H.sizes[l + 1], H.pcols[l]);
+    }
+    for (int l = 0; l < nlev; ++l) {
+        LevelHost &L = levels[l];
+        L.store.resize(L.pat.idx.size());
+        for (int i = 0; i < L.n; ++i)
+            for (int p = L.pat.ptr[i]; p < L.pat.ptr[i + 1]; ++p)
+                L.store[p] = store_pos(L, L.iperm[i], L.iperm[L.pat.idx[p]]);
+        if (l + 1 == nlev) break;
+        const LevelHost &C = levels[l + 1];
+        const int n = L.n, nc = C.n;
+        // prolongation, permuted, SoA
+        L.pc.assign(3 * (size_t)n, 0);
+        L.pw.assign(3 * (size_t)n, 0.0);
+        for (int r = 0; r < n; ++r) {
+            const int i = L.perm[r];
+            int first = -1;
+            for (int m = 0; m < 3; ++m)
+                if (H.pcols[l][3 * i + m] >= 0 && H.pw[l][3 * i + m] > 0.0) { first = C.iperm[H.pcols[l][3 * i + m]]; break; }
+            if (first < 0) { err = "empty prolongation row"; return -1; }
+            for (int m = 0; m < 3; ++m) {
+                const int col = H.pcols[l][3 * i + m];
+                const double w = H.pw[l][3 * i + m];
+                const bool used = col >= 0 && w > 0.0;
+                L.pc[(size_t)m * n + r] = used ? C.iperm[col] : first;
+                L.pw[(size_t)m * n + r] = used ? w : 0.0;
+            }
+        }
+        // R = P^T over permuted coarse rows, fine rows ascending
+        L.rptr.assign(nc + 1, 0);
+        for (int r = 0; r < n; ++r)
+            for (int m = 0; m < 3; ++m) if (L.pw[(size_t)m * n + r] > 0.0) L.rptr[L.pc[(size_t)m * n + r] + 1]++;
+        for (int a = 0; a < nc; ++a) L.rptr[a + 1] += L.rptr[a];
+        L.ridx.resize(L.rptr[nc]);
+        L.rw.resize(L.rptr[nc]);
+        {
+            std::vector<int32_t> fill(L.rptr.begin(), L.rptr.end() - 1);
+            for (int r = 0; r < n; ++r)
+                for (int m = 0; m < 3; ++m) {
+                    const double w = L.pw[(size_t)m * n + r];
+                    if (w > 0.0) {
+                        const int a = L.pc[(size_t)m * n + r];
+                        L.ridx[fill[a]] = r;
+                        L.rw[fill[a]] = w;
+                        fill[a]++;
+                    }
+                }
+        }
+        // T = A P pattern per permuted fine row; plan1 maps (source, slot) -> T offset
+        L.tptr.assign(n + 1, 0);
+        L.plan1ptr.assign(n + 1, 0);
+        std::vector<int32_t> tcols;
+        std::vector<int32_t> row;
+        for (int r = 0; r < n; ++r) {
+            row.clear();
+            auto add_src = [&](int src) {
+                for (int m = 0; m < 3; ++m)
+                    if (L.pw[(size_t)m * n + src] > 0.0) row.push_back(L.pc[(size_t)m * n + src]);
+            };
+            add_src(r);
+            for (int e = 0; e < L.sell.rowlen[r]; ++e) add_src(L.sell.pidx[L.sell.pptr[r] + e]);
+            std::sort(row.begin(), row.end());
+            row.erase(std::unique(row.begin(), row.end()), row.end());
+            if (row.size() > 65535) { err = "Galerkin row too long"; return -1; }
+            tcols.insert(tcols.end(), row.begin(), row.end());
+            L.tptr[r + 1] = (int32_t)tcols.size();
+            auto emit = [&](int src) {
+                for (int m = 0; m < 3; ++m) {
+                    const int b = L.pc[(size_t)m * n + src];
+                    const bool used = L.pw[(size_t)m * n + src] > 0.0;
+                    int off = 0;
+                    if (used) off = (int)(std::lower_bound(row.begin(), row.end(), b) - row.begin());
+                    L.plan1.push_back((uint16_t)off);
+                }
+            };
+            emit(r);
+            for (int e = 0; e < L.sell.rowlen[r]; ++e) emit(L.sell.pidx[L.sell.pptr[r] + e]);
+            L.plan1ptr[r + 1] = (int32_t)L.plan1.size();
+        }
+        // plan2: for coarse row a, for R entry (r, w), for T entry (r, b): position of (a, b)
+        L.plan2ptr.assign(nc + 1, 0);
+        for (int a = 0; a < nc; ++a) {
+            for (int q = L.rptr[a]; q < L.rptr[a + 1]; ++q) {
+                const int r = L.ridx[q];
+                for (int t = L.tptr[r]; t < L.tptr[r + 1]; ++t) {
+                    const int32_t pos = store_pos(C, a, tcols[t]);
+                    if (pos == INT32_MIN) { err = "Galerkin plan outside the symbolic pattern"; return -1; }
+                    L.plan2.push_back(pos);
+                }
+            }
+            if (L.plan2.size() > (size_t)INT32_MAX) { err = "Galerkin plan too large"; return -1; }
+            L.plan2ptr[a + 1] = (int32_t)L.plan2.size();
+        }
+    }
+    return 0;
+}
+
+}  // namespace smg

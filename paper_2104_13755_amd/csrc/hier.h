@@ -1,0 +1,95 @@
+// Host-side data structures of the surface-multigrid library.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace smg {
+
+// One decimation level produced by the successive self-parameterization.
+struct LevelOut {
+    std::vector<double> X;        // coarse positions, 3 per vertex
+    std::vector<int32_t> F;       // coarse triangles, 3 per face
+    std::vector<int32_t> pcols;   // fine vertex -> 3 coarse columns (-1 unused)
+    std::vector<double> pw;       // matching barycentric weights (0 unused)
+    double stats[8];
+};
+
+int ssp_decimate_level(const std::vector<double> &X, const std::vector<int32_t> &F, int target,
+                       bool interior_only, LevelOut &out);
+
+// Greedy coloring of a CSR pattern's off-diagonal graph (Alg. "Graph Coloring").
+int greedy_coloring(int n, const int32_t *rowptr, const int32_t *cols, std::vector<int32_t> &color);
+
+// Plain CSR pattern (+ optional values).
+struct Csr {
+    int n = 0, m = 0;
+    std::vector<int32_t> ptr, idx;
+};
+
+// Symbolic Galerkin pattern of P^T A P (rows/cols in natural coarse numbering,
+// ascending columns).  P given row-wise as ELL-3 (col < 0 unused).
+Csr galerkin_pattern(const Csr &A, int nc, const std::vector<int32_t> &pcols);
+
+// Sliced-ELL (64-row slices, column-major within a slice) layout of the
+// off-diagonal part of a level whose rows are permuted color-major.
+struct SellLayout {
+    int n = 0;                       // rows
+    int nslices = 0;
+    std::vector<int32_t> slice_row0; // first permuted row of each slice
+    std::vector<int32_t> slice_off;  // nslices + 1 element offsets (multiples of 64)
+    std::vector<int32_t> cols;       // permuted column per slot (padding: own row)
+    std::vector<int32_t> rowlen;     // off-diagonal entries per permuted row
+    std::vector<int32_t> color_row;  // ncolors + 1 row boundaries (permuted)
+    std::vector<int32_t> color_slice;// ncolors + 1 slice boundaries
+    std::vector<int32_t> row_slice;  // slice index of each permuted row
+    std::vector<int32_t> pptr, pidx; // permuted rows' off-diagonal columns, ascending
+    int64_t slots() const { return slice_off.empty() ? 0 : slice_off.back(); }
+    // slot of the e-th off-diagonal entry of permuted row r
+    int32_t slot(int r, int e) const {
+        const int s = row_slice[r];
+        return slice_off[s] + e * 64 + (r - slice_row0[s]);
+    }
+};
+
+// Everything the device needs for one level, built on the host.
+struct LevelHost {
+    int n = 0;
+    bool coarsest = false;
+    Csr pat;                         // natural-order pattern of A_l (with diagonal)
+    std::vector<int32_t> color;      // natural index -> color (smoothed levels)
+    int ncolors = 0;
+    std::vector<int32_t> perm;       // permuted position -> natural index
+    std::vector<int32_t> iperm;      // natural index -> permuted position
+    SellLayout sell;
+    // natural CSR entry -> storage position: >= 0 SELL slot, < 0 -> diag of
+    // permuted row (-1 - r).  On the coarsest level: dense column-major index.
+    std::vector<int32_t> store;
+    // prolongation to the next level, permuted both ways, SoA ELL-3
+    std::vector<int32_t> pc;         // 3 * n (slot m at m*n + r)
+    std::vector<double> pw;
+    // restriction R = P^T, CSR over permuted coarse rows
+    std::vector<int32_t> rptr, ridx;
+    std::vector<double> rw;
+    // Galerkin plan to the next level: T = A P, then A_next = P^T T
+    std::vector<int32_t> tptr;       // n + 1
+    std::vector<int32_t> plan1ptr;   // n + 1 (3 per source entry: diag + rowlen)
+    std::vector<uint16_t> plan1;     // offset within the T row
+    std::vector<int32_t> plan2ptr;   // n_next + 1
+    std::vector<int32_t> plan2;      // storage position in level l+1 (see `store`)
+};
+
+struct HierHost {
+    int nlev = 0;
+    std::vector<int> sizes;
+    std::vector<std::vector<int32_t>> pcols;   // natural ELL-3 per level
+    std::vector<std::vector<double>> pw;
+    std::vector<std::array<double, 8>> stats;
+};
+
+// Build every LevelHost from the level-0 pattern and the prolongations.
+int build_levels(const HierHost &H, const Csr &A0, std::vector<LevelHost> &levels, std::string &err);
+
+}  // namespace smg

@@ -1,0 +1,107 @@
+// Device kernels of the surface-multigrid V-cycle (gfx950) and their launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace smg {
+
+// Sliced-ELL level matrix (off-diagonal part) + diagonal, rows color-major.
+template <typename T>
+struct SellView {
+    int n;
+    const int32_t *slice_row0;   // nslices + 1 (sentinel n)
+    const int32_t *slice_off;    // nslices + 1
+    const int32_t *cols;
+    const T *vals;
+    const T *diag;
+};
+
+struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (CSR)
+    int n, nc;
+    const int32_t *pc;
+    const int32_t *rptr, *ridx;
+};
+
+// --- relaxation / residual / transfers (K right-hand sides, 1..4) ---
+template <typename T>
+hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T *b, T *x, int k,
+                           hipStream_t st);
+// r = b - A x over `nslices` slices; if partial != nullptr also writes
+// per-block (sum r^2, max |r|) per column into partial[blk * 2k ..]; the
+// block count is returned in *nblk.
+template <typename T>
+hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const T *x, T *r,
+                           int k, double *partial, int *nblk, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc, int k,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_prolong_add(const TransferView &P, const T *pw, const T *e, T *x, int k,
+                              hipStream_t st);
+
+// --- reductions ---
+// column sums of squares and max-abs of a dense n x k array (FP64)
+hipError_t launch_colnorm_partial(const double *v, int n, int k, double *partial, int *nblk,
+                                  hipStream_t st);
+hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double *out,
+                                 hipStream_t st);
+
+// --- coarsest level ---
+hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st);
+// x = (G G^T)^{-1} b; Tin/Tout double or float (FP32 inner cycles convert here)
+template <typename Tin, typename Tout>
+hipError_t launch_coarse_solve(const double *G, int n, const Tin *b, Tout *x, int k,
+                               hipStream_t st);
+
+// --- hierarchy values ---
+hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,
+                                 double *vals, double *diag, int *flag, hipStream_t st);
+hipError_t launch_galerkin_t(int n, const int32_t *tptr, const int32_t *plan1ptr,
+                             const uint16_t *plan1, const int32_t *row_slice,
+                             const int32_t *slice_row0, const int32_t *slice_off,
+                             const int32_t *rowlen, const int32_t *cols, const double *vals,
+                             const double *diag, const int32_t *pc, const double *pw,
+                             double *Tbuf, hipStream_t st);
+hipError_t launch_galerkin_c(int nc, const int32_t *plan2ptr, const int32_t *plan2,
+                             const int32_t *rptr, const int32_t *ridx, const double *rw,
+                             const int32_t *tptr, const double *Tbuf, double *vals, double *diag,
+                             hipStream_t st);
+
+// --- elementwise helpers ---
+template <typename T>
+hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t st);
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+// dst[r*k + q] = src[perm[r]*k + q]  (gather into permuted order) and inverse
+hipError_t launch_gather_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
+                              hipStream_t st);
+hipError_t launch_scatter_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
+                               hipStream_t st);
+hipError_t launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
+// FP64 iterative-refinement glue
+hipError_t launch_ir_down(const double *r64, const double *norms, float *r32, int n, int k,
+                          hipStream_t st);
+hipError_t launch_ir_up(const float *d32, const double *norms, double *x64, int n, int k,
+                        hipStream_t st);
+
+// --- assembly and adjoint helpers ---
+struct MeshView {
+    int n;
+    const int32_t *vf_ptr, *vf_face;     // vertex -> incident faces (CSR)
+    const int32_t *faces;                // m x 3
+    const int32_t *slot_a, *slot_b;      // per (vertex, incident face): CSR entry of the
+                                         // edges (v, next corner) and (v, previous corner)
+    const int32_t *edge_of_entry;        // CSR entry -> canonical edge id (-1 on the diagonal)
+    const int32_t *diag_pos;             // CSR entry of (v, v)
+    const int32_t *rowptr;
+};
+hipError_t launch_assemble(const MeshView &M, const double *V, double t, const double *mass_scale,
+                           const float *edge_w, double *a_vals, double *l_vals, double *mass,
+                           hipStream_t st);
+hipError_t launch_spmv_dot(const int32_t *rowptr, const int32_t *cols, const double *vals,
+                           const double *lam, const double *u, int n, double *partial,
+                           int *nblk, hipStream_t st);
+hipError_t launch_mass_grad(const double *lam, const double *m, const double *u, double *out,
+                            int n, hipStream_t st);
+
+}  // namespace smg

@@ -1,0 +1,774 @@
+// HIP kernels (gfx950, wave64) of the surface-multigrid V-cycle.
+//
+// Layout: every smoothed level stores the off-diagonal part of A_l in a
+// sliced-ELL format with 64-row slices (one wavefront per slice, one lane per
+// row, slot (lane, e) at slice_off + 64 e + lane), so the matrix stream of a
+// sweep is read fully coalesced with no cross-lane reduction.  Rows are
+// permuted color-major and slices never straddle two colors, so one color of a
+// multicolor Gauss-Seidel sweep (App. A) is one contiguous slice range.
+// Vectors with K right-hand sides are row-major n x K.
+#include "kernels.h"
+
+#include <cmath>
+
+namespace smg {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so neighbouring slices share an L2.
+__device__ __forceinline__ int xcd_block(int bid, int nblk) {
+    const int q = nblk >> 3, r = nblk & 7;
+    const int x = bid & 7, i = bid >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------- relaxation
+// x_i <- (b_i - sum_{j != i} A_ij x_j) / A_ii for every row i of one color.
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end,
+                                                     const int32_t *__restrict__ slice_row0,
+                                                     const int32_t *__restrict__ slice_off,
+                                                     const int32_t *__restrict__ cols,
+                                                     const T *__restrict__ vals,
+                                                     const T *__restrict__ diag,
+                                                     const T *__restrict__ b, T *__restrict__ x) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = s_begin + blk * (kBlock / 64) + (threadIdx.x >> 6);
+    if (s >= s_end) return;
+    const int lane = threadIdx.x & 63;
+    const int row = slice_row0[s] + lane;
+    if (row >= slice_row0[s + 1]) return;
+    const int o0 = slice_off[s];
+    const int w = (slice_off[s + 1] - o0) >> 6;
+    T acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = T(0);
+    int o = o0 + lane;
+    for (int e = 0; e < w; ++e, o += 64) {
+        const int c = cols[o];
+        const T a = vals[o];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)c * K + q];
+    }
+    const T d = diag[row];
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (b[(size_t)row * K + q] - acc[q]) / d;
+}
+
+// ------------------------------------------------------------------ residual
+// r = b - A x over all slices; optional per-block column (sum r^2, max |r|).
+template <int K, typename T, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_residual(int nslices,
+                                                     const int32_t *__restrict__ slice_row0,
+                                                     const int32_t *__restrict__ slice_off,
+                                                     const int32_t *__restrict__ cols,
+                                                     const T *__restrict__ vals,
+                                                     const T *__restrict__ diag,
+                                                     const T *__restrict__ b,
+                                                     const T *__restrict__ x, T *__restrict__ r,
+                                                     double *__restrict__ partial) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double sq[K], mx[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
+    if (s < nslices) {
+        const int row = slice_row0[s] + lane;
+        if (row < slice_row0[s + 1]) {
+            const int o0 = slice_off[s];
+            const int w = (slice_off[s + 1] - o0) >> 6;
+            const T d = diag[row];
+            T acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = d * x[(size_t)row * K + q];
+            int o = o0 + lane;
+            for (int e = 0; e < w; ++e, o += 64) {
+                const int c = cols[o];
+                const T a = vals[o];
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)c * K + q];
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const T rv = b[(size_t)row * K + q] - acc[q];
+                r[(size_t)row * K + q] = rv;
+                if (NORM) { sq[q] = (double)rv * (double)rv; mx[q] = fabs((double)rv); }
+            }
+        }
+    }
+    if (NORM) {
+        __shared__ double red[2 * K][kBlock / 64];
+        const int wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double a = wave_sum(sq[q]);
+            const double m = wave_max(mx[q]);
+            if (lane == 0) { red[q][wv] = a; red[K + q][wv] = m; }
+        }
+        __syncthreads();
+        if (threadIdx.x < K) {
+            const int q = threadIdx.x;
+            double a = 0.0, m = 0.0;
+            for (int i = 0; i < kBlock / 64; ++i) { a += red[q][i]; m = fmax(m, red[K + q][i]); }
+            partial[(size_t)blockIdx.x * 2 * K + q] = a;
+            partial[(size_t)blockIdx.x * 2 * K + K + q] = m;
+        }
+    }
+}
+
+// --------------------------------------------------------------- transfers
+// rc_a = sum_{i} R_ai r_i with R = P^T (gather; deterministic order)
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t *__restrict__ rptr,
+                                                     const int32_t *__restrict__ ridx,
+                                                     const T *__restrict__ rw,
+                                                     const T *__restrict__ r, T *__restrict__ rc) {
+    const int a = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (a >= nc) return;
+    T acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = T(0);
+    for (int p = rptr[a]; p < rptr[a + 1]; ++p) {
+        const int i = ridx[p];
+        const T w = rw[p];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += w * r[(size_t)i * K + q];
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) rc[(size_t)a * K + q] = acc[q];
+}
+
+// x_i += sum_m P_im e_{c_im}
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(int n, const int32_t *__restrict__ pc,
+                                                        const T *__restrict__ pw,
+                                                        const T *__restrict__ e,
+                                                        T *__restrict__ x) {
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = T(0);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int c = pc[(size_t)m * n + i];
+        const T w = pw[(size_t)m * n + i];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += w * e[(size_t)c * K + q];
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[(size_t)i * K + q] += acc[q];
+}
+
+// --------------------------------------------------------------- reductions
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_colnorm_partial(const double *__restrict__ v, int n,
+                                                            double *__restrict__ partial) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ double red[2 * K][kBlock / 64];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double a = i < n ? v[(size_t)i * K + q] : 0.0;
+        const double s = wave_sum(a * a), m = wave_max(fabs(a));
+        if (lane == 0) { red[q][wv] = s; red[K + q][wv] = m; }
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double a = 0.0, m = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) { a += red[q][w]; m = fmax(m, red[K + q][w]); }
+        partial[(size_t)blockIdx.x * 2 * K + q] = a;
+        partial[(size_t)blockIdx.x * 2 * K + K + q] = m;
+    }
+}
+
+// one block: out[q] = sum_b partial[b][q], out[K+q] = max_b partial[b][K+q]
+__global__ __launch_bounds__(1024) void k_reduce_partial(const double *__restrict__ partial,
+                                                         int nblk, int k, double *__restrict__ out) {
+    __shared__ double s_sum[1024], s_max[1024];
+    for (int q = 0; q < k; ++q) {
+        double a = 0.0, m = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            a += partial[(size_t)b * 2 * k + q];
+            m = fmax(m, partial[(size_t)b * 2 * k + k + q]);
+        }
+        s_sum[threadIdx.x] = a;
+        s_max[threadIdx.x] = m;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+                s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + w]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) { out[q] = s_sum[0]; out[k + q] = s_max[0]; }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- coarsest
+// Right-looking dense Cholesky of a column-major n x n matrix (lower part
+// used), one workgroup.  flag <- 1 if a pivot is not positive.
+__global__ __launch_bounds__(1024) void k_cholesky(double *__restrict__ A, int n,
+                                                   int *__restrict__ flag) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (threadIdx.x == 0) {
+            const double d = A[(size_t)j * n + j];
+            if (!(d > 0.0)) { bad = 1; *flag = 1; }
+            else A[(size_t)j * n + j] = sqrt(d);
+        }
+        __syncthreads();
+        if (bad) return;
+        const double djj = A[(size_t)j * n + j];
+        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(size_t)j * n + i] /= djj;
+        __syncthreads();
+        const int m = n - j - 1;
+        const int total = m * m;
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            const int i = j + 1 + t % m, c = j + 1 + t / m;
+            if (i >= c) A[(size_t)c * n + i] -= A[(size_t)j * n + i] * A[(size_t)j * n + c];
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        const int i = t % n, c = t / n;
+        if (i < c) A[(size_t)c * n + i] = 0.0;
+    }
+}
+
+// Forward then backward substitution with G (lower, column-major), blocked
+// in 64-column panels; one workgroup, the right-hand sides in LDS.
+template <int K, typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(const double *__restrict__ G, int n,
+                                                         const Tin *__restrict__ b,
+                                                         Tout *__restrict__ x) {
+    extern __shared__ double y[];   // n * K
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int t = tid; t < n * K; t += kBlock) y[t] = (double)b[t];
+    __syncthreads();
+    // forward: G z = b
+    for (int j0 = 0; j0 < n; j0 += 64) {
+        const int jb = min(64, n - j0);
+        if (wv == 0) {
+            for (int jj = 0; jj < jb; ++jj) {
+                const int j = j0 + jj;
+                const double g = G[(size_t)j * n + j];
+                double zj[K];
+#pragma unroll
+                for (int q = 0; q < K; ++q) zj[q] = y[j * K + q] / g;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == jj) {
+#pragma unroll
+                    for (int q = 0; q < K; ++q) y[j * K + q] = zj[q];
+                }
+                if (lane > jj && lane < jb) {
+                    const double gij = G[(size_t)j * n + j0 + lane];
+#pragma unroll
+                    for (int q = 0; q < K; ++q) y[(j0 + lane) * K + q] -= gij * zj[q];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        __syncthreads();
+        for (int i = j0 + jb + tid; i < n; i += kBlock) {
+            double acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = 0.0;
+            for (int jj = 0; jj < jb; ++jj) {
+                const double g = G[(size_t)(j0 + jj) * n + i];
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += g * y[(j0 + jj) * K + q];
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q) y[i * K + q] -= acc[q];
+        }
+        __syncthreads();
+    }
+    // backward: G^T x = z
+    const int npan = (n + 63) / 64;
+    for (int pnl = npan - 1; pnl >= 0; --pnl) {
+        const int j0 = pnl * 64, jb = min(64, n - j0), below = j0 + jb;
+        // y_j -= sum_{i >= below} G_ij x_i  (column j of G, rows below the panel)
+        for (int jj = wv; jj < jb; jj += kBlock / 64) {
+            const int j = j0 + jj;
+            double acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = 0.0;
+            for (int i = below + lane; i < n; i += 64) {
+                const double g = G[(size_t)j * n + i];
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += g * y[i * K + q];
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = wave_sum(acc[q]);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < K; ++q) y[j * K + q] -= acc[q];
+            }
+        }
+        __syncthreads();
+        if (wv == 0) {
+            for (int jj = jb - 1; jj >= 0; --jj) {
+                const int j = j0 + jj;
+                const double g = G[(size_t)j * n + j];
+                double xj[K];
+#pragma unroll
+                for (int q = 0; q < K; ++q) xj[q] = y[j * K + q] / g;
+                __builtin_amdgcn_wave_barrier();
+                if (lane == jj) {
+#pragma unroll
+                    for (int q = 0; q < K; ++q) y[j * K + q] = xj[q];
+                }
+                if (lane < jj) {
+                    const double gji = G[(size_t)(j0 + lane) * n + j];
+#pragma unroll
+                    for (int q = 0; q < K; ++q) y[(j0 + lane) * K + q] -= gji * xj[q];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < n * K; t += kBlock) x[t] = (Tout)y[t];
+}
+
+// ------------------------------------------------------- hierarchy values
+__global__ __launch_bounds__(kBlock) void k_scatter_values(const double *__restrict__ src,
+                                                           const int32_t *__restrict__ store,
+                                                           int64_t nnz, double *__restrict__ vals,
+                                                           double *__restrict__ diag,
+                                                           int *__restrict__ flag) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nnz) return;
+    const double v = src[p];
+    if (!isfinite(v)) *flag = 1;
+    const int32_t s = store[p];
+    if (s >= 0) vals[s] = v;
+    else diag[-1 - s] = v;
+}
+
+// T = A_l P_l, one thread per permuted fine row (owner of its T row).
+__global__ __launch_bounds__(kBlock) void k_galerkin_t(
+    int n, const int32_t *__restrict__ tptr, const int32_t *__restrict__ plan1ptr,
+    const uint16_t *__restrict__ plan1, const int32_t *__restrict__ row_slice,
+    const int32_t *__restrict__ slice_row0, const int32_t *__restrict__ slice_off,
+    const int32_t *__restrict__ rowlen, const int32_t *__restrict__ cols,
+    const double *__restrict__ vals, const double *__restrict__ diag,
+    const int32_t *__restrict__ pc, const double *__restrict__ pw, double *__restrict__ Tb) {
+    const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (r >= n) return;
+    const int t0 = tptr[r], t1 = tptr[r + 1];
+    for (int t = t0; t < t1; ++t) Tb[t] = 0.0;
+    const uint16_t *pl = plan1 + plan1ptr[r];
+    const double d = diag[r];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Tb[t0 + pl[m]] += d * pw[(size_t)m * n + r];
+    const int s = row_slice[r];
+    const int base = slice_off[s] + (r - slice_row0[s]);
+    const int len = rowlen[r];
+    for (int e = 0; e < len; ++e) {
+        const int slot = base + e * 64;
+        const int c = cols[slot];
+        const double a = vals[slot];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) Tb[t0 + pl[3 * (e + 1) + m]] += a * pw[(size_t)m * n + c];
+    }
+}
+
+// A_{l+1} = P^T T, one thread per permuted coarse row (owner of its entries).
+// Output storage must be zero on entry; pos >= 0 -> vals[pos], else diag.
+__global__ __launch_bounds__(kBlock) void k_galerkin_c(
+    int nc, const int32_t *__restrict__ plan2ptr, const int32_t *__restrict__ plan2,
+    const int32_t *__restrict__ rptr, const int32_t *__restrict__ ridx,
+    const double *__restrict__ rw, const int32_t *__restrict__ tptr,
+    const double *__restrict__ Tb, double *__restrict__ vals, double *__restrict__ diag) {
+    const int a = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (a >= nc) return;
+    int idx = plan2ptr[a];
+    for (int p = rptr[a]; p < rptr[a + 1]; ++p) {
+        const int r = ridx[p];
+        const double w = rw[p];
+        for (int t = tptr[r]; t < tptr[r + 1]; ++t) {
+            const int32_t pos = plan2[idx++];
+            const double v = w * Tb[t];
+            if (pos >= 0) vals[pos] += v;
+            else diag[-1 - pos] += v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ elementwise
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *__restrict__ p, T v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ s, float *__restrict__ d,
+                                                   int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+__global__ __launch_bounds__(kBlock) void k_gather_rows(const int32_t *__restrict__ perm,
+                                                        const double *__restrict__ src,
+                                                        double *__restrict__ dst, int n, int k) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * k) return;
+    const int r = (int)(t / k), q = (int)(t % k);
+    dst[t] = src[(size_t)perm[r] * k + q];
+}
+__global__ __launch_bounds__(kBlock) void k_scatter_rows(const int32_t *__restrict__ perm,
+                                                         const double *__restrict__ src,
+                                                         double *__restrict__ dst, int n, int k) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * k) return;
+    const int r = (int)(t / k), q = (int)(t % k);
+    dst[(size_t)perm[r] * k + q] = src[t];
+}
+__global__ __launch_bounds__(kBlock) void k_check_finite(const double *__restrict__ v, int64_t n,
+                                                         int *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && !isfinite(v[i])) *flag = 1;
+}
+// r32 = r64 / sigma_q with sigma_q = max |r_q| (1 if the column is zero)
+__global__ __launch_bounds__(kBlock) void k_ir_down(const double *__restrict__ r64,
+                                                    const double *__restrict__ norms,
+                                                    float *__restrict__ r32, int n, int k) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * k) return;
+    const int q = (int)(t % k);
+    const double s = norms[k + q];
+    r32[t] = (float)(s > 0.0 ? r64[t] / s : 0.0);
+}
+__global__ __launch_bounds__(kBlock) void k_ir_up(const float *__restrict__ d32,
+                                                  const double *__restrict__ norms,
+                                                  double *__restrict__ x64, int n, int k) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * k) return;
+    const int q = (int)(t % k);
+    const double s = norms[k + q];
+    x64[t] += (s > 0.0 ? s : 0.0) * (double)d32[t];
+}
+
+// ----------------------------------------------------------- assembly (K6)
+// Row v of A = diag(s m) + t L_w, with L_ij = -1/2 sum cot(opposite angles)
+// (times w_e), L_ii = -sum_j L_ij, m_v = sum of incident face areas / 3.
+// One thread owns row v; contributions are gathered from v's faces.
+__global__ __launch_bounds__(kBlock) void k_assemble(MeshView M, const double *__restrict__ V,
+                                                     double t, const double *__restrict__ s,
+                                                     const float *__restrict__ ew,
+                                                     double *__restrict__ a_vals,
+                                                     double *__restrict__ l_vals,
+                                                     double *__restrict__ mass) {
+    const int v = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (v >= M.n) return;
+    const int p0 = M.rowptr[v], p1 = M.rowptr[v + 1];
+    for (int p = p0; p < p1; ++p) a_vals[p] = 0.0;
+    double m = 0.0;
+    for (int q = M.vf_ptr[v]; q < M.vf_ptr[v + 1]; ++q) {
+        const int f = M.vf_face[q];
+        int c0 = 0;
+        while (M.faces[3 * f + c0] != v) ++c0;
+        const int a = M.faces[3 * f + (c0 + 1) % 3], b = M.faces[3 * f + (c0 + 2) % 3];
+        const double vx = V[3 * v], vy = V[3 * v + 1], vz = V[3 * v + 2];
+        const double ax = V[3 * a], ay = V[3 * a + 1], az = V[3 * a + 2];
+        const double bx = V[3 * b], by = V[3 * b + 1], bz = V[3 * b + 2];
+        // angle at b (opposite edge v-a): vectors b->v, b->a
+        double ux = vx - bx, uy = vy - by, uz = vz - bz, wx = ax - bx, wy = ay - by, wz = az - bz;
+        double cx = uy * wz - uz * wy, cy = uz * wx - ux * wz, cz = ux * wy - uy * wx;
+        const double cn = sqrt(cx * cx + cy * cy + cz * cz);
+        const double cot_b = (ux * wx + uy * wy + uz * wz) / cn;
+        // angle at a (opposite edge v-b): vectors a->v, a->b
+        ux = vx - ax; uy = vy - ay; uz = vz - az; wx = bx - ax; wy = by - ay; wz = bz - az;
+        cx = uy * wz - uz * wy; cy = uz * wx - ux * wz; cz = ux * wy - uy * wx;
+        const double cot_a = (ux * wx + uy * wy + uz * wz) / sqrt(cx * cx + cy * cy + cz * cz);
+        const int sa = M.slot_a[q], sb = M.slot_b[q];
+        const double wa = ew ? (double)ew[M.edge_of_entry[sa]] : 1.0;
+        const double wb = ew ? (double)ew[M.edge_of_entry[sb]] : 1.0;
+        a_vals[sa] += -0.5 * cot_b * wa;
+        a_vals[sb] += -0.5 * cot_a * wb;
+        m += cn / 6.0;   // area / 3 = |cross| / 6
+    }
+    double off = 0.0;
+    const int dp = M.diag_pos[v];
+    for (int p = p0; p < p1; ++p) {
+        if (p == dp) continue;
+        const double lv = a_vals[p];
+        off += lv;
+        if (l_vals) l_vals[p] = lv;
+        a_vals[p] = t * lv;
+    }
+    if (l_vals) l_vals[dp] = -off;
+    if (mass) mass[v] = m;
+    a_vals[dp] = t * (-off) + (s ? s[v] : 1.0) * m;
+}
+
+// per-block partial of sum_i lam_i (L u)_i, stored as (sum, 0) pairs
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ cols,
+                                                     const double *__restrict__ vals,
+                                                     const double *__restrict__ lam,
+                                                     const double *__restrict__ u, int n,
+                                                     double *__restrict__ partial) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        double acc = 0.0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) acc += vals[p] * u[cols[p]];
+        v = lam[i] * acc;
+    }
+    __shared__ double red[kBlock / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) a += red[w];
+        partial[2 * (size_t)blockIdx.x] = a;
+        partial[2 * (size_t)blockIdx.x + 1] = 0.0;
+    }
+}
+__global__ __launch_bounds__(kBlock) void k_mass_grad(const double *__restrict__ lam,
+                                                      const double *__restrict__ m,
+                                                      const double *__restrict__ u,
+                                                      double *__restrict__ out, int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = -lam[i] * m[i] * u[i];
+}
+
+inline int nblocks(int64_t n, int per = kBlock) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+// ============================================================== launchers
+#define SMG_K_SWITCH(k, CALL) \
+    switch (k) {              \
+    case 1: { constexpr int KK = 1; CALL; break; } \
+    case 2: { constexpr int KK = 2; CALL; break; } \
+    case 3: { constexpr int KK = 3; CALL; break; } \
+    case 4: { constexpr int KK = 4; CALL; break; } \
+    default: return hipErrorInvalidValue; }
+
+template <typename T>
+hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T *b, T *x, int k,
+                           hipStream_t st) {
+    const int ns = s_end - s_begin;
+    if (ns <= 0) return hipSuccess;
+    const int g = nblocks(ns, kBlock / 64);
+    SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kBlock, 0, st>>>(s_begin, s_end, A.slice_row0, A.slice_off,
+                                                             A.cols, A.vals, A.diag, b, x)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const T *x, T *r,
+                           int k, double *partial, int *nblk, hipStream_t st) {
+    const int ns = nslices;
+    const int g = nblocks(ns, kBlock / 64);
+    *nblk = g;
+    if (ns <= 0) return hipSuccess;
+    if (partial) {
+        SMG_K_SWITCH(k, (k_residual<KK, T, true><<<g, kBlock, 0, st>>>(ns, A.slice_row0, A.slice_off, A.cols,
+                                                                       A.vals, A.diag, b, x, r, partial)));
+    } else {
+        SMG_K_SWITCH(k, (k_residual<KK, T, false><<<g, kBlock, 0, st>>>(ns, A.slice_row0, A.slice_off, A.cols,
+                                                                        A.vals, A.diag, b, x, r, nullptr)));
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc, int k,
+                           hipStream_t st) {
+    if (P.nc <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_restrict<KK, T><<<nblocks(P.nc), kBlock, 0, st>>>(P.nc, P.rptr, P.ridx, rw, r, rc)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const TransferView &P, const T *pw, const T *e, T *x, int k,
+                              hipStream_t st) {
+    if (P.n <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_prolong_add<KK, T><<<nblocks(P.n), kBlock, 0, st>>>(P.n, P.pc, pw, e, x)));
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorm_partial(const double *v, int n, int k, double *partial, int *nblk,
+                                  hipStream_t st) {
+    const int g = nblocks(n);
+    *nblk = g;
+    if (n <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_colnorm_partial<KK><<<g, kBlock, 0, st>>>(v, n, partial)));
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double *out,
+                                 hipStream_t st) {
+    k_reduce_partial<<<1, 1024, 0, st>>>(partial, nblk, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st) {
+    k_cholesky<<<1, 1024, 0, st>>>(A, n, flag);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_coarse_solve(const double *G, int n, const Tin *b, Tout *x, int k,
+                               hipStream_t st) {
+    const size_t lds = (size_t)n * k * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    SMG_K_SWITCH(k, (k_coarse_solve<KK, Tin, Tout><<<1, kBlock, lds, st>>>(G, n, b, x)));
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,
+                                 double *vals, double *diag, int *flag, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    k_scatter_values<<<nblocks(nnz), kBlock, 0, st>>>(src, store, nnz, vals, diag, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_galerkin_t(int n, const int32_t *tptr, const int32_t *plan1ptr,
+                             const uint16_t *plan1, const int32_t *row_slice,
+                             const int32_t *slice_row0, const int32_t *slice_off,
+                             const int32_t *rowlen, const int32_t *cols, const double *vals,
+                             const double *diag, const int32_t *pc, const double *pw,
+                             double *Tbuf, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_galerkin_t<<<nblocks(n), kBlock, 0, st>>>(n, tptr, plan1ptr, plan1, row_slice, slice_row0,
+                                                slice_off, rowlen, cols, vals, diag, pc, pw, Tbuf);
+    return hipGetLastError();
+}
+
+hipError_t launch_galerkin_c(int nc, const int32_t *plan2ptr, const int32_t *plan2,
+                             const int32_t *rptr, const int32_t *ridx, const double *rw,
+                             const int32_t *tptr, const double *Tbuf, double *vals, double *diag,
+                             hipStream_t st) {
+    if (nc <= 0) return hipSuccess;
+    k_galerkin_c<<<nblocks(nc), kBlock, 0, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw, tptr, Tbuf,
+                                                 vals, diag);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_fill<T><<<nblocks(n), kBlock, 0, st>>>(p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_to_f32<<<nblocks(n), kBlock, 0, st>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_gather_rows<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(perm, src, dst, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_scatter_rows<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(perm, src, dst, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_check_finite<<<nblocks(n), kBlock, 0, st>>>(v, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_down(const double *r64, const double *norms, float *r32, int n, int k,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_ir_down<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(r64, norms, r32, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_up(const float *d32, const double *norms, double *x64, int n, int k,
+                        hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_ir_up<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(d32, norms, x64, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const MeshView &M, const double *V, double t, const double *mass_scale,
+                           const float *edge_w, double *a_vals, double *l_vals, double *mass,
+                           hipStream_t st) {
+    if (M.n <= 0) return hipSuccess;
+    k_assemble<<<nblocks(M.n), kBlock, 0, st>>>(M, V, t, mass_scale, edge_w, a_vals, l_vals, mass);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_dot(const int32_t *rowptr, const int32_t *cols, const double *vals,
+                           const double *lam, const double *u, int n, double *partial,
+                           int *nblk, hipStream_t st) {
+    const int g = nblocks(n);
+    *nblk = g;
+    if (n <= 0) return hipSuccess;
+    k_spmv_dot<<<g, kBlock, 0, st>>>(rowptr, cols, vals, lam, u, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_mass_grad(const double *lam, const double *m, const double *u, double *out,
+                            int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_mass_grad<<<nblocks(n), kBlock, 0, st>>>(lam, m, u, out, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_gs_color<double>(const SellView<double> &, int, int, const double *,
+                                            double *, int, hipStream_t);
+template hipError_t launch_gs_color<float>(const SellView<float> &, int, int, const float *,
+                                           float *, int, hipStream_t);
+template hipError_t launch_residual<double>(const SellView<double> &, int, const double *,
+                                            const double *, double *, int, double *, int *,
+                                            hipStream_t);
+template hipError_t launch_residual<float>(const SellView<float> &, int, const float *,
+                                           const float *, float *, int, double *, int *,
+                                           hipStream_t);
+template hipError_t launch_restrict<double>(const TransferView &, const double *, const double *,
+                                            double *, int, hipStream_t);
+template hipError_t launch_restrict<float>(const TransferView &, const float *, const float *,
+                                           float *, int, hipStream_t);
+template hipError_t launch_prolong_add<double>(const TransferView &, const double *,
+                                               const double *, double *, int, hipStream_t);
+template hipError_t launch_prolong_add<float>(const TransferView &, const float *, const float *,
+                                              float *, int, hipStream_t);
+template hipError_t launch_coarse_solve<double, double>(const double *, int, const double *,
+                                                        double *, int, hipStream_t);
+template hipError_t launch_coarse_solve<float, float>(const double *, int, const float *, float *,
+                                                      int, hipStream_t);
+template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
+template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
+template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);
+
+}  // namespace smg

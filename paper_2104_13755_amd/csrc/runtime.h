@@ -1,0 +1,90 @@
+// Device-side state of a solver (private to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "smg.h"
+
+namespace smg {
+
+struct DevLevel {
+    int n = 0, ncolors = 0, nslices = 0;
+    bool coarsest = false;
+    int64_t slots = 0, nnz_nat = 0;
+    std::vector<int32_t> color_slice;      // host copy of slice boundaries per color
+    std::vector<int32_t> pat_ptr, pat_idx; // natural CSR pattern (host)
+    std::vector<int32_t> store_h;          // natural entry -> storage (host)
+    std::vector<int32_t> color_h;          // natural color ids (host)
+    int32_t *perm = nullptr, *store = nullptr;
+    // sliced ELL (smoothed levels)
+    int32_t *slice_row0 = nullptr, *slice_off = nullptr, *cols = nullptr, *rowlen = nullptr,
+            *row_slice = nullptr;
+    double *vals = nullptr, *diag = nullptr;
+    float *vals32 = nullptr, *diag32 = nullptr;
+    // coarsest: A_H (dense_a) and its Cholesky factor (dense), column-major
+    double *dense = nullptr, *dense_a = nullptr;
+    // transfers to the next level and the Galerkin plan
+    int32_t *pc = nullptr, *rptr = nullptr, *ridx = nullptr;
+    double *pw = nullptr, *rw = nullptr;
+    float *pw32 = nullptr, *rw32 = nullptr;
+    int32_t *tptr = nullptr, *plan1ptr = nullptr, *plan2ptr = nullptr, *plan2 = nullptr;
+    uint16_t *plan1 = nullptr;
+    // work vectors, n x 4 (permuted order)
+    double *x = nullptr, *b = nullptr, *r = nullptr;
+    float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+};
+
+struct MeshDev {
+    bool attached = false;
+    int n = 0, m = 0, nedges = 0;
+    int32_t *faces = nullptr, *vf_ptr = nullptr, *vf_face = nullptr, *slot_a = nullptr,
+            *slot_b = nullptr, *eoe = nullptr, *diag_pos = nullptr, *rowptr = nullptr,
+            *cols = nullptr;
+};
+
+struct CycleGraph {
+    int k, precision;
+    hipStream_t stream;
+    hipGraphExec_t exec;
+};
+
+smg_status fail(smg_status st, const std::string &msg);
+
+}  // namespace smg
+
+struct smg_solver_s {
+    int device = 0, nlev = 0, mu_pre = 2, mu_post = 2;
+    bool values_set = false;
+    std::vector<smg::DevLevel> lev;
+    smg::MeshDev mesh;
+    double *tbuf = nullptr;        // Galerkin T = A P scratch
+    double *partial = nullptr;     // per-block reduction partials
+    int64_t npartial = 0;
+    double *norms = nullptr;       // reduced (sum r^2, max |r|) per column
+    int *flag = nullptr;           // [0] non-finite, [1] not SPD
+    double *h_norms = nullptr;     // pinned
+    int *h_flag = nullptr;         // pinned
+    std::vector<void *> owned;
+    std::vector<smg::CycleGraph> graphs;
+    hipStream_t gstream = nullptr;  // capture/replay stream for cycle graphs
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    ~smg_solver_s();
+};
+
+namespace smg {
+smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st);
+template <typename T>
+smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st);
+template <typename T>
+smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t st);
+smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st);
+smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st,
+                           hipGraphExec_t *out);
+smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_x, int k,
+                                  const smg_solve_params *p, smg_solve_info *info,
+                                  hipStream_t st);
+}  // namespace smg

@@ -1,0 +1,247 @@
+"""Python binding of libsmg: argument marshalling only.
+
+Every step of the solve (assembly, Galerkin, Cholesky, relaxation, residual,
+transfers, norms) runs in the library's HIP kernels; torch supplies device
+memory and the current stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_c = ctypes.c_void_p
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(_c)
+
+
+def _t_ptr(t):
+    return _c(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return _c(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t, shape=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def mesh_pattern(n, F):
+    """CSR pattern {diagonal} U {mesh edges} (int32 rowptr, cols)."""
+    lib = L.load()
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    nnz = ctypes.c_int32(0)
+    L.check(lib.smg_mesh_pattern(n, _np_ptr(F), len(F), _np_ptr(rowptr), None, ctypes.byref(nnz)), "mesh_pattern")
+    cols = np.zeros(nnz.value, dtype=np.int32)
+    L.check(lib.smg_mesh_pattern(n, _np_ptr(F), len(F), _np_ptr(rowptr), _np_ptr(cols), ctypes.byref(nnz)), "mesh_pattern")
+    return rowptr, cols
+
+
+def color_pattern(rowptr, cols):
+    """Greedy coloring of a CSR pattern's off-diagonal graph (host)."""
+    lib = L.load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    n = len(rowptr) - 1
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    nc = lib.smg_color_pattern(n, _np_ptr(rowptr), _np_ptr(cols), _np_ptr(out))
+    if nc < 0:
+        L.check(nc, "color_pattern")
+    return out[:n], nc
+
+
+class Hierarchy:
+    """Host-side prolongations P_1..P_H (owned by libsmg)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        self._lib = L.load()
+
+    @classmethod
+    def build(cls, V, F, n_levels=0, min_coarse=500, interior_only=False):
+        lib = L.load()
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        o = L.PreOpts(int(n_levels), int(min_coarse), int(bool(interior_only)))
+        h = _c()
+        L.check(lib.smg_pre_build(_np_ptr(V), len(V), _np_ptr(F), len(F), ctypes.byref(o), ctypes.byref(h)), "pre_build")
+        return cls(h)
+
+    @classmethod
+    def from_prolongations(cls, sizes, pcols, pws):
+        lib = L.load()
+        sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+        pcols = [np.ascontiguousarray(p, dtype=np.int32) for p in pcols]
+        pws = [np.ascontiguousarray(p, dtype=np.float64) for p in pws]
+        nl = len(sizes)
+        arr_c = (_c * max(1, nl - 1))(*[_np_ptr(p) for p in pcols])
+        arr_w = (_c * max(1, nl - 1))(*[_np_ptr(p) for p in pws])
+        h = _c()
+        L.check(lib.smg_hier_from_prolongations(nl, _np_ptr(sizes), arr_c, arr_w, ctypes.byref(h)), "hier_from_prolongations")
+        return cls(h)
+
+    @property
+    def num_levels(self):
+        return self._lib.smg_hier_num_levels(self._h)
+
+    @property
+    def sizes(self):
+        return [self._lib.smg_hier_level_size(self._h, l) for l in range(self.num_levels)]
+
+    def prolongation(self, l):
+        n = self.sizes[l]
+        cols = np.zeros((n, 3), dtype=np.int32)
+        w = np.zeros((n, 3), dtype=np.float64)
+        L.check(self._lib.smg_hier_get_prolongation(self._h, l, _np_ptr(cols), _np_ptr(w)), "get_prolongation")
+        return cols, w
+
+    def stats(self, l):
+        s = np.zeros(8)
+        L.check(self._lib.smg_hier_stats(self._h, l, _np_ptr(s)), "hier_stats")
+        keys = ["collapses", "fails", "interior", "one_boundary", "b_case1", "b_case2", "b_case3", "max_clamp"]
+        return {k: (float(v) if k == "max_clamp" else int(v)) for k, v in zip(keys, s)}
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.smg_hier_free(self._h)
+            self._h = None
+
+
+PRECISION = {"fp64": L.SMG_FP64, "fp32ir": L.SMG_FP32_IR}
+
+
+class Solver:
+    """Device-resident multigrid solver of one mesh."""
+
+    def __init__(self, hier, rowptr, cols, device=0, mu_pre=2, mu_post=2, faces=None):
+        self._lib = L.load()
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        self.rowptr, self.cols = rowptr, cols
+        self.n = len(rowptr) - 1
+        self.nnz = len(cols)
+        self.device = device
+        o = L.Opts(int(mu_pre), int(mu_post))
+        h = _c()
+        L.check(self._lib.smg_solver_create(device, hier._h, _np_ptr(rowptr), _np_ptr(cols), ctypes.byref(o), ctypes.byref(h)), "solver_create")
+        self._s = h
+        if faces is not None:
+            F = np.ascontiguousarray(faces, dtype=np.int32)
+            L.check(self._lib.smg_solver_attach_mesh(self._s, _np_ptr(F), len(F)), "attach_mesh")
+
+    def __del__(self):
+        if getattr(self, "_s", None):
+            self._lib.smg_solver_destroy(self._s)
+            self._s = None
+
+    # ---- structure ------------------------------------------------------
+    @property
+    def num_levels(self):
+        return self._lib.smg_num_levels(self._s)
+
+    def level_size(self, l):
+        return self._lib.smg_level_size(self._s, l)
+
+    def level_nnz(self, l):
+        return self._lib.smg_level_nnz(self._s, l)
+
+    def colors(self, l):
+        n = self.level_size(l)
+        out = np.zeros(max(n, 1), dtype=np.int32)
+        nc = self._lib.smg_level_colors(self._s, l, _np_ptr(out))
+        return out[:n], nc
+
+    def level_matrix(self, l):
+        import scipy.sparse as sp
+        n, nnz = self.level_size(l), self.level_nnz(l)
+        rp = np.zeros(n + 1, dtype=np.int32)
+        ci = np.zeros(nnz, dtype=np.int32)
+        v = np.zeros(nnz, dtype=np.float64)
+        L.check(self._lib.smg_get_level_matrix(self._s, l, _np_ptr(rp), _np_ptr(ci), _np_ptr(v)), "get_level_matrix")
+        return sp.csr_matrix((v, ci, rp), shape=(n, n))
+
+    def coarse_factor(self):
+        n = self.level_size(self.num_levels - 1)
+        G = np.zeros(n * n, dtype=np.float64)
+        L.check(self._lib.smg_get_coarse_factor(self._s, _np_ptr(G)), "get_coarse_factor")
+        return G.reshape(n, n).T.copy()   # column-major -> row-major
+
+    # ---- values ---------------------------------------------------------
+    def assemble(self, V, t, mass_scale=None, edge_w=None, want_l=False, want_mass=False):
+        dev = V.device
+        a = torch.empty(self.nnz, dtype=torch.float64, device=dev)
+        lv = torch.empty(self.nnz, dtype=torch.float64, device=dev) if want_l else None
+        m = torch.empty(self.n, dtype=torch.float64, device=dev) if want_mass else None
+        if edge_w is not None and edge_w.dtype != torch.float32:
+            raise TypeError("edge weights must be float32")
+        L.check(self._lib.smg_assemble(self._s, _t_ptr(_dev_f64(V, (self.n, 3))), float(t),
+                                       _t_ptr(mass_scale), _t_ptr(edge_w), _t_ptr(a), _t_ptr(lv),
+                                       _t_ptr(m), _stream()), "assemble")
+        return a, lv, m
+
+    def set_values(self, a_vals):
+        L.check(self._lib.smg_set_values(self._s, _t_ptr(_dev_f64(a_vals, (self.nnz,))), _stream()), "set_values")
+
+    # ---- solve ----------------------------------------------------------
+    def solve(self, b, rtol=1e-8, max_cycles=100, precision="fp64", fixed_cycles=0,
+              use_graph=False, raise_on_error=True):
+        b2 = b if b.dim() == 2 else b.unsqueeze(1)
+        b2 = _dev_f64(b2.contiguous())
+        k = b2.shape[1]
+        x = torch.empty_like(b2)
+        p = L.SolveParams(float(rtol), int(max_cycles), PRECISION[precision], int(fixed_cycles), int(bool(use_graph)))
+        info = L.SolveInfo()
+        st = self._lib.smg_solve(self._s, _t_ptr(b2), _t_ptr(x), k, ctypes.byref(p), ctypes.byref(info), _stream())
+        if raise_on_error:
+            L.check(st, "solve")
+        out = dict(status=st, cycles=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
+        return (x if b.dim() == 2 else x[:, 0]), out
+
+    def vcycle(self, b, x):
+        k = b.shape[1]
+        L.check(self._lib.smg_vcycle(self._s, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), k, _stream()), "vcycle")
+        return x
+
+    # ---- single steps (level-natural numbering) ------------------------
+    def residual(self, l, b, x):
+        r = torch.empty_like(b)
+        L.check(self._lib.smg_residual(self._s, l, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), _t_ptr(r), b.shape[1], _stream()), "residual")
+        return r
+
+    def smooth(self, l, b, x, sweeps):
+        L.check(self._lib.smg_smooth(self._s, l, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), b.shape[1], sweeps, _stream()), "smooth")
+        return x
+
+    def restrict(self, l, r):
+        rc = torch.empty((self.level_size(l + 1), r.shape[1]), dtype=torch.float64, device=r.device)
+        L.check(self._lib.smg_restrict(self._s, l, _t_ptr(_dev_f64(r)), _t_ptr(rc), r.shape[1], _stream()), "restrict")
+        return rc
+
+    def prolong_add(self, l, e, x):
+        L.check(self._lib.smg_prolong_add(self._s, l, _t_ptr(_dev_f64(e)), _t_ptr(_dev_f64(x)), x.shape[1], _stream()), "prolong_add")
+        return x
+
+    def coarse_solve(self, b):
+        x = torch.empty_like(b)
+        L.check(self._lib.smg_coarse_solve(self._s, _t_ptr(_dev_f64(b)), _t_ptr(x), b.shape[1], _stream()), "coarse_solve")
+        return x
+
+    # ---- adjoint helpers ----------------------------------------------
+    def spmv_dot(self, l_vals, lam, u):
+        out = ctypes.c_double(0.0)
+        L.check(self._lib.smg_spmv_dot(self._s, _t_ptr(_dev_f64(l_vals)), _t_ptr(_dev_f64(lam)), _t_ptr(_dev_f64(u)), ctypes.byref(out), _stream()), "spmv_dot")
+        return out.value
+
+    def mass_grad(self, lam, m, u):
+        out = torch.empty_like(lam)
+        L.check(self._lib.smg_mass_grad(self._s, _t_ptr(_dev_f64(lam)), _t_ptr(_dev_f64(m)), _t_ptr(_dev_f64(u)), _t_ptr(out), _stream()), "mass_grad")
+        return out

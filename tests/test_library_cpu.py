@@ -1,0 +1,111 @@
+"""Host-side checks of libsmg (no GPU): the C ABI loads and exports every
+declared symbol; the host precompute (successive self-parameterization,
+coloring) matches the oracle's independent implementation."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from conftest import ROOT
+import synth
+from oracle import assemble as AS, hierarchy as OH
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "smg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(smg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_2104_13755_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.SIGNATURES) >= set(names)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2104_13755_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+
+
+def _p_matrix(cols, w, shape):
+    n = len(cols)
+    m = w > 0
+    return sp.csr_matrix((w[m], (np.repeat(np.arange(n), 3).reshape(n, 3)[m], cols[m])), shape=shape)
+
+
+@pytest.mark.parametrize("mesh", ["icosphere", "torus", "disc", "heightfield"])
+def test_precompute_matches_oracle(mesh):
+    from paper_2104_13755_amd.solver import Hierarchy
+    rng = np.random.default_rng(8)
+    if mesh == "icosphere":
+        V, F = synth.small_icosphere(4, seed=12, sigma=0.01)
+    elif mesh == "torus":
+        V, F = synth.torus_grid(80, 30, 1.0, 0.3, rng, jitter=0.2)
+    elif mesh == "disc":
+        V, F = synth.flat_disc(45, 39, seed=6, jitter=0.1)
+    else:
+        V, F = synth.disc_grid(50, 47, rng, 0.1, height=lambda x, y: 0.1 * np.sin(3 * x) * np.cos(2 * y))
+    h = Hierarchy.build(V, F, n_levels=4)
+    Ps, _, st = OH.prolongations(V, F, n_levels=4)
+    assert h.sizes == [len(V)] + [P.shape[1] for P in Ps]
+    for l, P in enumerate(Ps):
+        c, w = h.prolongation(l)
+        Pp = _p_matrix(c, w, P.shape)
+        assert ((Pp != 0) != (P != 0)).nnz == 0
+        assert abs(Pp - P).max() < 1e-12
+        s = h.stats(l)
+        for key in ("collapses", "interior", "one_boundary", "b_case1", "b_case2", "b_case3"):
+            assert s[key] == st[l][key]
+
+
+def test_flat_interior_closed_form_product():
+    """Product SSP on the flat disc with interior-only collapses reproduces
+    linear functions exactly (the planar closed form)."""
+    from paper_2104_13755_amd.solver import Hierarchy
+    V, F = synth.flat_disc(32, seed=11, jitter=0.1)
+    h = Hierarchy.build(V, F, n_levels=2, interior_only=True)
+    c, w = h.prolongation(0)
+    Vc_ref = OH.native.ssp_level(V, F, OH.next_target(len(V)), interior_only=True)[0]
+    P = _p_matrix(c, w, (len(V), h.sizes[1]))
+    assert abs(P @ Vc_ref[:, :2] - V[:, :2]).max() < 1e-13
+
+
+def test_coloring_matches_oracle():
+    from paper_2104_13755_amd.solver import color_pattern
+    V, F = synth.small_icosphere(4, seed=2)
+    A, _, _ = AS.system(V, F, 1e-2)
+    Ps, _, _ = OH.prolongations(V, F, n_levels=3)
+    A1 = OH.galerkin(A, Ps[0])
+    for M in (A, A1):
+        col_o, nc_o = OH.coloring(M)
+        col_p, nc_p = color_pattern(M.indptr, M.indices)
+        assert nc_o == nc_p and np.array_equal(col_o, col_p)
+
+
+def test_mesh_pattern_matches_oracle():
+    from paper_2104_13755_amd.solver import mesh_pattern
+    V, F = synth.flat_disc(17, 23, seed=1)
+    rp, ci = mesh_pattern(len(V), F)
+    ip, ii = AS.pattern(len(V), F)
+    assert np.array_equal(rp, ip) and np.array_equal(ci, ii)
+
+
+def test_precompute_rejects_bad_input():
+    from paper_2104_13755_amd.solver import Hierarchy
+    from paper_2104_13755_amd._lib import SmgError
+    V, F = synth.flat_disc(8, seed=0)
+    Fb = F.copy()
+    Fb[0, 0] = len(V) + 5
+    with pytest.raises(SmgError):
+        Hierarchy.build(V, Fb, n_levels=2)
