@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark: surface-multigrid V-cycle solves/s at 1M vertices to relative
+residual 1e-8, mixed precision (FP32 cycles inside FP64 refinement) vs FP64.
+
+Workload: jittered torus grid 1000 x 1000 (1,000,000 vertices, 2,000,000
+triangles), R = 1, r = 0.3, A = M + 1e-2 L, three right-hand sides b = M X
+(vertex coordinates), 7 levels, 2 + 2 multicolor Gauss-Seidel sweeps, dense
+FP64 Cholesky on the coarsest level.
+
+One step = on-device assembly of A_0, Galerkin refresh of every level,
+coarsest Cholesky, and the full solve of the 3-RHS system to 1e-8 (the
+hierarchy precompute is geometry-only and runs once, untimed, as in the
+paper).  Prints ONE JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def gpu_setup(w, n_levels):
+    import torch
+    from paper_2104_13755_amd.solver import Hierarchy, Solver, mesh_pattern
+    t0 = time.perf_counter()
+    h = Hierarchy.build(w["V"], w["F"], n_levels=n_levels)
+    t_pre = time.perf_counter() - t0
+    log(f"hierarchy precompute {t_pre:.1f}s sizes={h.sizes}")
+    rp, ci = mesh_pattern(len(w["V"]), w["F"])
+    t0 = time.perf_counter()
+    S = Solver(h, rp, ci, faces=w["F"])
+    t_up = time.perf_counter() - t0
+    log(f"device setup {t_up:.1f}s")
+    Vd = torch.tensor(w["V"], dtype=torch.float64, device="cuda")
+    a, _, m = S.assemble(Vd, w["t"], want_mass=True)
+    S.set_values(a)
+    b = (m[:, None] * torch.tensor(w["u"], dtype=torch.float64, device="cuda")).contiguous()
+    return S, h, Vd, b, dict(precompute_s=t_pre, device_setup_s=t_up)
+
+
+def run_steps(S, Vd, t, b, rtol, precision, steps, use_graph):
+    import torch
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a, _, _ = S.assemble(Vd, t)
+        S.set_values(a)
+        x, info = S.solve(b, rtol=rtol, precision=precision, use_graph=use_graph)
+        infos.append(info)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, infos, x
+
+
+def time_solve_only(S, b, rtol, precision, steps, use_graph):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x, info = S.solve(b, rtol=rtol, precision=precision, use_graph=use_graph)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, info
+
+
+def cpu_baseline(w, n_levels, rtol):
+    """The oracle, untouched, on the same workload: its own hierarchy (untimed
+    setup, as the paper excludes precompute), then one timed step = assembly +
+    Galerkin refresh + coarsest Cholesky + FP64 solve to rtol."""
+    from threadpoolctl import threadpool_limits
+    from oracle import assemble as AS, vcycle as OV, hierarchy as OH
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        Ps, _, _ = OH.prolongations(w["V"], w["F"], n_levels=n_levels)
+        A, L, m = AS.system(w["V"], w["F"], w["t"])
+        S = OV.Solver(Ps, A)
+        b = m[:, None] * w["u"]
+        log(f"oracle setup {time.perf_counter() - t0:.1f}s")
+        t1 = time.perf_counter()
+        A, L, m = AS.system(w["V"], w["F"], w["t"])
+        S.set_values(A)
+        x, cycles, hist = S.solve(b, rtol, max_cycles=500)
+        dt = time.perf_counter() - t1
+    log(f"oracle step {dt:.1f}s cycles={cycles}")
+    return dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
+                sample="one full step (assembly, Galerkin refresh, Cholesky, FP64 solve of the "
+                       "3-RHS system to 1e-8) on the full 1M-vertex workload; single thread",
+                step_s=dt, cycles=int(cycles))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, nargs=2, default=(1000, 1000))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--profile-kind", default="gs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    rtol = 1e-8
+    n_levels = 7
+    w = synth.workload_c2(*args.size)
+    log(f"workload {w['name']} n={len(w['V'])} faces={len(w['F'])}")
+    S, h, Vd, b, setup = gpu_setup(w, n_levels)
+    use_graph = bool(args.graph)
+
+    # warmup both precisions
+    for prec in ("fp32ir", "fp64"):
+        run_steps(S, Vd, w["t"], b, rtol, prec, args.warmup, use_graph)
+    # timed region: mixed precision, the dominant kernel timed per launch
+    S.profile_enable(args.profile_kind, 0)
+    t_mixed, infos_m, x_m = run_steps(S, Vd, w["t"], b, rtol, "fp32ir", args.steps, use_graph)
+    prof = S.profile_read()
+    S.profile_enable(None)
+    log(f"mixed: {t_mixed / args.steps * 1e3:.2f} ms/step cycles={infos_m[-1]['cycles']} res={max(infos_m[-1]['rel_res']):.2e}")
+    t_fp64, infos_d, x_d = run_steps(S, Vd, w["t"], b, rtol, "fp64", args.steps, use_graph)
+    log(f"fp64: {t_fp64 / args.steps * 1e3:.2f} ms/step cycles={infos_d[-1]['cycles']} res={max(infos_d[-1]['rel_res']):.2e}")
+    so_m, _ = time_solve_only(S, b, rtol, "fp32ir", args.steps, use_graph)
+    so_d, _ = time_solve_only(S, b, rtol, "fp64", args.steps, use_graph)
+    diff = float(torch.linalg.norm(x_m - x_d) / torch.linalg.norm(x_d))
+
+    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else None
+    per_launch_bytes = prof["bytes"] / max(1, prof["launches"])
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "kernel": f"k_gs_color<K=3,float> level 0 ({args.profile_kind})",
+                "launches": prof["launches"], "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"]),
+                "algorithmic_bytes_per_launch": per_launch_bytes}
+    value = args.steps / t_mixed
+    out = {
+        "metric": "V-cycle solves/s + HBM GB/s at 1M verts to rel residual 1e-8, mixed vs FP64",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_mixed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32/f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']} torus R=1 r=0.3 jitter 0.2, A=M+1e-2 L, 3 RHS b=M X, "
+                               f"{n_levels} levels, mu 2/2, rtol 1e-8",
+                   "vertices": len(w["V"]), "levels": h.sizes, "rhs": 3, "graph": use_graph},
+        "fp64": {"value": args.steps / t_fp64, "ms_per_step": t_fp64 / args.steps * 1e3,
+                 "cycles": infos_d[-1]["cycles"], "rel_res": infos_d[-1]["rel_res"],
+                 "solve_only_per_s": 1.0 / so_d},
+        "mixed": {"cycles": infos_m[-1]["cycles"], "rel_res": infos_m[-1]["rel_res"],
+                  "solve_only_per_s": 1.0 / so_m, "rel_diff_vs_fp64": diff},
+        "setup": setup,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, n_levels, rtol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

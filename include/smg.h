@@ -113,6 +113,13 @@ smg_status smg_mesh_pattern(int32_t n, const int32_t *F, int32_t m, int32_t *row
 typedef struct {
     int32_t mu_pre;        /* pre-relaxation sweeps (Sec. 5 default 2)  */
     int32_t mu_post;       /* post-relaxation sweeps (Sec. 5 default 2) */
+    int32_t tail_rows;     /* levels with at most this many rows (and all
+                              coarser ones) run in one single-workgroup kernel
+                              per cycle; 0 = 20000, < 0 = never             */
+    int32_t lanes_per_row[16]; /* per level 1/2/4/8 lanes per matrix row in
+                              the relaxation/residual kernels; 0 = rule by
+                              mean row length (launch shape only: results do
+                              not depend on it beyond summation order)     */
 } smg_opts;
 
 /* Upload a hierarchy for the level-0 pattern (a0_rowptr, a0_cols: host CSR,
@@ -172,7 +179,9 @@ smg_status smg_restrict(smg_solver s, int32_t level, const double *d_r, double *
 /* x += P_l e  (prolong correction and update) */
 smg_status smg_prolong_add(smg_solver s, int32_t level, const double *d_e, double *d_x,
                            int32_t k, smg_stream stream);
-/* x = A_H^{-1} b by the Cholesky factor (coarsest direct solve) */
+/* x = A_H^{-1} b, the coarsest direct solve: A_H^{-1} is formed once per
+ * smg_set_values from the Cholesky factor G (A_H^{-1} = G^{-T} G^{-1}) and
+ * applied as a dense FP64 product */
 smg_status smg_coarse_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                             smg_stream stream);
 /* One V-cycle at level 0 in place on x (precision SMG_FP64 only). */
@@ -208,6 +217,20 @@ smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const double *d_la
 /* d_out[i] = -lambda_i * m_i * u_i */
 smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const double *d_m,
                          const double *d_u, double *d_out, smg_stream stream);
+
+/* --- per-launch kernel timing (HIP events on the launch stream) --- */
+enum { SMG_PROF_GS = 0, SMG_PROF_RESIDUAL = 1, SMG_PROF_RESTRICT = 2, SMG_PROF_PROLONG = 3,
+       SMG_PROF_COARSE = 4, SMG_PROF_GALERKIN = 5 };
+/* Record a pair of events around every launch of kernel `kind` on level
+ * `level` (any precision) until disabled (kind < 0).  Works in eager mode;
+ * solves with use_graph run their cycles eagerly while profiling is on. */
+smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level);
+/* Totals since enable: summed launch durations (ms), launch count, and the
+ * algorithmic bytes of those launches (matrix entries and vector traffic the
+ * method must move: z (s + 4) + n s + 3 k n s for a relaxation color or a
+ * residual, s = 8 or 4 bytes per value, z off-diagonal entries, n rows, k
+ * right-hand sides; x gathers counted once).  Synchronizes the device. */
+smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches, double *bytes);
 
 /* ------------------------------------------------------------------------ */
 /* Batching: many solvers in one persistent launch.                          */

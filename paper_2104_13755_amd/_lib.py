@@ -22,7 +22,8 @@ class PreOpts(ctypes.Structure):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("mu_pre", c_int32), ("mu_post", c_int32)]
+    _fields_ = [("mu_pre", c_int32), ("mu_post", c_int32), ("tail_rows", c_int32),
+                ("lanes_per_row", c_int32 * 16)]
 
 
 class SolveParams(ctypes.Structure):
@@ -75,6 +76,8 @@ SIGNATURES = {
     "smg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_spmv_dot": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, P_f64, c_void_p]),
     "smg_mass_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "smg_profile_enable": (c_int32, [c_void_p, c_int32, c_int32]),
+    "smg_profile_read": (c_int32, [c_void_p, P_f64, ctypes.POINTER(c_int64), P_f64]),
     "smg_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(BatchOpts), ctypes.POINTER(c_void_p)]),
     "smg_batch_destroy": (None, [c_void_p]),
     "smg_batch_solve": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), P_i32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),

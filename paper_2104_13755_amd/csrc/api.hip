@@ -257,9 +257,12 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     S->mu_pre = opts && opts->mu_pre >= 0 ? opts->mu_pre : 2;
     S->mu_post = opts && opts->mu_post >= 0 ? opts->mu_post : 2;
     if (!opts) S->mu_pre = S->mu_post = 2;
+    const int tail_rows = (opts && opts->tail_rows != 0) ? opts->tail_rows : 20000;
+    std::vector<int> lpr(16, 0);
+    if (opts) for (int l = 0; l < 16; ++l) lpr[l] = opts->lanes_per_row[l];
     std::vector<LevelHost> levels;
     std::string err;
-    if (build_levels(h->H, A0, levels, err) != 0) return fail(SMG_ERR_INVALID_ARG, "hierarchy setup: " + err);
+    if (build_levels(h->H, A0, lpr, levels, err) != 0) return fail(SMG_ERR_INVALID_ARG, "hierarchy setup: " + err);
     S->nlev = h->H.nlev;
     S->lev.resize(S->nlev);
     int64_t tmax = 1;
@@ -281,9 +284,20 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
         if (L.coarsest) {
             CHK(dalloc(&D.dense, (size_t)L.n * L.n, S->owned));
             CHK(dalloc(&D.dense_a, (size_t)L.n * L.n, S->owned));
+            CHK(dalloc(&D.dense_w, (size_t)L.n * L.n, S->owned));
+            CHK(dalloc(&D.dense_inv, (size_t)L.n * L.n, S->owned));
         } else {
             const SellLayout &Sl = L.sell;
             D.nslices = Sl.nslices;
+            D.lpr = Sl.lpr;
+            CHK(dupload(&D.color_row, Sl.color_row, S->owned));
+            for (int c = 0; c < L.ncolors; ++c) {
+                int64_t z = 0;
+                for (int r = Sl.color_row[c]; r < Sl.color_row[c + 1]; ++r) z += Sl.rowlen[r];
+                D.color_rows.push_back(Sl.color_row[c + 1] - Sl.color_row[c]);
+                D.color_nnz.push_back(z);
+                D.offdiag_nnz += z;
+            }
             D.color_slice = Sl.color_slice;
             D.slots = Sl.slots();
             std::vector<int32_t> row0 = Sl.slice_row0;
@@ -324,6 +338,24 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
         L = LevelHost();
     }
     CHK(dalloc(&S->tbuf, (size_t)tmax, S->owned));
+    // single-workgroup tail: the first level with at most tail_rows rows
+    if (tail_rows > 0)
+        for (int l = 0; l < S->nlev; ++l)
+            if (S->lev[l].n <= tail_rows) { S->tail_first = l; break; }
+    {
+        std::vector<TailLevel<double>> t64(S->nlev);
+        std::vector<TailLevel<float>> t32(S->nlev);
+        for (int l = 0; l < S->nlev; ++l) {
+            const DevLevel &D = S->lev[l];
+            t64[l] = {D.n, D.ncolors, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
+                      D.rowlen, D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw, D.rptr, D.ridx, D.rw};
+            t32[l] = {D.n, D.ncolors, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
+                      D.rowlen, D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32, D.pc, D.pw32, D.rptr,
+                      D.ridx, D.rw32};
+        }
+        CHK(dupload(&S->tail64, t64, S->owned));
+        CHK(dupload(&S->tail32, t32, S->owned));
+    }
     int64_t maxblk = (nmax + 255) / 256 + 1;
     for (const DevLevel &D : S->lev) maxblk = std::max<int64_t>(maxblk, (D.nslices + 3) / 4 + 1);
     S->npartial = 2 * 4 * maxblk;
@@ -345,6 +377,7 @@ smg_solver_s::~smg_solver_s() {
     for (void *p : owned) (void)hipFree(p);
     if (h_norms) (void)hipHostFree(h_norms);
     if (h_flag) (void)hipHostFree(h_flag);
+    for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -472,7 +505,7 @@ smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t 
         DevLevel &D = s->lev[l];
         DevLevel &C = s->lev[l + 1];
         HIPCHK(launch_galerkin_t(D.n, D.tptr, D.plan1ptr, D.plan1, D.row_slice, D.slice_row0,
-                                 D.slice_off, D.rowlen, D.cols, D.vals, D.diag, D.pc, D.pw,
+                                 D.slice_off, D.lpr, D.rowlen, D.cols, D.vals, D.diag, D.pc, D.pw,
                                  s->tbuf, st));
         HIPCHK(launch_galerkin_c(C.n, D.plan2ptr, D.plan2, D.rptr, D.ridx, D.rw, D.tptr, s->tbuf,
                                  C.coarsest ? C.dense_a : C.vals, C.coarsest ? nullptr : C.diag, st));
@@ -487,6 +520,7 @@ smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t 
     HIPCHK(hipMemcpyAsync(Lc.dense, Lc.dense_a, (size_t)Lc.n * Lc.n * sizeof(double),
                           hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_cholesky(Lc.dense, Lc.n, s->flag + 1, st));
+    HIPCHK(launch_coarse_inverse(Lc.dense, Lc.n, Lc.dense_w, Lc.dense_inv, st));
     return SMG_OK;
 }
 
@@ -532,12 +566,15 @@ template <typename T>
 static SellView<T> sell_view(const DevLevel &D);
 template <>
 SellView<double> sell_view<double>(const DevLevel &D) {
-    return {D.n, D.slice_row0, D.slice_off, D.cols, D.vals, D.diag};
+    return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals, D.diag};
 }
 template <>
 SellView<float> sell_view<float>(const DevLevel &D) {
-    return {D.n, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32};
+    return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32};
 }
+template <typename T> static const TailLevel<T> *tail_desc(const smg_solver_s *s);
+template <> const TailLevel<double> *tail_desc<double>(const smg_solver_s *s) { return s->tail64; }
+template <> const TailLevel<float> *tail_desc<float>(const smg_solver_s *s) { return s->tail32; }
 static TransferView transfer_view(const DevLevel &D, const DevLevel &C) {
     return {D.n, C.n, D.pc, D.rptr, D.ridx};
 }
@@ -561,9 +598,14 @@ template <typename T>
 smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st) {
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
+    const double sb = sizeof(T);
     for (int sw = 0; sw < sweeps; ++sw)
-        for (int c = 0; c < D.ncolors; ++c)
+        for (int c = 0; c < D.ncolors; ++c) {
+            const int pi = prof_begin(s, SMG_PROF_GS, l,
+                                      D.color_nnz[c] * (sb + 4) + D.color_rows[c] * sb * (1 + 3 * k), st);
             HIPCHK(launch_gs_color<T>(A, D.color_slice[c], D.color_slice[c + 1], bbuf<T>(D), xbuf<T>(D), k, st));
+            prof_end(s, pi, st);
+        }
     return SMG_OK;
 }
 
@@ -571,8 +613,11 @@ template <typename T>
 smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t st) {
     DevLevel &D = s->lev[l];
     int nblk = 0;
+    const double sb = sizeof(T);
+    const int pi = prof_begin(s, SMG_PROF_RESIDUAL, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
     HIPCHK(launch_residual<T>(sell_view<T>(D), D.nslices, bbuf<T>(D), xbuf<T>(D), rbuf<T>(D), k,
                               norms ? s->partial : nullptr, &nblk, st));
+    prof_end(s, pi, st);
     if (norms) HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st));
     return SMG_OK;
 }
@@ -582,7 +627,12 @@ template <typename T>
 smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st) {
     DevLevel &D = s->lev[l];
     if (D.coarsest) {
-        HIPCHK((launch_coarse_solve<T, T>(D.dense, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
+        HIPCHK((launch_coarse_solve<T, T>(D.dense_inv, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
+        return SMG_OK;
+    }
+    if (l >= s->tail_first) {   // this level and all coarser ones in one launch
+        HIPCHK(launch_vcycle_tail<T>(tail_desc<T>(s), l, s->nlev, s->mu_pre, s->mu_post,
+                                     s->lev[s->nlev - 1].dense_inv, k, st));
         return SMG_OK;
     }
     DevLevel &C = s->lev[l + 1];
@@ -677,7 +727,7 @@ extern "C" smg_status smg_coarse_solve(smg_solver s, const double *d_b, double *
     if (!d_b || !d_x) return fail(SMG_ERR_INVALID_ARG, "null vector");
     HIPCHK(hipSetDevice(s->device));
     const DevLevel &D = s->lev[s->nlev - 1];
-    HIPCHK((launch_coarse_solve<double, double>(D.dense, D.n, d_b, d_x, k, (hipStream_t)stream)));
+    HIPCHK((launch_coarse_solve<double, double>(D.dense_inv, D.n, d_b, d_x, k, (hipStream_t)stream)));
     return SMG_OK;
 }
 
@@ -741,7 +791,8 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
     // graph capture needs a capturable stream: the cycles then run on the
     // solver's own stream, ordered after and before the caller's work
     hipStream_t st = caller;
-    if (p->use_graph) {
+    const bool graphs = p->use_graph && s->prof_kind < 0;
+    if (graphs) {
         st = s->gstream;
         HIPCHK(hipEventRecord(s->ev_in, caller));
         HIPCHK(hipStreamWaitEvent(st, s->ev_in, 0));
@@ -766,7 +817,7 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
     int cycles = 0;
     smg_status status = SMG_OK;
     hipGraphExec_t gexec = nullptr;
-    if (p->use_graph) CHK(get_cycle_graph(s, k, p->precision, st, &gexec));
+    if (graphs) CHK(get_cycle_graph(s, k, p->precision, st, &gexec));
     for (;;) {
         double worst = 0.0;
         for (int q = 0; q < k; ++q) worst = std::max(worst, rho[q]);
@@ -802,6 +853,7 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
         for (int q = 0; q < 4; ++q) info->rel_res[q] = q < k ? rho[q] : 0.0;
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+    if (s->prof_kind >= 0) CHK(prof_collect(s));
     if (status == SMG_ERR_NO_CONVERGENCE) return fail(status, "cycle cap reached");
     if (status == SMG_ERR_NONFINITE) return fail(status, "non-finite residual");
     return SMG_OK;
@@ -814,7 +866,7 @@ smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_
                                   const smg_solve_params *p, smg_solve_info *info, hipStream_t st) {
     (void)p;
     const DevLevel &D = s->lev[0];
-    HIPCHK((launch_coarse_solve<double, double>(D.dense, D.n, d_b, d_x, k, st)));
+    HIPCHK((launch_coarse_solve<double, double>(D.dense_inv, D.n, d_b, d_x, k, st)));
     HIPCHK(hipStreamSynchronize(st));
     if (info) {
         info->cycles = 1;
@@ -869,5 +921,67 @@ extern "C" smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const 
     if (!s || !d_lambda || !d_m || !d_u || !d_out) return fail(SMG_ERR_INVALID_ARG, "null argument");
     HIPCHK(hipSetDevice(s->device));
     HIPCHK(launch_mass_grad(d_lambda, d_m, d_u, d_out, s->lev[0].n, (hipStream_t)stream));
+    return SMG_OK;
+}
+
+// --------------------------------------------------------------- profiling
+namespace smg {
+
+int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st) {
+    if (s->prof_kind != kind || s->prof_level != level) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
+    while (s->prof_pool.size() < 2 * (s->prof_used + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        s->prof_pool.push_back(e);
+    }
+    const int idx = (int)s->prof_used++;
+    s->prof_bytes_pending.push_back(bytes);
+    (void)hipEventRecord(s->prof_pool[2 * idx], st);
+    return idx;
+}
+
+void prof_end(smg_solver_s *s, int idx, hipStream_t st) {
+    if (idx < 0) return;
+    (void)hipEventRecord(s->prof_pool[2 * idx + 1], st);
+}
+
+smg_status prof_collect(smg_solver_s *s) {
+    for (size_t i = 0; i < s->prof_used; ++i) {
+        HIPCHK(hipEventSynchronize(s->prof_pool[2 * i + 1]));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, s->prof_pool[2 * i], s->prof_pool[2 * i + 1]));
+        s->prof_ms += ms;
+        s->prof_bytes += s->prof_bytes_pending[i];
+        s->prof_launches++;
+    }
+    s->prof_used = 0;
+    s->prof_bytes_pending.clear();
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+extern "C" smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level) {
+    if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
+    HIPCHK(hipSetDevice(s->device));
+    CHK(prof_collect(s));
+    s->prof_kind = kind;
+    s->prof_level = level;
+    s->prof_ms = 0.0;
+    s->prof_bytes = 0.0;
+    s->prof_launches = 0;
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches,
+                                       double *bytes) {
+    if (!s || !total_ms || !launches || !bytes) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    HIPCHK(hipSetDevice(s->device));
+    CHK(prof_collect(s));
+    *total_ms = s->prof_ms;
+    *launches = s->prof_launches;
+    *bytes = s->prof_bytes;
     return SMG_OK;
 }

@@ -80,10 +80,19 @@ Csr galerkin_pattern(const Csr &A, int nc, const std::vector<int32_t> &pcols) {
     return C;
 }
 
-static void build_sell(LevelHost &L) {
+int default_lanes_per_row(double avg) {
+    if (avg < 10.0) return 1;
+    if (avg < 20.0) return 2;
+    if (avg < 40.0) return 4;
+    return 8;
+}
+
+static void build_sell(LevelHost &L, int lpr) {
     SellLayout &S = L.sell;
     const int n = L.n;
     S.n = n;
+    S.lpr = lpr;
+    const int rps = 64 / lpr;   // rows per slice
     // permuted off-diagonal pattern, ascending permuted columns
     S.pptr.assign(n + 1, 0);
     S.rowlen.assign(n, 0);
@@ -106,10 +115,10 @@ static void build_sell(LevelHost &L) {
     S.color_slice.assign(1, 0);
     S.row_slice.assign(n, 0);
     for (int c = 0; c < L.ncolors; ++c) {
-        for (int r0 = S.color_row[c]; r0 < S.color_row[c + 1]; r0 += 64) {
-            const int r1 = std::min(r0 + 64, S.color_row[c + 1]);
+        for (int r0 = S.color_row[c]; r0 < S.color_row[c + 1]; r0 += rps) {
+            const int r1 = std::min(r0 + rps, S.color_row[c + 1]);
             int w = 0;
-            for (int r = r0; r < r1; ++r) { w = std::max(w, S.rowlen[r]); S.row_slice[r] = (int)S.slice_row0.size(); }
+            for (int r = r0; r < r1; ++r) { w = std::max(w, (S.rowlen[r] + lpr - 1) / lpr); S.row_slice[r] = (int)S.slice_row0.size(); }
             S.slice_row0.push_back(r0);
             S.slice_off.push_back(S.slice_off.back() + 64 * w);
         }
@@ -120,10 +129,11 @@ static void build_sell(LevelHost &L) {
     for (int s = 0; s < S.nslices; ++s) {
         const int w = (S.slice_off[s + 1] - S.slice_off[s]) / 64;
         for (int t = 0; t < 64; ++t) {
-            const int r = S.slice_row0[s] + t;
+            const int r = S.slice_row0[s] + t / lpr, j = t % lpr;
             const bool valid = r < n && S.row_slice[r] == s;
-            for (int e = 0; e < w; ++e) {
-                const int slot = S.slice_off[s] + e * 64 + t;
+            for (int q = 0; q < w; ++q) {
+                const int e = q * lpr + j;
+                const int slot = S.slice_off[s] + q * 64 + t;
                 if (valid && e < S.rowlen[r]) S.cols[slot] = S.pidx[S.pptr[r] + e];
                 else S.cols[slot] = valid ? r : S.slice_row0[s];   // padding: weight 0
             }
@@ -142,7 +152,8 @@ static int32_t store_pos(const LevelHost &L, int r, int c) {
     return S.slot(r, (int)(it - b));
 }
 
-int build_levels(const HierHost &H, const Csr &A0, std::vector<LevelHost> &levels, std::string &err) {
+int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
+                 std::vector<LevelHost> &levels, std::string &err) {
     const int nlev = H.nlev;
     levels.assign(nlev, LevelHost());
     Csr pat = A0;
@@ -170,7 +181,12 @@ int build_levels(const HierHost &H, const Csr &A0, std::vector<LevelHost> &level
             std::iota(L.perm.begin(), L.perm.end(), 0);
         }
         for (int r = 0; r < L.n; ++r) L.iperm[L.perm[r]] = r;
-        if (!L.coarsest) build_sell(L);
+        if (!L.coarsest) {
+            int lanes = (l < (int)lpr.size() && lpr[l] > 0) ? lpr[l]
+                        : default_lanes_per_row((double)(pat.idx.size() - L.n) / std::max(1, L.n));
+            if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8) { err = "lanes per row must be 1, 2, 4 or 8"; return -1; }
+            build_sell(L, lanes);
+        }
         if (l + 1 < nlev) pat = galerkin_pattern(pat, H.sizes[l + 1], H.pcols[l]);
     }
     for (int l = 0; l < nlev; ++l) {

@@ -33,10 +33,13 @@ struct Csr {
 // ascending columns).  P given row-wise as ELL-3 (col < 0 unused).
 Csr galerkin_pattern(const Csr &A, int nc, const std::vector<int32_t> &pcols);
 
-// Sliced-ELL (64-row slices, column-major within a slice) layout of the
-// off-diagonal part of a level whose rows are permuted color-major.
+// Sliced-ELL layout of the off-diagonal part of a level whose rows are
+// permuted color-major.  A slice is one wavefront: 64 / lpr rows, each row
+// spread over lpr adjacent lanes (entry e of a row sits in lane e % lpr of its
+// group, element e / lpr), elements stored column-major (64 slots apart).
 struct SellLayout {
     int n = 0;                       // rows
+    int lpr = 1;                     // lanes per row (1, 2, 4 or 8)
     int nslices = 0;
     std::vector<int32_t> slice_row0; // first permuted row of each slice
     std::vector<int32_t> slice_off;  // nslices + 1 element offsets (multiples of 64)
@@ -50,7 +53,7 @@ struct SellLayout {
     // slot of the e-th off-diagonal entry of permuted row r
     int32_t slot(int r, int e) const {
         const int s = row_slice[r];
-        return slice_off[s] + e * 64 + (r - slice_row0[s]);
+        return slice_off[s] + (e / lpr) * 64 + (r - slice_row0[s]) * lpr + (e % lpr);
     }
 };
 
@@ -89,7 +92,12 @@ struct HierHost {
     std::vector<std::array<double, 8>> stats;
 };
 
+// Lanes per row for a level whose rows average `avg` off-diagonal entries.
+int default_lanes_per_row(double avg);
+
 // Build every LevelHost from the level-0 pattern and the prolongations.
-int build_levels(const HierHost &H, const Csr &A0, std::vector<LevelHost> &levels, std::string &err);
+// lpr[l] > 0 forces the lanes per row of level l (else the default rule).
+int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
+                 std::vector<LevelHost> &levels, std::string &err);
 
 }  // namespace smg

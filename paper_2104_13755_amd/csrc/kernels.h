@@ -10,6 +10,7 @@ namespace smg {
 template <typename T>
 struct SellView {
     int n;
+    int lpr;                     // lanes per row
     const int32_t *slice_row0;   // nslices + 1 (sentinel n)
     const int32_t *slice_off;    // nslices + 1
     const int32_t *cols;
@@ -49,17 +50,36 @@ hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double 
 
 // --- coarsest level ---
 hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st);
-// x = (G G^T)^{-1} b; Tin/Tout double or float (FP32 inner cycles convert here)
+// Ainv = (G G^T)^{-1} from the Cholesky factor G (W: n x n scratch)
+hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv, hipStream_t st);
+// x = A_H^{-1} b in FP64; Tin/Tout double or float (FP32 inner cycles convert here)
 template <typename Tin, typename Tout>
-hipError_t launch_coarse_solve(const double *G, int n, const Tin *b, Tout *x, int k,
+hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x, int k,
                                hipStream_t st);
+
+// --- single-workgroup V-cycle over the small levels ---
+template <typename T>
+struct TailLevel {
+    int n, ncolors, lpr;
+    const int32_t *color_row;     // ncolors + 1 permuted row boundaries
+    const int32_t *slice_row0, *slice_off, *row_slice, *rowlen, *cols;
+    const T *vals, *diag;
+    T *x, *b, *r;
+    const int32_t *pc;            // prolongation to the next level (SoA ELL-3)
+    const T *pw;
+    const int32_t *rptr, *ridx;   // restriction into the next level
+    const T *rw;
+};
+template <typename T>
+hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
+                              const double *Ainv, int k, hipStream_t st);
 
 // --- hierarchy values ---
 hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,
                                  double *vals, double *diag, int *flag, hipStream_t st);
 hipError_t launch_galerkin_t(int n, const int32_t *tptr, const int32_t *plan1ptr,
                              const uint16_t *plan1, const int32_t *row_slice,
-                             const int32_t *slice_row0, const int32_t *slice_off,
+                             const int32_t *slice_row0, const int32_t *slice_off, int lpr,
                              const int32_t *rowlen, const int32_t *cols, const double *vals,
                              const double *diag, const int32_t *pc, const double *pw,
                              double *Tbuf, hipStream_t st);

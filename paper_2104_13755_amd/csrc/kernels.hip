@@ -15,6 +15,7 @@ namespace smg {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kTail = 1024;   // threads of the single-workgroup tail kernel
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of logical blocks so neighbouring slices share an L2.
@@ -36,9 +37,37 @@ __device__ __forceinline__ T wave_max(T v) {
 }
 
 // ---------------------------------------------------------------- relaxation
+// Sum of one row's off-diagonal products over the lpr lanes of its group.
+template <int K, typename T>
+__device__ __forceinline__ void row_gather(int o, int w, int lpr, const int32_t *__restrict__ cols,
+                                           const T *__restrict__ vals, const T *__restrict__ x,
+                                           T (&acc)[K]) {
+    int e = 0;
+    for (; e + 4 <= w; e += 4) {          // four independent gathers in flight
+        int c[4];
+        T a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { c[u] = cols[o + u * 64]; a[u] = vals[o + u * 64]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] += a[u] * x[(size_t)c[u] * K + q];
+        o += 4 * 64;
+    }
+    for (; e < w; ++e, o += 64) {
+        const int c = cols[o];
+        const T a = vals[o];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)c * K + q];
+    }
+    for (int m = lpr >> 1; m > 0; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+}
+
 // x_i <- (b_i - sum_{j != i} A_ij x_j) / A_ii for every row i of one color.
 template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end,
+__global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end, int lpr,
                                                      const int32_t *__restrict__ slice_row0,
                                                      const int32_t *__restrict__ slice_off,
                                                      const int32_t *__restrict__ cols,
@@ -49,29 +78,25 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end,
     const int s = s_begin + blk * (kBlock / 64) + (threadIdx.x >> 6);
     if (s >= s_end) return;
     const int lane = threadIdx.x & 63;
-    const int row = slice_row0[s] + lane;
-    if (row >= slice_row0[s + 1]) return;
+    const int row = slice_row0[s] + lane / lpr;
+    if (row >= slice_row0[s + 1]) return;   // whole lane groups leave together
     const int o0 = slice_off[s];
     const int w = (slice_off[s + 1] - o0) >> 6;
     T acc[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = T(0);
-    int o = o0 + lane;
-    for (int e = 0; e < w; ++e, o += 64) {
-        const int c = cols[o];
-        const T a = vals[o];
+    row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
+    if ((lane & (lpr - 1)) == 0) {
+        const T d = diag[row];
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)c * K + q];
+        for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (b[(size_t)row * K + q] - acc[q]) / d;
     }
-    const T d = diag[row];
-#pragma unroll
-    for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (b[(size_t)row * K + q] - acc[q]) / d;
 }
 
 // ------------------------------------------------------------------ residual
 // r = b - A x over all slices; optional per-block column (sum r^2, max |r|).
 template <int K, typename T, bool NORM>
-__global__ __launch_bounds__(kBlock) void k_residual(int nslices,
+__global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
                                                      const int32_t *__restrict__ slice_row0,
                                                      const int32_t *__restrict__ slice_off,
                                                      const int32_t *__restrict__ cols,
@@ -87,26 +112,22 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices,
 #pragma unroll
     for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
     if (s < nslices) {
-        const int row = slice_row0[s] + lane;
+        const int row = slice_row0[s] + lane / lpr;
         if (row < slice_row0[s + 1]) {
             const int o0 = slice_off[s];
             const int w = (slice_off[s + 1] - o0) >> 6;
-            const T d = diag[row];
             T acc[K];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = d * x[(size_t)row * K + q];
-            int o = o0 + lane;
-            for (int e = 0; e < w; ++e, o += 64) {
-                const int c = cols[o];
-                const T a = vals[o];
+            for (int q = 0; q < K; ++q) acc[q] = T(0);
+            row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
+            if ((lane & (lpr - 1)) == 0) {
+                const T d = diag[row];
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)c * K + q];
-            }
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const T rv = b[(size_t)row * K + q] - acc[q];
-                r[(size_t)row * K + q] = rv;
-                if (NORM) { sq[q] = (double)rv * (double)rv; mx[q] = fabs((double)rv); }
+                for (int q = 0; q < K; ++q) {
+                    const T rv = b[(size_t)row * K + q] - (acc[q] + d * x[(size_t)row * K + q]);
+                    r[(size_t)row * K + q] = rv;
+                    if (NORM) { sq[q] = (double)rv * (double)rv; mx[q] = fabs((double)rv); }
+                }
             }
         }
     }
@@ -255,104 +276,169 @@ __global__ __launch_bounds__(1024) void k_cholesky(double *__restrict__ A, int n
     }
 }
 
-// Forward then backward substitution with G (lower, column-major), blocked
-// in 64-column panels; one workgroup, the right-hand sides in LDS.
+// W = G^{-1} for the lower-triangular Cholesky factor G (column-major): one
+// thread per column j solves G w_j = e_j by forward substitution.
+__global__ __launch_bounds__(kBlock) void k_tri_inverse(const double *__restrict__ G, int n,
+                                                        double *__restrict__ W) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    for (int i = 0; i < j; ++i) W[(size_t)j * n + i] = 0.0;
+    W[(size_t)j * n + j] = 1.0 / G[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+        double s = 0.0;
+        for (int m = j; m < i; ++m) s += G[(size_t)m * n + i] * W[(size_t)j * n + m];
+        W[(size_t)j * n + i] = -s / G[(size_t)i * n + i];
+    }
+}
+
+// A^{-1} = W^T W (symmetric), entry (i, j) = sum_{m >= max(i,j)} W_mi W_mj.
+__global__ __launch_bounds__(kBlock) void k_inverse_product(const double *__restrict__ W, int n,
+                                                            double *__restrict__ Ainv) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    const int i = (int)(t % n), j = (int)(t / n);
+    double s = 0.0;
+    for (int m = max(i, j); m < n; ++m) s += W[(size_t)i * n + m] * W[(size_t)j * n + m];
+    Ainv[(size_t)j * n + i] = s;
+}
+
+// x = A_H^{-1} b (the coarsest direct solve), one thread per row, FP64
+// accumulation; Ainv symmetric so column i is row i.
 template <int K, typename Tin, typename Tout>
-__global__ __launch_bounds__(kBlock) void k_coarse_solve(const double *__restrict__ G, int n,
+__global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *__restrict__ Ainv, int n,
                                                          const Tin *__restrict__ b,
                                                          Tout *__restrict__ x) {
-    extern __shared__ double y[];   // n * K
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int t = tid; t < n * K; t += kBlock) y[t] = (double)b[t];
-    __syncthreads();
-    // forward: G z = b
-    for (int j0 = 0; j0 < n; j0 += 64) {
-        const int jb = min(64, n - j0);
-        if (wv == 0) {
-            for (int jj = 0; jj < jb; ++jj) {
-                const int j = j0 + jj;
-                const double g = G[(size_t)j * n + j];
-                double zj[K];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double acc[K];
 #pragma unroll
-                for (int q = 0; q < K; ++q) zj[q] = y[j * K + q] / g;
-                __builtin_amdgcn_wave_barrier();
-                if (lane == jj) {
+    for (int q = 0; q < K; ++q) acc[q] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double a = Ainv[(size_t)j * n + i];
 #pragma unroll
-                    for (int q = 0; q < K; ++q) y[j * K + q] = zj[q];
+        for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(size_t)j * K + q];
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[(size_t)i * K + q] = (Tout)acc[q];
+}
+
+// ------------------------------------------------------------ tail V-cycle
+// All levels from `first` down to the coarsest in ONE workgroup: relaxation
+// colors, residual, restriction, coarsest solve, prolongation, separated by
+// workgroup barriers (Alg. "V-cycle" for the small levels, one launch).
+template <int K, typename T>
+__device__ void tail_relax(const TailLevel<T> &L, int sweeps) {
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int c = 0; c < L.ncolors; ++c) {
+            const int r0 = L.color_row[c], r1 = L.color_row[c + 1];
+            for (int r = r0 + (int)threadIdx.x; r < r1; r += kTail) {
+                const int s = L.row_slice[r];
+                const int base = L.slice_off[s] + (r - L.slice_row0[s]) * L.lpr;
+                const int len = L.rowlen[r];
+                T acc[K];
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] = T(0);
+                for (int e = 0; e < len; ++e) {
+                    const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
+                    const int cc = L.cols[slot];
+                    const T a = L.vals[slot];
+#pragma unroll
+                    for (int q = 0; q < K; ++q) acc[q] += a * L.x[(size_t)cc * K + q];
                 }
-                if (lane > jj && lane < jb) {
-                    const double gij = G[(size_t)j * n + j0 + lane];
+                const T d = L.diag[r];
 #pragma unroll
-                    for (int q = 0; q < K; ++q) y[(j0 + lane) * K + q] -= gij * zj[q];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int q = 0; q < K; ++q) L.x[(size_t)r * K + q] = (L.b[(size_t)r * K + q] - acc[q]) / d;
             }
+            __syncthreads();
+        }
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__restrict__ lv, int first,
+                                                       int nlev, int mu_pre, int mu_post,
+                                                       const double *__restrict__ Ainv) {
+    const int last = nlev - 1;   // coarsest
+    for (int l = first; l < last; ++l) {
+        const TailLevel<T> L = lv[l];
+        if (l > first) {
+            for (int t = threadIdx.x; t < L.n * K; t += kTail) L.x[t] = T(0);
+            __syncthreads();
+        }
+        tail_relax<K, T>(L, mu_pre);
+        // residual
+        for (int r = threadIdx.x; r < L.n; r += kTail) {
+            const int s = L.row_slice[r];
+            const int base = L.slice_off[s] + (r - L.slice_row0[s]) * L.lpr;
+            const int len = L.rowlen[r];
+            T acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = T(0);
+            for (int e = 0; e < len; ++e) {
+                const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
+                const int cc = L.cols[slot];
+                const T a = L.vals[slot];
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += a * L.x[(size_t)cc * K + q];
+            }
+            const T d = L.diag[r];
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                L.r[(size_t)r * K + q] = L.b[(size_t)r * K + q] - (acc[q] + d * L.x[(size_t)r * K + q]);
         }
         __syncthreads();
-        for (int i = j0 + jb + tid; i < n; i += kBlock) {
-            double acc[K];
+        // restriction into the next level's b
+        const TailLevel<T> C = lv[l + 1];
+        for (int a = threadIdx.x; a < C.n; a += kTail) {
+            T acc[K];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = 0.0;
-            for (int jj = 0; jj < jb; ++jj) {
-                const double g = G[(size_t)(j0 + jj) * n + i];
+            for (int q = 0; q < K; ++q) acc[q] = T(0);
+            for (int p = L.rptr[a]; p < L.rptr[a + 1]; ++p) {
+                const int i = L.ridx[p];
+                const T w = L.rw[p];
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += g * y[(j0 + jj) * K + q];
+                for (int q = 0; q < K; ++q) acc[q] += w * L.r[(size_t)i * K + q];
             }
 #pragma unroll
-            for (int q = 0; q < K; ++q) y[i * K + q] -= acc[q];
+            for (int q = 0; q < K; ++q) C.b[(size_t)a * K + q] = acc[q];
         }
         __syncthreads();
     }
-    // backward: G^T x = z
-    const int npan = (n + 63) / 64;
-    for (int pnl = npan - 1; pnl >= 0; --pnl) {
-        const int j0 = pnl * 64, jb = min(64, n - j0), below = j0 + jb;
-        // y_j -= sum_{i >= below} G_ij x_i  (column j of G, rows below the panel)
-        for (int jj = wv; jj < jb; jj += kBlock / 64) {
-            const int j = j0 + jj;
+    {   // coarsest: x = A^{-1} b in FP64
+        const TailLevel<T> C = lv[last];
+        for (int i = threadIdx.x; i < C.n; i += kTail) {
             double acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = 0.0;
-            for (int i = below + lane; i < n; i += 64) {
-                const double g = G[(size_t)j * n + i];
+            for (int j = 0; j < C.n; ++j) {
+                const double a = Ainv[(size_t)j * C.n + i];
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += g * y[i * K + q];
+                for (int q = 0; q < K; ++q) acc[q] += a * (double)C.b[(size_t)j * K + q];
             }
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = wave_sum(acc[q]);
-            if (lane == 0) {
-#pragma unroll
-                for (int q = 0; q < K; ++q) y[j * K + q] -= acc[q];
-            }
-        }
-        __syncthreads();
-        if (wv == 0) {
-            for (int jj = jb - 1; jj >= 0; --jj) {
-                const int j = j0 + jj;
-                const double g = G[(size_t)j * n + j];
-                double xj[K];
-#pragma unroll
-                for (int q = 0; q < K; ++q) xj[q] = y[j * K + q] / g;
-                __builtin_amdgcn_wave_barrier();
-                if (lane == jj) {
-#pragma unroll
-                    for (int q = 0; q < K; ++q) y[j * K + q] = xj[q];
-                }
-                if (lane < jj) {
-                    const double gji = G[(size_t)(j0 + lane) * n + j];
-#pragma unroll
-                    for (int q = 0; q < K; ++q) y[(j0 + lane) * K + q] -= gji * xj[q];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            for (int q = 0; q < K; ++q) C.x[(size_t)i * K + q] = (T)acc[q];
         }
         __syncthreads();
     }
-    for (int t = tid; t < n * K; t += kBlock) x[t] = (Tout)y[t];
+    for (int l = last - 1; l >= first; --l) {
+        const TailLevel<T> L = lv[l];
+        const TailLevel<T> C = lv[l + 1];
+        for (int i = threadIdx.x; i < L.n; i += kTail) {
+            T acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = T(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const int c = L.pc[(size_t)m * L.n + i];
+                const T w = L.pw[(size_t)m * L.n + i];
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += w * C.x[(size_t)c * K + q];
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q) L.x[(size_t)i * K + q] += acc[q];
+        }
+        __syncthreads();
+        tail_relax<K, T>(L, mu_post);
+    }
 }
 
 // ------------------------------------------------------- hierarchy values
@@ -374,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_values(const double *__restr
 __global__ __launch_bounds__(kBlock) void k_galerkin_t(
     int n, const int32_t *__restrict__ tptr, const int32_t *__restrict__ plan1ptr,
     const uint16_t *__restrict__ plan1, const int32_t *__restrict__ row_slice,
-    const int32_t *__restrict__ slice_row0, const int32_t *__restrict__ slice_off,
+    const int32_t *__restrict__ slice_row0, const int32_t *__restrict__ slice_off, int lpr,
     const int32_t *__restrict__ rowlen, const int32_t *__restrict__ cols,
     const double *__restrict__ vals, const double *__restrict__ diag,
     const int32_t *__restrict__ pc, const double *__restrict__ pw, double *__restrict__ Tb) {
@@ -387,10 +473,10 @@ __global__ __launch_bounds__(kBlock) void k_galerkin_t(
 #pragma unroll
     for (int m = 0; m < 3; ++m) Tb[t0 + pl[m]] += d * pw[(size_t)m * n + r];
     const int s = row_slice[r];
-    const int base = slice_off[s] + (r - slice_row0[s]);
+    const int base = slice_off[s] + (r - slice_row0[s]) * lpr;
     const int len = rowlen[r];
     for (int e = 0; e < len; ++e) {
-        const int slot = base + e * 64;
+        const int slot = base + (e / lpr) * 64 + (e % lpr);
         const int c = cols[slot];
         const double a = vals[slot];
 #pragma unroll
@@ -577,7 +663,7 @@ hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T
     const int ns = s_end - s_begin;
     if (ns <= 0) return hipSuccess;
     const int g = nblocks(ns, kBlock / 64);
-    SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kBlock, 0, st>>>(s_begin, s_end, A.slice_row0, A.slice_off,
+    SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kBlock, 0, st>>>(s_begin, s_end, A.lpr, A.slice_row0, A.slice_off,
                                                              A.cols, A.vals, A.diag, b, x)));
     return hipGetLastError();
 }
@@ -590,10 +676,10 @@ hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const 
     *nblk = g;
     if (ns <= 0) return hipSuccess;
     if (partial) {
-        SMG_K_SWITCH(k, (k_residual<KK, T, true><<<g, kBlock, 0, st>>>(ns, A.slice_row0, A.slice_off, A.cols,
+        SMG_K_SWITCH(k, (k_residual<KK, T, true><<<g, kBlock, 0, st>>>(ns, A.lpr, A.slice_row0, A.slice_off, A.cols,
                                                                        A.vals, A.diag, b, x, r, partial)));
     } else {
-        SMG_K_SWITCH(k, (k_residual<KK, T, false><<<g, kBlock, 0, st>>>(ns, A.slice_row0, A.slice_off, A.cols,
+        SMG_K_SWITCH(k, (k_residual<KK, T, false><<<g, kBlock, 0, st>>>(ns, A.lpr, A.slice_row0, A.slice_off, A.cols,
                                                                         A.vals, A.diag, b, x, r, nullptr)));
     }
     return hipGetLastError();
@@ -636,11 +722,24 @@ hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st) {
 }
 
 template <typename Tin, typename Tout>
-hipError_t launch_coarse_solve(const double *G, int n, const Tin *b, Tout *x, int k,
+hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x, int k,
                                hipStream_t st) {
-    const size_t lds = (size_t)n * k * sizeof(double);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    SMG_K_SWITCH(k, (k_coarse_solve<KK, Tin, Tout><<<1, kBlock, lds, st>>>(G, n, b, x)));
+    if (n <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_coarse_apply<KK, Tin, Tout><<<nblocks(n), kBlock, 0, st>>>(Ainv, n, b, x)));
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_tri_inverse<<<nblocks(n), kBlock, 0, st>>>(G, n, W);
+    k_inverse_product<<<nblocks((int64_t)n * n), kBlock, 0, st>>>(W, n, Ainv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
+                              const double *Ainv, int k, hipStream_t st) {
+    SMG_K_SWITCH(k, (k_vcycle_tail<KK, T><<<1, kTail, 0, st>>>(lv, first, nlev, mu_pre, mu_post, Ainv)));
     return hipGetLastError();
 }
 
@@ -653,13 +752,13 @@ hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_
 
 hipError_t launch_galerkin_t(int n, const int32_t *tptr, const int32_t *plan1ptr,
                              const uint16_t *plan1, const int32_t *row_slice,
-                             const int32_t *slice_row0, const int32_t *slice_off,
+                             const int32_t *slice_row0, const int32_t *slice_off, int lpr,
                              const int32_t *rowlen, const int32_t *cols, const double *vals,
                              const double *diag, const int32_t *pc, const double *pw,
                              double *Tbuf, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     k_galerkin_t<<<nblocks(n), kBlock, 0, st>>>(n, tptr, plan1ptr, plan1, row_slice, slice_row0,
-                                                slice_off, rowlen, cols, vals, diag, pc, pw, Tbuf);
+                                                slice_off, lpr, rowlen, cols, vals, diag, pc, pw, Tbuf);
     return hipGetLastError();
 }
 
@@ -767,6 +866,10 @@ template hipError_t launch_coarse_solve<double, double>(const double *, int, con
                                                         double *, int, hipStream_t);
 template hipError_t launch_coarse_solve<float, float>(const double *, int, const float *, float *,
                                                       int, hipStream_t);
+template hipError_t launch_vcycle_tail<double>(const TailLevel<double> *, int, int, int, int,
+                                               const double *, int, hipStream_t);
+template hipError_t launch_vcycle_tail<float>(const TailLevel<float> *, int, int, int, int,
+                                              const double *, int, hipStream_t);
 template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
 template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);

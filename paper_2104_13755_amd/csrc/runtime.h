@@ -7,12 +7,16 @@
 #include <string>
 #include <vector>
 
+#include "kernels.h"
 #include "smg.h"
 
 namespace smg {
 
 struct DevLevel {
-    int n = 0, ncolors = 0, nslices = 0;
+    int n = 0, ncolors = 0, nslices = 0, lpr = 1;
+    int32_t *color_row = nullptr;                 // device, ncolors + 1
+    std::vector<int64_t> color_rows, color_nnz;   // per color: rows, off-diagonal entries
+    int64_t offdiag_nnz = 0;
     bool coarsest = false;
     int64_t slots = 0, nnz_nat = 0;
     std::vector<int32_t> color_slice;      // host copy of slice boundaries per color
@@ -25,8 +29,9 @@ struct DevLevel {
             *row_slice = nullptr;
     double *vals = nullptr, *diag = nullptr;
     float *vals32 = nullptr, *diag32 = nullptr;
-    // coarsest: A_H (dense_a) and its Cholesky factor (dense), column-major
-    double *dense = nullptr, *dense_a = nullptr;
+    // coarsest: A_H (dense_a), its Cholesky factor (dense), G^{-1} (dense_w)
+    // and A_H^{-1} (dense_inv), all column-major
+    double *dense = nullptr, *dense_a = nullptr, *dense_w = nullptr, *dense_inv = nullptr;
     // transfers to the next level and the Galerkin plan
     int32_t *pc = nullptr, *rptr = nullptr, *ridx = nullptr;
     double *pw = nullptr, *rw = nullptr;
@@ -58,6 +63,9 @@ smg_status fail(smg_status st, const std::string &msg);
 
 struct smg_solver_s {
     int device = 0, nlev = 0, mu_pre = 2, mu_post = 2;
+    int tail_first = 1 << 30;      // first level run by the single-workgroup tail kernel
+    smg::TailLevel<double> *tail64 = nullptr;   // device descriptors, one per level
+    smg::TailLevel<float> *tail32 = nullptr;
     bool values_set = false;
     std::vector<smg::DevLevel> lev;
     smg::MeshDev mesh;
@@ -71,6 +79,13 @@ struct smg_solver_s {
     std::vector<void *> owned;
     std::vector<smg::CycleGraph> graphs;
     hipStream_t gstream = nullptr;  // capture/replay stream for cycle graphs
+    // per-launch profiling
+    int prof_kind = -1, prof_level = -1;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<double> prof_bytes_pending;      // bytes of each recorded pair
+    size_t prof_used = 0;
+    double prof_ms = 0.0, prof_bytes = 0.0;
+    int64_t prof_launches = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     ~smg_solver_s();
 };
@@ -84,6 +99,10 @@ smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t
 smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st);
 smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st,
                            hipGraphExec_t *out);
+// profiling helpers: begin returns the event pair index or -1
+int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st);
+void prof_end(smg_solver_s *s, int idx, hipStream_t st);
+smg_status prof_collect(smg_solver_s *s);
 smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_x, int k,
                                   const smg_solve_params *p, smg_solve_info *info,
                                   hipStream_t st);

@@ -38,6 +38,7 @@
 #include <cstring>
 #include <limits>
 #include <queue>
+#include <unordered_set>
 #include <vector>
 
 namespace smg {
@@ -252,6 +253,13 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
 
     double st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int alive = n;
+    // Edges that failed a validity test.  They leave the queue and come back
+    // only when a collapse changes their neighbourhood; every other edge keeps
+    // its single queue entry (its length never changes: new vertices get new
+    // ids), so re-inserting it would only add an equal-key duplicate.
+    std::unordered_set<uint64_t> failed;
+    auto ekey = [](int lo, int hi) { return ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi; };
+    auto fail_edge = [&](int lo, int hi) { failed.insert(ekey(lo, hi)); st[1]++; };
     std::vector<std::pair<int, int> > la, lb, tmp;
     std::vector<int> before, ring, moved;
     Joint cur, best;
@@ -265,11 +273,11 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
             const auto &f = S.tri[t];
             if (f[0] == b || f[1] == b || f[2] == b) { if (nshared < 3) shared_tris[nshared] = t; ++nshared; }
         }
-        if (nshared < 1 || nshared > 2) { st[1]++; continue; }
+        if (nshared < 1 || nshared > 2) { fail_edge(a, b); continue; }
         const bool ba = S.on_boundary(a, tmp), bb = S.on_boundary(b, tmp);
         const bool boundary_edge = nshared == 1;
-        if (interior_only && (ba || bb)) { st[1]++; continue; }
-        if (!boundary_edge && ba && bb) { st[1]++; continue; }
+        if (interior_only && (ba || bb)) { fail_edge(a, b); continue; }
+        if (!boundary_edge && ba && bb) { fail_edge(a, b); continue; }
         // link condition: common neighbours == opposite corners of the shared triangles
         S.link(a, la);
         S.link(b, lb);
@@ -287,10 +295,10 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
         std::set_intersection(na.begin(), na.end(), nb.begin(), nb.end(), std::back_inserter(common));
         std::vector<int> opps = opp;
         std::sort(opps.begin(), opps.end());
-        if (common != opps) { st[1]++; continue; }
+        if (common != opps) { fail_edge(a, b); continue; }
         bool ear = false;
         for (int o : opp) if (S.star[o].size() < 2) ear = true;
-        if (ear) { st[1]++; continue; }
+        if (ear) { fail_edge(a, b); continue; }
 
         int i = a, j = b, kind = 0, p = -1, q = -1;
         if (boundary_edge) {
@@ -302,7 +310,7 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
             }
             p = S.boundary_neighbour_except(i, j, tmp);
             q = S.boundary_neighbour_except(j, i, tmp);
-            if (p < 0 || q < 0 || p == q || p == j || q == i) { st[1]++; continue; }
+            if (p < 0 || q < 0 || p == q || p == j || q == i) { fail_edge(a, b); continue; }
         } else if (ba || bb) {
             kind = 1;
             if (ba) { j = a; i = b; } else { i = a; j = b; }
@@ -389,7 +397,7 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
             if (!flatten(S, cur, fixed, val)) continue;
             if (chosen < 0 || cur.energy < best.energy) { chosen = cs; best = cur; }
         }
-        if (chosen < 0) { S.X.resize(3 * (size_t)k); st[1]++; continue; }
+        if (chosen < 0) { S.X.resize(3 * (size_t)k); fail_edge(a, b); continue; }
 
         // move the query points of the before patch into the after patch
         moved.clear();
@@ -454,16 +462,23 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
         if (kind == 0) st[2]++;
         else if (kind == 1) st[3]++;
         else st[4 + chosen]++;
-        // re-key every edge with an endpoint in the new 1-ring of k
+        // queue the new edges at k and re-enable failed edges whose
+        // neighbourhood (an endpoint in the new 1-ring of k) changed
         S.link(k, la);
-        for (int s = -1; s < (int)la.size(); ++s) {
-            const int x = s < 0 ? k : la[s].first;
-            S.link(x, lb);
-            for (auto &pr : lb) {
-                const int y = pr.first;
-                pq.push({S.sqdist(x, y), std::min(x, y), std::max(x, y)});
+        for (auto &pr : la) pq.push({S.sqdist(k, pr.first), pr.first, k});
+        if (!failed.empty())
+            for (auto &pr : la) {
+                const int x = pr.first;
+                S.link(x, lb);
+                for (auto &qr : lb) {
+                    const int y = qr.first;
+                    auto it = failed.find(ekey(std::min(x, y), std::max(x, y)));
+                    if (it != failed.end()) {
+                        failed.erase(it);
+                        pq.push({S.sqdist(x, y), std::min(x, y), std::max(x, y)});
+                    }
+                }
             }
-        }
     }
 
     // compact the coarse mesh (ascending old ids / triangle ids)

@@ -122,7 +122,8 @@ PRECISION = {"fp64": L.SMG_FP64, "fp32ir": L.SMG_FP32_IR}
 class Solver:
     """Device-resident multigrid solver of one mesh."""
 
-    def __init__(self, hier, rowptr, cols, device=0, mu_pre=2, mu_post=2, faces=None):
+    def __init__(self, hier, rowptr, cols, device=0, mu_pre=2, mu_post=2, faces=None,
+                 tail_rows=0, lanes_per_row=None):
         self._lib = L.load()
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -130,7 +131,9 @@ class Solver:
         self.n = len(rowptr) - 1
         self.nnz = len(cols)
         self.device = device
-        o = L.Opts(int(mu_pre), int(mu_post))
+        lpr = list(lanes_per_row or [])
+        o = L.Opts(int(mu_pre), int(mu_post), int(tail_rows),
+                   (ctypes.c_int32 * 16)(*(lpr + [0] * (16 - len(lpr)))))
         h = _c()
         L.check(self._lib.smg_solver_create(device, hier._h, _np_ptr(rowptr), _np_ptr(cols), ctypes.byref(o), ctypes.byref(h)), "solver_create")
         self._s = h
@@ -234,6 +237,19 @@ class Solver:
         x = torch.empty_like(b)
         L.check(self._lib.smg_coarse_solve(self._s, _t_ptr(_dev_f64(b)), _t_ptr(x), b.shape[1], _stream()), "coarse_solve")
         return x
+
+    # ---- per-launch timing --------------------------------------------
+    PROF = {"gs": 0, "residual": 1, "restrict": 2, "prolong": 3, "coarse": 4, "galerkin": 5}
+
+    def profile_enable(self, kind, level=0):
+        L.check(self._lib.smg_profile_enable(self._s, self.PROF[kind] if kind else -1, level), "profile_enable")
+
+    def profile_read(self):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        by = ctypes.c_double(0.0)
+        L.check(self._lib.smg_profile_read(self._s, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)), "profile_read")
+        return dict(ms=ms.value, launches=n.value, bytes=by.value)
 
     # ---- adjoint helpers ----------------------------------------------
     def spmv_dot(self, l_vals, lam, u):

@@ -59,13 +59,13 @@ class Problem:
         self.oracle = OV.Solver(self.Ps, self.A)
         self.sizes = [len(V)] + [P.shape[1] for P in self.Ps]
 
-    def gpu_solver(self, mu_pre=2, mu_post=2, faces=False):
+    def gpu_solver(self, mu_pre=2, mu_post=2, faces=False, **kw):
         import torch
         from paper_2104_13755_amd.solver import Hierarchy, Solver
         ells = [ell3(P) for P in self.Ps]
         h = Hierarchy.from_prolongations(self.sizes, [e[0] for e in ells], [e[1] for e in ells])
         S = Solver(h, self.A.indptr, self.A.indices, mu_pre=mu_pre, mu_post=mu_post,
-                   faces=self.F if faces else None)
+                   faces=self.F if faces else None, **kw)
         S.set_values(torch.tensor(self.A.data, dtype=torch.float64, device="cuda"))
         return S
 

@@ -145,3 +145,45 @@ def test_assembly_parity(prob):
     assert rel(_np(mm), m) < 1e-14
     a0, _, _ = S.assemble(_t(prob.V), prob.t)
     assert rel(_np(a0), prob.A.data) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [dict(tail_rows=-1, lanes_per_row=[1, 1, 1, 1, 1]),
+                                   dict(tail_rows=-1, lanes_per_row=[2, 2, 2, 2, 2]),
+                                   dict(tail_rows=-1, lanes_per_row=[1, 4, 8, 4, 2]),
+                                   dict(tail_rows=500, lanes_per_row=[8, 8, 8, 8, 8]),
+                                   dict(tail_rows=0)],
+                         ids=["untailed-l1", "untailed-l2", "untailed-mixed", "tail500-l8", "default"])
+def test_launch_shapes(shape):
+    """Launch shape (single-workgroup tail, lanes per row) changes nothing but
+    summation order: every shape matches the oracle V-cycle and solve."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    p = _shape_problem()
+    S = p.gpu_solver(**shape)
+    O = p.oracle
+    rng = np.random.default_rng(9)
+    n = p.sizes[0]
+    for k in (1, 3):
+        b = rng.uniform(-1, 1, (n, k))
+        x0 = rng.uniform(-1, 1, (n, k))
+        assert rel(_np(S.vcycle(_t(b), _t(x0))), O.vcycle(0, x0.copy(), b)) < 1e-12
+        for l in range(O.nlev - 1):
+            bl = rng.uniform(-1, 1, (p.sizes[l], k))
+            xl = rng.uniform(-1, 1, (p.sizes[l], k))
+            assert rel(_np(S.smooth(l, _t(bl), _t(xl), 2)), O.relax(l, xl.copy(), bl, 2)) < 1e-13
+            assert rel(_np(S.residual(l, _t(bl), _t(xl))), O.residual(l, xl, bl)) < 1e-13
+    b = p.m[:, None] * rng.uniform(-1, 1, (n, 2))
+    xo, co, _ = O.solve(b, 1e-10)
+    for prec, tol in (("fp64", 1e-12), ("fp32ir", 1e-6)):
+        xg, info = S.solve(_t(b), rtol=1e-10, precision=prec)
+        assert max(info["rel_res"]) <= 1e-10
+        assert np.linalg.norm(_np(xg) - xo) / np.linalg.norm(xo) < tol
+
+
+_SHAPE_PROBLEM = []
+
+
+def _shape_problem():
+    if not _SHAPE_PROBLEM:
+        _SHAPE_PROBLEM.append(Problem("heightfield-70x66", n_levels=5))
+    return _SHAPE_PROBLEM[0]
