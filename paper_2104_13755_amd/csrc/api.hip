@@ -257,7 +257,7 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     S->mu_pre = opts && opts->mu_pre >= 0 ? opts->mu_pre : 2;
     S->mu_post = opts && opts->mu_post >= 0 ? opts->mu_post : 2;
     if (!opts) S->mu_pre = S->mu_post = 2;
-    const int tail_rows = (opts && opts->tail_rows != 0) ? opts->tail_rows : 20000;
+    const int tail_rows = (opts && opts->tail_rows != 0) ? opts->tail_rows : 1000;
     std::vector<int> lpr(16, 0);
     if (opts) for (int l = 0; l < 16; ++l) lpr[l] = opts->lanes_per_row[l];
     std::vector<LevelHost> levels;

@@ -302,52 +302,93 @@ __global__ __launch_bounds__(kBlock) void k_inverse_product(const double *__rest
     Ainv[(size_t)j * n + i] = s;
 }
 
-// x = A_H^{-1} b (the coarsest direct solve), one thread per row, FP64
+// x = A_H^{-1} b (the coarsest direct solve), 4 lanes per row, FP64
 // accumulation; Ainv symmetric so column i is row i.
 template <int K, typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *__restrict__ Ainv, int n,
                                                          const Tin *__restrict__ b,
                                                          Tout *__restrict__ x) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int i = t >> 2, j = t & 3;
     double acc[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
-    for (int j = 0; j < n; ++j) {
-        const double a = Ainv[(size_t)j * n + i];
+    if (i < n)
+        for (int jj = j; jj < n; jj += 4) {
+            const double a = Ainv[(size_t)jj * n + i];
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(size_t)j * K + q];
+            for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(size_t)jj * K + q];
+        }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        acc[q] += __shfl_xor(acc[q], 1, 64);
+        acc[q] += __shfl_xor(acc[q], 2, 64);
     }
+    if (i < n && j == 0) {
 #pragma unroll
-    for (int q = 0; q < K; ++q) x[(size_t)i * K + q] = (Tout)acc[q];
+        for (int q = 0; q < K; ++q) x[(size_t)i * K + q] = (Tout)acc[q];
+    }
 }
 
 // ------------------------------------------------------------ tail V-cycle
 // All levels from `first` down to the coarsest in ONE workgroup: relaxation
 // colors, residual, restriction, coarsest solve, prolongation, separated by
 // workgroup barriers (Alg. "V-cycle" for the small levels, one launch).
+// Rows are handled by groups of G = lpr lanes (the layout's own grouping, so
+// a group reads adjacent slots) and every lane keeps four independent
+// gathers in flight: one workgroup is latency-bound, not bandwidth-bound.
+
+// off-diagonal sum of row r (valid) over its lane group; all lanes call it
+template <int K, typename T>
+__device__ __forceinline__ void tail_row_sum(const TailLevel<T> &L, int r, bool valid, int j,
+                                             const T *__restrict__ x, T (&acc)[K]) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = T(0);
+    const int G = L.lpr;
+    if (valid) {
+        const int s = L.row_slice[r];
+        const int base = L.slice_off[s] + (r - L.slice_row0[s]) * G + j;
+        const int len = L.rowlen[r];
+        const int nq = (len - j + G - 1) / G;   // entries of this lane: e = j + G q
+        int qq = 0;
+        for (; qq + 4 <= nq; qq += 4) {
+            int c[4];
+            T a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { c[u] = L.cols[base + (qq + u) * 64]; a[u] = L.vals[base + (qq + u) * 64]; }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += a[u] * x[(size_t)c[u] * K + q];
+        }
+        for (; qq < nq; ++qq) {
+            const int cc = L.cols[base + qq * 64];
+            const T a = L.vals[base + qq * 64];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)cc * K + q];
+        }
+    }
+    for (int m = G >> 1; m > 0; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+}
+
 template <int K, typename T>
 __device__ void tail_relax(const TailLevel<T> &L, int sweeps) {
+    const int G = L.lpr, j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = kTail / G;
     for (int sw = 0; sw < sweeps; ++sw)
         for (int c = 0; c < L.ncolors; ++c) {
             const int r0 = L.color_row[c], r1 = L.color_row[c + 1];
-            for (int r = r0 + (int)threadIdx.x; r < r1; r += kTail) {
-                const int s = L.row_slice[r];
-                const int base = L.slice_off[s] + (r - L.slice_row0[s]) * L.lpr;
-                const int len = L.rowlen[r];
+            for (int rb = r0; rb < r1; rb += per) {
+                const int r = rb + g;
+                const bool valid = r < r1;
                 T acc[K];
+                tail_row_sum<K, T>(L, r, valid, j, L.x, acc);
+                if (valid && j == 0) {
+                    const T d = L.diag[r];
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] = T(0);
-                for (int e = 0; e < len; ++e) {
-                    const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
-                    const int cc = L.cols[slot];
-                    const T a = L.vals[slot];
-#pragma unroll
-                    for (int q = 0; q < K; ++q) acc[q] += a * L.x[(size_t)cc * K + q];
+                    for (int q = 0; q < K; ++q) L.x[(size_t)r * K + q] = (L.b[(size_t)r * K + q] - acc[q]) / d;
                 }
-                const T d = L.diag[r];
-#pragma unroll
-                for (int q = 0; q < K; ++q) L.x[(size_t)r * K + q] = (L.b[(size_t)r * K + q] - acc[q]) / d;
             }
             __syncthreads();
         }
@@ -365,57 +406,86 @@ __global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__res
             __syncthreads();
         }
         tail_relax<K, T>(L, mu_pre);
-        // residual
-        for (int r = threadIdx.x; r < L.n; r += kTail) {
-            const int s = L.row_slice[r];
-            const int base = L.slice_off[s] + (r - L.slice_row0[s]) * L.lpr;
-            const int len = L.rowlen[r];
-            T acc[K];
+        {   // residual
+            const int G = L.lpr, j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = kTail / G;
+            for (int rb = 0; rb < L.n; rb += per) {
+                const int r = rb + g;
+                const bool valid = r < L.n;
+                T acc[K];
+                tail_row_sum<K, T>(L, r, valid, j, L.x, acc);
+                if (valid && j == 0) {
+                    const T d = L.diag[r];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = T(0);
-            for (int e = 0; e < len; ++e) {
-                const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
-                const int cc = L.cols[slot];
-                const T a = L.vals[slot];
-#pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += a * L.x[(size_t)cc * K + q];
+                    for (int q = 0; q < K; ++q)
+                        L.r[(size_t)r * K + q] = L.b[(size_t)r * K + q] - (acc[q] + d * L.x[(size_t)r * K + q]);
+                }
             }
-            const T d = L.diag[r];
-#pragma unroll
-            for (int q = 0; q < K; ++q)
-                L.r[(size_t)r * K + q] = L.b[(size_t)r * K + q] - (acc[q] + d * L.x[(size_t)r * K + q]);
         }
         __syncthreads();
-        // restriction into the next level's b
+        // restriction into the next level's b (4 lanes per coarse row)
         const TailLevel<T> C = lv[l + 1];
-        for (int a = threadIdx.x; a < C.n; a += kTail) {
-            T acc[K];
+        {
+            const int j = threadIdx.x & 3, per = kTail / 4;
+            for (int ab = 0; ab < C.n; ab += per) {
+                const int a = ab + (int)threadIdx.x / 4;
+                T acc[K];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = T(0);
-            for (int p = L.rptr[a]; p < L.rptr[a + 1]; ++p) {
-                const int i = L.ridx[p];
-                const T w = L.rw[p];
+                for (int q = 0; q < K; ++q) acc[q] = T(0);
+                if (a < C.n) {
+                    for (int p = L.rptr[a] + j; p < L.rptr[a + 1]; p += 4) {
+                        const int i = L.ridx[p];
+                        const T w = L.rw[p];
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += w * L.r[(size_t)i * K + q];
+                        for (int q = 0; q < K; ++q) acc[q] += w * L.r[(size_t)i * K + q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    acc[q] += __shfl_xor(acc[q], 1, 64);
+                    acc[q] += __shfl_xor(acc[q], 2, 64);
+                }
+                if (a < C.n && j == 0) {
+#pragma unroll
+                    for (int q = 0; q < K; ++q) C.b[(size_t)a * K + q] = acc[q];
+                }
             }
-#pragma unroll
-            for (int q = 0; q < K; ++q) C.b[(size_t)a * K + q] = acc[q];
         }
         __syncthreads();
     }
-    {   // coarsest: x = A^{-1} b in FP64
+    {   // coarsest: x = A^{-1} b in FP64, 4 lanes per row
         const TailLevel<T> C = lv[last];
-        for (int i = threadIdx.x; i < C.n; i += kTail) {
+        const int j = threadIdx.x & 3, per = kTail / 4;
+        for (int ib = 0; ib < C.n; ib += per) {
+            const int i = ib + (int)threadIdx.x / 4;
             double acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = 0.0;
-            for (int j = 0; j < C.n; ++j) {
-                const double a = Ainv[(size_t)j * C.n + i];
+            if (i < C.n) {
+                int jj = j;
+                for (; jj + 12 < C.n; jj += 16) {
+                    double a[4];
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += a * (double)C.b[(size_t)j * K + q];
+                    for (int u = 0; u < 4; ++u) a[u] = Ainv[(size_t)(jj + 4 * u) * C.n + i];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int q = 0; q < K; ++q) acc[q] += a[u] * (double)C.b[(size_t)(jj + 4 * u) * K + q];
+                }
+                for (; jj < C.n; jj += 4) {
+                    const double a = Ainv[(size_t)jj * C.n + i];
+#pragma unroll
+                    for (int q = 0; q < K; ++q) acc[q] += a * (double)C.b[(size_t)jj * K + q];
+                }
             }
 #pragma unroll
-            for (int q = 0; q < K; ++q) C.x[(size_t)i * K + q] = (T)acc[q];
+            for (int q = 0; q < K; ++q) {
+                acc[q] += __shfl_xor(acc[q], 1, 64);
+                acc[q] += __shfl_xor(acc[q], 2, 64);
+            }
+            if (i < C.n && j == 0) {
+#pragma unroll
+                for (int q = 0; q < K; ++q) C.x[(size_t)i * K + q] = (T)acc[q];
+            }
         }
         __syncthreads();
     }
@@ -725,7 +795,7 @@ template <typename Tin, typename Tout>
 hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x, int k,
                                hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    SMG_K_SWITCH(k, (k_coarse_apply<KK, Tin, Tout><<<nblocks(n), kBlock, 0, st>>>(Ainv, n, b, x)));
+    SMG_K_SWITCH(k, (k_coarse_apply<KK, Tin, Tout><<<nblocks(4 * (int64_t)n), kBlock, 0, st>>>(Ainv, n, b, x)));
     return hipGetLastError();
 }
 
