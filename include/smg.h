@@ -222,9 +222,10 @@ smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const double *d_m
 /* --- per-launch kernel timing (HIP events on the launch stream) --- */
 enum { SMG_PROF_GS = 0, SMG_PROF_RESIDUAL = 1, SMG_PROF_RESTRICT = 2, SMG_PROF_PROLONG = 3,
        SMG_PROF_COARSE = 4, SMG_PROF_GALERKIN = 5 };
-/* Record a pair of events around every launch of kernel `kind` on level
- * `level` (any precision) until disabled (kind < 0).  Works in eager mode;
- * solves with use_graph run their cycles eagerly while profiling is on. */
+/* Time every launch of kernel `kind` on level `level` (-1: every level; any
+ * precision) with start/stop events stamped by the dispatch itself, until
+ * disabled (kind < 0).  Solves with use_graph run their cycles eagerly while
+ * profiling is on. */
 smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level);
 /* Totals since enable: summed launch durations (ms), launch count, and the
  * algorithmic bytes of those launches (matrix entries and vector traffic the

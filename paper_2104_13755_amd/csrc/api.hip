@@ -603,8 +603,8 @@ smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
         for (int c = 0; c < D.ncolors; ++c) {
             const int pi = prof_begin(s, SMG_PROF_GS, l,
                                       D.color_nnz[c] * (sb + 4) + D.color_rows[c] * sb * (1 + 3 * k), st);
-            HIPCHK(launch_gs_color<T>(A, D.color_slice[c], D.color_slice[c + 1], bbuf<T>(D), xbuf<T>(D), k, st));
-            prof_end(s, pi, st);
+            HIPCHK(launch_gs_color<T>(A, D.color_slice[c], D.color_slice[c + 1], bbuf<T>(D), xbuf<T>(D), k, st,
+                                      prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
         }
     return SMG_OK;
 }
@@ -616,8 +616,7 @@ smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t
     const double sb = sizeof(T);
     const int pi = prof_begin(s, SMG_PROF_RESIDUAL, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
     HIPCHK(launch_residual<T>(sell_view<T>(D), D.nslices, bbuf<T>(D), xbuf<T>(D), rbuf<T>(D), k,
-                              norms ? s->partial : nullptr, &nblk, st));
-    prof_end(s, pi, st);
+                              norms ? s->partial : nullptr, &nblk, st, prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
     if (norms) HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st));
     return SMG_OK;
 }
@@ -928,7 +927,7 @@ extern "C" smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const 
 namespace smg {
 
 int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st) {
-    if (s->prof_kind != kind || s->prof_level != level) return -1;
+    if (s->prof_kind != kind || (s->prof_level >= 0 && s->prof_level != level)) return -1;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
     while (s->prof_pool.size() < 2 * (s->prof_used + 1)) {
@@ -938,13 +937,11 @@ int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t s
     }
     const int idx = (int)s->prof_used++;
     s->prof_bytes_pending.push_back(bytes);
-    (void)hipEventRecord(s->prof_pool[2 * idx], st);
     return idx;
 }
 
-void prof_end(smg_solver_s *s, int idx, hipStream_t st) {
-    if (idx < 0) return;
-    (void)hipEventRecord(s->prof_pool[2 * idx + 1], st);
+hipEvent_t prof_ev(smg_solver_s *s, int idx, int which) {
+    return idx < 0 ? nullptr : s->prof_pool[2 * idx + which];
 }
 
 smg_status prof_collect(smg_solver_s *s) {

@@ -25,15 +25,18 @@ struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (CSR)
 };
 
 // --- relaxation / residual / transfers (K right-hand sides, 1..4) ---
+// ev0/ev1 (optional): events stamped by the dispatch itself when the kernel
+// starts and ends (hipExtLaunchKernelGGL), for per-launch timing.
 template <typename T>
 hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T *b, T *x, int k,
-                           hipStream_t st);
+                           hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // r = b - A x over `nslices` slices; if partial != nullptr also writes
 // per-block (sum r^2, max |r|) per column into partial[blk * 2k ..]; the
 // block count is returned in *nblk.
 template <typename T>
 hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const T *x, T *r,
-                           int k, double *partial, int *nblk, hipStream_t st);
+                           int k, double *partial, int *nblk, hipStream_t st,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc, int k,
                            hipStream_t st);

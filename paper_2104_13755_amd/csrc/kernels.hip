@@ -9,6 +9,8 @@
 // Vectors with K right-hand sides are row-major n x K.
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace smg {
@@ -276,18 +278,24 @@ __global__ __launch_bounds__(1024) void k_cholesky(double *__restrict__ A, int n
     }
 }
 
-// W = G^{-1} for the lower-triangular Cholesky factor G (column-major): one
-// thread per column j solves G w_j = e_j by forward substitution.
-__global__ __launch_bounds__(kBlock) void k_tri_inverse(const double *__restrict__ G, int n,
-                                                        double *__restrict__ W) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    for (int i = 0; i < j; ++i) W[(size_t)j * n + i] = 0.0;
-    W[(size_t)j * n + j] = 1.0 / G[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-        double s = 0.0;
-        for (int m = j; m < i; ++m) s += G[(size_t)m * n + i] * W[(size_t)j * n + m];
-        W[(size_t)j * n + i] = -s / G[(size_t)i * n + i];
+// W = G^{-1} for the lower-triangular Cholesky factor G (column-major), one
+// workgroup, right-looking: start from W = I, then for each row j scale row j
+// by 1/G_jj and eliminate it from the rows below (parallel over the
+// (row, column) pairs of the trailing block).
+__global__ __launch_bounds__(1024) void k_tri_inverse(const double *__restrict__ G, int n,
+                                                      double *__restrict__ W) {
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) W[t] = (t % n == t / n) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double inv = 1.0 / G[(size_t)j * n + j];
+        for (int c = threadIdx.x; c <= j; c += blockDim.x) W[(size_t)c * n + j] *= inv;
+        __syncthreads();
+        const int rows = n - j - 1, cols = j + 1;
+        for (int t = threadIdx.x; t < rows * cols; t += blockDim.x) {
+            const int i = j + 1 + t % rows, c = t / rows;
+            W[(size_t)c * n + i] -= G[(size_t)j * n + i] * W[(size_t)c * n + j];
+        }
+        __syncthreads();
     }
 }
 
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_inverse_product(const double *__rest
     if (t >= (int64_t)n * n) return;
     const int i = (int)(t % n), j = (int)(t / n);
     double s = 0.0;
-    for (int m = max(i, j); m < n; ++m) s += W[(size_t)i * n + m] * W[(size_t)j * n + m];
+    for (int m = max(i, j); m < n; ++m) s += W[(size_t)i * n + m] * W[(size_t)j * n + m];   // W_mi W_mj
     Ainv[(size_t)j * n + i] = s;
 }
 
@@ -729,22 +737,41 @@ inline int nblocks(int64_t n, int per = kBlock) { return (int)((n + per - 1) / p
 
 template <typename T>
 hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T *b, T *x, int k,
-                           hipStream_t st) {
+                           hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     const int ns = s_end - s_begin;
     if (ns <= 0) return hipSuccess;
     const int g = nblocks(ns, kBlock / 64);
-    SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kBlock, 0, st>>>(s_begin, s_end, A.lpr, A.slice_row0, A.slice_off,
-                                                             A.cols, A.vals, A.diag, b, x)));
+    if (ev0) {
+        SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_gs_color<KK, T>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
+                                               s_begin, s_end, A.lpr, A.slice_row0, A.slice_off, A.cols,
+                                               A.vals, A.diag, b, x)));
+    } else {
+        SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kBlock, 0, st>>>(s_begin, s_end, A.lpr, A.slice_row0, A.slice_off,
+                                                                 A.cols, A.vals, A.diag, b, x)));
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const T *x, T *r,
-                           int k, double *partial, int *nblk, hipStream_t st) {
+                           int k, double *partial, int *nblk, hipStream_t st, hipEvent_t ev0,
+                           hipEvent_t ev1) {
     const int ns = nslices;
     const int g = nblocks(ns, kBlock / 64);
     *nblk = g;
     if (ns <= 0) return hipSuccess;
+    if (ev0) {
+        if (partial) {
+            SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_residual<KK, T, true>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
+                                                   ns, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
+                                                   b, x, r, partial)));
+        } else {
+            SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_residual<KK, T, false>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
+                                                   ns, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
+                                                   b, x, r, (double *)nullptr)));
+        }
+        return hipGetLastError();
+    }
     if (partial) {
         SMG_K_SWITCH(k, (k_residual<KK, T, true><<<g, kBlock, 0, st>>>(ns, A.lpr, A.slice_row0, A.slice_off, A.cols,
                                                                        A.vals, A.diag, b, x, r, partial)));
@@ -801,7 +828,7 @@ hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x,
 
 hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_tri_inverse<<<nblocks(n), kBlock, 0, st>>>(G, n, W);
+    k_tri_inverse<<<1, 1024, 0, st>>>(G, n, W);
     k_inverse_product<<<nblocks((int64_t)n * n), kBlock, 0, st>>>(W, n, Ainv);
     return hipGetLastError();
 }
@@ -915,15 +942,15 @@ hipError_t launch_mass_grad(const double *lam, const double *m, const double *u,
 }
 
 template hipError_t launch_gs_color<double>(const SellView<double> &, int, int, const double *,
-                                            double *, int, hipStream_t);
+                                            double *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_gs_color<float>(const SellView<float> &, int, int, const float *,
-                                           float *, int, hipStream_t);
+                                           float *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_residual<double>(const SellView<double> &, int, const double *,
                                             const double *, double *, int, double *, int *,
-                                            hipStream_t);
+                                            hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_residual<float>(const SellView<float> &, int, const float *,
                                            const float *, float *, int, double *, int *,
-                                           hipStream_t);
+                                           hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_restrict<double>(const TransferView &, const double *, const double *,
                                             double *, int, hipStream_t);
 template hipError_t launch_restrict<float>(const TransferView &, const float *, const float *,

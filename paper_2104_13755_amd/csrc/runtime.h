@@ -99,9 +99,10 @@ smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t
 smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st);
 smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st,
                            hipGraphExec_t *out);
-// profiling helpers: begin returns the event pair index or -1
+// profiling helpers: begin returns the event pair index or -1; prof_ev gives
+// the start (0) / stop (1) event to hand to the launch (null when not profiled)
 int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st);
-void prof_end(smg_solver_s *s, int idx, hipStream_t st);
+hipEvent_t prof_ev(smg_solver_s *s, int idx, int which);
 smg_status prof_collect(smg_solver_s *s);
 smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_x, int k,
                                   const smg_solve_params *p, smg_solve_info *info,
