@@ -36,7 +36,8 @@ class SolveInfo(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("wg_per_mesh_min", c_int32), ("block_rows", c_int32)]
+    _fields_ = [("threads", c_int32), ("lanes_level0", c_int32), ("lanes_coarse", c_int32),
+                ("cache_file", ctypes.c_char_p)]
 
 
 SMG_OK = 0
@@ -82,6 +83,7 @@ SIGNATURES = {
     "smg_batch_destroy": (None, [c_void_p]),
     "smg_batch_solve": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), P_i32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_batch_autotune": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "smg_batch_shape": (c_int32, [c_void_p, P_i32]),
     "smg_status_string": (ctypes.c_char_p, [c_int32]),
     "smg_last_error": (ctypes.c_char_p, []),
 }

@@ -347,9 +347,9 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
         std::vector<TailLevel<float>> t32(S->nlev);
         for (int l = 0; l < S->nlev; ++l) {
             const DevLevel &D = S->lev[l];
-            t64[l] = {D.n, D.ncolors, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
+            t64[l] = {D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
                       D.rowlen, D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw, D.rptr, D.ridx, D.rw};
-            t32[l] = {D.n, D.ncolors, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
+            t32[l] = {D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
                       D.rowlen, D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32, D.pc, D.pw32, D.rptr,
                       D.ridx, D.rw32};
         }

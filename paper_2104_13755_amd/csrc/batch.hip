@@ -1,48 +1,308 @@
-// Batched solve of many independent meshes (first version: the meshes'
-// solves are enqueued one after another on the caller's stream).
+// Batched solves: every mesh's whole solve in one persistent kernel (one
+// workgroup per mesh), replayed from a captured hipGraph, with an autotuner
+// over the launch shape.
 #include "smg.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <memory>
+#include <numeric>
 #include <string>
 #include <vector>
 
+#include "kernels.h"
 #include "runtime.h"
 
 using namespace smg;
 
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
 struct smg_batch_s {
     std::vector<smg_solver> solvers;
-    smg_batch_opts opts{};
+    int device = 0, count = 0;
+    int threads = 1024, lanes0 = 1, lanes_c = 8;          // launch shape
+    std::string cache_file;
+    uint64_t key = 0;                                      // workload fingerprint for the cache
+    std::vector<TailLevel<double>> h64;                    // per mesh, nlev entries each
+    std::vector<TailLevel<float>> h32;
+    std::vector<int> off;                                  // first descriptor of mesh i
+    TailLevel<double> *d64 = nullptr;
+    TailLevel<float> *d32 = nullptr;
+    BatchMesh *d_mesh = nullptr;
+    int32_t *d_order = nullptr;
+    double *d_out = nullptr, *h_out = nullptr;
+    std::vector<BatchMesh> hm;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_threads = 0;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // last solve's inputs, for the autotuner
+    std::vector<const double *> last_b;
+    std::vector<double *> last_x;
+    std::vector<int32_t> last_k;
+    smg_solve_params last_p{};
+    bool have_last = false;
+    ~smg_batch_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (d64) (void)hipFree(d64);
+        if (d32) (void)hipFree(d32);
+        if (d_mesh) (void)hipFree(d_mesh);
+        if (d_order) (void)hipFree(d_order);
+        if (d_out) (void)hipFree(d_out);
+        if (h_out) (void)hipHostFree(h_out);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
 };
+
+static void apply_shape(smg_batch_s *b) {
+    for (int i = 0; i < b->count; ++i) {
+        const int nlev = b->solvers[i]->nlev;
+        for (int l = 0; l < nlev; ++l) {
+            const int lanes = l == 0 ? b->lanes0 : b->lanes_c;
+            b->h64[b->off[i] + l].grp = lanes;
+            b->h32[b->off[i] + l].grp = lanes;
+        }
+    }
+}
+
+static smg_status upload_descriptors(smg_batch_s *b) {
+    apply_shape(b);
+    HIPCHK(hipMemcpy(b->d64, b->h64.data(), b->h64.size() * sizeof(TailLevel<double>), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d32, b->h32.data(), b->h32.size() * sizeof(TailLevel<float>), hipMemcpyHostToDevice));
+    return SMG_OK;
+}
+
+static bool read_cache(smg_batch_s *b) {
+    if (b->cache_file.empty()) return false;
+    FILE *f = std::fopen(b->cache_file.c_str(), "r");
+    if (!f) return false;
+    unsigned long long key;
+    int t, l0, lc;
+    bool found = false;
+    while (std::fscanf(f, "%llx %d %d %d", &key, &t, &l0, &lc) == 4)
+        if (key == b->key) { b->threads = t; b->lanes0 = l0; b->lanes_c = lc; found = true; }
+    std::fclose(f);
+    return found;
+}
+
+static void write_cache(smg_batch_s *b) {
+    if (b->cache_file.empty()) return;
+    FILE *f = std::fopen(b->cache_file.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%llx %d %d %d\n", (unsigned long long)b->key, b->threads, b->lanes0, b->lanes_c);
+    std::fclose(f);
+}
 
 extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
                                        const smg_batch_opts *o, smg_batch *out) {
     if (!solvers || count < 1 || !out) return fail(SMG_ERR_INVALID_ARG, "smg_batch_create: bad arguments");
-    auto *b = new smg_batch_s;
+    auto b = std::make_unique<smg_batch_s>();
     b->solvers.assign(solvers, solvers + count);
-    if (o) b->opts = *o;
-    *out = b;
+    b->count = count;
+    b->device = solvers[0]->device;
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+    for (int i = 0; i < count; ++i) {
+        smg_solver s = solvers[i];
+        if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver in batch");
+        if (s->device != b->device) return fail(SMG_ERR_INVALID_ARG, "batched solvers must share a device");
+        if (s->nlev < 2) return fail(SMG_ERR_INVALID_ARG, "batched solvers need at least two levels");
+        b->off.push_back((int)b->h64.size());
+        for (int l = 0; l < s->nlev; ++l) {
+            const DevLevel &D = s->lev[l];
+            b->h64.push_back({D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off,
+                              D.row_slice, D.rowlen, D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw,
+                              D.rptr, D.ridx, D.rw});
+            b->h32.push_back({D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off,
+                              D.row_slice, D.rowlen, D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32,
+                              D.pc, D.pw32, D.rptr, D.ridx, D.rw32});
+            mix((uint64_t)D.n);
+            mix((uint64_t)D.nnz_nat);
+        }
+    }
+    b->key = key;
+    if (o && o->cache_file) b->cache_file = o->cache_file;
+    read_cache(b.get());
+    if (o && o->threads) b->threads = o->threads;
+    if (o && o->lanes_level0) b->lanes0 = o->lanes_level0;
+    if (o && o->lanes_coarse) b->lanes_c = o->lanes_coarse;
+    if (b->threads != 256 && b->threads != 512 && b->threads != 1024) return fail(SMG_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
+    if (b->lanes0 != 1 && b->lanes0 != 2) return fail(SMG_ERR_INVALID_ARG, "lanes_level0 must be 1 or 2");
+    if (b->lanes_c != 1 && b->lanes_c != 2 && b->lanes_c != 4 && b->lanes_c != 8) return fail(SMG_ERR_INVALID_ARG, "lanes_coarse must be 1, 2, 4 or 8");
+    HIPCHK(hipSetDevice(b->device));
+    HIPCHK(hipMalloc((void **)&b->d64, b->h64.size() * sizeof(TailLevel<double>)));
+    HIPCHK(hipMalloc((void **)&b->d32, b->h32.size() * sizeof(TailLevel<float>)));
+    HIPCHK(hipMalloc((void **)&b->d_mesh, count * sizeof(BatchMesh)));
+    HIPCHK(hipMalloc((void **)&b->d_order, count * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&b->d_out, count * 8 * sizeof(double)));
+    HIPCHK(hipHostMalloc((void **)&b->h_out, count * 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    // largest meshes first, so the longest solves start first
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return solvers[a]->lev[0].nnz_nat > solvers[c]->lev[0].nnz_nat;
+    });
+    HIPCHK(hipMemcpy(b->d_order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice));
+    smg_status st = upload_descriptors(b.get());
+    if (st) return st;
+    b->hm.resize(count);
+    *out = b.release();
     return SMG_OK;
 }
 
-extern "C" void smg_batch_destroy(smg_batch b) { delete b; }
+extern "C" void smg_batch_destroy(smg_batch b) {
+    if (b) (void)hipSetDevice(b->device);
+    delete b;
+}
+
+// enqueue one batched solve on b->stream (graph on the first call per shape)
+static smg_status batch_enqueue(smg_batch_s *b) {
+    if (b->exec && b->graph_threads != b->threads) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (!b->exec) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_batch_solve(b->d_mesh, b->d_order, b->count, b->threads, b->stream);
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(SMG_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(SMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        b->graph_threads = b->threads;
+    }
+    HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    return SMG_OK;
+}
 
 extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, double *const *d_x,
                                       const int32_t *k, const smg_solve_params *p,
                                       smg_solve_info *infos, smg_stream stream) {
     if (!b || !d_b || !d_x || !k || !p) return fail(SMG_ERR_INVALID_ARG, "smg_batch_solve: null argument");
-    smg_status worst = SMG_OK;
-    for (size_t i = 0; i < b->solvers.size(); ++i) {
-        smg_status st = smg_solve(b->solvers[i], d_b[i], d_x[i], k[i], p, infos ? &infos[i] : nullptr, stream);
-        if (st != SMG_OK && worst == SMG_OK) worst = st;
+    if (p->precision != SMG_FP64 && p->precision != SMG_FP32_IR) return fail(SMG_ERR_INVALID_ARG, "bad precision");
+    HIPCHK(hipSetDevice(b->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < b->count; ++i) {
+        smg_solver s = b->solvers[i];
+        if (!s->values_set) return fail(SMG_ERR_STATE, "batch member without values");
+        if (k[i] < 1 || k[i] > 4 || !d_b[i] || !d_x[i]) return fail(SMG_ERR_INVALID_ARG, "bad right-hand side");
+        BatchMesh &M = b->hm[i];
+        M.k = k[i];
+        M.nlev = s->nlev;
+        M.mu_pre = s->mu_pre;
+        M.mu_post = s->mu_post;
+        M.max_cycles = p->max_cycles;
+        M.precision = p->precision == SMG_FP64 ? 0 : 1;
+        M.rtol = p->rtol;
+        M.l0 = b->h64[b->off[i]];
+        M.l0.grp = b->lanes0;
+        M.lv32 = b->d32 + b->off[i];
+        M.lv64 = b->d64 + b->off[i];
+        M.Ainv = s->lev[s->nlev - 1].dense_inv;
+        M.perm0 = s->lev[0].perm;
+        M.b_user = d_b[i];
+        M.x_user = d_x[i];
+        M.out = b->d_out + 8 * i;
     }
-    return worst;
+    b->last_b.assign(d_b, d_b + b->count);
+    b->last_x.assign(d_x, d_x + b->count);
+    b->last_k.assign(k, k + b->count);
+    b->last_p = *p;
+    b->have_last = true;
+    hipStream_t caller = (hipStream_t)stream;
+    HIPCHK(hipEventRecord(b->ev_in, caller));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    HIPCHK(hipMemcpyAsync(b->d_mesh, b->hm.data(), b->count * sizeof(BatchMesh), hipMemcpyHostToDevice, b->stream));
+    smg_status st = batch_enqueue(b);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(b->h_out, b->d_out, b->count * 8 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipEventRecord(b->ev_out, b->stream));
+    HIPCHK(hipStreamWaitEvent(caller, b->ev_out, 0));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    smg_status worst = SMG_OK;
+    for (int i = 0; i < b->count; ++i) {
+        const double *o = b->h_out + 8 * i;
+        bool conv = true, finite = true;
+        for (int q = 0; q < k[i]; ++q) {
+            if (!std::isfinite(o[1 + q])) finite = false;
+            else if (o[1 + q] > p->rtol) conv = false;
+        }
+        if (!finite) worst = SMG_ERR_NONFINITE;
+        else if (!conv && worst == SMG_OK) worst = SMG_ERR_NO_CONVERGENCE;
+        if (infos) {
+            infos[i].cycles = (int32_t)o[0];
+            infos[i].k = k[i];
+            for (int q = 0; q < 4; ++q) infos[i].rel_res[q] = q < k[i] ? o[1 + q] : 0.0;
+            infos[i].ms = ms;
+        }
+    }
+    if (worst == SMG_ERR_NONFINITE) return fail(worst, "non-finite residual in a batch member");
+    if (worst == SMG_ERR_NO_CONVERGENCE) return fail(worst, "a batch member hit the cycle cap");
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_batch_shape(smg_batch b, int32_t *shape3) {
+    if (!b || !shape3) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    shape3[0] = b->threads;
+    shape3[1] = b->lanes0;
+    shape3[2] = b->lanes_c;
+    return SMG_OK;
 }
 
 extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_stream stream) {
-    (void)budget_ms;
-    (void)stream;
     if (!b) return fail(SMG_ERR_INVALID_ARG, "null batch");
+    if (!b->have_last) return fail(SMG_ERR_STATE, "autotune needs a previous smg_batch_solve");
+    HIPCHK(hipSetDevice(b->device));
+    struct Shape { int t, l0, lc; };
+    std::vector<Shape> cands;
+    for (int t : {1024, 512, 256})
+        for (int lc : {8, 4, 2})
+            for (int l0 : {1, 2}) cands.push_back({t, l0, lc});
+    const Shape orig{b->threads, b->lanes0, b->lanes_c};
+    Shape bestS = orig;
+    double best = 1e300;
+    const auto start = std::chrono::steady_clock::now();
+    for (const Shape &c : cands) {
+        const double spent = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - start).count();
+        if (spent > budget_ms && best < 1e300) break;
+        b->threads = c.t;
+        b->lanes0 = c.l0;
+        b->lanes_c = c.lc;
+        smg_status st = upload_descriptors(b);
+        if (st) return st;
+        double tmin = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            st = smg_batch_solve(b, b->last_b.data(), b->last_x.data(), b->last_k.data(), &b->last_p, nullptr, stream);
+            if (st != SMG_OK && st != SMG_ERR_NO_CONVERGENCE) return st;
+            tmin = std::min(tmin, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        if (tmin < best) { best = tmin; bestS = c; }
+    }
+    b->threads = bestS.t;
+    b->lanes0 = bestS.l0;
+    b->lanes_c = bestS.lc;
+    smg_status st = upload_descriptors(b);
+    if (st) return st;
+    write_cache(b);
     return SMG_OK;
 }

@@ -64,6 +64,7 @@ hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x,
 template <typename T>
 struct TailLevel {
     int n, ncolors, lpr;
+    int grp;                      // lanes cooperating on one row (1,2,4,8) in one-workgroup code
     const int32_t *color_row;     // ncolors + 1 permuted row boundaries
     const int32_t *slice_row0, *slice_off, *row_slice, *rowlen, *cols;
     const T *vals, *diag;
@@ -76,6 +77,22 @@ struct TailLevel {
 template <typename T>
 hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
                               const double *Ainv, int k, hipStream_t st);
+
+// --- batched solve: one workgroup per mesh, whole FP32-in-FP64 solve ---
+struct BatchMesh {
+    int k, nlev, mu_pre, mu_post, max_cycles, precision;   // precision: 0 FP64, 1 FP32 + FP64 IR
+    double rtol;
+    TailLevel<double> l0;             // level 0 in FP64 (x, b, r, matrix)
+    const TailLevel<float> *lv32;     // every level in FP32 (device array)
+    const TailLevel<double> *lv64;    // every level in FP64 (device array)
+    const double *Ainv;               // coarsest inverse
+    const int32_t *perm0;             // level-0 color-major position -> vertex
+    const double *b_user;             // n x k, caller order
+    double *x_user;                   // n x k, caller order
+    double *out;                      // [cycles, rel_res[k]]
+};
+hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *order, int count, int threads,
+                              hipStream_t st);
 
 // --- hierarchy values ---
 hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,

@@ -342,36 +342,41 @@ __global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *__restric
 // All levels from `first` down to the coarsest in ONE workgroup: relaxation
 // colors, residual, restriction, coarsest solve, prolongation, separated by
 // workgroup barriers (Alg. "V-cycle" for the small levels, one launch).
-// Rows are handled by groups of G = lpr lanes (the layout's own grouping, so
-// a group reads adjacent slots) and every lane keeps four independent
-// gathers in flight: one workgroup is latency-bound, not bandwidth-bound.
+// Rows are handled by groups of G lanes (G = L.grp, by default the layout's
+// lanes per row, so a group reads adjacent slots) and every lane keeps four
+// independent gathers in flight: one workgroup is latency-bound, not
+// bandwidth-bound.  The same code runs whole solves in the batched kernel.
 
 // off-diagonal sum of row r (valid) over its lane group; all lanes call it
 template <int K, typename T>
-__device__ __forceinline__ void tail_row_sum(const TailLevel<T> &L, int r, bool valid, int j,
-                                             const T *__restrict__ x, T (&acc)[K]) {
+__device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool valid, int j, int G,
+                                           const T *__restrict__ x, T (&acc)[K]) {
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = T(0);
-    const int G = L.lpr;
     if (valid) {
         const int s = L.row_slice[r];
-        const int base = L.slice_off[s] + (r - L.slice_row0[s]) * G + j;
+        const int base = L.slice_off[s] + (r - L.slice_row0[s]) * L.lpr;
         const int len = L.rowlen[r];
-        const int nq = (len - j + G - 1) / G;   // entries of this lane: e = j + G q
-        int qq = 0;
-        for (; qq + 4 <= nq; qq += 4) {
+        int e = j;
+        for (; e + 3 * G < len; e += 4 * G) {   // four independent gathers in flight
             int c[4];
             T a[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { c[u] = L.cols[base + (qq + u) * 64]; a[u] = L.vals[base + (qq + u) * 64]; }
+            for (int u = 0; u < 4; ++u) {
+                const int ee = e + u * G;
+                const int slot = base + (ee / L.lpr) * 64 + (ee % L.lpr);
+                c[u] = L.cols[slot];
+                a[u] = L.vals[slot];
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int q = 0; q < K; ++q) acc[q] += a[u] * x[(size_t)c[u] * K + q];
         }
-        for (; qq < nq; ++qq) {
-            const int cc = L.cols[base + qq * 64];
-            const T a = L.vals[base + qq * 64];
+        for (; e < len; e += G) {
+            const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
+            const int cc = L.cols[slot];
+            const T a = L.vals[slot];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)cc * K + q];
         }
@@ -382,8 +387,9 @@ __device__ __forceinline__ void tail_row_sum(const TailLevel<T> &L, int r, bool 
 }
 
 template <int K, typename T>
-__device__ void tail_relax(const TailLevel<T> &L, int sweeps) {
-    const int G = L.lpr, j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = kTail / G;
+__device__ void wg_relax(const TailLevel<T> &L, int sweeps) {
+    const int nt = blockDim.x, G = L.grp;
+    const int j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = nt / G;
     for (int sw = 0; sw < sweeps; ++sw)
         for (int c = 0; c < L.ncolors; ++c) {
             const int r0 = L.color_row[c], r1 = L.color_row[c + 1];
@@ -391,7 +397,7 @@ __device__ void tail_relax(const TailLevel<T> &L, int sweeps) {
                 const int r = rb + g;
                 const bool valid = r < r1;
                 T acc[K];
-                tail_row_sum<K, T>(L, r, valid, j, L.x, acc);
+                wg_row_sum<K, T>(L, r, valid, j, G, L.x, acc);
                 if (valid && j == 0) {
                     const T d = L.diag[r];
 #pragma unroll
@@ -402,38 +408,46 @@ __device__ void tail_relax(const TailLevel<T> &L, int sweeps) {
         }
 }
 
+// r = b - A x on one level; optional per-thread column sums / maxima (FP64)
 template <int K, typename T>
-__global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__restrict__ lv, int first,
-                                                       int nlev, int mu_pre, int mu_post,
-                                                       const double *__restrict__ Ainv) {
+__device__ void wg_residual(const TailLevel<T> &L, double (*sq)[K] = nullptr, double (*mx)[K] = nullptr) {
+    const int nt = blockDim.x, G = L.grp;
+    const int j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = nt / G;
+    for (int rb = 0; rb < L.n; rb += per) {
+        const int r = rb + g;
+        const bool valid = r < L.n;
+        T acc[K];
+        wg_row_sum<K, T>(L, r, valid, j, G, L.x, acc);
+        if (valid && j == 0) {
+            const T d = L.diag[r];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const T rv = L.b[(size_t)r * K + q] - (acc[q] + d * L.x[(size_t)r * K + q]);
+                L.r[(size_t)r * K + q] = rv;
+                if (sq) { (*sq)[q] += (double)rv * (double)rv; (*mx)[q] = fmax((*mx)[q], fabs((double)rv)); }
+            }
+        }
+    }
+}
+
+template <int K, typename T>
+__device__ void wg_vcycle(const TailLevel<T> *__restrict__ lv, int first, int nlev, int mu_pre,
+                          int mu_post, const double *__restrict__ Ainv) {
+    const int nt = blockDim.x;
     const int last = nlev - 1;   // coarsest
     for (int l = first; l < last; ++l) {
         const TailLevel<T> L = lv[l];
         if (l > first) {
-            for (int t = threadIdx.x; t < L.n * K; t += kTail) L.x[t] = T(0);
+            for (int t = threadIdx.x; t < L.n * K; t += nt) L.x[t] = T(0);
             __syncthreads();
         }
-        tail_relax<K, T>(L, mu_pre);
-        {   // residual
-            const int G = L.lpr, j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = kTail / G;
-            for (int rb = 0; rb < L.n; rb += per) {
-                const int r = rb + g;
-                const bool valid = r < L.n;
-                T acc[K];
-                tail_row_sum<K, T>(L, r, valid, j, L.x, acc);
-                if (valid && j == 0) {
-                    const T d = L.diag[r];
-#pragma unroll
-                    for (int q = 0; q < K; ++q)
-                        L.r[(size_t)r * K + q] = L.b[(size_t)r * K + q] - (acc[q] + d * L.x[(size_t)r * K + q]);
-                }
-            }
-        }
+        wg_relax<K, T>(L, mu_pre);
+        wg_residual<K, T>(L);
         __syncthreads();
         // restriction into the next level's b (4 lanes per coarse row)
         const TailLevel<T> C = lv[l + 1];
         {
-            const int j = threadIdx.x & 3, per = kTail / 4;
+            const int j = threadIdx.x & 3, per = nt / 4;
             for (int ab = 0; ab < C.n; ab += per) {
                 const int a = ab + (int)threadIdx.x / 4;
                 T acc[K];
@@ -462,7 +476,7 @@ __global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__res
     }
     {   // coarsest: x = A^{-1} b in FP64, 4 lanes per row
         const TailLevel<T> C = lv[last];
-        const int j = threadIdx.x & 3, per = kTail / 4;
+        const int j = threadIdx.x & 3, per = nt / 4;
         for (int ib = 0; ib < C.n; ib += per) {
             const int i = ib + (int)threadIdx.x / 4;
             double acc[K];
@@ -500,7 +514,7 @@ __global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__res
     for (int l = last - 1; l >= first; --l) {
         const TailLevel<T> L = lv[l];
         const TailLevel<T> C = lv[l + 1];
-        for (int i = threadIdx.x; i < L.n; i += kTail) {
+        for (int i = threadIdx.x; i < L.n; i += nt) {
             T acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = T(0);
@@ -515,7 +529,132 @@ __global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__res
             for (int q = 0; q < K; ++q) L.x[(size_t)i * K + q] += acc[q];
         }
         __syncthreads();
-        tail_relax<K, T>(L, mu_post);
+        wg_relax<K, T>(L, mu_post);
+    }
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__restrict__ lv, int first,
+                                                       int nlev, int mu_pre, int mu_post,
+                                                       const double *__restrict__ Ainv) {
+    wg_vcycle<K, T>(lv, first, nlev, mu_pre, mu_post, Ainv);
+}
+
+// ---------------------------------------------------------- batched solve
+// One workgroup per mesh runs Alg. "Galerkin Surface Multigrid Solver" to
+// convergence: FP64 level-0 residual and norms, FP32 V-cycle on r / max|r|,
+// FP64 update, with the convergence test on the device.  Meshes never wait
+// for each other; converged meshes' workgroups exit.
+template <int K>
+__device__ void wg_block_reduce(double (&v)[K], bool take_max, double *red) {
+    // red: at least 2 * K * (blockDim / 64) doubles of LDS
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = take_max ? wave_max(v[q]) : wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) red[q * nw + wv] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a = take_max ? fmax(a, red[q * nw + w]) : a + red[q * nw + w];
+        v[q] = a;
+    }
+    __syncthreads();
+}
+
+template <int K>
+__device__ void batch_mesh(const BatchMesh &M) {
+    __shared__ double red[4 * 16];
+    const TailLevel<double> L0 = M.l0;
+    const int n = L0.n, nt = blockDim.x;
+    // b (caller order) -> level-0 color-major order; x = 0; r = b
+    for (int t = threadIdx.x; t < n * K; t += nt) {
+        const int r = t / K, q = t % K;
+        const double v = M.b_user[(size_t)M.perm0[r] * K + q];
+        L0.b[t] = v;
+        L0.r[t] = v;
+        L0.x[t] = 0.0;
+    }
+    __syncthreads();
+    double bn[K], sq[K], mx[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
+    for (int t = threadIdx.x; t < n * K; t += nt) {
+        const double v = L0.b[t];
+        // column of t is t % K
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (t % K == q) { sq[q] += v * v; mx[q] = fmax(mx[q], fabs(v)); }
+    }
+    wg_block_reduce<K>(sq, false, red);
+    wg_block_reduce<K>(mx, true, red);
+    double rho[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { bn[q] = sqrt(sq[q]); rho[q] = bn[q] > 0.0 ? 1.0 : 0.0; }
+    const TailLevel<float> F0 = M.lv32[0];
+    int cycles = 0;
+    for (;;) {
+        double worst = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) worst = fmax(worst, rho[q]);
+        if (!(worst > M.rtol) || cycles >= M.max_cycles) break;
+        if (M.precision == 0) {   // plain FP64 V-cycle on (b, x) of level 0
+            wg_vcycle<K, double>(M.lv64, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
+        } else {
+        // r32 = r / max|r| ; x32 = 0
+        for (int t = threadIdx.x; t < n * K; t += nt) {
+            const int q = t % K;
+            double s = 0.0;
+#pragma unroll
+            for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
+            F0.b[t] = (float)(s > 0.0 ? L0.r[t] / s : 0.0);
+            F0.x[t] = 0.0f;
+        }
+        __syncthreads();
+        wg_vcycle<K, float>(M.lv32, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
+        for (int t = threadIdx.x; t < n * K; t += nt) {
+            const int q = t % K;
+            double s = 0.0;
+#pragma unroll
+            for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
+            L0.x[t] += s * (double)F0.x[t];
+        }
+        __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
+        wg_residual<K, double>(L0, &sq, &mx);
+        wg_block_reduce<K>(sq, false, red);
+        wg_block_reduce<K>(mx, true, red);
+        ++cycles;
+#pragma unroll
+        for (int q = 0; q < K; ++q) rho[q] = bn[q] > 0.0 ? sqrt(sq[q]) / bn[q] : sqrt(sq[q]);
+        bool finite = true;
+#pragma unroll
+        for (int q = 0; q < K; ++q) finite = finite && isfinite(rho[q]);
+        if (!finite) break;
+    }
+    for (int t = threadIdx.x; t < n * K; t += nt) {
+        const int r = t / K, q = t % K;
+        M.x_user[(size_t)M.perm0[r] * K + q] = L0.x[t];
+    }
+    if (threadIdx.x == 0) {
+        M.out[0] = (double)cycles;
+#pragma unroll
+        for (int q = 0; q < K; ++q) M.out[1 + q] = rho[q];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_batch_solve(const BatchMesh *__restrict__ meshes,
+                                                      const int32_t *__restrict__ order) {
+    const BatchMesh M = meshes[order[blockIdx.x]];
+    switch (M.k) {
+    case 1: batch_mesh<1>(M); break;
+    case 2: batch_mesh<2>(M); break;
+    case 3: batch_mesh<3>(M); break;
+    default: batch_mesh<4>(M); break;
     }
 }
 
@@ -837,6 +976,14 @@ template <typename T>
 hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
                               const double *Ainv, int k, hipStream_t st) {
     SMG_K_SWITCH(k, (k_vcycle_tail<KK, T><<<1, kTail, 0, st>>>(lv, first, nlev, mu_pre, mu_post, Ainv)));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *order, int count, int threads,
+                              hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+    k_batch_solve<<<count, threads, 0, st>>>(meshes, order);
     return hipGetLastError();
 }
 
