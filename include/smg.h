@@ -238,17 +238,20 @@ smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches, d
 /* Batching: many solvers in one persistent launch.                          */
 
 typedef struct {
-    int32_t threads;          /* workgroup size per mesh: 256, 512, 1024; 0 = tuned/default */
+    int32_t threads;          /* workgroup size: 256, 512, 1024; 0 = tuned/default */
     int32_t lanes_level0;     /* lanes per row on level 0: 1 or 2; 0 = tuned/default */
     int32_t lanes_coarse;     /* lanes per row on the Galerkin levels: 1,2,4,8; 0 = tuned/default */
+    int32_t team_max;         /* most workgroups per mesh (1..64); 0 = tuned/default */
     const char *cache_file;   /* autotune cache (read at create, written by autotune); may be NULL */
 } smg_batch_opts;
 
 /* Group solvers (same device, at least two levels each) for batched solves:
- * one persistent kernel runs every mesh's whole solve, one workgroup per
- * mesh (meshes ordered by size, largest first), each looping over its own
- * V-cycles with the convergence test on the device; converged meshes stop.
- * The solvers must outlive the batch.  Errors: INVALID_ARG, OOM. */
+ * one persistent kernel runs every mesh's whole solve.  Each mesh is worked
+ * by a team of workgroups (1..team_max, in proportion to its size, all
+ * resident at once; largest meshes first) that loops over its own V-cycles
+ * with barriers between dependent phases and the convergence test on the
+ * device; converged meshes stop.  The solvers must outlive the batch.
+ * Errors: INVALID_ARG, OOM. */
 smg_status smg_batch_create(const smg_solver *solvers, int32_t count, const smg_batch_opts *o,
                             smg_batch *out);
 void smg_batch_destroy(smg_batch b);
@@ -258,18 +261,20 @@ void smg_batch_destroy(smg_batch b);
  * (captured on the first call and after a launch-shape change).  infos
  * (count entries) may be NULL; fixed_cycles and use_graph are ignored.
  * Returns NO_CONVERGENCE if any mesh hit max_cycles (its x is the last
- * iterate), NONFINITE if any residual became non-finite. */
+ * iterate), NONFINITE if any residual became non-finite, HIP if a team
+ * barrier wait timed out (every wait is bounded; the kernel always ends). */
 smg_status smg_batch_solve(smg_batch b, const double *const *d_b, double *const *d_x,
                            const int32_t *k, const smg_solve_params *p, smg_solve_info *infos,
                            smg_stream stream);
 /* Autotuner: re-runs the last smg_batch_solve for candidate launch shapes
- * (workgroup size, lanes per row on level 0 and on the Galerkin levels),
+ * (workgroups per mesh, workgroup size, lanes per row on level 0 and on the
+ * Galerkin levels),
  * keeps the fastest, and writes it to the cache file if one was given.  It
  * never changes mu, the levels, the coloring or the color order.  budget_ms
  * bounds the search.  Errors: STATE (no previous solve). */
 smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_stream stream);
-/* Current launch shape: threads, lanes_level0, lanes_coarse. */
-smg_status smg_batch_shape(smg_batch b, int32_t *shape3);
+/* Current launch shape: threads, lanes_level0, lanes_coarse, team_max. */
+smg_status smg_batch_shape(smg_batch b, int32_t *shape4);
 
 const char *smg_status_string(smg_status st);
 const char *smg_last_error(void);

@@ -37,7 +37,7 @@ class SolveInfo(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("lanes_level0", c_int32), ("lanes_coarse", c_int32),
-                ("cache_file", ctypes.c_char_p)]
+                ("team_max", c_int32), ("cache_file", ctypes.c_char_p)]
 
 
 SMG_OK = 0

@@ -14,12 +14,12 @@ class BatchSolver:
     paper_2104_13755_amd.solver.Solver objects with values set; they must
     outlive the batch."""
 
-    def __init__(self, solvers, threads=0, lanes_level0=0, lanes_coarse=0, cache_file=None):
+    def __init__(self, solvers, threads=0, lanes_level0=0, lanes_coarse=0, team_max=0, cache_file=None):
         self._lib = L.load()
         self.solvers = list(solvers)
         arr = (_c * len(self.solvers))(*[s._s for s in self.solvers])
         self._cache = cache_file.encode() if cache_file else None
-        o = L.BatchOpts(int(threads), int(lanes_level0), int(lanes_coarse), self._cache)
+        o = L.BatchOpts(int(threads), int(lanes_level0), int(lanes_coarse), int(team_max), self._cache)
         h = _c()
         L.check(self._lib.smg_batch_create(arr, len(self.solvers), ctypes.byref(o), ctypes.byref(h)), "batch_create")
         self._b = h
@@ -49,6 +49,6 @@ class BatchSolver:
         return self.shape()
 
     def shape(self):
-        s = (ctypes.c_int32 * 3)()
+        s = (ctypes.c_int32 * 4)()
         L.check(self._lib.smg_batch_shape(self._b, s), "batch_shape")
-        return dict(threads=s[0], lanes_level0=s[1], lanes_coarse=s[2])
+        return dict(threads=s[0], lanes_level0=s[1], lanes_coarse=s[2], team_max=s[3])

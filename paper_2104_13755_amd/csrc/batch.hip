@@ -29,7 +29,14 @@ using namespace smg;
 struct smg_batch_s {
     std::vector<smg_solver> solvers;
     int device = 0, count = 0;
-    int threads = 1024, lanes0 = 1, lanes_c = 8;          // launch shape
+    int threads = 1024, lanes0 = 1, lanes_c = 8, team_max = 8;   // launch shape
+    int cus = 0, total_blocks = 0;
+    std::vector<int32_t> team;                             // workgroups per mesh
+    int32_t *d_team_mesh = nullptr, *d_team_rank = nullptr;
+    unsigned *d_ctr = nullptr;
+    int *d_abort = nullptr;
+    double *d_partial = nullptr;
+    int *h_abort = nullptr;
     std::string cache_file;
     uint64_t key = 0;                                      // workload fingerprint for the cache
     std::vector<TailLevel<double>> h64;                    // per mesh, nlev entries each
@@ -38,12 +45,11 @@ struct smg_batch_s {
     TailLevel<double> *d64 = nullptr;
     TailLevel<float> *d32 = nullptr;
     BatchMesh *d_mesh = nullptr;
-    int32_t *d_order = nullptr;
     double *d_out = nullptr, *h_out = nullptr;
     std::vector<BatchMesh> hm;
     hipStream_t stream = nullptr;
     hipGraphExec_t exec = nullptr;
-    int graph_threads = 0;
+    int graph_threads = 0, graph_blocks = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     // last solve's inputs, for the autotuner
     std::vector<const double *> last_b;
@@ -56,7 +62,12 @@ struct smg_batch_s {
         if (d64) (void)hipFree(d64);
         if (d32) (void)hipFree(d32);
         if (d_mesh) (void)hipFree(d_mesh);
-        if (d_order) (void)hipFree(d_order);
+        if (d_team_mesh) (void)hipFree(d_team_mesh);
+        if (d_team_rank) (void)hipFree(d_team_rank);
+        if (d_ctr) (void)hipFree(d_ctr);
+        if (d_abort) (void)hipFree(d_abort);
+        if (d_partial) (void)hipFree(d_partial);
+        if (h_abort) (void)hipHostFree(h_abort);
         if (d_out) (void)hipFree(d_out);
         if (h_out) (void)hipHostFree(h_out);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -76,7 +87,48 @@ static void apply_shape(smg_batch_s *b) {
     }
 }
 
+// Workgroups per mesh: proportional to the mesh's level-0 entries, between 1
+// and team_max, scaled down until every workgroup of the launch can be
+// resident at once (the team barriers need co-residency).  Blocks of the
+// largest meshes come first.
+static smg_status layout_teams(smg_batch_s *b) {
+    const int per_cu = batch_blocks_per_cu(b->threads);
+    if (per_cu < 1) return fail(SMG_ERR_HIP, "batched kernel cannot be resident");
+    const int capacity = per_cu * b->cus;
+    int64_t zmax = 1;
+    for (smg_solver s : b->solvers) zmax = std::max<int64_t>(zmax, s->lev[0].nnz_nat);
+    int tmax = b->team_max;
+    for (;;) {
+        int total = 0;
+        b->team.assign(b->count, 1);
+        for (int i = 0; i < b->count; ++i) {
+            const double share = (double)b->solvers[i]->lev[0].nnz_nat / (double)zmax;
+            b->team[i] = std::max(1, std::min(tmax, (int)std::lround(share * tmax)));
+            total += b->team[i];
+        }
+        if (total <= capacity || tmax == 1) { b->total_blocks = total; break; }
+        --tmax;
+    }
+    if (b->total_blocks > capacity) return fail(SMG_ERR_INVALID_ARG, "batch too large to be resident at once");
+    std::vector<int32_t> order(b->count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return b->solvers[a]->lev[0].nnz_nat > b->solvers[c]->lev[0].nnz_nat;
+    });
+    std::vector<int32_t> tm, tr;
+    for (int i : order)
+        for (int r = 0; r < b->team[i]; ++r) { tm.push_back(i); tr.push_back(r); }
+    if (b->d_team_mesh) { (void)hipFree(b->d_team_mesh); (void)hipFree(b->d_team_rank); }
+    HIPCHK(hipMalloc((void **)&b->d_team_mesh, tm.size() * sizeof(int32_t)));
+    HIPCHK(hipMalloc((void **)&b->d_team_rank, tr.size() * sizeof(int32_t)));
+    HIPCHK(hipMemcpy(b->d_team_mesh, tm.data(), tm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->d_team_rank, tr.data(), tr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return SMG_OK;
+}
+
 static smg_status upload_descriptors(smg_batch_s *b) {
+    smg_status st = layout_teams(b);
+    if (st) return st;
     apply_shape(b);
     HIPCHK(hipMemcpy(b->d64, b->h64.data(), b->h64.size() * sizeof(TailLevel<double>), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->d32, b->h32.data(), b->h32.size() * sizeof(TailLevel<float>), hipMemcpyHostToDevice));
@@ -90,8 +142,9 @@ static bool read_cache(smg_batch_s *b) {
     unsigned long long key;
     int t, l0, lc;
     bool found = false;
-    while (std::fscanf(f, "%llx %d %d %d", &key, &t, &l0, &lc) == 4)
-        if (key == b->key) { b->threads = t; b->lanes0 = l0; b->lanes_c = lc; found = true; }
+    int tmx;
+    while (std::fscanf(f, "%llx %d %d %d %d", &key, &t, &l0, &lc, &tmx) == 5)
+        if (key == b->key) { b->threads = t; b->lanes0 = l0; b->lanes_c = lc; b->team_max = tmx; found = true; }
     std::fclose(f);
     return found;
 }
@@ -100,7 +153,8 @@ static void write_cache(smg_batch_s *b) {
     if (b->cache_file.empty()) return;
     FILE *f = std::fopen(b->cache_file.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%llx %d %d %d\n", (unsigned long long)b->key, b->threads, b->lanes0, b->lanes_c);
+    std::fprintf(f, "%llx %d %d %d %d\n", (unsigned long long)b->key, b->threads, b->lanes0, b->lanes_c,
+                 b->team_max);
     std::fclose(f);
 }
 
@@ -137,6 +191,8 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
     if (o && o->threads) b->threads = o->threads;
     if (o && o->lanes_level0) b->lanes0 = o->lanes_level0;
     if (o && o->lanes_coarse) b->lanes_c = o->lanes_coarse;
+    if (o && o->team_max) b->team_max = o->team_max;
+    if (b->team_max < 1 || b->team_max > 64) return fail(SMG_ERR_INVALID_ARG, "team_max must be 1..64");
     if (b->threads != 256 && b->threads != 512 && b->threads != 1024) return fail(SMG_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
     if (b->lanes0 != 1 && b->lanes0 != 2) return fail(SMG_ERR_INVALID_ARG, "lanes_level0 must be 1 or 2");
     if (b->lanes_c != 1 && b->lanes_c != 2 && b->lanes_c != 4 && b->lanes_c != 8) return fail(SMG_ERR_INVALID_ARG, "lanes_coarse must be 1, 2, 4 or 8");
@@ -144,19 +200,20 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
     HIPCHK(hipMalloc((void **)&b->d64, b->h64.size() * sizeof(TailLevel<double>)));
     HIPCHK(hipMalloc((void **)&b->d32, b->h32.size() * sizeof(TailLevel<float>)));
     HIPCHK(hipMalloc((void **)&b->d_mesh, count * sizeof(BatchMesh)));
-    HIPCHK(hipMalloc((void **)&b->d_order, count * sizeof(int32_t)));
     HIPCHK(hipMalloc((void **)&b->d_out, count * 8 * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&b->d_ctr, count * sizeof(unsigned)));
+    HIPCHK(hipMalloc((void **)&b->d_abort, count * sizeof(int)));
+    HIPCHK(hipMalloc((void **)&b->d_partial, (size_t)count * 8 * 64 * sizeof(double)));
+    HIPCHK(hipHostMalloc((void **)&b->h_abort, count * sizeof(int), hipHostMallocDefault));
+    {
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, b->device));
+        b->cus = prop.multiProcessorCount;
+    }
     HIPCHK(hipHostMalloc((void **)&b->h_out, count * 8 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
-    // largest meshes first, so the longest solves start first
-    std::vector<int32_t> order(count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-        return solvers[a]->lev[0].nnz_nat > solvers[c]->lev[0].nnz_nat;
-    });
-    HIPCHK(hipMemcpy(b->d_order, order.data(), count * sizeof(int32_t), hipMemcpyHostToDevice));
     smg_status st = upload_descriptors(b.get());
     if (st) return st;
     b->hm.resize(count);
@@ -171,14 +228,16 @@ extern "C" void smg_batch_destroy(smg_batch b) {
 
 // enqueue one batched solve on b->stream (graph on the first call per shape)
 static smg_status batch_enqueue(smg_batch_s *b) {
-    if (b->exec && b->graph_threads != b->threads) {
+    if (b->exec && (b->graph_threads != b->threads || b->graph_blocks != b->total_blocks)) {
         (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (!b->exec) {
         hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = launch_batch_solve(b->d_mesh, b->d_order, b->count, b->threads, b->stream);
+        hipError_t e = launch_batch_solve(b->d_mesh, b->d_team_mesh, b->d_team_rank, b->total_blocks,
+                                          b->threads, b->d_ctr, b->d_abort, b->d_partial, b->count,
+                                          b->stream);
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
@@ -188,6 +247,7 @@ static smg_status batch_enqueue(smg_batch_s *b) {
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return fail(SMG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         b->graph_threads = b->threads;
+        b->graph_blocks = b->total_blocks;
     }
     HIPCHK(hipGraphLaunch(b->exec, b->stream));
     return SMG_OK;
@@ -221,6 +281,7 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
         M.b_user = d_b[i];
         M.x_user = d_x[i];
         M.out = b->d_out + 8 * i;
+        M.team = b->team[i];
     }
     b->last_b.assign(d_b, d_b + b->count);
     b->last_x.assign(d_x, d_x + b->count);
@@ -234,11 +295,14 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
     smg_status st = batch_enqueue(b);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(b->h_out, b->d_out, b->count * 8 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipMemcpyAsync(b->h_abort, b->d_abort, b->count * sizeof(int), hipMemcpyDeviceToHost, b->stream));
     HIPCHK(hipEventRecord(b->ev_out, b->stream));
     HIPCHK(hipStreamWaitEvent(caller, b->ev_out, 0));
     HIPCHK(hipStreamSynchronize(b->stream));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     smg_status worst = SMG_OK;
+    for (int i = 0; i < b->count; ++i)
+        if (b->h_abort[i]) return fail(SMG_ERR_HIP, "batched solve: a team barrier timed out (workgroups not co-resident?)");
     for (int i = 0; i < b->count; ++i) {
         const double *o = b->h_out + 8 * i;
         bool conv = true, finite = true;
@@ -265,6 +329,7 @@ extern "C" smg_status smg_batch_shape(smg_batch b, int32_t *shape3) {
     shape3[0] = b->threads;
     shape3[1] = b->lanes0;
     shape3[2] = b->lanes_c;
+    shape3[3] = b->team_max;
     return SMG_OK;
 }
 
@@ -272,12 +337,13 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
     if (!b) return fail(SMG_ERR_INVALID_ARG, "null batch");
     if (!b->have_last) return fail(SMG_ERR_STATE, "autotune needs a previous smg_batch_solve");
     HIPCHK(hipSetDevice(b->device));
-    struct Shape { int t, l0, lc; };
+    struct Shape { int t, l0, lc, tm; };
     std::vector<Shape> cands;
-    for (int t : {1024, 512, 256})
-        for (int lc : {8, 4, 2})
-            for (int l0 : {1, 2}) cands.push_back({t, l0, lc});
-    const Shape orig{b->threads, b->lanes0, b->lanes_c};
+    for (int tm : {8, 16, 4, 32, 2})
+        for (int t : {1024, 512, 256})
+            for (int lc : {8, 4})
+                for (int l0 : {1, 2}) cands.push_back({t, l0, lc, tm});
+    const Shape orig{b->threads, b->lanes0, b->lanes_c, b->team_max};
     Shape bestS = orig;
     double best = 1e300;
     const auto start = std::chrono::steady_clock::now();
@@ -287,6 +353,7 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
         b->threads = c.t;
         b->lanes0 = c.l0;
         b->lanes_c = c.lc;
+        b->team_max = c.tm;
         smg_status st = upload_descriptors(b);
         if (st) return st;
         double tmin = 1e300;
@@ -301,6 +368,7 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
     b->threads = bestS.t;
     b->lanes0 = bestS.l0;
     b->lanes_c = bestS.lc;
+    b->team_max = bestS.tm;
     smg_status st = upload_descriptors(b);
     if (st) return st;
     write_cache(b);

@@ -81,6 +81,7 @@ hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int m
 // --- batched solve: one workgroup per mesh, whole FP32-in-FP64 solve ---
 struct BatchMesh {
     int k, nlev, mu_pre, mu_post, max_cycles, precision;   // precision: 0 FP64, 1 FP32 + FP64 IR
+    int team;                         // workgroups cooperating on this mesh (<= 64)
     double rtol;
     TailLevel<double> l0;             // level 0 in FP64 (x, b, r, matrix)
     const TailLevel<float> *lv32;     // every level in FP32 (device array)
@@ -91,8 +92,14 @@ struct BatchMesh {
     double *x_user;                   // n x k, caller order
     double *out;                      // [cycles, rel_res[k]]
 };
-hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *order, int count, int threads,
+// team_mesh / team_rank: mesh and member index of every workgroup; ctrs and
+// aborts (count entries) are cleared by the launch; partials: count * 512.
+hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
+                              const int32_t *team_rank, int nblocks_total, int threads,
+                              unsigned *ctrs, int *aborts, double *partials, int count,
                               hipStream_t st);
+// resident workgroups of the batched kernel per compute unit
+int batch_blocks_per_cu(int threads);
 
 // --- hierarchy values ---
 hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,

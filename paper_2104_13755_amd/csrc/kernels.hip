@@ -338,14 +338,82 @@ __global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *__restric
     }
 }
 
-// ------------------------------------------------------------ tail V-cycle
-// All levels from `first` down to the coarsest in ONE workgroup: relaxation
-// colors, residual, restriction, coarsest solve, prolongation, separated by
-// workgroup barriers (Alg. "V-cycle" for the small levels, one launch).
-// Rows are handled by groups of G lanes (G = L.grp, by default the layout's
-// lanes per row, so a group reads adjacent slots) and every lane keeps four
-// independent gathers in flight: one workgroup is latency-bound, not
-// bandwidth-bound.  The same code runs whole solves in the batched kernel.
+// ------------------------------------------------------------ team V-cycle
+// A team runs Alg. "V-cycle" over a range of levels with barriers between its
+// dependent phases (relaxation colors, residual, restriction, coarsest solve,
+// prolongation).  A team is one workgroup (barrier = __syncthreads), or
+// several workgroups of one batched mesh synchronised through a counter with
+// agent-scope release/acquire.  Every wait is bounded: a wait that times out
+// raises the team's abort flag, after which no member waits any more, so the
+// kernel always drains (results are then invalid and the host reports it).
+// Rows are handled by groups of G lanes (G = L.grp) and every lane keeps four
+// independent gathers in flight.
+struct Team {
+    int tid, nthreads;      // thread index within the team, team size
+    int rank, nblk;         // workgroup index within the team, team workgroups
+    unsigned *ctr;          // barrier counter (nblk > 1)
+    int *abort;             // raised when a wait times out
+    unsigned target;        // arrivals expected at the next barrier
+    double *partial;        // nblk * 8 doubles for team reductions
+};
+
+__device__ __forceinline__ Team single_team() {
+    return Team{(int)threadIdx.x, (int)blockDim.x, 0, 1, nullptr, nullptr, 0u, nullptr};
+}
+
+__device__ void team_sync(Team &T) {
+    __syncthreads();
+    if (T.nblk > 1) {
+        T.target += (unsigned)T.nblk;
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(T.ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned spins = 0;
+            while (__hip_atomic_load(T.ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < T.target) {
+                if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 22)) {
+                    __hip_atomic_store(T.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// team-wide sum or max of K doubles; every team thread gets the result
+template <int K>
+__device__ void team_reduce(Team &T, double (&v)[K], bool take_max) {
+    __shared__ double red[4 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = take_max ? wave_max(v[q]) : wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) red[q * nw + wv] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a = take_max ? fmax(a, red[q * nw + w]) : a + red[q * nw + w];
+        v[q] = a;
+    }
+    __syncthreads();
+    if (T.nblk > 1) {
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int q = 0; q < K; ++q) T.partial[T.rank * 8 + q] = v[q];
+        team_sync(T);
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double a = 0.0;
+            for (int r = 0; r < T.nblk; ++r)
+                a = take_max ? fmax(a, T.partial[r * 8 + q]) : a + T.partial[r * 8 + q];
+            v[q] = a;
+        }
+        team_sync(T);   // the partial slots may be reused afterwards
+    }
+}
 
 // off-diagonal sum of row r (valid) over its lane group; all lanes call it
 template <int K, typename T>
@@ -387,9 +455,9 @@ __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool va
 }
 
 template <int K, typename T>
-__device__ void wg_relax(const TailLevel<T> &L, int sweeps) {
-    const int nt = blockDim.x, G = L.grp;
-    const int j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = nt / G;
+__device__ void wg_relax(Team &tm, const TailLevel<T> &L, int sweeps) {
+    const int G = L.grp;
+    const int j = tm.tid & (G - 1), g = tm.tid / G, per = tm.nthreads / G;
     for (int sw = 0; sw < sweeps; ++sw)
         for (int c = 0; c < L.ncolors; ++c) {
             const int r0 = L.color_row[c], r1 = L.color_row[c + 1];
@@ -404,15 +472,16 @@ __device__ void wg_relax(const TailLevel<T> &L, int sweeps) {
                     for (int q = 0; q < K; ++q) L.x[(size_t)r * K + q] = (L.b[(size_t)r * K + q] - acc[q]) / d;
                 }
             }
-            __syncthreads();
+            team_sync(tm);
         }
 }
 
 // r = b - A x on one level; optional per-thread column sums / maxima (FP64)
 template <int K, typename T>
-__device__ void wg_residual(const TailLevel<T> &L, double (*sq)[K] = nullptr, double (*mx)[K] = nullptr) {
-    const int nt = blockDim.x, G = L.grp;
-    const int j = threadIdx.x & (G - 1), g = threadIdx.x / G, per = nt / G;
+__device__ void wg_residual(Team &tm, const TailLevel<T> &L, double (*sq)[K] = nullptr,
+                            double (*mx)[K] = nullptr) {
+    const int G = L.grp;
+    const int j = tm.tid & (G - 1), g = tm.tid / G, per = tm.nthreads / G;
     for (int rb = 0; rb < L.n; rb += per) {
         const int r = rb + g;
         const bool valid = r < L.n;
@@ -431,25 +500,25 @@ __device__ void wg_residual(const TailLevel<T> &L, double (*sq)[K] = nullptr, do
 }
 
 template <int K, typename T>
-__device__ void wg_vcycle(const TailLevel<T> *__restrict__ lv, int first, int nlev, int mu_pre,
-                          int mu_post, const double *__restrict__ Ainv) {
-    const int nt = blockDim.x;
+__device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int first, int nlev,
+                          int mu_pre, int mu_post, const double *__restrict__ Ainv) {
+    const int nt = tm.nthreads;
     const int last = nlev - 1;   // coarsest
     for (int l = first; l < last; ++l) {
         const TailLevel<T> L = lv[l];
         if (l > first) {
-            for (int t = threadIdx.x; t < L.n * K; t += nt) L.x[t] = T(0);
-            __syncthreads();
+            for (int t = tm.tid; t < L.n * K; t += nt) L.x[t] = T(0);
+            team_sync(tm);
         }
-        wg_relax<K, T>(L, mu_pre);
-        wg_residual<K, T>(L);
-        __syncthreads();
+        wg_relax<K, T>(tm, L, mu_pre);
+        wg_residual<K, T>(tm, L);
+        team_sync(tm);
         // restriction into the next level's b (4 lanes per coarse row)
         const TailLevel<T> C = lv[l + 1];
         {
-            const int j = threadIdx.x & 3, per = nt / 4;
+            const int j = tm.tid & 3, per = nt / 4;
             for (int ab = 0; ab < C.n; ab += per) {
-                const int a = ab + (int)threadIdx.x / 4;
+                const int a = ab + tm.tid / 4;
                 T acc[K];
 #pragma unroll
                 for (int q = 0; q < K; ++q) acc[q] = T(0);
@@ -472,13 +541,13 @@ __device__ void wg_vcycle(const TailLevel<T> *__restrict__ lv, int first, int nl
                 }
             }
         }
-        __syncthreads();
+        team_sync(tm);
     }
     {   // coarsest: x = A^{-1} b in FP64, 4 lanes per row
         const TailLevel<T> C = lv[last];
-        const int j = threadIdx.x & 3, per = nt / 4;
+        const int j = tm.tid & 3, per = nt / 4;
         for (int ib = 0; ib < C.n; ib += per) {
-            const int i = ib + (int)threadIdx.x / 4;
+            const int i = ib + tm.tid / 4;
             double acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = 0.0;
@@ -509,12 +578,12 @@ __device__ void wg_vcycle(const TailLevel<T> *__restrict__ lv, int first, int nl
                 for (int q = 0; q < K; ++q) C.x[(size_t)i * K + q] = (T)acc[q];
             }
         }
-        __syncthreads();
+        team_sync(tm);
     }
     for (int l = last - 1; l >= first; --l) {
         const TailLevel<T> L = lv[l];
         const TailLevel<T> C = lv[l + 1];
-        for (int i = threadIdx.x; i < L.n; i += nt) {
+        for (int i = tm.tid; i < L.n; i += nt) {
             T acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] = T(0);
@@ -528,8 +597,8 @@ __device__ void wg_vcycle(const TailLevel<T> *__restrict__ lv, int first, int nl
 #pragma unroll
             for (int q = 0; q < K; ++q) L.x[(size_t)i * K + q] += acc[q];
         }
-        __syncthreads();
-        wg_relax<K, T>(L, mu_post);
+        team_sync(tm);
+        wg_relax<K, T>(tm, L, mu_post);
     }
 }
 
@@ -537,59 +606,38 @@ template <int K, typename T>
 __global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__restrict__ lv, int first,
                                                        int nlev, int mu_pre, int mu_post,
                                                        const double *__restrict__ Ainv) {
-    wg_vcycle<K, T>(lv, first, nlev, mu_pre, mu_post, Ainv);
+    Team tm = single_team();
+    wg_vcycle<K, T>(tm, lv, first, nlev, mu_pre, mu_post, Ainv);
 }
 
 // ---------------------------------------------------------- batched solve
-// One workgroup per mesh runs Alg. "Galerkin Surface Multigrid Solver" to
-// convergence: FP64 level-0 residual and norms, FP32 V-cycle on r / max|r|,
-// FP64 update, with the convergence test on the device.  Meshes never wait
-// for each other; converged meshes' workgroups exit.
+// A team of workgroups per mesh runs Alg. "Galerkin Surface Multigrid
+// Solver" to convergence: FP64 level-0 residual and norms, FP32 V-cycle on
+// r / max|r|, FP64 update, with the convergence test on the device.  Meshes
+// never wait for each other; converged meshes' teams exit.
 template <int K>
-__device__ void wg_block_reduce(double (&v)[K], bool take_max, double *red) {
-    // red: at least 2 * K * (blockDim / 64) doubles of LDS
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int q = 0; q < K; ++q) v[q] = take_max ? wave_max(v[q]) : wave_sum(v[q]);
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < K; ++q) red[q * nw + wv] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        double a = 0.0;
-        for (int w = 0; w < nw; ++w) a = take_max ? fmax(a, red[q * nw + w]) : a + red[q * nw + w];
-        v[q] = a;
-    }
-    __syncthreads();
-}
-
-template <int K>
-__device__ void batch_mesh(const BatchMesh &M) {
-    __shared__ double red[4 * 16];
+__device__ void batch_mesh(Team &tm, const BatchMesh &M) {
     const TailLevel<double> L0 = M.l0;
-    const int n = L0.n, nt = blockDim.x;
+    const int n = L0.n, nt = tm.nthreads;
     // b (caller order) -> level-0 color-major order; x = 0; r = b
-    for (int t = threadIdx.x; t < n * K; t += nt) {
+    for (int t = tm.tid; t < n * K; t += nt) {
         const int r = t / K, q = t % K;
         const double v = M.b_user[(size_t)M.perm0[r] * K + q];
         L0.b[t] = v;
         L0.r[t] = v;
         L0.x[t] = 0.0;
     }
-    __syncthreads();
     double bn[K], sq[K], mx[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
-    for (int t = threadIdx.x; t < n * K; t += nt) {
-        const double v = L0.b[t];
-        // column of t is t % K
+    for (int t = tm.tid; t < n * K; t += nt) {
+        const double v = M.b_user[(size_t)M.perm0[t / K] * K + t % K];
 #pragma unroll
         for (int q = 0; q < K; ++q)
             if (t % K == q) { sq[q] += v * v; mx[q] = fmax(mx[q], fabs(v)); }
     }
-    wg_block_reduce<K>(sq, false, red);
-    wg_block_reduce<K>(mx, true, red);
+    team_reduce<K>(tm, sq, false);
+    team_reduce<K>(tm, mx, true);
     double rho[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) { bn[q] = sqrt(sq[q]); rho[q] = bn[q] > 0.0 ? 1.0 : 0.0; }
@@ -601,33 +649,33 @@ __device__ void batch_mesh(const BatchMesh &M) {
         for (int q = 0; q < K; ++q) worst = fmax(worst, rho[q]);
         if (!(worst > M.rtol) || cycles >= M.max_cycles) break;
         if (M.precision == 0) {   // plain FP64 V-cycle on (b, x) of level 0
-            wg_vcycle<K, double>(M.lv64, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
+            wg_vcycle<K, double>(tm, M.lv64, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
         } else {
-        // r32 = r / max|r| ; x32 = 0
-        for (int t = threadIdx.x; t < n * K; t += nt) {
-            const int q = t % K;
-            double s = 0.0;
+            // r32 = r / max|r| ; x32 = 0
+            for (int t = tm.tid; t < n * K; t += nt) {
+                const int q = t % K;
+                double s = 0.0;
 #pragma unroll
-            for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
-            F0.b[t] = (float)(s > 0.0 ? L0.r[t] / s : 0.0);
-            F0.x[t] = 0.0f;
-        }
-        __syncthreads();
-        wg_vcycle<K, float>(M.lv32, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
-        for (int t = threadIdx.x; t < n * K; t += nt) {
-            const int q = t % K;
-            double s = 0.0;
+                for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
+                F0.b[t] = (float)(s > 0.0 ? L0.r[t] / s : 0.0);
+                F0.x[t] = 0.0f;
+            }
+            team_sync(tm);
+            wg_vcycle<K, float>(tm, M.lv32, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
+            for (int t = tm.tid; t < n * K; t += nt) {
+                const int q = t % K;
+                double s = 0.0;
 #pragma unroll
-            for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
-            L0.x[t] += s * (double)F0.x[t];
-        }
-        __syncthreads();
+                for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
+                L0.x[t] += s * (double)F0.x[t];
+            }
+            team_sync(tm);
         }
 #pragma unroll
         for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
-        wg_residual<K, double>(L0, &sq, &mx);
-        wg_block_reduce<K>(sq, false, red);
-        wg_block_reduce<K>(mx, true, red);
+        wg_residual<K, double>(tm, L0, &sq, &mx);
+        team_reduce<K>(tm, sq, false);
+        team_reduce<K>(tm, mx, true);
         ++cycles;
 #pragma unroll
         for (int q = 0; q < K; ++q) rho[q] = bn[q] > 0.0 ? sqrt(sq[q]) / bn[q] : sqrt(sq[q]);
@@ -636,25 +684,40 @@ __device__ void batch_mesh(const BatchMesh &M) {
         for (int q = 0; q < K; ++q) finite = finite && isfinite(rho[q]);
         if (!finite) break;
     }
-    for (int t = threadIdx.x; t < n * K; t += nt) {
+    for (int t = tm.tid; t < n * K; t += nt) {
         const int r = t / K, q = t % K;
         M.x_user[(size_t)M.perm0[r] * K + q] = L0.x[t];
     }
-    if (threadIdx.x == 0) {
+    if (tm.tid == 0) {
         M.out[0] = (double)cycles;
 #pragma unroll
         for (int q = 0; q < K; ++q) M.out[1 + q] = rho[q];
     }
 }
 
+// block b works for mesh team_mesh[b] as member team_rank[b] of team_size[mesh]
 __global__ __launch_bounds__(1024) void k_batch_solve(const BatchMesh *__restrict__ meshes,
-                                                      const int32_t *__restrict__ order) {
-    const BatchMesh M = meshes[order[blockIdx.x]];
+                                                      const int32_t *__restrict__ team_mesh,
+                                                      const int32_t *__restrict__ team_rank,
+                                                      unsigned *__restrict__ ctrs,
+                                                      int *__restrict__ aborts,
+                                                      double *__restrict__ partials) {
+    const int m = team_mesh[blockIdx.x];
+    const BatchMesh M = meshes[m];
+    Team tm;
+    tm.rank = team_rank[blockIdx.x];
+    tm.nblk = M.team;
+    tm.tid = tm.rank * (int)blockDim.x + (int)threadIdx.x;
+    tm.nthreads = tm.nblk * (int)blockDim.x;
+    tm.ctr = ctrs + m;
+    tm.abort = aborts + m;
+    tm.target = 0u;
+    tm.partial = partials + (size_t)m * 8 * 64;
     switch (M.k) {
-    case 1: batch_mesh<1>(M); break;
-    case 2: batch_mesh<2>(M); break;
-    case 3: batch_mesh<3>(M); break;
-    default: batch_mesh<4>(M); break;
+    case 1: batch_mesh<1>(tm, M); break;
+    case 2: batch_mesh<2>(tm, M); break;
+    case 3: batch_mesh<3>(tm, M); break;
+    default: batch_mesh<4>(tm, M); break;
     }
 }
 
@@ -979,12 +1042,22 @@ hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int m
     return hipGetLastError();
 }
 
-hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *order, int count, int threads,
+hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
+                              const int32_t *team_rank, int nblocks_total, int threads,
+                              unsigned *ctrs, int *aborts, double *partials, int count,
                               hipStream_t st) {
-    if (count <= 0) return hipSuccess;
+    if (nblocks_total <= 0) return hipSuccess;
     if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-    k_batch_solve<<<count, threads, 0, st>>>(meshes, order);
+    k_fill<unsigned><<<nblocks(count), kBlock, 0, st>>>(ctrs, 0u, count);
+    k_fill<int><<<nblocks(count), kBlock, 0, st>>>(aborts, 0, count);
+    k_batch_solve<<<nblocks_total, threads, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
     return hipGetLastError();
+}
+
+int batch_blocks_per_cu(int threads) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_solve, threads, 0) != hipSuccess) return 0;
+    return occ;
 }
 
 hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,
@@ -1117,5 +1190,6 @@ template hipError_t launch_vcycle_tail<float>(const TailLevel<float> *, int, int
 template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
 template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);
+template hipError_t launch_fill<unsigned>(unsigned *, unsigned, int64_t, hipStream_t);
 
 }  // namespace smg
