@@ -28,6 +28,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic():
+    """Traffic per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_gs_color_f32_torus1M.md")
+    src = os.path.join(ROOT, "paper_2104_13755_amd", "csrc", "kernels.hip")
+    try:
+        txt = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None, None
+    m = re.search(r"kernels_hip_sha256: ([0-9a-f]+)", txt)
+    if not m or m.group(1) != sha:
+        return None, None
+    a = re.search(r"traffic_bytes_per_launch_every_level: (\d+)", txt)
+    z = re.search(r"traffic_bytes_per_launch_level0: (\d+)", txt)
+    return (float(a.group(1)) if a else None), (float(z.group(1)) if z else None)
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -254,6 +274,8 @@ def main():
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="short run for hardware counters: a 256 MiB copy (calibration), then 3 mixed cycles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
@@ -276,6 +298,17 @@ def main():
     log(f"workload {w['name']} n={len(w['V'])} faces={len(w['F'])}")
     S, h, Vd, b, setup = gpu_setup(w, n_levels)
     use_graph = bool(args.graph)
+    if args.pmc_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)   # plain streaming kernel: reads and writes 256 MiB
+        torch.cuda.synchronize()
+        S.solve(b, fixed_cycles=3, precision="fp32ir")
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "copy_bytes_read": src.numel() * 8,
+                          "copy_bytes_written": dst.numel() * 8, "cycles": 3}), flush=True)
+        return
 
     # warmup both precisions
     for prec in ("fp32ir", "fp64"):
@@ -299,9 +332,10 @@ def main():
     diff = float(torch.linalg.norm(x_m - x_d) / torch.linalg.norm(x_d))
 
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else None
+    traffic_all, traffic_l0 = measured_traffic() if args.profile_kind == "gs" else (None, None)
     per_launch_bytes = prof["bytes"] / max(1, prof["launches"])
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic_all,
                 "kernel": "k_gs_color<3, float> (multicolor Gauss-Seidel, FP32 cycles, every level)"
                           if args.profile_kind == "gs" else f"{args.profile_kind} (every level)",
                 "launches": prof["launches"], "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"]),
@@ -312,7 +346,8 @@ def main():
                            "frac": prof0["bytes"] / (prof0["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS if prof0["ms"] > 0 else None,
                            "launches": prof0["launches"],
                            "avg_launch_us": prof0["ms"] * 1e3 / max(1, prof0["launches"]),
-                           "algorithmic_bytes_per_launch": prof0["bytes"] / max(1, prof0["launches"])}}
+                           "algorithmic_bytes_per_launch": prof0["bytes"] / max(1, prof0["launches"]),
+                           "traffic": traffic_l0}}
     value = args.steps / t_mixed
     out = {
         "metric": "V-cycle solves/s + HBM GB/s at 1M verts to rel residual 1e-8, mixed vs FP64",
