@@ -1,0 +1,81 @@
+"""Full-size parity in the benchmark's launch configuration: the 1,000,000-
+vertex torus (3 RHS, 7 levels).  The oracle builds everything itself (its
+own assembly, successive self-parameterization, Galerkin levels, coloring)
+and every output is compared whole: A_0, P_l, A_l, colors, coarsest factor,
+three fixed FP64 V-cycles, and the converged FP64 / mixed solutions checked
+with the oracle's own residual."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from helpers import gpu_available, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(900)
+def test_torus_1m_bench_configuration():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import torch
+    from oracle import assemble as AS, hierarchy as OH, vcycle as OV
+    from paper_2104_13755_amd.solver import Hierarchy, Solver, mesh_pattern
+    w = synth.workload_c2()
+    V, F, t = w["V"], w["F"], w["t"]
+    print("\n[full] product setup", flush=True)
+    h = Hierarchy.build(V, F, n_levels=7)
+    rp, ci = mesh_pattern(len(V), F)
+    S = Solver(h, rp, ci, faces=F)                  # default launch shape, as bench.py
+    Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+    a, _, mg = S.assemble(Vd, t, want_mass=True)
+    S.set_values(a)
+    print("[full] oracle assembly and hierarchy", flush=True)
+    A, L, m = AS.system(V, F, t)
+    # Assembly rounding: each cotangent is dot/|cross| with relative error
+    # ~ eps / sin(angle); across an edge whose two opposite angles are near 0
+    # and 180 degrees the two cotangents nearly cancel, so the entry's error is
+    # that relative error times |cot| (up to ~1e2 on this jittered grid):
+    # ~1e-13 of the largest entry (observed 2.1e-13 elementwise, 1.1e-13 in
+    # the Frobenius norm).  Bounds: 1e-12 elementwise of the largest entry,
+    # 5e-13 in the Frobenius norm; any formula mistake is O(1).
+    an = a.cpu().numpy()
+    assert rel(an, A.data) < 1e-12
+    assert np.linalg.norm(an - A.data) / np.linalg.norm(A.data) < 5e-13
+    assert rel(mg.cpu().numpy(), m) < 1e-14
+    # hierarchy and V-cycle parity on identical A_0 values
+    S.set_values(torch.tensor(A.data, dtype=torch.float64, device="cuda"))
+    Ps, _, _ = OH.prolongations(V, F, n_levels=7)
+    assert h.sizes == [len(V)] + [P.shape[1] for P in Ps]
+    for l, P in enumerate(Ps):
+        c, wt = h.prolongation(l)
+        n = len(c)
+        msk = wt > 0
+        Pp = sp.csr_matrix((wt[msk], (np.repeat(np.arange(n), 3).reshape(n, 3)[msk], c[msk])), shape=P.shape)
+        assert ((Pp != 0) != (P != 0)).nnz == 0, l
+        assert abs(Pp - P).max() < 1e-12, l
+    print("[full] oracle Galerkin and coloring", flush=True)
+    O = OV.Solver(Ps, A)
+    for l in range(O.nlev):
+        Ag = S.level_matrix(l)
+        assert np.array_equal(Ag.indptr, O.A[l].indptr) and np.array_equal(Ag.indices, O.A[l].indices), l
+        assert rel(Ag.data, O.A[l].data) < 1e-13, l
+        if l < O.nlev - 1:
+            col, nc = S.colors(l)
+            assert nc == O.colors[l][1] and np.array_equal(col, O.colors[l][0]), l
+    assert rel(S.coarse_factor(), O.G) < 1e-12
+    b = m[:, None] * V
+    bd = torch.tensor(b, dtype=torch.float64, device="cuda")
+    print("[full] three fixed cycles", flush=True)
+    xg, _ = S.solve(bd, fixed_cycles=3, precision="fp64")
+    xo, _, _ = O.solve(b, 0.0, fixed_cycles=3)
+    assert np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-12
+    print("[full] converged solves (the library's own assembly, as bench.py)", flush=True)
+    S.set_values(a)
+    for prec in ("fp64", "fp32ir"):
+        x, info = S.solve(bd, rtol=1e-8, precision=prec)
+        x = x.cpu().numpy()
+        res = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+        print(f"[full] {prec}: cycles={info['cycles']} oracle residual={res.max():.3e}", flush=True)
+        assert res.max() <= 1e-8 * 1.0001
+        assert info["cycles"] == 44
