@@ -115,7 +115,10 @@ typedef struct {
     int32_t mu_post;       /* post-relaxation sweeps (Sec. 5 default 2) */
     int32_t tail_rows;     /* levels with at most this many rows (and all
                               coarser ones) run in one single-workgroup kernel
-                              per cycle; 0 = 1000, < 0 = never              */
+                              per cycle, their iterates held in LDS (a level
+                              joins only if the whole tail fits one
+                              workgroup's LDS for the call's precision and
+                              k); 0 = 4096, < 0 = never                     */
     int32_t lanes_per_row[16]; /* per level 1/2/4/8 lanes per matrix row in
                               the relaxation/residual kernels; 0 = rule (1 if
                               the mean row has < 10 entries, else 8); launch

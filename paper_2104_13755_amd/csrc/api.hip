@@ -21,6 +21,9 @@ using namespace smg;
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
+// levels with at most this many rows (and all coarser ones) form the
+// one-workgroup LDS tail unless the caller chooses otherwise
+static constexpr int kTailRowsDefault = 4096;
 
 namespace smg {
 smg_status fail(smg_status st, const std::string &msg) {
@@ -257,7 +260,7 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     S->mu_pre = opts && opts->mu_pre >= 0 ? opts->mu_pre : 2;
     S->mu_post = opts && opts->mu_post >= 0 ? opts->mu_post : 2;
     if (!opts) S->mu_pre = S->mu_post = 2;
-    const int tail_rows = (opts && opts->tail_rows != 0) ? opts->tail_rows : 1000;
+    const int tail_rows = (opts && opts->tail_rows != 0) ? opts->tail_rows : kTailRowsDefault;
     std::vector<int> lpr(16, 0);
     if (opts) for (int l = 0; l < 16; ++l) lpr[l] = opts->lanes_per_row[l];
     std::vector<LevelHost> levels;
@@ -267,6 +270,8 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     S->lev.resize(S->nlev);
     int64_t tmax = 1;
     int nmax = 1;
+    std::vector<int32_t> tpass_h, twave_h;
+    int npass_before = 0, nwave_before = 0;
     for (int l = 0; l < S->nlev; ++l) {
         LevelHost &L = levels[l];
         DevLevel &D = S->lev[l];
@@ -320,13 +325,51 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
             CHK(dupload(&D.ridx, L.ridx, S->owned));
             CHK(dupload(&D.rw, L.rw, S->owned));
             CHK(dupload(&D.rw32, rw32, S->owned));
+            CHK(dupload(&D.rs_off, L.rs_off, S->owned));
+            CHK(dupload(&D.rs_idx, L.rs_idx, S->owned));
+            CHK(dupload(&D.rs_w, L.rs_w, S->owned));
+            std::vector<float> rsw32(L.rs_w.begin(), L.rs_w.end());
+            CHK(dupload(&D.rs_w32, rsw32, S->owned));
             CHK(dupload(&D.tptr, L.tptr, S->owned));
             CHK(dupload(&D.plan1ptr, L.plan1ptr, S->owned));
             CHK(dupload(&D.plan1, L.plan1, S->owned));
             CHK(dupload(&D.plan2ptr, L.plan2ptr, S->owned));
             CHK(dupload(&D.plan2, L.plan2, S->owned));
+            CHK(dupload(&D.optr, L.optr, S->owned));
+            CHK(dupload(&D.opos, L.opos, S->owned));
+            D.tmax = L.tmax;
+            D.cmax = L.cmax;
             tmax = std::max<int64_t>(tmax, L.tptr.back());
+            if (tail_rows > 0 && L.n <= tail_rows) {   // records of the LDS tail
+                TailLayout T;
+                build_tail_layout(L, levels[l + 1].n, kTailThreads, T);
+                if (!check_tail_layout(T, L.n, kTailThreads, err)) return fail(SMG_ERR_INVALID_ARG, err);
+                D.tl = true;
+                D.tl_lg = 0;
+                while ((1 << D.tl_lg) < T.grp) ++D.tl_lg;
+                D.tl_npass = (int)T.pass.size() / 4;
+                D.tl_nwave = (int)T.wave.size() / 2;
+                D.tl_nrec = (int64_t)T.src.size();
+                D.tl_rk = T.rk;
+                for (size_t p = 0; p < T.pass.size(); p += 4) {   // first wavefront: global index
+                    tpass_h.insert(tpass_h.end(), T.pass.begin() + p, T.pass.begin() + p + 3);
+                    tpass_h.push_back(T.pass[p + 3] + nwave_before);
+                }
+                twave_h.insert(twave_h.end(), T.wave.begin(), T.wave.end());
+                CHK(dupload(&D.tl_src, T.src, S->owned));
+                CHK(dupload(&D.tl_cols, T.cols, S->owned));
+                CHK(dalloc(&D.tl_rec, (size_t)std::max<int64_t>(1, D.tl_nrec), S->owned));
+                CHK(dalloc(&D.tl_rec32, (size_t)std::max<int64_t>(1, D.tl_nrec), S->owned));
+                CHK(dupload(&D.tl_ridx, T.ridx, S->owned));
+                CHK(dupload(&D.tl_rw, T.rw, S->owned));
+                std::vector<float> trw32(T.rw.begin(), T.rw.end());
+                CHK(dupload(&D.tl_rw32, trw32, S->owned));
+            }
         }
+        D.tl_pass0 = npass_before;
+        npass_before += D.tl_npass;
+        D.tl_wave0 = nwave_before;
+        nwave_before += D.tl_nwave;
         const size_t nk = (size_t)L.n * 4;
         CHK(dalloc(&D.x, nk, S->owned));
         CHK(dalloc(&D.b, nk, S->owned));
@@ -338,23 +381,49 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
         L = LevelHost();
     }
     CHK(dalloc(&S->tbuf, (size_t)tmax, S->owned));
-    // single-workgroup tail: the first level with at most tail_rows rows
-    if (tail_rows > 0)
-        for (int l = 0; l < S->nlev; ++l)
-            if (S->lev[l].n <= tail_rows) { S->tail_first = l; break; }
+    // LDS tail: per precision and k, the finest level from which every level
+    // has records and the tail's LDS footprint fits one workgroup
     {
-        std::vector<TailLevel<double>> t64(S->nlev);
-        std::vector<TailLevel<float>> t32(S->nlev);
+        int dev_lds = 0;
+        HIPCHK(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+        const int last = S->nlev - 1;
+        std::vector<int64_t> nsum(S->nlev + 1, 0);
+        for (int l = 0; l < S->nlev; ++l) nsum[l + 1] = nsum[l] + S->lev[l].n;
+        size_t need[2] = {0, 0};
+        for (int pr = 0; pr < 2; ++pr)
+            for (int k = 1; k <= 4; ++k) {
+                S->tail_first[pr][k] = last;
+                S->tail_lds[pr][k].assign(S->nlev, 0);
+                for (int l = last - 1; l >= 0 && S->lev[l].tl; --l) {
+                    const size_t bytes = tail_lds_bytes(npass_before - S->lev[l].tl_pass0,
+                                                        nwave_before - S->lev[l].tl_wave0, nsum[last + 1] - nsum[l],
+                                                        S->lev[last].n, k, pr == 0 ? 8 : 4);
+                    if (bytes > (size_t)dev_lds) break;
+                    S->tail_first[pr][k] = l;
+                    S->tail_lds[pr][k][l] = bytes;
+                    need[pr] = std::max(need[pr], bytes);
+                }
+            }
+        if (need[0]) HIPCHK(tail_lds_allow<double>(need[0]));
+        if (need[1]) HIPCHK(tail_lds_allow<float>(need[1]));
+        S->lev[last].tl_pass0 = npass_before;
+        S->lev[last].tl_wave0 = nwave_before;
+        if (tpass_h.empty()) tpass_h.assign(4, 0);
+        if (twave_h.empty()) twave_h.assign(2, 0);
+        CHK(dupload(&S->tpass, tpass_h, S->owned));
+        CHK(dupload(&S->twave, twave_h, S->owned));
+        std::vector<LdsLevel<double>> t64(S->nlev);
+        std::vector<LdsLevel<float>> t32(S->nlev);
         for (int l = 0; l < S->nlev; ++l) {
             const DevLevel &D = S->lev[l];
-            t64[l] = {D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
-                      D.rowlen, D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw, D.rptr, D.ridx, D.rw};
-            t32[l] = {D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off, D.row_slice,
-                      D.rowlen, D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32, D.pc, D.pw32, D.rptr,
-                      D.ridx, D.rw32};
+            const int nc = l + 1 < S->nlev ? S->lev[l + 1].n : 0;
+            t64[l] = {D.n, D.tl_lg, D.tl_pass0, D.tl_npass, D.tl_wave0, (int)nsum[l], D.tl_rec, D.diag,
+                      D.b, D.r, D.x, D.pc, D.pw, D.tl_rk, nc, D.tl_ridx, D.tl_rw};
+            t32[l] = {D.n, D.tl_lg, D.tl_pass0, D.tl_npass, D.tl_wave0, (int)nsum[l], D.tl_rec32, D.diag32,
+                      D.b32, D.r32, D.x32, D.pc, D.pw32, D.tl_rk, nc, D.tl_ridx, D.tl_rw32};
         }
-        CHK(dupload(&S->tail64, t64, S->owned));
-        CHK(dupload(&S->tail32, t32, S->owned));
+        CHK(dupload(&S->lds64, t64, S->owned));
+        CHK(dupload(&S->lds32, t32, S->owned));
     }
     int64_t maxblk = (nmax + 255) / 256 + 1;
     for (const DevLevel &D : S->lev) maxblk = std::max<int64_t>(maxblk, (D.nslices + 3) / 4 + 1);
@@ -504,17 +573,20 @@ smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t 
     for (int l = 0; l + 1 < s->nlev; ++l) {
         DevLevel &D = s->lev[l];
         DevLevel &C = s->lev[l + 1];
-        HIPCHK(launch_galerkin_t(D.n, D.tptr, D.plan1ptr, D.plan1, D.row_slice, D.slice_row0,
-                                 D.slice_off, D.lpr, D.rowlen, D.cols, D.vals, D.diag, D.pc, D.pw,
-                                 s->tbuf, st));
-        HIPCHK(launch_galerkin_c(C.n, D.plan2ptr, D.plan2, D.rptr, D.ridx, D.rw, D.tptr, s->tbuf,
-                                 C.coarsest ? C.dense_a : C.vals, C.coarsest ? nullptr : C.diag, st));
+        HIPCHK(launch_galerkin_t(D.n, D.tmax, D.tptr, D.plan1ptr, D.plan1, D.row_slice, D.slice_row0,
+                                 D.slice_off, D.lpr, D.rowlen, D.cols, D.vals, D.diag, D.pw, s->tbuf, st));
+        HIPCHK(launch_galerkin_c(C.n, D.cmax, D.plan2ptr, D.plan2, D.rptr, D.ridx, D.rw, D.tptr, s->tbuf,
+                                 D.optr, D.opos, C.coarsest ? C.dense_a : C.vals, C.coarsest ? nullptr : C.diag, st));
     }
     for (int l = 0; l < s->nlev; ++l) {
         DevLevel &D = s->lev[l];
         if (D.coarsest) continue;
         HIPCHK(launch_to_f32(D.vals, D.vals32, D.slots, st));
         HIPCHK(launch_to_f32(D.diag, D.diag32, D.n, st));
+    }
+    for (int l = 0; l < s->nlev; ++l) {
+        DevLevel &D = s->lev[l];
+        if (D.tl) HIPCHK(launch_gather_records(D.tl_src, D.tl_cols, D.tl_nrec, D.vals, D.vals32, D.tl_rec, D.tl_rec32, st));
     }
     DevLevel &Lc = s->lev[s->nlev - 1];
     HIPCHK(hipMemcpyAsync(Lc.dense, Lc.dense_a, (size_t)Lc.n * Lc.n * sizeof(double),
@@ -572,11 +644,11 @@ template <>
 SellView<float> sell_view<float>(const DevLevel &D) {
     return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32};
 }
-template <typename T> static const TailLevel<T> *tail_desc(const smg_solver_s *s);
-template <> const TailLevel<double> *tail_desc<double>(const smg_solver_s *s) { return s->tail64; }
-template <> const TailLevel<float> *tail_desc<float>(const smg_solver_s *s) { return s->tail32; }
+template <typename T> static const LdsLevel<T> *tail_desc(const smg_solver_s *s);
+template <> const LdsLevel<double> *tail_desc<double>(const smg_solver_s *s) { return s->lds64; }
+template <> const LdsLevel<float> *tail_desc<float>(const smg_solver_s *s) { return s->lds32; }
 static TransferView transfer_view(const DevLevel &D, const DevLevel &C) {
-    return {D.n, C.n, D.pc, D.rptr, D.ridx};
+    return {D.n, C.n, D.pc, D.rs_off, D.rs_idx};
 }
 template <typename T> static T *xbuf(DevLevel &D);
 template <> double *xbuf<double>(DevLevel &D) { return D.x; }
@@ -591,8 +663,8 @@ template <typename T> static const T *pwbuf(const DevLevel &D);
 template <> const double *pwbuf<double>(const DevLevel &D) { return D.pw; }
 template <> const float *pwbuf<float>(const DevLevel &D) { return D.pw32; }
 template <typename T> static const T *rwbuf(const DevLevel &D);
-template <> const double *rwbuf<double>(const DevLevel &D) { return D.rw; }
-template <> const float *rwbuf<float>(const DevLevel &D) { return D.rw32; }
+template <> const double *rwbuf<double>(const DevLevel &D) { return D.rs_w; }
+template <> const float *rwbuf<float>(const DevLevel &D) { return D.rs_w32; }
 
 template <typename T>
 smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st) {
@@ -629,9 +701,10 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st) {
         HIPCHK((launch_coarse_solve<T, T>(D.dense_inv, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
         return SMG_OK;
     }
-    if (l >= s->tail_first) {   // this level and all coarser ones in one launch
-        HIPCHK(launch_vcycle_tail<T>(tail_desc<T>(s), l, s->nlev, s->mu_pre, s->mu_post,
-                                     s->lev[s->nlev - 1].dense_inv, k, st));
+    const int pr = sizeof(T) == 8 ? 0 : 1;
+    if (l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
+        HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
+                                  s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st));
         return SMG_OK;
     }
     DevLevel &C = s->lev[l + 1];
@@ -700,7 +773,7 @@ extern "C" smg_status smg_restrict(smg_solver s, int32_t l, const double *d_r, d
     hipStream_t st = (hipStream_t)stream;
     DevLevel &D = s->lev[l], &C = s->lev[l + 1];
     HIPCHK(launch_gather_rows(D.perm, d_r, D.r, D.n, k, st));
-    HIPCHK(launch_restrict<double>(transfer_view(D, C), D.rw, D.r, C.b, k, st));
+    HIPCHK(launch_restrict<double>(transfer_view(D, C), D.rs_w, D.r, C.b, k, st));
     HIPCHK(launch_scatter_rows(C.perm, C.b, d_rc, C.n, k, st));
     return SMG_OK;
 }

@@ -177,6 +177,12 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
             for (int c = 0; c < L.ncolors; ++c) cnt[c + 1] += cnt[c];
             L.sell.color_row = cnt;
             for (int i = 0; i < L.n; ++i) L.perm[cnt[L.color[i]]++] = i;
+            if (l > 0) {   // Galerkin levels: rows of a color by descending length (less padding)
+                auto len = [&](int i) { return pat.ptr[i + 1] - pat.ptr[i]; };
+                for (int c = 0; c < L.ncolors; ++c)
+                    std::stable_sort(L.perm.begin() + L.sell.color_row[c], L.perm.begin() + L.sell.color_row[c + 1],
+                                     [&](int a, int b) { return len(a) > len(b); });
+            }
         } else {
             std::iota(L.perm.begin(), L.perm.end(), 0);
         }
@@ -235,6 +241,26 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
                     }
                 }
         }
+        {
+            const int ns = (nc + 63) / 64;
+            L.rs_off.assign(ns + 1, 0);
+            for (int s = 0; s < ns; ++s) {
+                int wmax = 0;
+                for (int a = s * 64; a < std::min(nc, s * 64 + 64); ++a) wmax = std::max(wmax, L.rptr[a + 1] - L.rptr[a]);
+                L.rs_off[s + 1] = L.rs_off[s] + 64 * wmax;
+            }
+            L.rs_idx.assign(L.rs_off[ns], 0);
+            L.rs_w.assign(L.rs_off[ns], 0.0);
+            for (int a = 0; a < nc; ++a) {
+                const int s = a / 64, lane = a % 64, w = (L.rs_off[s + 1] - L.rs_off[s]) / 64;
+                const int len = L.rptr[a + 1] - L.rptr[a];
+                for (int k = 0; k < w; ++k) {
+                    const size_t at = (size_t)L.rs_off[s] + 64 * k + lane;
+                    L.rs_idx[at] = len ? L.ridx[L.rptr[a] + std::min(k, len - 1)] : 0;
+                    L.rs_w[at] = k < len ? L.rw[L.rptr[a] + k] : 0.0;
+                }
+            }
+        }
         // T = A P pattern per permuted fine row; plan1 maps (source, slot) -> T offset
         L.tptr.assign(n + 1, 0);
         L.plan1ptr.assign(n + 1, 0);
@@ -253,6 +279,7 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
             if (row.size() > 65535) { err = "Galerkin row too long"; return -1; }
             tcols.insert(tcols.end(), row.begin(), row.end());
             L.tptr[r + 1] = (int32_t)tcols.size();
+            L.tmax = std::max(L.tmax, (int)row.size());
             auto emit = [&](int src) {
                 for (int m = 0; m < 3; ++m) {
                     const int b = L.pc[(size_t)m * n + src];
@@ -266,15 +293,35 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
             for (int e = 0; e < L.sell.rowlen[r]; ++e) emit(L.sell.pidx[L.sell.pptr[r] + e]);
             L.plan1ptr[r + 1] = (int32_t)L.plan1.size();
         }
-        // plan2: for coarse row a, for R entry (r, w), for T entry (r, b): position of (a, b)
+        // local slots of coarse row a (permuted): its pattern columns (permuted,
+        // ascending), each with its storage position in level l+1
+        L.optr.assign(nc + 1, 0);
+        L.opos.clear();
+        std::vector<int32_t> ocol;   // permuted column of each local slot
+        for (int a = 0; a < nc; ++a) {
+            const int i = C.perm[a];
+            const size_t o0 = ocol.size();
+            for (int p = C.pat.ptr[i]; p < C.pat.ptr[i + 1]; ++p) ocol.push_back(C.iperm[C.pat.idx[p]]);
+            std::sort(ocol.begin() + o0, ocol.end());
+            for (size_t k = o0; k < ocol.size(); ++k) {
+                const int32_t pos = store_pos(C, a, ocol[k]);
+                if (pos == INT32_MIN) { err = "coarse pattern without storage"; return -1; }
+                L.opos.push_back(pos);
+            }
+            L.optr[a + 1] = (int32_t)ocol.size();
+            L.cmax = std::max(L.cmax, (int)(ocol.size() - o0));
+            if (ocol.size() - o0 > 65535) { err = "coarse row too long"; return -1; }
+        }
+        // plan2: for coarse row a, for R entry (r, w), for T entry (r, b): local slot of (a, b)
         L.plan2ptr.assign(nc + 1, 0);
         for (int a = 0; a < nc; ++a) {
+            const int32_t *ob = ocol.data() + L.optr[a], *oe = ocol.data() + L.optr[a + 1];
             for (int q = L.rptr[a]; q < L.rptr[a + 1]; ++q) {
                 const int r = L.ridx[q];
                 for (int t = L.tptr[r]; t < L.tptr[r + 1]; ++t) {
-                    const int32_t pos = store_pos(C, a, tcols[t]);
-                    if (pos == INT32_MIN) { err = "Galerkin plan outside the symbolic pattern"; return -1; }
-                    L.plan2.push_back(pos);
+                    const int32_t *it = std::lower_bound(ob, oe, tcols[t]);
+                    if (it == oe || *it != tcols[t]) { err = "Galerkin plan outside the symbolic pattern"; return -1; }
+                    L.plan2.push_back((uint16_t)(it - ob));
                 }
             }
             if (L.plan2.size() > (size_t)INT32_MAX) { err = "Galerkin plan too large"; return -1; }
@@ -282,6 +329,77 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
         }
     }
     return 0;
+}
+
+void build_tail_layout(const LevelHost &L, int nc, int threads, TailLayout &out) {
+    const SellLayout &S = L.sell;
+    out = TailLayout();
+    int maxrows = 1;
+    for (int c = 0; c + 1 < (int)S.color_row.size(); ++c)
+        maxrows = std::max(maxrows, S.color_row[c + 1] - S.color_row[c]);
+    int g = 1;   // widest lane group (<= 64) that still fits a whole color in one pass
+    while (g < 64 && (int64_t)maxrows * g * 2 <= threads) g *= 2;
+    out.grp = g;
+    const int per = threads / g;
+    int64_t off = 0;
+    for (int c = 0; c + 1 < (int)S.color_row.size(); ++c) {
+        const int r0 = S.color_row[c], r1 = S.color_row[c + 1];
+        for (int p0 = r0; p0 < r1; p0 += per) {
+            const int nr = std::min(per, r1 - p0), nt = nr * g, nw = (nt + 63) / 64;
+            const bool last = p0 + per >= r1;
+            out.pass.insert(out.pass.end(), {p0, nr, (int)last << 16, (int32_t)(out.wave.size() / 2)});
+            for (int w = 0; w < nw; ++w) {
+                int kmax = 0;
+                for (int t = w * 64; t < std::min(nt, w * 64 + 64); t += g)
+                    kmax = std::max(kmax, (S.rowlen[p0 + t / g] + g - 1) / g);
+                out.wave.insert(out.wave.end(), {(int32_t)off, kmax});
+                for (int k = 0; k < kmax; ++k)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int t = w * 64 + lane, r = p0 + t / g, e = k * g + t % g;
+                        const bool ok = t < nt && e < S.rowlen[r];
+                        const int32_t slot = ok ? S.slot(r, e) : -1;
+                        out.src.push_back(slot);
+                        out.cols.push_back(ok ? S.cols[slot] : 0);
+                    }
+                off += 64 * (int64_t)kmax;
+            }
+        }
+    }
+    out.nc = nc;
+    for (int a = 0; a < nc; ++a) out.rk = std::max(out.rk, L.rptr[a + 1] - L.rptr[a]);
+    out.ridx.assign((size_t)out.rk * nc, 0);
+    out.rw.assign((size_t)out.rk * nc, 0.0);
+    for (int a = 0; a < nc; ++a)
+        for (int p = L.rptr[a]; p < L.rptr[a + 1]; ++p) {
+            const size_t at = (size_t)(p - L.rptr[a]) * nc + a;
+            out.ridx[at] = L.ridx[p];
+            out.rw[at] = L.rw[p];
+        }
+}
+
+bool check_tail_layout(const TailLayout &T, int n, int threads, std::string &err) {
+    const int g = T.grp;
+    if (g < 1 || g > 64 || (g & (g - 1))) { err = "tail: bad lane group"; return false; }
+    int64_t off = 0;
+    size_t wv = 0;
+    for (size_t p = 0; p + 3 < T.pass.size(); p += 4) {
+        const int r0 = T.pass[p], nr = T.pass[p + 1];
+        const int nw = (nr * g + 63) / 64;
+        if (r0 < 0 || nr < 1 || r0 + nr > n || (int64_t)nr * g > threads || T.pass[p + 3] != (int)wv) {
+            err = "tail: bad pass";
+            return false;
+        }
+        for (int w = 0; w < nw; ++w, ++wv) {
+            if (2 * wv + 1 >= T.wave.size() || T.wave[2 * wv] != off || T.wave[2 * wv + 1] < 0) { err = "tail: bad wave"; return false; }
+            off += 64 * (int64_t)T.wave[2 * wv + 1];
+        }
+    }
+    if (2 * wv != T.wave.size()) { err = "tail: wave count"; return false; }
+    if (off != (int64_t)T.src.size() || T.cols.size() != T.src.size()) { err = "tail: record count"; return false; }
+    for (int32_t c : T.cols) if (c < 0 || c >= n) { err = "tail: record column"; return false; }
+    if (T.ridx.size() != (size_t)T.rk * T.nc || T.rw.size() != T.ridx.size()) { err = "tail: restriction size"; return false; }
+    for (int32_t i : T.ridx) if (i < 0 || i >= n) { err = "tail: restriction index"; return false; }
+    return true;
 }
 
 }  // namespace smg

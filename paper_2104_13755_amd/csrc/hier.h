@@ -76,13 +76,48 @@ struct LevelHost {
     // restriction R = P^T, CSR over permuted coarse rows
     std::vector<int32_t> rptr, ridx;
     std::vector<double> rw;
-    // Galerkin plan to the next level: T = A P, then A_next = P^T T
+    // the same R as sliced ELL: 64 coarse rows per slice, entry k of row a at
+    // rs_off[a / 64] + 64 k + a % 64 (padding: index of the row's first entry
+    // or 0, weight 0)
+    std::vector<int32_t> rs_off, rs_idx;
+    std::vector<double> rs_w;
+    // Galerkin plan to the next level: T = A P, then A_next = P^T T.  Each row
+    // of T and of A_next is accumulated in its own local slots (a row owner
+    // adds its contributions in a fixed order, so results are deterministic).
     std::vector<int32_t> tptr;       // n + 1
     std::vector<int32_t> plan1ptr;   // n + 1 (3 per source entry: diag + rowlen)
     std::vector<uint16_t> plan1;     // offset within the T row
+    int tmax = 0;                    // longest T row
     std::vector<int32_t> plan2ptr;   // n_next + 1
-    std::vector<int32_t> plan2;      // storage position in level l+1 (see `store`)
+    std::vector<uint16_t> plan2;     // local slot within the coarse row
+    std::vector<int32_t> optr;       // n_next + 1: local slots of each coarse row
+    std::vector<int32_t> opos;       // local slot -> storage position in level l+1 (see `store`)
+    int cmax = 0;                    // most local slots of a coarse row
 };
+
+// Record layout of one smoothed level for the one-workgroup tail kernel,
+// whose iterate lives in LDS.  Rows of a color are processed in passes of
+// `threads / grp` rows, each row by `grp` adjacent lanes (thread t of a pass:
+// row row0 + t / grp).  Each wavefront w of a pass reads its own `kmax` rounds
+// of records, record (k, lane) at wave offset + 64 k + lane, holding entry
+// k * grp + t % grp of the thread's row (padding: column 0, weight 0).  The
+// restriction into the next level is an ELL of width rk, entry k of coarse row
+// a at k * nc + a (padding: index 0, weight 0).
+struct TailLayout {
+    int grp = 1;
+    std::vector<int32_t> pass;    // 4 per pass: row0, nrows, (last of its color) << 16, first wave
+    std::vector<int32_t> wave;    // 2 per wavefront: record offset, rounds
+    std::vector<int32_t> src;     // record -> SELL slot of the level (-1 padding)
+    std::vector<int32_t> cols;    // record -> permuted column
+    int rk = 0, nc = 0;
+    std::vector<int32_t> ridx;    // rk * nc
+    std::vector<double> rw;
+};
+// threads: workgroup size of the tail kernel; nc: rows of the next level.
+void build_tail_layout(const LevelHost &L, int nc, int threads, TailLayout &out);
+// Bounds of every index the tail kernel derives from a layout of a level with
+// n rows (records, pass rows, restriction); false + message if one is out.
+bool check_tail_layout(const TailLayout &T, int n, int threads, std::string &err);
 
 struct HierHost {
     int nlev = 0;

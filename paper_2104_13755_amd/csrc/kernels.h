@@ -18,10 +18,10 @@ struct SellView {
     const T *diag;
 };
 
-struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (CSR)
+struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (sliced ELL, 64 rows)
     int n, nc;
     const int32_t *pc;
-    const int32_t *rptr, *ridx;
+    const int32_t *rs_off, *rs_idx;
 };
 
 // --- relaxation / residual / transfers (K right-hand sides, 1..4) ---
@@ -74,9 +74,55 @@ struct TailLevel {
     const int32_t *rptr, *ridx;   // restriction into the next level
     const T *rw;
 };
+
+// --- one-workgroup tail with every iterate in LDS ---
+// Levels first..nlev-1 of a cycle in one workgroup of kTailThreads threads:
+// x of every tail level and b of the coarsest live in LDS; matrices are read
+// as pass records (see TailLayout in hier.h); b and r of the smoothed tail
+// levels stay in global memory (b of the first level is the caller's).
+constexpr int kTailThreads = 1024;
+// one matrix entry of a pass record stream (column in the level's permuted numbering)
+template <typename T> struct TailRec;
+template <> struct alignas(8) TailRec<float> { int32_t col; float val; };
+template <> struct alignas(16) TailRec<double> { int32_t col, pad; double val; };
 template <typename T>
-hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
-                              const double *Ainv, int k, hipStream_t st);
+struct LdsLevel {
+    int n, lg_grp;                    // rows; log2 of the lanes per row
+    int pass0, npass;                 // this level's passes in the pass table
+    int wave0;                        // this level's first entry in the wavefront table
+    int nsum;                         // rows of all finer levels (LDS offsets)
+    const TailRec<T> *rec;            // pass records
+    const T *diag;
+    T *b, *r;                         // n x k, permuted order
+    T *x;                             // n x k; read and written for the first level only
+    const int32_t *pc;                // prolongation from the next level (SoA ELL-3)
+    const T *pw;
+    int rk, nc;                       // restriction into the next level: ELL rk x nc
+    const int32_t *ridx;
+    const T *rw;
+};
+// passes: 4 ints per pass (row0, nrows, last-of-color << 16, first wavefront);
+// waves: 2 ints per wavefront (record offset, rounds); lds_bytes from
+// tail_lds_bytes().
+template <typename T>
+hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves,
+                           int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
+                           size_t lds_bytes, hipStream_t st);
+// grant k_tail_lds<*, T> `bytes` of dynamic LDS
+template <typename T>
+hipError_t tail_lds_allow(size_t bytes);
+// LDS bytes of a tail from level `first`: pass and wavefront tables + x of
+// every tail level + b of the coarsest, rows padded to kp = (k == 3 ? 4 : k).
+inline size_t tail_lds_bytes(int npass, int nwave, int64_t rows_x, int n_coarsest, int k,
+                             size_t value_bytes) {
+    const int kp = k == 3 ? 4 : k;
+    const size_t tables = ((size_t)npass * 16 + (size_t)nwave * 8 + 15) / 16 * 16;
+    return tables + ((size_t)rows_x + (size_t)n_coarsest) * kp * value_bytes;
+}
+// rec64[i] = {cols[i], src[i] >= 0 ? vals[src[i]] : 0}, rec32 likewise from vals32
+hipError_t launch_gather_records(const int32_t *src, const int32_t *cols, int64_t n,
+                                 const double *vals, const float *vals32, TailRec<double> *rec64,
+                                 TailRec<float> *rec32, hipStream_t st);
 
 // --- batched solve: one workgroup per mesh, whole FP32-in-FP64 solve ---
 struct BatchMesh {
@@ -104,16 +150,20 @@ int batch_blocks_per_cu(int threads);
 // --- hierarchy values ---
 hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,
                                  double *vals, double *diag, int *flag, hipStream_t st);
-hipError_t launch_galerkin_t(int n, const int32_t *tptr, const int32_t *plan1ptr,
+// T = A P and A_{l+1} = P^T T, one thread per row accumulating in its own
+// LDS slots (tmax: longest T row; cmax: most local slots of a coarse row;
+// either at most kGalerkinMaxSlots).  Storage of level l+1 is overwritten
+// entry by entry (opos >= 0 -> vals[opos], else diag[-1 - opos]).
+constexpr int kGalerkinMaxSlots = 320;
+hipError_t launch_galerkin_t(int n, int tmax, const int32_t *tptr, const int32_t *plan1ptr,
                              const uint16_t *plan1, const int32_t *row_slice,
                              const int32_t *slice_row0, const int32_t *slice_off, int lpr,
                              const int32_t *rowlen, const int32_t *cols, const double *vals,
-                             const double *diag, const int32_t *pc, const double *pw,
-                             double *Tbuf, hipStream_t st);
-hipError_t launch_galerkin_c(int nc, const int32_t *plan2ptr, const int32_t *plan2,
+                             const double *diag, const double *pw, double *Tbuf, hipStream_t st);
+hipError_t launch_galerkin_c(int nc, int cmax, const int32_t *plan2ptr, const uint16_t *plan2,
                              const int32_t *rptr, const int32_t *ridx, const double *rw,
-                             const int32_t *tptr, const double *Tbuf, double *vals, double *diag,
-                             hipStream_t st);
+                             const int32_t *tptr, const double *Tbuf, const int32_t *optr,
+                             const int32_t *opos, double *vals, double *diag, hipStream_t st);
 
 // --- elementwise helpers ---
 template <typename T>

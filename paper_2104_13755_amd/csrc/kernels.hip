@@ -17,7 +17,6 @@ namespace smg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kTail = 1024;   // threads of the single-workgroup tail kernel
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of logical blocks so neighbouring slices share an L2.
@@ -156,20 +155,36 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
 // --------------------------------------------------------------- transfers
 // rc_a = sum_{i} R_ai r_i with R = P^T (gather; deterministic order)
 template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t *__restrict__ rptr,
-                                                     const int32_t *__restrict__ ridx,
+__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t *__restrict__ rs_off,
+                                                     const int32_t *__restrict__ rs_idx,
                                                      const T *__restrict__ rw,
                                                      const T *__restrict__ r, T *__restrict__ rc) {
+    constexpr int CH = 8;
     const int a = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (a >= nc) return;
+    const int s = a >> 6, lane = a & 63;
+    const int o0 = rs_off[s] + lane, w = (rs_off[s + 1] - rs_off[s]) >> 6;
     T acc[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = T(0);
-    for (int p = rptr[a]; p < rptr[a + 1]; ++p) {
-        const int i = ridx[p];
-        const T w = rw[p];
+    for (int k0 = 0; k0 < w; k0 += CH) {   // all loads of a chunk in flight; rounds past w weigh 0
+        int i[CH];
+        T wt[CH];
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += w * r[(size_t)i * K + q];
+        for (int u = 0; u < CH; ++u) {
+            const int at = o0 + 64 * min(k0 + u, w - 1);
+            i[u] = rs_idx[at];
+            wt[u] = k0 + u < w ? rw[at] : T(0);
+        }
+        T rv[CH][K];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) rv[u][q] = r[(size_t)i[u] * K + q];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] += wt[u] * rv[u][q];
     }
 #pragma unroll
     for (int q = 0; q < K; ++q) rc[(size_t)a * K + q] = acc[q];
@@ -276,6 +291,97 @@ __global__ __launch_bounds__(1024) void k_cholesky(double *__restrict__ A, int n
         const int i = t % n, c = t / n;
         if (i < c) A[(size_t)c * n + i] = 0.0;
     }
+}
+
+// Blocked right-looking Cholesky A = G G^T (column-major n x n, lower
+// triangle; upper triangle zeroed), one workgroup.  A panel of nb columns is
+// factored in LDS (ld = rows of the panel), written back, and the trailing
+// lower triangle receives the panel's rank-nb update in 2 x 2 register blocks.
+__global__ __launch_bounds__(1024) void k_cholesky_blocked(double *__restrict__ A, int n, int nbmax,
+                                                           int *__restrict__ flag) {
+    extern __shared__ double pan[];
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += nbmax) {
+        const int nb = min(nbmax, n - k0), m = n - k0;
+        for (int t = tid; t < m * nb; t += nt) {
+            const int i = t % m, c = t / m;
+            pan[c * m + i] = A[(size_t)(k0 + c) * n + k0 + i];
+        }
+        __syncthreads();
+        for (int j = 0; j < nb; ++j) {
+            if (tid == 0) {
+                const double d = pan[j * m + j];
+                if (!(d > 0.0)) { bad = 1; *flag = 1; }
+                else pan[j * m + j] = sqrt(d);
+            }
+            __syncthreads();
+            if (bad) return;
+            const double djj = pan[j * m + j];
+            for (int i = j + 1 + tid; i < m; i += nt) pan[j * m + i] /= djj;
+            __syncthreads();
+            const int w = nb - j - 1;
+            for (int t = tid; t < w * m; t += nt) {
+                const int c = j + 1 + t / m, i = t % m;
+                if (i >= c) pan[c * m + i] -= pan[j * m + i] * pan[j * m + c];
+            }
+            __syncthreads();
+        }
+        for (int t = tid; t < m * nb; t += nt) {
+            const int i = t % m, c = t / m;
+            if (i >= c) A[(size_t)(k0 + c) * n + k0 + i] = pan[c * m + i];
+        }
+        const int mt = m - nb;                       // trailing block rows/cols nb..m-1 of the panel frame
+        const int nbk = (mt + 1) / 2;                // 2 x 2 blocks per side
+        const int ntri = nbk * (nbk + 1) / 2;
+        for (int b = tid; b < ntri; b += nt) {
+            int bi = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+            while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+            while (bi * (bi + 1) / 2 > b) --bi;
+            const int bc = b - bi * (bi + 1) / 2;
+            const int i0 = nb + 2 * bi, c0 = nb + 2 * bc;
+            const bool i1ok = i0 + 1 < m, c1ok = c0 + 1 < m;
+            double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+            for (int q = 0; q < nb; ++q) {
+                const double li0 = pan[q * m + i0], li1 = i1ok ? pan[q * m + i0 + 1] : 0.0;
+                const double lc0 = pan[q * m + c0], lc1 = c1ok ? pan[q * m + c0 + 1] : 0.0;
+                s00 += li0 * lc0; s01 += li0 * lc1; s10 += li1 * lc0; s11 += li1 * lc1;
+            }
+            double *col0 = A + (size_t)(k0 + c0) * n + k0, *col1 = col0 + n;
+            col0[i0] -= s00;                                   // i0 >= c0 always
+            if (i1ok) col0[i0 + 1] -= s10;
+            if (c1ok && i0 >= c0 + 1) col1[i0] -= s01;
+            if (c1ok && i1ok) col1[i0 + 1] -= s11;             // i0 + 1 >= c0 + 1
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < n * n; t += nt) {
+        const int i = t % n, c = t / n;
+        if (i < c) A[(size_t)c * n + i] = 0.0;
+    }
+}
+
+// W = G^{-1} one column per wavefront: forward substitution G w = e_c in
+// column order (w_k /= G_kk, then w_i -= G_ik w_k below), w kept in LDS.
+__global__ __launch_bounds__(256) void k_tri_inverse_cols(const double *__restrict__ G, int n,
+                                                          double *__restrict__ W) {
+    extern __shared__ double wb[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + wv;
+    if (c >= n) return;
+    double *w = wb + (size_t)wv * n;
+    for (int i = lane; i < n; i += 64) w[i] = i == c ? 1.0 : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int k = c; k < n; ++k) {
+        const double wk = w[k] / G[(size_t)k * n + k];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane == 0) w[k] = wk;
+        for (int i = k + 1 + lane; i < n; i += 64) w[i] -= G[(size_t)k * n + i] * wk;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    for (int i = lane; i < n; i += 64) W[(size_t)c * n + i] = i >= c ? w[i] : 0.0;
 }
 
 // W = G^{-1} for the lower-triangular Cholesky factor G (column-major), one
@@ -602,13 +708,314 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
     }
 }
 
-template <int K, typename T>
-__global__ __launch_bounds__(kTail) void k_vcycle_tail(const TailLevel<T> *__restrict__ lv, int first,
-                                                       int nlev, int mu_pre, int mu_post,
-                                                       const double *__restrict__ Ainv) {
-    Team tm = single_team();
-    wg_vcycle<K, T>(tm, lv, first, nlev, mu_pre, mu_post, Ainv);
+// ------------------------------------------------------ LDS-resident tail
+// One workgroup runs Alg. "V-cycle" over the coarse end of the hierarchy
+// with the iterate x of every tail level (and b of the coarsest) in LDS, rows
+// padded to KP values.  Each relaxation pass issues all its independent loads
+// (records, diagonal, b) at once and gathers x from LDS, so a color costs one
+// memory round trip (mostly L2 hits) plus one workgroup barrier.  Pointers
+// read from the level descriptors are marked global explicitly (the compiler
+// cannot infer it) so loads need not wait on LDS traffic, and every load of a
+// chunk is unconditional (clamped index, masked value) so all are in flight.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p, size_t i) {
+    return ((const __attribute__((address_space(1))) T *)p)[i];
 }
+template <typename T>
+__device__ __forceinline__ void gst(T *p, size_t i, T v) {
+    ((__attribute__((address_space(1))) T *)p)[i] = v;
+}
+
+template <typename T, int K, int KP>
+__device__ __forceinline__ void lds_get(const T *xs, int c, T (&v)[K]) {
+    if constexpr (KP == 4 && sizeof(T) == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(xs + (size_t)c * 4);
+        const T t4[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] = t4[q];
+    } else if constexpr (KP == 4 && sizeof(T) == 8) {
+        const double2 a = *reinterpret_cast<const double2 *>(xs + (size_t)c * 4);
+        const double2 b = *reinterpret_cast<const double2 *>(xs + (size_t)c * 4 + 2);
+        const T t4[4] = {a.x, a.y, b.x, b.y};
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] = t4[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] = xs[(size_t)c * KP + q];
+    }
+}
+
+// acc += sum over this thread's records (rounds k < kmax, 64 apart) in
+// chunks of CH rounds; rounds past kmax re-read the last record with weight 0,
+// so nothing in a chunk is conditional
+// one record as a single 8- or 16-byte global load
+typedef int vint2 __attribute__((ext_vector_type(2)));
+typedef int vint4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ TailRec<float> rec_load(const TailRec<float> *p, size_t i) {
+    const vint2 v = gld(reinterpret_cast<const vint2 *>(p), i);
+    return TailRec<float>{v.x, __int_as_float(v.y)};
+}
+__device__ __forceinline__ TailRec<double> rec_load(const TailRec<double> *p, size_t i) {
+    const vint4 v = gld(reinterpret_cast<const vint4 *>(p), i);
+    return TailRec<double>{v.x, 0, __hiloint2double(v.w, v.z)};
+}
+
+template <int CH, int K, int KP, typename T>
+__device__ __forceinline__ void tail_gather_ch(const TailRec<T> *rp, int k0, int kmax, const T *xs,
+                                               T (&acc)[K]) {
+    TailRec<T> rr[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) rr[u] = rec_load(rp, (size_t)min(k0 + u, kmax - 1) * 64);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const T w = k0 + u < kmax ? rr[u].val : T(0);
+        T xv[K];
+        lds_get<T, K, KP>(xs, rr[u].col, xv);
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += w * xv[q];
+    }
+}
+// full chunks of 8 rounds, then one chunk of 2, 4, 6 or 8 for the rest
+template <int K, int KP, typename T>
+__device__ __forceinline__ void tail_gather(const TailRec<T> *rp, int kmax, const T *xs, T (&acc)[K]) {
+    int k0 = 0;
+    for (; k0 + 8 <= kmax; k0 += 8) tail_gather_ch<8, K, KP, T>(rp, k0, kmax, xs, acc);
+    const int rem = kmax - k0;
+    if (rem <= 0) return;
+    if (rem <= 2) tail_gather_ch<2, K, KP, T>(rp, k0, kmax, xs, acc);
+    else if (rem <= 4) tail_gather_ch<4, K, KP, T>(rp, k0, kmax, xs, acc);
+    else if (rem <= 6) tail_gather_ch<6, K, KP, T>(rp, k0, kmax, xs, acc);
+    else tail_gather_ch<8, K, KP, T>(rp, k0, kmax, xs, acc);
+}
+
+// one pass row: diagonal, b and the off-diagonal sum over the lane group
+// (the wavefront's record offset and rounds come from the LDS table)
+template <int K, int KP, typename T>
+__device__ __forceinline__ void tail_row(const LdsLevel<T> &L, const int2 *wv, int tid, int row, int G,
+                                         const T *xs, T &d, T (&bq)[K], T (&acc)[K]) {
+    const int2 W = wv[tid >> 6];
+    const int off = __builtin_amdgcn_readfirstlane(W.x), kmax = __builtin_amdgcn_readfirstlane(W.y);
+    d = gld(L.diag, row);
+#pragma unroll
+    for (int q = 0; q < K; ++q) { bq[q] = gld(L.b, (size_t)row * K + q); acc[q] = T(0); }
+    tail_gather<K, KP, T>(L.rec + off + (tid & 63), kmax, xs, acc);
+    for (int m = G >> 1; m > 0; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+}
+
+// Multicolor Gauss-Seidel on one tail level (App. A): passes in color order,
+// a barrier after the last pass of every color.
+template <int K, int KP, typename T>
+__device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, T *xs, int sweeps) {
+    const int tid = threadIdx.x, lg = L.lg_grp, G = 1 << lg;
+    const int g = tid >> lg, j = tid & (G - 1);
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int p = 0; p < L.npass; ++p) {
+            const int4 P = sp[p];
+            const int nta = P.y << lg;
+            if (tid < nta) {
+                const int row = P.x + g;
+                T d, bq[K], acc[K];
+                tail_row<K, KP, T>(L, swv + P.w, tid, row, G, xs, d, bq, acc);
+                if (j == 0)
+#pragma unroll
+                    for (int q = 0; q < K; ++q) xs[(size_t)row * KP + q] = (bq[q] - acc[q]) / d;
+            }
+            if (P.z >> 16) __syncthreads();
+        }
+}
+
+// r = b - A x on one tail level (r in global memory); no barrier inside
+template <int K, int KP, typename T>
+__device__ void tail_residual(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, const T *xs) {
+    const int tid = threadIdx.x, lg = L.lg_grp, G = 1 << lg;
+    const int g = tid >> lg, j = tid & (G - 1);
+    for (int p = 0; p < L.npass; ++p) {
+        const int4 P = sp[p];
+        const int nta = P.y << lg;
+        if (tid < nta) {
+            const int row = P.x + g;
+            T d, bq[K], acc[K];
+            tail_row<K, KP, T>(L, swv + P.w, tid, row, G, xs, d, bq, acc);
+            if (j == 0) {
+                T xv[K];
+                lds_get<T, K, KP>(xs, row, xv);
+#pragma unroll
+                for (int q = 0; q < K; ++q) gst(L.r, (size_t)row * K + q, bq[q] - (acc[q] + d * xv[q]));
+            }
+        }
+    }
+}
+
+// b_{l+1} = R r (R = P^T as ELL); into LDS (bl) for the coarsest level, else
+// into the next level's global b, whose x is then cleared in LDS
+template <int K, int KP, typename T>
+__device__ void tail_restrict(const LdsLevel<T> &L, T *bc_global, T *bl, T *xc) {
+    constexpr int CH = 8;
+    const int tid = threadIdx.x, nt = blockDim.x, nc = L.nc, rk = L.rk;
+    for (int a = tid; a < nc; a += nt) {
+        T acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = T(0);
+        for (int k0 = 0; k0 < rk; k0 += CH) {
+            int c[CH];
+            T w[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const size_t at = (size_t)min(k0 + u, rk - 1) * nc + a;
+                c[u] = gld(L.ridx, at);
+                w[u] = k0 + u < rk ? gld(L.rw, at) : T(0);
+            }
+            T rv[CH][K];
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+#pragma unroll
+                for (int q = 0; q < K; ++q) rv[u][q] = gld((const T *)L.r, (size_t)c[u] * K + q);
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+#pragma unroll
+                for (int q = 0; q < K; ++q) acc[q] += w[u] * rv[u][q];
+        }
+        if (bl) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) bl[(size_t)a * KP + q] = acc[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < K; ++q) gst(bc_global, (size_t)a * K + q, acc[q]);
+        }
+    }
+    if (!bl)
+        for (int t = tid; t < nc * KP; t += nt) xc[t] = T(0);
+}
+
+// coarsest: x = A_H^{-1} b in FP64 (A_H^{-1} column-major), 4 lanes per row
+template <int K, int KP, typename T>
+__device__ void tail_coarse(int n, const double *__restrict__ Ainv, const T *bl, T *xl) {
+    constexpr int CH = 8;
+    const int tid = threadIdx.x, nt = blockDim.x, j = tid & 3;
+    for (int ib = 0; ib < n; ib += nt / 4) {
+        const int i = ib + tid / 4;
+        const int ic = min(i, n - 1);
+        double acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = 0.0;
+        for (int j0 = j; j0 < n; j0 += 4 * CH) {
+            double a[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) a[u] = Ainv[(size_t)min(j0 + 4 * u, n - 1) * n + ic];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int jj = j0 + 4 * u;
+                if (jj < n) {
+                    T bv[K];
+                    lds_get<T, K, KP>(bl, jj, bv);
+#pragma unroll
+                    for (int q = 0; q < K; ++q) acc[q] += a[u] * (double)bv[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            acc[q] += __shfl_xor(acc[q], 1, 64);
+            acc[q] += __shfl_xor(acc[q], 2, 64);
+        }
+        if (i < n && j == 0)
+#pragma unroll
+            for (int q = 0; q < K; ++q) xl[(size_t)i * KP + q] = (T)acc[q];
+    }
+}
+
+// x_l += P_l x_{l+1}
+template <int K, int KP, typename T>
+__device__ void tail_prolong(const LdsLevel<T> &L, T *xs, const T *xc) {
+    const int tid = threadIdx.x, nt = blockDim.x, n = L.n;
+    for (int i = tid; i < n; i += nt) {
+        T acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = T(0);
+        int c[3];
+        T w[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) { c[m] = gld(L.pc, (size_t)m * n + i); w[m] = gld(L.pw, (size_t)m * n + i); }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            T xv[K];
+            lds_get<T, K, KP>(xc, c[m], xv);
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] += w[m] * xv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) xs[(size_t)i * KP + q] += acc[q];
+    }
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__restrict__ lv,
+                                                           const int4 *__restrict__ passes,
+                                                           const int2 *__restrict__ waves, int first,
+                                                           int nlev, int mu_pre, int mu_post,
+                                                           const double *__restrict__ Ainv) {
+    constexpr int KP = K == 3 ? 4 : K;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, nt = blockDim.x, last = nlev - 1;
+    const int pbeg = lv[first].pass0, pend = lv[last].pass0;
+    const int wbeg = lv[first].wave0, wend = lv[last].wave0;
+    int4 *sp = reinterpret_cast<int4 *>(smem);
+    int2 *swv = reinterpret_cast<int2 *>(smem + (size_t)(pend - pbeg) * sizeof(int4));
+    for (int i = tid; i < pend - pbeg; i += nt) {
+        int4 P = passes[pbeg + i];
+        P.w -= wbeg;   // wavefront index relative to the LDS copy
+        sp[i] = P;
+    }
+    for (int i = tid; i < wend - wbeg; i += nt) swv[i] = waves[wbeg + i];
+    const size_t tables = ((size_t)(pend - pbeg) * 16 + (size_t)(wend - wbeg) * 8 + 15) / 16 * 16;
+    T *xall = reinterpret_cast<T *>(smem + tables);
+    const int base = lv[first].nsum;
+    T *bl = xall + (size_t)(lv[last].nsum + lv[last].n - base) * KP;
+    {
+        const int n0 = lv[first].n;
+        const T *xg = lv[first].x;
+        for (int t = tid; t < n0 * K; t += nt) xall[(size_t)(t / K) * KP + t % K] = gld(xg, t);
+    }
+    __syncthreads();
+    for (int l = first; l < last; ++l) {
+        const LdsLevel<T> L = lv[l];
+        T *xs = xall + (size_t)(L.nsum - base) * KP;
+        T *xc = xall + (size_t)(L.nsum + L.n - base) * KP;
+        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_pre);
+        tail_residual<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs);
+        __syncthreads();
+        tail_restrict<K, KP, T>(L, lv[l + 1].b, l + 1 == last ? bl : nullptr, xc);
+        __syncthreads();
+    }
+    tail_coarse<K, KP, T>(lv[last].n, Ainv, bl, xall + (size_t)(lv[last].nsum - base) * KP);
+    __syncthreads();
+    for (int l = last - 1; l >= first; --l) {
+        const LdsLevel<T> L = lv[l];
+        T *xs = xall + (size_t)(L.nsum - base) * KP;
+        tail_prolong<K, KP, T>(L, xs, xall + (size_t)(L.nsum + L.n - base) * KP);
+        __syncthreads();
+        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_post);
+    }
+    {
+        const int n0 = lv[first].n;
+        T *xg = lv[first].x;
+        for (int t = tid; t < n0 * K; t += nt) gst(xg, t, xall[(size_t)(t / K) * KP + t % K]);
+    }
+}
+
+__global__ void k_gather_records(const int32_t *__restrict__ src, const int32_t *__restrict__ cols,
+                                 int64_t n, const double *__restrict__ vals,
+                                 const float *__restrict__ vals32, TailRec<double> *__restrict__ rec64,
+                                 TailRec<float> *__restrict__ rec32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t s = src[i], c = cols[i];
+    rec64[i] = TailRec<double>{c, 0, s >= 0 ? vals[s] : 0.0};
+    rec32[i] = TailRec<float>{c, s >= 0 ? vals32[s] : 0.0f};
+}
+
 
 // ---------------------------------------------------------- batched solve
 // A team of workgroups per mesh runs Alg. "Galerkin Surface Multigrid
@@ -736,53 +1143,70 @@ __global__ __launch_bounds__(kBlock) void k_scatter_values(const double *__restr
     else diag[-1 - s] = v;
 }
 
-// T = A_l P_l, one thread per permuted fine row (owner of its T row).
-__global__ __launch_bounds__(kBlock) void k_galerkin_t(
+// T = A P, one thread per permuted fine row (owner of its T row): the row is
+// accumulated in the thread's own LDS slots (slot k of thread j at k * bs + j)
+// in a fixed order (diagonal term, then the off-diagonal entries), then
+// written out contiguously.
+__global__ __launch_bounds__(64) void k_galerkin_t(
     int n, const int32_t *__restrict__ tptr, const int32_t *__restrict__ plan1ptr,
     const uint16_t *__restrict__ plan1, const int32_t *__restrict__ row_slice,
     const int32_t *__restrict__ slice_row0, const int32_t *__restrict__ slice_off, int lpr,
     const int32_t *__restrict__ rowlen, const int32_t *__restrict__ cols,
     const double *__restrict__ vals, const double *__restrict__ diag,
-    const int32_t *__restrict__ pc, const double *__restrict__ pw, double *__restrict__ Tb) {
-    const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const double *__restrict__ pw, double *__restrict__ Tb) {
+    extern __shared__ double acc_t[];
+    const int bs = blockDim.x, j = threadIdx.x;
+    const int r = blockIdx.x * bs + j;
     if (r >= n) return;
-    const int t0 = tptr[r], t1 = tptr[r + 1];
-    for (int t = t0; t < t1; ++t) Tb[t] = 0.0;
+    double *acc = acc_t + j;
+    const int t0 = tptr[r], len = tptr[r + 1] - t0;
+    for (int k = 0; k < len; ++k) acc[k * bs] = 0.0;
     const uint16_t *pl = plan1 + plan1ptr[r];
     const double d = diag[r];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) Tb[t0 + pl[m]] += d * pw[(size_t)m * n + r];
+    for (int m = 0; m < 3; ++m) acc[pl[m] * bs] += d * pw[(size_t)m * n + r];
     const int s = row_slice[r];
     const int base = slice_off[s] + (r - slice_row0[s]) * lpr;
-    const int len = rowlen[r];
-    for (int e = 0; e < len; ++e) {
+    const int rl = rowlen[r];
+#pragma unroll 4
+    for (int e = 0; e < rl; ++e) {
         const int slot = base + (e / lpr) * 64 + (e % lpr);
         const int c = cols[slot];
         const double a = vals[slot];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) Tb[t0 + pl[3 * (e + 1) + m]] += a * pw[(size_t)m * n + c];
+        for (int m = 0; m < 3; ++m) acc[pl[3 * (e + 1) + m] * bs] += a * pw[(size_t)m * n + c];
     }
+    for (int k = 0; k < len; ++k) Tb[t0 + k] = acc[k * bs];
 }
 
-// A_{l+1} = P^T T, one thread per permuted coarse row (owner of its entries).
-// Output storage must be zero on entry; pos >= 0 -> vals[pos], else diag.
-__global__ __launch_bounds__(kBlock) void k_galerkin_c(
-    int nc, const int32_t *__restrict__ plan2ptr, const int32_t *__restrict__ plan2,
+// A_{l+1} = P^T T, one thread per permuted coarse row: contributions w T_rb
+// in (R entry, T entry) order into the row's local LDS slots, then each slot
+// stored to its position in level l+1.
+__global__ __launch_bounds__(64) void k_galerkin_c(
+    int nc, const int32_t *__restrict__ plan2ptr, const uint16_t *__restrict__ plan2,
     const int32_t *__restrict__ rptr, const int32_t *__restrict__ ridx,
     const double *__restrict__ rw, const int32_t *__restrict__ tptr,
-    const double *__restrict__ Tb, double *__restrict__ vals, double *__restrict__ diag) {
-    const int a = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const double *__restrict__ Tb, const int32_t *__restrict__ optr,
+    const int32_t *__restrict__ opos, double *__restrict__ vals, double *__restrict__ diag) {
+    extern __shared__ double acc_c[];
+    const int bs = blockDim.x, j = threadIdx.x;
+    const int a = blockIdx.x * bs + j;
     if (a >= nc) return;
+    double *acc = acc_c + j;
+    const int o0 = optr[a], len = optr[a + 1] - o0;
+    for (int k = 0; k < len; ++k) acc[k * bs] = 0.0;
     int idx = plan2ptr[a];
     for (int p = rptr[a]; p < rptr[a + 1]; ++p) {
         const int r = ridx[p];
         const double w = rw[p];
-        for (int t = tptr[r]; t < tptr[r + 1]; ++t) {
-            const int32_t pos = plan2[idx++];
-            const double v = w * Tb[t];
-            if (pos >= 0) vals[pos] += v;
-            else diag[-1 - pos] += v;
-        }
+        const int t1 = tptr[r + 1];
+#pragma unroll 4
+        for (int t = tptr[r]; t < t1; ++t) acc[plan2[idx++] * bs] += w * Tb[t];
+    }
+    for (int k = 0; k < len; ++k) {
+        const int32_t pos = opos[o0 + k];
+        if (pos >= 0) vals[pos] = acc[k * bs];
+        else diag[-1 - pos] = acc[k * bs];
     }
 }
 
@@ -988,7 +1412,7 @@ template <typename T>
 hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc, int k,
                            hipStream_t st) {
     if (P.nc <= 0) return hipSuccess;
-    SMG_K_SWITCH(k, (k_restrict<KK, T><<<nblocks(P.nc), kBlock, 0, st>>>(P.nc, P.rptr, P.ridx, rw, r, rc)));
+    SMG_K_SWITCH(k, (k_restrict<KK, T><<<nblocks(P.nc), kBlock, 0, st>>>(P.nc, P.rs_off, P.rs_idx, rw, r, rc)));
     return hipGetLastError();
 }
 
@@ -1016,7 +1440,17 @@ hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double 
 }
 
 hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st) {
-    k_cholesky<<<1, 1024, 0, st>>>(A, n, flag);
+    if (n <= 0) return hipSuccess;
+    int nb = 16;   // panel width: the panel (n x nb doubles) must fit 128 KB of LDS
+    while (nb > 1 && (size_t)n * nb * sizeof(double) > 128 * 1024) nb >>= 1;
+    const size_t lds = (size_t)n * nb * sizeof(double);
+    if (lds > 128 * 1024) {   // very large coarsest level: unblocked, in global memory
+        k_cholesky<<<1, 1024, 0, st>>>(A, n, flag);
+        return hipGetLastError();
+    }
+    hipError_t e = hipFuncSetAttribute((const void *)k_cholesky_blocked, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_cholesky_blocked<<<1, 1024, lds, st>>>(A, n, nb, flag);
     return hipGetLastError();
 }
 
@@ -1030,15 +1464,45 @@ hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x,
 
 hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_tri_inverse<<<1, 1024, 0, st>>>(G, n, W);
+    const size_t lds = (size_t)4 * n * sizeof(double);
+    if (lds <= 128 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_tri_inverse_cols, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        k_tri_inverse_cols<<<(n + 3) / 4, 256, lds, st>>>(G, n, W);
+    } else {
+        k_tri_inverse<<<1, 1024, 0, st>>>(G, n, W);
+    }
     k_inverse_product<<<nblocks((int64_t)n * n), kBlock, 0, st>>>(W, n, Ainv);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_vcycle_tail(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
-                              const double *Ainv, int k, hipStream_t st) {
-    SMG_K_SWITCH(k, (k_vcycle_tail<KK, T><<<1, kTail, 0, st>>>(lv, first, nlev, mu_pre, mu_post, Ainv)));
+hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves,
+                           int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
+                           size_t lds_bytes, hipStream_t st) {
+    SMG_K_SWITCH(k, (k_tail_lds<KK, T><<<1, kTailThreads, lds_bytes, st>>>(
+                        lv, reinterpret_cast<const int4 *>(passes), reinterpret_cast<const int2 *>(waves),
+                        first, nlev, mu_pre, mu_post, Ainv)));
+    return hipGetLastError();
+}
+
+// Dynamic LDS above the default limit must be granted per kernel once.
+template <typename T>
+hipError_t tail_lds_allow(size_t bytes) {
+    hipError_t e = hipSuccess;
+    for (const void *f : {(const void *)k_tail_lds<1, T>, (const void *)k_tail_lds<2, T>,
+                          (const void *)k_tail_lds<3, T>, (const void *)k_tail_lds<4, T>})
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return e;
+}
+template hipError_t tail_lds_allow<double>(size_t);
+template hipError_t tail_lds_allow<float>(size_t);
+
+hipError_t launch_gather_records(const int32_t *src, const int32_t *cols, int64_t n,
+                                 const double *vals, const float *vals32, TailRec<double> *rec64,
+                                 TailRec<float> *rec32, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_gather_records<<<nblocks(n), kBlock, 0, st>>>(src, cols, n, vals, vals32, rec64, rec32);
     return hipGetLastError();
 }
 
@@ -1067,25 +1531,41 @@ hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_galerkin_t(int n, const int32_t *tptr, const int32_t *plan1ptr,
+// threads per block so that every thread has `slots` doubles of LDS
+static int galerkin_block(int slots) {
+    int bs = 64;
+    while (bs > 1 && (size_t)bs * slots * sizeof(double) > 160 * 1024) bs >>= 1;
+    return bs;
+}
+
+hipError_t launch_galerkin_t(int n, int tmax, const int32_t *tptr, const int32_t *plan1ptr,
                              const uint16_t *plan1, const int32_t *row_slice,
                              const int32_t *slice_row0, const int32_t *slice_off, int lpr,
                              const int32_t *rowlen, const int32_t *cols, const double *vals,
-                             const double *diag, const int32_t *pc, const double *pw,
-                             double *Tbuf, hipStream_t st) {
+                             const double *diag, const double *pw, double *Tbuf, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_galerkin_t<<<nblocks(n), kBlock, 0, st>>>(n, tptr, plan1ptr, plan1, row_slice, slice_row0,
-                                                slice_off, lpr, rowlen, cols, vals, diag, pc, pw, Tbuf);
+    const int slots = tmax > 0 ? tmax : 1, bs = galerkin_block(slots);
+    const size_t lds = (size_t)bs * slots * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)k_galerkin_t, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_galerkin_t<<<(n + bs - 1) / bs, bs, lds, st>>>(n, tptr, plan1ptr, plan1, row_slice, slice_row0,
+                                                     slice_off, lpr, rowlen, cols, vals, diag, pw, Tbuf);
     return hipGetLastError();
 }
 
-hipError_t launch_galerkin_c(int nc, const int32_t *plan2ptr, const int32_t *plan2,
+hipError_t launch_galerkin_c(int nc, int cmax, const int32_t *plan2ptr, const uint16_t *plan2,
                              const int32_t *rptr, const int32_t *ridx, const double *rw,
-                             const int32_t *tptr, const double *Tbuf, double *vals, double *diag,
-                             hipStream_t st) {
+                             const int32_t *tptr, const double *Tbuf, const int32_t *optr,
+                             const int32_t *opos, double *vals, double *diag, hipStream_t st) {
     if (nc <= 0) return hipSuccess;
-    k_galerkin_c<<<nblocks(nc), kBlock, 0, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw, tptr, Tbuf,
-                                                 vals, diag);
+    const int slots = cmax > 0 ? cmax : 1, bs = galerkin_block(slots);
+    const size_t lds = (size_t)bs * slots * sizeof(double);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)k_galerkin_c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_galerkin_c<<<(nc + bs - 1) / bs, bs, lds, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw, tptr, Tbuf,
+                                                      optr, opos, vals, diag);
     return hipGetLastError();
 }
 
@@ -1183,10 +1663,10 @@ template hipError_t launch_coarse_solve<double, double>(const double *, int, con
                                                         double *, int, hipStream_t);
 template hipError_t launch_coarse_solve<float, float>(const double *, int, const float *, float *,
                                                       int, hipStream_t);
-template hipError_t launch_vcycle_tail<double>(const TailLevel<double> *, int, int, int, int,
-                                               const double *, int, hipStream_t);
-template hipError_t launch_vcycle_tail<float>(const TailLevel<float> *, int, int, int, int,
-                                              const double *, int, hipStream_t);
+template hipError_t launch_tail_lds<double>(const LdsLevel<double> *, const int32_t *, const int32_t *,
+                                            int, int, int, int, const double *, int, size_t, hipStream_t);
+template hipError_t launch_tail_lds<float>(const LdsLevel<float> *, const int32_t *, const int32_t *,
+                                           int, int, int, int, const double *, int, size_t, hipStream_t);
 template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
 template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);

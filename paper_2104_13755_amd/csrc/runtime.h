@@ -33,11 +33,23 @@ struct DevLevel {
     // and A_H^{-1} (dense_inv), all column-major
     double *dense = nullptr, *dense_a = nullptr, *dense_w = nullptr, *dense_inv = nullptr;
     // transfers to the next level and the Galerkin plan
-    int32_t *pc = nullptr, *rptr = nullptr, *ridx = nullptr;
+    int32_t *pc = nullptr, *rptr = nullptr, *ridx = nullptr, *rs_off = nullptr, *rs_idx = nullptr;
+    double *rs_w = nullptr;
+    float *rs_w32 = nullptr;
     double *pw = nullptr, *rw = nullptr;
     float *pw32 = nullptr, *rw32 = nullptr;
-    int32_t *tptr = nullptr, *plan1ptr = nullptr, *plan2ptr = nullptr, *plan2 = nullptr;
-    uint16_t *plan1 = nullptr;
+    int32_t *tptr = nullptr, *plan1ptr = nullptr, *plan2ptr = nullptr, *optr = nullptr, *opos = nullptr;
+    uint16_t *plan1 = nullptr, *plan2 = nullptr;
+    int tmax = 0, cmax = 0;           // longest T row, most local slots of a coarse row
+    // LDS-tail records (levels small enough for the one-workgroup tail)
+    bool tl = false;
+    int tl_lg = 0, tl_npass = 0, tl_pass0 = 0, tl_nwave = 0, tl_wave0 = 0, tl_rk = 0;
+    int64_t tl_nrec = 0;
+    int32_t *tl_src = nullptr, *tl_cols = nullptr, *tl_ridx = nullptr;
+    smg::TailRec<double> *tl_rec = nullptr;
+    smg::TailRec<float> *tl_rec32 = nullptr;
+    double *tl_rw = nullptr;
+    float *tl_rw32 = nullptr;
     // work vectors, n x 4 (permuted order)
     double *x = nullptr, *b = nullptr, *r = nullptr;
     float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
@@ -63,9 +75,14 @@ smg_status fail(smg_status st, const std::string &msg);
 
 struct smg_solver_s {
     int device = 0, nlev = 0, mu_pre = 2, mu_post = 2;
-    int tail_first = 1 << 30;      // first level run by the single-workgroup tail kernel
-    smg::TailLevel<double> *tail64 = nullptr;   // device descriptors, one per level
-    smg::TailLevel<float> *tail32 = nullptr;
+    // first level run by the one-workgroup LDS tail, per precision (0 FP64,
+    // 1 FP32) and right-hand-side count k (index k); nlev - 1 = no tail
+    int tail_first[2][5] = {};
+    smg::LdsLevel<double> *lds64 = nullptr;   // device descriptors, one per level
+    smg::LdsLevel<float> *lds32 = nullptr;
+    int32_t *tpass = nullptr;                  // pass table of all tail levels
+    int32_t *twave = nullptr;                  // wavefront table of all tail levels
+    std::vector<size_t> tail_lds[2][5];        // LDS bytes of a tail from level l
     bool values_set = false;
     std::vector<smg::DevLevel> lev;
     smg::MeshDev mesh;
