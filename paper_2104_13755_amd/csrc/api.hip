@@ -325,6 +325,7 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
             CHK(dupload(&D.ridx, L.ridx, S->owned));
             CHK(dupload(&D.rw, L.rw, S->owned));
             CHK(dupload(&D.rw32, rw32, S->owned));
+            D.rs_lanes = L.rs_lanes;
             CHK(dupload(&D.rs_off, L.rs_off, S->owned));
             CHK(dupload(&D.rs_idx, L.rs_idx, S->owned));
             CHK(dupload(&D.rs_w, L.rs_w, S->owned));
@@ -648,7 +649,7 @@ template <typename T> static const LdsLevel<T> *tail_desc(const smg_solver_s *s)
 template <> const LdsLevel<double> *tail_desc<double>(const smg_solver_s *s) { return s->lds64; }
 template <> const LdsLevel<float> *tail_desc<float>(const smg_solver_s *s) { return s->lds32; }
 static TransferView transfer_view(const DevLevel &D, const DevLevel &C) {
-    return {D.n, C.n, D.pc, D.rs_off, D.rs_idx};
+    return {D.n, C.n, D.rs_lanes, D.pc, D.rs_off, D.rs_idx};
 }
 template <typename T> static T *xbuf(DevLevel &D);
 template <> double *xbuf<double>(DevLevel &D) { return D.x; }
@@ -711,8 +712,8 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st) {
     const TransferView P = transfer_view(D, C);
     CHK(smooth_level<T>(s, l, k, s->mu_pre, st));                  // pre-relaxation
     CHK(residual_level<T>(s, l, k, false, st));                    // r = b - A x'
-    HIPCHK(launch_restrict<T>(P, rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st));   // P^T r
-    if (!C.coarsest) HIPCHK(launch_fill<T>(xbuf<T>(C), T(0), (int64_t)C.n * k, st));
+    // P^T r; the coarse iterate starts from zero
+    HIPCHK(launch_restrict<T>(P, rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st, C.coarsest ? nullptr : xbuf<T>(C)));
     CHK(vcycle_from<T>(s, l + 1, k, st));                           // coarse correction
     HIPCHK(launch_prolong_add<T>(P, pwbuf<T>(D), xbuf<T>(C), xbuf<T>(D), k, st));  // x' + P c
     CHK(smooth_level<T>(s, l, k, s->mu_post, st));                 // post-relaxation
@@ -834,8 +835,8 @@ smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st) 
     if (precision == SMG_FP64) {
         CHK(vcycle_from<double>(s, 0, k, st));
     } else {
+        // x32 is zero here: cleared at the start of the solve and by every ir_up
         HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
-        HIPCHK(launch_fill<float>(D.x32, 0.0f, (int64_t)D.n * k, st));
         CHK(vcycle_from<float>(s, 0, k, st));
         HIPCHK(launch_ir_up(D.x32, s->norms, D.x, D.n, k, st));
     }
@@ -873,6 +874,7 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
     HIPCHK(launch_check_finite(d_b, (int64_t)D.n * k, s->flag, st));
     HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
     HIPCHK(launch_fill<double>(D.x, 0.0, (int64_t)D.n * k, st));
+    HIPCHK(launch_fill<float>(D.x32, 0.0f, (int64_t)D.n * k, st));
     // r = b for x0 = 0 (FP32_IR needs r and its max-norm in s->norms)
     int nblk = 0;
     HIPCHK(hipMemcpyAsync(D.r, D.b, (size_t)D.n * k * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -242,22 +242,23 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
                 }
         }
         {
-            const int ns = (nc + 63) / 64;
+            const int LR = L.rs_lanes, rps = 64 / LR, ns = (nc + rps - 1) / rps;
             L.rs_off.assign(ns + 1, 0);
             for (int s = 0; s < ns; ++s) {
                 int wmax = 0;
-                for (int a = s * 64; a < std::min(nc, s * 64 + 64); ++a) wmax = std::max(wmax, L.rptr[a + 1] - L.rptr[a]);
+                for (int a = s * rps; a < std::min(nc, s * rps + rps); ++a)
+                    wmax = std::max(wmax, (L.rptr[a + 1] - L.rptr[a] + LR - 1) / LR);
                 L.rs_off[s + 1] = L.rs_off[s] + 64 * wmax;
             }
             L.rs_idx.assign(L.rs_off[ns], 0);
             L.rs_w.assign(L.rs_off[ns], 0.0);
             for (int a = 0; a < nc; ++a) {
-                const int s = a / 64, lane = a % 64, w = (L.rs_off[s + 1] - L.rs_off[s]) / 64;
+                const int s = a / rps, g = a % rps, w = (L.rs_off[s + 1] - L.rs_off[s]) / 64;
                 const int len = L.rptr[a + 1] - L.rptr[a];
-                for (int k = 0; k < w; ++k) {
-                    const size_t at = (size_t)L.rs_off[s] + 64 * k + lane;
-                    L.rs_idx[at] = len ? L.ridx[L.rptr[a] + std::min(k, len - 1)] : 0;
-                    L.rs_w[at] = k < len ? L.rw[L.rptr[a] + k] : 0.0;
+                for (int e = 0; e < w * LR; ++e) {
+                    const size_t at = (size_t)L.rs_off[s] + 64 * (e / LR) + g * LR + e % LR;
+                    L.rs_idx[at] = len ? L.ridx[L.rptr[a] + std::min(e, len - 1)] : 0;
+                    L.rs_w[at] = e < len ? L.rw[L.rptr[a] + e] : 0.0;
                 }
             }
         }

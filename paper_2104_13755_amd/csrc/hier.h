@@ -76,9 +76,11 @@ struct LevelHost {
     // restriction R = P^T, CSR over permuted coarse rows
     std::vector<int32_t> rptr, ridx;
     std::vector<double> rw;
-    // the same R as sliced ELL: 64 coarse rows per slice, entry k of row a at
-    // rs_off[a / 64] + 64 k + a % 64 (padding: index of the row's first entry
-    // or 0, weight 0)
+    // the same R as sliced ELL with rs_lanes lanes per coarse row: 64 /
+    // rs_lanes rows per slice, entry e of row a (slice s, g = a % rows per
+    // slice) at rs_off[s] + 64 (e / rs_lanes) + g rs_lanes + e % rs_lanes
+    // (padding: index of the row's first entry or 0, weight 0)
+    int rs_lanes = 4;
     std::vector<int32_t> rs_off, rs_idx;
     std::vector<double> rs_w;
     // Galerkin plan to the next level: T = A P, then A_next = P^T T.  Each row

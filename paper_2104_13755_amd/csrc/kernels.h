@@ -18,8 +18,8 @@ struct SellView {
     const T *diag;
 };
 
-struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (sliced ELL, 64 rows)
-    int n, nc;
+struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (sliced ELL, rs_lanes lanes per row)
+    int n, nc, rs_lanes;
     const int32_t *pc;
     const int32_t *rs_off, *rs_idx;
 };
@@ -37,9 +37,10 @@ template <typename T>
 hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const T *x, T *r,
                            int k, double *partial, int *nblk, hipStream_t st,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// rc = R r; xc (optional): cleared alongside (the next level's iterate)
 template <typename T>
 hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc, int k,
-                           hipStream_t st);
+                           hipStream_t st, T *xc = nullptr);
 template <typename T>
 hipError_t launch_prolong_add(const TransferView &P, const T *pw, const T *e, T *x, int k,
                               hipStream_t st);
@@ -178,7 +179,8 @@ hipError_t launch_check_finite(const double *v, int64_t n, int *flag, hipStream_
 // FP64 iterative-refinement glue
 hipError_t launch_ir_down(const double *r64, const double *norms, float *r32, int n, int k,
                           hipStream_t st);
-hipError_t launch_ir_up(const float *d32, const double *norms, double *x64, int n, int k,
+// x64 += s d32 (s = max|r| per column), then d32 = 0 for the next cycle
+hipError_t launch_ir_up(float *d32, const double *norms, double *x64, int n, int k,
                         hipStream_t st);
 
 // --- assembly and adjoint helpers ---

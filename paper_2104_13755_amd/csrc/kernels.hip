@@ -39,27 +39,43 @@ __device__ __forceinline__ T wave_max(T v) {
 
 // ---------------------------------------------------------------- relaxation
 // Sum of one row's off-diagonal products over the lpr lanes of its group.
+// Rounds are taken in chunks whose loads are all issued before any is used:
+// full chunks of 8, then one chunk of 2, 4 or 8 for the rest (a round past w
+// re-reads the last one with weight 0), so a row costs one matrix round trip
+// and one gather round trip per chunk.  Products are added in round order.
+template <int CH, int K, typename T>
+__device__ __forceinline__ void gather_chunk(int o, int e, int w, const int32_t *__restrict__ cols,
+                                             const T *__restrict__ vals, const T *__restrict__ x,
+                                             T (&acc)[K]) {
+    int c[CH];
+    T a[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+        const int at = o + 64 * min(e + u, w - 1);
+        c[u] = cols[at];
+        a[u] = e + u < w ? vals[at] : T(0);
+    }
+    T xv[CH][K];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int q = 0; q < K; ++q) xv[u][q] = x[(size_t)c[u] * K + q];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += a[u] * xv[u][q];
+}
 template <int K, typename T>
 __device__ __forceinline__ void row_gather(int o, int w, int lpr, const int32_t *__restrict__ cols,
                                            const T *__restrict__ vals, const T *__restrict__ x,
                                            T (&acc)[K]) {
     int e = 0;
-    for (; e + 4 <= w; e += 4) {          // four independent gathers in flight
-        int c[4];
-        T a[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { c[u] = cols[o + u * 64]; a[u] = vals[o + u * 64]; }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] += a[u] * x[(size_t)c[u] * K + q];
-        o += 4 * 64;
-    }
-    for (; e < w; ++e, o += 64) {
-        const int c = cols[o];
-        const T a = vals[o];
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)c * K + q];
+    for (; e + 8 <= w; e += 8) gather_chunk<8, K, T>(o, e, w, cols, vals, x, acc);
+    const int rem = w - e;
+    if (rem > 0) {
+        if (rem <= 2) gather_chunk<2, K, T>(o, e, w, cols, vals, x, acc);
+        else if (rem <= 4) gather_chunk<4, K, T>(o, e, w, cols, vals, x, acc);
+        else gather_chunk<8, K, T>(o, e, w, cols, vals, x, acc);
     }
     for (int m = lpr >> 1; m > 0; m >>= 1)
 #pragma unroll
@@ -83,14 +99,14 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end, int
     if (row >= slice_row0[s + 1]) return;   // whole lane groups leave together
     const int o0 = slice_off[s];
     const int w = (slice_off[s + 1] - o0) >> 6;
-    T acc[K];
+    const T d = diag[row];   // issued with the matrix loads, used after the gather
+    T bq[K], acc[K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = T(0);
+    for (int q = 0; q < K; ++q) { bq[q] = b[(size_t)row * K + q]; acc[q] = T(0); }
     row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
     if ((lane & (lpr - 1)) == 0) {
-        const T d = diag[row];
 #pragma unroll
-        for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (b[(size_t)row * K + q] - acc[q]) / d;
+        for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (bq[q] - acc[q]) / d;
     }
 }
 
@@ -117,15 +133,19 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
         if (row < slice_row0[s + 1]) {
             const int o0 = slice_off[s];
             const int w = (slice_off[s + 1] - o0) >> 6;
-            T acc[K];
+            const T d = diag[row];
+            T bq[K], xo[K], acc[K];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = T(0);
+            for (int q = 0; q < K; ++q) {
+                bq[q] = b[(size_t)row * K + q];
+                xo[q] = x[(size_t)row * K + q];
+                acc[q] = T(0);
+            }
             row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
             if ((lane & (lpr - 1)) == 0) {
-                const T d = diag[row];
 #pragma unroll
                 for (int q = 0; q < K; ++q) {
-                    const T rv = b[(size_t)row * K + q] - (acc[q] + d * x[(size_t)row * K + q]);
+                    const T rv = bq[q] - (acc[q] + d * xo[q]);
                     r[(size_t)row * K + q] = rv;
                     if (NORM) { sq[q] = (double)rv * (double)rv; mx[q] = fabs((double)rv); }
                 }
@@ -155,14 +175,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
 // --------------------------------------------------------------- transfers
 // rc_a = sum_{i} R_ai r_i with R = P^T (gather; deterministic order)
 template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t *__restrict__ rs_off,
+__global__ __launch_bounds__(kBlock) void k_restrict(int nc, int lr, const int32_t *__restrict__ rs_off,
                                                      const int32_t *__restrict__ rs_idx,
                                                      const T *__restrict__ rw,
-                                                     const T *__restrict__ r, T *__restrict__ rc) {
+                                                     const T *__restrict__ r, T *__restrict__ rc,
+                                                     T *__restrict__ xc) {
     constexpr int CH = 8;
-    const int a = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (a >= nc) return;
-    const int s = a >> 6, lane = a & 63;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int s = t >> 6, lane = t & 63, rps = 64 / lr;
+    if (s * rps >= nc) return;   // whole wavefronts leave together
+    const int a = s * rps + lane / lr, j = lane & (lr - 1);
     const int o0 = rs_off[s] + lane, w = (rs_off[s + 1] - rs_off[s]) >> 6;
     T acc[K];
 #pragma unroll
@@ -186,8 +208,16 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, const int32_t *__re
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] += wt[u] * rv[u][q];
     }
+    for (int m = lr >> 1; m > 0; m >>= 1)
 #pragma unroll
-    for (int q = 0; q < K; ++q) rc[(size_t)a * K + q] = acc[q];
+        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+    if (a < nc && j == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            rc[(size_t)a * K + q] = acc[q];
+            if (xc) xc[(size_t)a * K + q] = T(0);
+        }
+    }
 }
 
 // x_i += sum_m P_im e_{c_im}
@@ -1252,7 +1282,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_down(const double *__restrict__ r
     const double s = norms[k + q];
     r32[t] = (float)(s > 0.0 ? r64[t] / s : 0.0);
 }
-__global__ __launch_bounds__(kBlock) void k_ir_up(const float *__restrict__ d32,
+__global__ __launch_bounds__(kBlock) void k_ir_up(float *__restrict__ d32,
                                                   const double *__restrict__ norms,
                                                   double *__restrict__ x64, int n, int k) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1260,6 +1290,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_up(const float *__restrict__ d32,
     const int q = (int)(t % k);
     const double s = norms[k + q];
     x64[t] += (s > 0.0 ? s : 0.0) * (double)d32[t];
+    d32[t] = 0.0f;
 }
 
 // ----------------------------------------------------------- assembly (K6)
@@ -1396,9 +1427,7 @@ hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const 
                                                    ns, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
                                                    b, x, r, (double *)nullptr)));
         }
-        return hipGetLastError();
-    }
-    if (partial) {
+    } else if (partial) {
         SMG_K_SWITCH(k, (k_residual<KK, T, true><<<g, kBlock, 0, st>>>(ns, A.lpr, A.slice_row0, A.slice_off, A.cols,
                                                                        A.vals, A.diag, b, x, r, partial)));
     } else {
@@ -1410,9 +1439,12 @@ hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const 
 
 template <typename T>
 hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc, int k,
-                           hipStream_t st) {
+                           hipStream_t st, T *xc) {
     if (P.nc <= 0) return hipSuccess;
-    SMG_K_SWITCH(k, (k_restrict<KK, T><<<nblocks(P.nc), kBlock, 0, st>>>(P.nc, P.rs_off, P.rs_idx, rw, r, rc)));
+    const int lr = P.rs_lanes, rps = 64 / lr;
+    const int64_t threads = (int64_t)((P.nc + rps - 1) / rps) * 64;
+    SMG_K_SWITCH(k, (k_restrict<KK, T><<<nblocks(threads), kBlock, 0, st>>>(P.nc, lr, P.rs_off, P.rs_idx, rw, r,
+                                                                            rc, xc)));
     return hipGetLastError();
 }
 
@@ -1609,7 +1641,7 @@ hipError_t launch_ir_down(const double *r64, const double *norms, float *r32, in
     return hipGetLastError();
 }
 
-hipError_t launch_ir_up(const float *d32, const double *norms, double *x64, int n, int k,
+hipError_t launch_ir_up(float *d32, const double *norms, double *x64, int n, int k,
                         hipStream_t st) {
     if (n <= 0) return hipSuccess;
     k_ir_up<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(d32, norms, x64, n, k);
@@ -1652,9 +1684,9 @@ template hipError_t launch_residual<float>(const SellView<float> &, int, const f
                                            const float *, float *, int, double *, int *,
                                            hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_restrict<double>(const TransferView &, const double *, const double *,
-                                            double *, int, hipStream_t);
+                                            double *, int, hipStream_t, double *);
 template hipError_t launch_restrict<float>(const TransferView &, const float *, const float *,
-                                           float *, int, hipStream_t);
+                                           float *, int, hipStream_t, float *);
 template hipError_t launch_prolong_add<double>(const TransferView &, const double *,
                                                const double *, double *, int, hipStream_t);
 template hipError_t launch_prolong_add<float>(const TransferView &, const float *, const float *,

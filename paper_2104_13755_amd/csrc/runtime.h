@@ -36,6 +36,7 @@ struct DevLevel {
     int32_t *pc = nullptr, *rptr = nullptr, *ridx = nullptr, *rs_off = nullptr, *rs_idx = nullptr;
     double *rs_w = nullptr;
     float *rs_w32 = nullptr;
+    int rs_lanes = 4;
     double *pw = nullptr, *rw = nullptr;
     float *pw32 = nullptr, *rw32 = nullptr;
     int32_t *tptr = nullptr, *plan1ptr = nullptr, *plan2ptr = nullptr, *optr = nullptr, *opos = nullptr;
