@@ -353,16 +353,19 @@ void build_tail_layout(const LevelHost &L, int nc, int threads, TailLayout &out)
                 int kmax = 0;
                 for (int t = w * 64; t < std::min(nt, w * 64 + 64); t += g)
                     kmax = std::max(kmax, (S.rowlen[p0 + t / g] + g - 1) / g);
-                out.wave.insert(out.wave.end(), {(int32_t)off, kmax});
-                for (int k = 0; k < kmax; ++k)
-                    for (int lane = 0; lane < 64; ++lane) {
-                        const int t = w * 64 + lane, r = p0 + t / g, e = k * g + t % g;
-                        const bool ok = t < nt && e < S.rowlen[r];
-                        const int32_t slot = ok ? S.slot(r, e) : -1;
-                        out.src.push_back(slot);
-                        out.cols.push_back(ok ? S.cols[slot] : 0);
-                    }
-                off += 64 * (int64_t)kmax;
+                const int npair = (kmax + 1) / 2;   // rounds in pairs: record (k, lane) at 128 (k / 2) + 2 lane + k % 2
+                out.wave.insert(out.wave.end(), {(int32_t)off, npair});
+                for (int pr = 0; pr < npair; ++pr)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int h = 0; h < 2; ++h) {
+                            const int k = 2 * pr + h;
+                            const int t = w * 64 + lane, r = p0 + t / g, e = k * g + t % g;
+                            const bool ok = t < nt && e < S.rowlen[r];
+                            const int32_t slot = ok ? S.slot(r, e) : -1;
+                            out.src.push_back(slot);
+                            out.cols.push_back(ok ? S.cols[slot] : 0);
+                        }
+                off += 128 * (int64_t)npair;
             }
         }
     }
@@ -392,7 +395,7 @@ bool check_tail_layout(const TailLayout &T, int n, int threads, std::string &err
         }
         for (int w = 0; w < nw; ++w, ++wv) {
             if (2 * wv + 1 >= T.wave.size() || T.wave[2 * wv] != off || T.wave[2 * wv + 1] < 0) { err = "tail: bad wave"; return false; }
-            off += 64 * (int64_t)T.wave[2 * wv + 1];
+            off += 128 * (int64_t)T.wave[2 * wv + 1];
         }
     }
     if (2 * wv != T.wave.size()) { err = "tail: wave count"; return false; }

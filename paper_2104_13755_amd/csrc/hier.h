@@ -100,15 +100,17 @@ struct LevelHost {
 // Record layout of one smoothed level for the one-workgroup tail kernel,
 // whose iterate lives in LDS.  Rows of a color are processed in passes of
 // `threads / grp` rows, each row by `grp` adjacent lanes (thread t of a pass:
-// row row0 + t / grp).  Each wavefront w of a pass reads its own `kmax` rounds
-// of records, record (k, lane) at wave offset + 64 k + lane, holding entry
-// k * grp + t % grp of the thread's row (padding: column 0, weight 0).  The
+// row row0 + t / grp).  Each wavefront w of a pass reads its own rounds of
+// records in pairs, record (k, lane) at wave offset + 128 (k / 2) + 2 lane +
+// k % 2 (a lane's two records of a pair are adjacent: one 16-byte load in
+// FP32), holding entry k * grp + t % grp of the thread's row (padding: column
+// 0, weight 0).  The
 // restriction into the next level is an ELL of width rk, entry k of coarse row
 // a at k * nc + a (padding: index 0, weight 0).
 struct TailLayout {
     int grp = 1;
     std::vector<int32_t> pass;    // 4 per pass: row0, nrows, (last of its color) << 16, first wave
-    std::vector<int32_t> wave;    // 2 per wavefront: record offset, rounds
+    std::vector<int32_t> wave;    // 2 per wavefront: record offset, pairs of rounds
     std::vector<int32_t> src;     // record -> SELL slot of the level (-1 padding)
     std::vector<int32_t> cols;    // record -> permuted column
     int rk = 0, nc = 0;

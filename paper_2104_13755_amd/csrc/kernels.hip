@@ -778,44 +778,50 @@ __device__ __forceinline__ void lds_get(const T *xs, int c, T (&v)[K]) {
 // acc += sum over this thread's records (rounds k < kmax, 64 apart) in
 // chunks of CH rounds; rounds past kmax re-read the last record with weight 0,
 // so nothing in a chunk is conditional
-// one record as a single 8- or 16-byte global load
-typedef int vint2 __attribute__((ext_vector_type(2)));
+// A lane's two records of a pair: one 16-byte load in FP32 (one compute
+// unit streams 16-byte loads from L2 about twice as fast as 8-byte ones),
+// two in FP64.
 typedef int vint4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ TailRec<float> rec_load(const TailRec<float> *p, size_t i) {
-    const vint2 v = gld(reinterpret_cast<const vint2 *>(p), i);
-    return TailRec<float>{v.x, __int_as_float(v.y)};
+__device__ __forceinline__ void pair_load(const TailRec<float> *p, size_t i, int (&c)[2], float (&v)[2]) {
+    const vint4 a = gld(reinterpret_cast<const vint4 *>(p + i), 0);
+    c[0] = a.x; v[0] = __int_as_float(a.y); c[1] = a.z; v[1] = __int_as_float(a.w);
 }
-__device__ __forceinline__ TailRec<double> rec_load(const TailRec<double> *p, size_t i) {
-    const vint4 v = gld(reinterpret_cast<const vint4 *>(p), i);
-    return TailRec<double>{v.x, 0, __hiloint2double(v.w, v.z)};
+__device__ __forceinline__ void pair_load(const TailRec<double> *p, size_t i, int (&c)[2], double (&v)[2]) {
+    const vint4 a = gld(reinterpret_cast<const vint4 *>(p + i), 0);
+    const vint4 b = gld(reinterpret_cast<const vint4 *>(p + i + 1), 0);
+    c[0] = a.x; v[0] = __hiloint2double(a.w, a.z); c[1] = b.x; v[1] = __hiloint2double(b.w, b.z);
 }
 
+// acc += this lane's records of pairs [p0, p0 + CH) (pairs past np re-read the
+// last one with weight 0), all loads issued before any is used
 template <int CH, int K, int KP, typename T>
-__device__ __forceinline__ void tail_gather_ch(const TailRec<T> *rp, int k0, int kmax, const T *xs,
+__device__ __forceinline__ void tail_gather_ch(const TailRec<T> *rp, int p0, int np, const T *xs,
                                                T (&acc)[K]) {
-    TailRec<T> rr[CH];
+    int c[CH][2];
+    T v[CH][2];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) rr[u] = rec_load(rp, (size_t)min(k0 + u, kmax - 1) * 64);
+    for (int u = 0; u < CH; ++u) pair_load(rp, (size_t)min(p0 + u, np - 1) * 128, c[u], v[u]);
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-        const T w = k0 + u < kmax ? rr[u].val : T(0);
-        T xv[K];
-        lds_get<T, K, KP>(xs, rr[u].col, xv);
+    for (int u = 0; u < CH; ++u)
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += w * xv[q];
-    }
+        for (int h = 0; h < 2; ++h) {
+            const T w = p0 + u < np ? v[u][h] : T(0);
+            T xv[K];
+            lds_get<T, K, KP>(xs, c[u][h], xv);
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] += w * xv[q];
+        }
 }
-// full chunks of 8 rounds, then one chunk of 2, 4, 6 or 8 for the rest
+// full chunks of 4 pairs, then one chunk of 1, 2 or 4 pairs for the rest
 template <int K, int KP, typename T>
-__device__ __forceinline__ void tail_gather(const TailRec<T> *rp, int kmax, const T *xs, T (&acc)[K]) {
-    int k0 = 0;
-    for (; k0 + 8 <= kmax; k0 += 8) tail_gather_ch<8, K, KP, T>(rp, k0, kmax, xs, acc);
-    const int rem = kmax - k0;
+__device__ __forceinline__ void tail_gather(const TailRec<T> *rp, int np, const T *xs, T (&acc)[K]) {
+    int p0 = 0;
+    for (; p0 + 4 <= np; p0 += 4) tail_gather_ch<4, K, KP, T>(rp, p0, np, xs, acc);
+    const int rem = np - p0;
     if (rem <= 0) return;
-    if (rem <= 2) tail_gather_ch<2, K, KP, T>(rp, k0, kmax, xs, acc);
-    else if (rem <= 4) tail_gather_ch<4, K, KP, T>(rp, k0, kmax, xs, acc);
-    else if (rem <= 6) tail_gather_ch<6, K, KP, T>(rp, k0, kmax, xs, acc);
-    else tail_gather_ch<8, K, KP, T>(rp, k0, kmax, xs, acc);
+    if (rem == 1) tail_gather_ch<1, K, KP, T>(rp, p0, np, xs, acc);
+    else if (rem == 2) tail_gather_ch<2, K, KP, T>(rp, p0, np, xs, acc);
+    else tail_gather_ch<4, K, KP, T>(rp, p0, np, xs, acc);
 }
 
 // one pass row: diagonal, b and the off-diagonal sum over the lane group
@@ -828,7 +834,7 @@ __device__ __forceinline__ void tail_row(const LdsLevel<T> &L, const int2 *wv, i
     d = gld(L.diag, row);
 #pragma unroll
     for (int q = 0; q < K; ++q) { bq[q] = gld(L.b, (size_t)row * K + q); acc[q] = T(0); }
-    tail_gather<K, KP, T>(L.rec + off + (tid & 63), kmax, xs, acc);
+    tail_gather<K, KP, T>(L.rec + off + 2 * (tid & 63), kmax, xs, acc);
     for (int m = G >> 1; m > 0; m >>= 1)
 #pragma unroll
         for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
