@@ -78,6 +78,7 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
     h->H.nlev = nlev;
     h->H.sizes.push_back(n);
     std::vector<double> X(V, V + 3 * (size_t)n);
+    h->H.X.push_back(X);
     std::vector<int32_t> Fv(F, F + 3 * (size_t)m);
     for (int l = 0; l + 1 < nlev; ++l) {
         LevelOut lo;
@@ -91,6 +92,7 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
         X = std::move(lo.X);
         Fv = std::move(lo.F);
         h->H.sizes.push_back((int)(X.size() / 3));
+        h->H.X.push_back(X);
     }
     // zero-column removal (App. B): drop coarse vertices that receive no
     // weight, and the matching rows of the next prolongation.
@@ -104,6 +106,12 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
         for (int a = 0; a < nc; ++a) if (used[a]) newid[a] = cnt++;
         if (cnt == nc) continue;
         for (auto &c : h->H.pcols[l]) if (c >= 0) c = newid[c];
+        {
+            std::vector<double> Xc;
+            for (int a = 0; a < nc; ++a)
+                if (used[a]) Xc.insert(Xc.end(), h->H.X[l + 1].begin() + 3 * a, h->H.X[l + 1].begin() + 3 * a + 3);
+            h->H.X[l + 1] = std::move(Xc);
+        }
         if (l + 2 < nlev) {
             std::vector<int32_t> pc2;
             std::vector<double> pw2;
@@ -265,7 +273,8 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     if (opts) for (int l = 0; l < 16; ++l) lpr[l] = opts->lanes_per_row[l];
     std::vector<LevelHost> levels;
     std::string err;
-    if (build_levels(h->H, A0, lpr, levels, err) != 0) return fail(SMG_ERR_INVALID_ARG, "hierarchy setup: " + err);
+    if (build_levels(h->H, A0, lpr, tail_rows > 0 ? tail_rows : 0, levels, err) != 0)
+        return fail(SMG_ERR_INVALID_ARG, "hierarchy setup: " + err);
     S->nlev = h->H.nlev;
     S->lev.resize(S->nlev);
     int64_t tmax = 1;

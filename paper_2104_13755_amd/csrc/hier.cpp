@@ -152,7 +152,27 @@ static int32_t store_pos(const LevelHost &L, int r, int c) {
     return S.slot(r, (int)(it - b));
 }
 
-int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
+// 30-bit Morton key of each vertex: positions quantized to 1024 cells along
+// the bounding box's longest side, bits of x, y, z interleaved
+static std::vector<int64_t> morton_keys(const std::vector<double> &X) {
+    const size_t n = X.size() / 3;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (size_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], X[3 * i + d]); hi[d] = std::max(hi[d], X[3 * i + d]); }
+    const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<int64_t> key(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+        int64_t q[3];
+        for (int d = 0; d < 3; ++d) q[d] = std::min<int64_t>(1023, (int64_t)((X[3 * i + d] - lo[d]) / ext * 1023.0 + 0.5));
+        int64_t k = 0;
+        for (int b = 0; b < 10; ++b)
+            for (int d = 0; d < 3; ++d) k |= ((q[d] >> b) & 1) << (3 * b + d);
+        key[i] = k;
+    }
+    return key;
+}
+
+int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, int sort_rows,
                  std::vector<LevelHost> &levels, std::string &err) {
     const int nlev = H.nlev;
     levels.assign(nlev, LevelHost());
@@ -177,11 +197,16 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
             for (int c = 0; c < L.ncolors; ++c) cnt[c + 1] += cnt[c];
             L.sell.color_row = cnt;
             for (int i = 0; i < L.n; ++i) L.perm[cnt[L.color[i]]++] = i;
-            if (l > 0) {   // Galerkin levels: rows of a color by descending length (less padding)
+            if (l > 0 && L.n <= sort_rows) {   // tail levels: rows of a color by descending length
                 auto len = [&](int i) { return pat.ptr[i + 1] - pat.ptr[i]; };
                 for (int c = 0; c < L.ncolors; ++c)
                     std::stable_sort(L.perm.begin() + L.sell.color_row[c], L.perm.begin() + L.sell.color_row[c + 1],
                                      [&](int a, int b) { return len(a) > len(b); });
+            } else if (l < (int)H.X.size() && H.X[l].size() == 3 * (size_t)L.n) {
+                const std::vector<int64_t> key = morton_keys(H.X[l]);
+                for (int c = 0; c < L.ncolors; ++c)
+                    std::stable_sort(L.perm.begin() + L.sell.color_row[c], L.perm.begin() + L.sell.color_row[c + 1],
+                                     [&](int a, int b) { return key[a] < key[b]; });
             }
         } else {
             std::iota(L.perm.begin(), L.perm.end(), 0);

@@ -126,6 +126,7 @@ bool check_tail_layout(const TailLayout &T, int n, int threads, std::string &err
 struct HierHost {
     int nlev = 0;
     std::vector<int> sizes;
+    std::vector<std::vector<double>> X;        // vertex positions per level (3 each) when known
     std::vector<std::vector<int32_t>> pcols;   // natural ELL-3 per level
     std::vector<std::vector<double>> pw;
     std::vector<std::array<double, 8>> stats;
@@ -136,7 +137,12 @@ int default_lanes_per_row(double avg);
 
 // Build every LevelHost from the level-0 pattern and the prolongations.
 // lpr[l] > 0 forces the lanes per row of level l (else the default rule).
-int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr,
+// Inside a color, rows of Galerkin levels with at most sort_rows rows are
+// ordered by descending length (the one-workgroup tail reads them by
+// wavefront); all other levels follow a Morton curve through the vertex
+// positions when H.X holds them (neighbours' iterates then share cache
+// lines), else the natural order.
+int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, int sort_rows,
                  std::vector<LevelHost> &levels, std::string &err);
 
 }  // namespace smg

@@ -88,17 +88,22 @@ def test_finite_differences_655k():
     fd = (ell(t + h, s) - ell(t - h, s)) / (2 * h)
     print(f"[grad] dt fd={fd:.10e} adjoint={dt:.10e}", flush=True)
     assert abs(fd - dt) <= 1e-6 * abs(dt)
-    # dl/ds_i at 8 sources (largest responses) and along a random direction
+    # dl/ds_i at 8 sources (largest responses) and along a random direction.
+    # Step 1e-4: the central quotient carries rounding noise ~ ulp(l) / (2h)
+    # (l ~ 1e5, so ~1.4e-5 at h = 1e-6, as large as the 1e-6 relative bar on
+    # dl/ds_i ~ 10); at 1e-4 the noise is 1.4e-7 and the O(h^2) truncation of
+    # the smooth l(s) stays far below the bar.
     dsn = ds.cpu().numpy()
+    hs = 1e-4
     for i in w["sources"][:8]:
         e = torch.zeros_like(s)
-        e[int(i)] = 1e-6
-        fdi = (ell(t, s + e) - ell(t, s - e)) / 2e-6
+        e[int(i)] = hs
+        fdi = (ell(t, s + e) - ell(t, s - e)) / (2 * hs)
         assert abs(fdi - dsn[i]) <= 1e-6 * abs(dsn[i]) + 1e-9 * np.abs(dsn).max(), (i, fdi, dsn[i])
     rng = np.random.default_rng(0)
     d = torch.tensor(rng.normal(size=P.n), dtype=torch.float64, device="cuda")
     d /= torch.linalg.norm(d)
-    hd = 1e-6
+    hd = 1e-4
     fdd = (ell(t, s + hd * d) - ell(t, s - hd * d)) / (2 * hd)
     ref = float((ds * d).sum())
     assert abs(fdd - ref) <= 1e-6 * abs(ref) + 1e-9 * float(torch.linalg.norm(ds))
