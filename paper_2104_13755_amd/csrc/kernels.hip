@@ -53,7 +53,7 @@ __device__ __forceinline__ void gather_chunk(int o, int e, int w, const int32_t 
     for (int u = 0; u < CH; ++u) {
         const int at = o + 64 * min(e + u, w - 1);
         c[u] = cols[at];
-        a[u] = e + u < w ? vals[at] : T(0);
+        a[u] = vals[at] * (e + u < w ? T(1) : T(0));   // padding rounds weigh 0 (values are finite)
     }
     T xv[CH][K];
 #pragma unroll
@@ -95,16 +95,20 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end, int
     const int s = s_begin + blk * (kBlock / 64) + (threadIdx.x >> 6);
     if (s >= s_end) return;
     const int lane = threadIdx.x & 63;
-    const int row = slice_row0[s] + lane / lpr;
-    if (row >= slice_row0[s + 1]) return;   // whole lane groups leave together
-    const int o0 = slice_off[s];
-    const int w = (slice_off[s + 1] - o0) >> 6;
-    const T d = diag[row];   // issued with the matrix loads, used after the gather
+    // the slice's bounds, diagonal and b are loaded together; lanes past the
+    // slice's last row work on (padding) data of its first row and store nothing
+    const int r0 = slice_row0[s], r1 = slice_row0[s + 1];
+    const int o0 = slice_off[s], o1 = slice_off[s + 1];
+    const int row = r0 + (lane >> __builtin_ctz(lpr));
+    const bool valid = row < r1;
+    const int rw = valid ? row : r0;
+    const int w = (o1 - o0) >> 6;
+    const T d = diag[rw];
     T bq[K], acc[K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) { bq[q] = b[(size_t)row * K + q]; acc[q] = T(0); }
+    for (int q = 0; q < K; ++q) { bq[q] = b[(size_t)rw * K + q]; acc[q] = T(0); }
     row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
-    if ((lane & (lpr - 1)) == 0) {
+    if (valid && (lane & (lpr - 1)) == 0) {
 #pragma unroll
         for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (bq[q] - acc[q]) / d;
     }
@@ -129,20 +133,23 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
 #pragma unroll
     for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
     if (s < nslices) {
-        const int row = slice_row0[s] + lane / lpr;
-        if (row < slice_row0[s + 1]) {
-            const int o0 = slice_off[s];
-            const int w = (slice_off[s + 1] - o0) >> 6;
-            const T d = diag[row];
+        const int r0 = slice_row0[s], r1 = slice_row0[s + 1];
+        const int o0 = slice_off[s], o1 = slice_off[s + 1];
+        const int row = r0 + (lane >> __builtin_ctz(lpr));
+        const bool valid = row < r1;
+        const int rw = valid ? row : r0;
+        {
+            const int w = (o1 - o0) >> 6;
+            const T d = diag[rw];
             T bq[K], xo[K], acc[K];
 #pragma unroll
             for (int q = 0; q < K; ++q) {
-                bq[q] = b[(size_t)row * K + q];
-                xo[q] = x[(size_t)row * K + q];
+                bq[q] = b[(size_t)rw * K + q];
+                xo[q] = x[(size_t)rw * K + q];
                 acc[q] = T(0);
             }
             row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
-            if ((lane & (lpr - 1)) == 0) {
+            if (valid && (lane & (lpr - 1)) == 0) {
 #pragma unroll
                 for (int q = 0; q < K; ++q) {
                     const T rv = bq[q] - (acc[q] + d * xo[q]);
