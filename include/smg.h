@@ -120,9 +120,12 @@ typedef struct {
                               workgroup's LDS for the call's precision and
                               k); 0 = 4096, < 0 = never                     */
     int32_t lanes_per_row[16]; /* per level 1/2/4/8 lanes per matrix row in
-                              the relaxation/residual kernels; 0 = rule (1 if
-                              the mean row has < 10 entries, else 8); launch
-                              shape only: results do not depend on it beyond
+                              the relaxation/residual kernels and, on levels
+                              of the one-workgroup tail, in its passes; 0 =
+                              rule (kernels: 1 if the mean row has < 10
+                              entries, else 8; tail: the widest group up to
+                              4 that fits a whole color in one pass); launch shape
+                              only: results do not depend on it beyond
                               summation order                              */
 } smg_opts;
 

@@ -352,7 +352,7 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
             tmax = std::max<int64_t>(tmax, L.tptr.back());
             if (tail_rows > 0 && L.n <= tail_rows) {   // records of the LDS tail
                 TailLayout T;
-                build_tail_layout(L, levels[l + 1].n, kTailThreads, T);
+                build_tail_layout(L, levels[l + 1].n, kTailThreads, lpr[l], T);
                 if (!check_tail_layout(T, L.n, kTailThreads, err)) return fail(SMG_ERR_INVALID_ARG, err);
                 D.tl = true;
                 D.tl_lg = 0;

@@ -357,14 +357,18 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, 
     return 0;
 }
 
-void build_tail_layout(const LevelHost &L, int nc, int threads, TailLayout &out) {
+void build_tail_layout(const LevelHost &L, int nc, int threads, int grp, TailLayout &out) {
     const SellLayout &S = L.sell;
     out = TailLayout();
     int maxrows = 1;
     for (int c = 0; c + 1 < (int)S.color_row.size(); ++c)
         maxrows = std::max(maxrows, S.color_row[c + 1] - S.color_row[c]);
-    int g = 1;   // widest lane group (<= 64) that still fits a whole color in one pass
-    while (g < 64 && (int64_t)maxrows * g * 2 <= threads) g *= 2;
+    // widest lane group up to 4 that still fits a whole color in one pass (a
+    // full-size sweep: wider groups spend more in the cross-lane reduction
+    // than they save in record rounds)
+    int g = 1;
+    while (g < 4 && (int64_t)maxrows * g * 2 <= threads) g *= 2;
+    if (grp > 0) g = std::min(grp, 64);
     out.grp = g;
     const int per = threads / g;
     int64_t off = 0;

@@ -117,8 +117,10 @@ struct TailLayout {
     std::vector<int32_t> ridx;    // rk * nc
     std::vector<double> rw;
 };
-// threads: workgroup size of the tail kernel; nc: rows of the next level.
-void build_tail_layout(const LevelHost &L, int nc, int threads, TailLayout &out);
+// threads: workgroup size of the tail kernel; nc: rows of the next level;
+// grp > 0 forces the lanes per row (else the widest group up to 4 that fits
+// a whole color in one pass).
+void build_tail_layout(const LevelHost &L, int nc, int threads, int grp, TailLayout &out);
 // Bounds of every index the tail kernel derives from a layout of a level with
 // n rows (records, pass rows, restriction); false + message if one is out.
 bool check_tail_layout(const TailLayout &T, int n, int threads, std::string &err);

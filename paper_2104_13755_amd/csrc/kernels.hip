@@ -17,6 +17,7 @@ namespace smg {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kGsBlock = 64;   // one wavefront per block: a color's slices spread over more compute units
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of logical blocks so neighbouring slices share an L2.
@@ -84,7 +85,7 @@ __device__ __forceinline__ void row_gather(int o, int w, int lpr, const int32_t 
 
 // x_i <- (b_i - sum_{j != i} A_ij x_j) / A_ii for every row i of one color.
 template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end, int lpr,
+__global__ __launch_bounds__(kGsBlock) void k_gs_color(int s_begin, int s_end, int lpr,
                                                      const int32_t *__restrict__ slice_row0,
                                                      const int32_t *__restrict__ slice_off,
                                                      const int32_t *__restrict__ cols,
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int s_begin, int s_end, int
                                                      const T *__restrict__ diag,
                                                      const T *__restrict__ b, T *__restrict__ x) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s = s_begin + blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int s = s_begin + blk * (kGsBlock / 64) + (threadIdx.x >> 6);
     if (s >= s_end) return;
     const int lane = threadIdx.x & 63;
     // the slice's bounds, diagonal and b are loaded together; lanes past the
@@ -1410,13 +1411,13 @@ hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T
                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     const int ns = s_end - s_begin;
     if (ns <= 0) return hipSuccess;
-    const int g = nblocks(ns, kBlock / 64);
+    const int g = nblocks(ns, kGsBlock / 64);
     if (ev0) {
-        SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_gs_color<KK, T>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
+        SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_gs_color<KK, T>, dim3(g), dim3(kGsBlock), 0, st, ev0, ev1, 0,
                                                s_begin, s_end, A.lpr, A.slice_row0, A.slice_off, A.cols,
                                                A.vals, A.diag, b, x)));
     } else {
-        SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kBlock, 0, st>>>(s_begin, s_end, A.lpr, A.slice_row0, A.slice_off,
+        SMG_K_SWITCH(k, (k_gs_color<KK, T><<<g, kGsBlock, 0, st>>>(s_begin, s_end, A.lpr, A.slice_row0, A.slice_off,
                                                                  A.cols, A.vals, A.diag, b, x)));
     }
     return hipGetLastError();
