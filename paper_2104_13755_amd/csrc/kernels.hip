@@ -38,6 +38,17 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
+// Loads and stores through pointers read from descriptors in memory, marked
+// global explicitly (the compiler cannot infer it and would use flat accesses).
+template <typename T>
+__device__ __forceinline__ T gld(const T *p, size_t i) {
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void gst(T *p, size_t i, T v) {
+    ((__attribute__((address_space(1))) T *)p)[i] = v;
+}
+
 // ---------------------------------------------------------------- relaxation
 // Sum of one row's off-diagonal products over the lpr lanes of its group.
 // Rounds are taken in chunks whose loads are all issued before any is used:
@@ -566,9 +577,9 @@ __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool va
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = T(0);
     if (valid) {
-        const int s = L.row_slice[r];
-        const int base = L.slice_off[s] + (r - L.slice_row0[s]) * L.lpr;
-        const int len = L.rowlen[r];
+        const int s = gld(L.row_slice, r);
+        const int base = gld(L.slice_off, s) + (r - gld(L.slice_row0, s)) * L.lpr;
+        const int len = gld(L.rowlen, r);
         int e = j;
         for (; e + 3 * G < len; e += 4 * G) {   // four independent gathers in flight
             int c[4];
@@ -577,8 +588,8 @@ __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool va
             for (int u = 0; u < 4; ++u) {
                 const int ee = e + u * G;
                 const int slot = base + (ee / L.lpr) * 64 + (ee % L.lpr);
-                c[u] = L.cols[slot];
-                a[u] = L.vals[slot];
+                c[u] = gld(L.cols, slot);
+                a[u] = gld(L.vals, slot);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -587,8 +598,8 @@ __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool va
         }
         for (; e < len; e += G) {
             const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
-            const int cc = L.cols[slot];
-            const T a = L.vals[slot];
+            const int cc = gld(L.cols, slot);
+            const T a = gld(L.vals, slot);
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)cc * K + q];
         }
@@ -604,16 +615,16 @@ __device__ void wg_relax(Team &tm, const TailLevel<T> &L, int sweeps) {
     const int j = tm.tid & (G - 1), g = tm.tid / G, per = tm.nthreads / G;
     for (int sw = 0; sw < sweeps; ++sw)
         for (int c = 0; c < L.ncolors; ++c) {
-            const int r0 = L.color_row[c], r1 = L.color_row[c + 1];
+            const int r0 = gld(L.color_row, c), r1 = gld(L.color_row, c + 1);
             for (int rb = r0; rb < r1; rb += per) {
                 const int r = rb + g;
                 const bool valid = r < r1;
                 T acc[K];
                 wg_row_sum<K, T>(L, r, valid, j, G, L.x, acc);
                 if (valid && j == 0) {
-                    const T d = L.diag[r];
+                    const T d = gld(L.diag, r);
 #pragma unroll
-                    for (int q = 0; q < K; ++q) L.x[(size_t)r * K + q] = (L.b[(size_t)r * K + q] - acc[q]) / d;
+                    for (int q = 0; q < K; ++q) gst(L.x, (size_t)r * K + q, (gld(L.b, (size_t)r * K + q) - acc[q]) / d);
                 }
             }
             team_sync(tm);
@@ -632,11 +643,11 @@ __device__ void wg_residual(Team &tm, const TailLevel<T> &L, double (*sq)[K] = n
         T acc[K];
         wg_row_sum<K, T>(L, r, valid, j, G, L.x, acc);
         if (valid && j == 0) {
-            const T d = L.diag[r];
+            const T d = gld(L.diag, r);
 #pragma unroll
             for (int q = 0; q < K; ++q) {
-                const T rv = L.b[(size_t)r * K + q] - (acc[q] + d * L.x[(size_t)r * K + q]);
-                L.r[(size_t)r * K + q] = rv;
+                const T rv = gld(L.b, (size_t)r * K + q) - (acc[q] + d * gld(L.x, (size_t)r * K + q));
+                gst(L.r, (size_t)r * K + q, rv);
                 if (sq) { (*sq)[q] += (double)rv * (double)rv; (*mx)[q] = fmax((*mx)[q], fabs((double)rv)); }
             }
         }
@@ -651,7 +662,7 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
     for (int l = first; l < last; ++l) {
         const TailLevel<T> L = lv[l];
         if (l > first) {
-            for (int t = tm.tid; t < L.n * K; t += nt) L.x[t] = T(0);
+            for (int t = tm.tid; t < L.n * K; t += nt) gst(L.x, t, T(0));
             team_sync(tm);
         }
         wg_relax<K, T>(tm, L, mu_pre);
@@ -667,11 +678,11 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
 #pragma unroll
                 for (int q = 0; q < K; ++q) acc[q] = T(0);
                 if (a < C.n) {
-                    for (int p = L.rptr[a] + j; p < L.rptr[a + 1]; p += 4) {
-                        const int i = L.ridx[p];
-                        const T w = L.rw[p];
+                    for (int p = gld(L.rptr, a) + j; p < gld(L.rptr, a + 1); p += 4) {
+                        const int i = gld(L.ridx, p);
+                        const T w = gld(L.rw, p);
 #pragma unroll
-                        for (int q = 0; q < K; ++q) acc[q] += w * L.r[(size_t)i * K + q];
+                        for (int q = 0; q < K; ++q) acc[q] += w * gld(L.r, (size_t)i * K + q);
                     }
                 }
 #pragma unroll
@@ -681,7 +692,7 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
                 }
                 if (a < C.n && j == 0) {
 #pragma unroll
-                    for (int q = 0; q < K; ++q) C.b[(size_t)a * K + q] = acc[q];
+                    for (int q = 0; q < K; ++q) gst(C.b, (size_t)a * K + q, acc[q]);
                 }
             }
         }
@@ -700,16 +711,16 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
                 for (; jj + 12 < C.n; jj += 16) {
                     double a[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] = Ainv[(size_t)(jj + 4 * u) * C.n + i];
+                    for (int u = 0; u < 4; ++u) a[u] = gld(Ainv, (size_t)(jj + 4 * u) * C.n + i);
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
 #pragma unroll
-                        for (int q = 0; q < K; ++q) acc[q] += a[u] * (double)C.b[(size_t)(jj + 4 * u) * K + q];
+                        for (int q = 0; q < K; ++q) acc[q] += a[u] * (double)gld(C.b, (size_t)(jj + 4 * u) * K + q);
                 }
                 for (; jj < C.n; jj += 4) {
-                    const double a = Ainv[(size_t)jj * C.n + i];
+                    const double a = gld(Ainv, (size_t)jj * C.n + i);
 #pragma unroll
-                    for (int q = 0; q < K; ++q) acc[q] += a * (double)C.b[(size_t)jj * K + q];
+                    for (int q = 0; q < K; ++q) acc[q] += a * (double)gld(C.b, (size_t)jj * K + q);
                 }
             }
 #pragma unroll
@@ -719,7 +730,7 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
             }
             if (i < C.n && j == 0) {
 #pragma unroll
-                for (int q = 0; q < K; ++q) C.x[(size_t)i * K + q] = (T)acc[q];
+                for (int q = 0; q < K; ++q) gst(C.x, (size_t)i * K + q, (T)acc[q]);
             }
         }
         team_sync(tm);
@@ -733,13 +744,13 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
             for (int q = 0; q < K; ++q) acc[q] = T(0);
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const int c = L.pc[(size_t)m * L.n + i];
-                const T w = L.pw[(size_t)m * L.n + i];
+                const int c = gld(L.pc, (size_t)m * L.n + i);
+                const T w = gld(L.pw, (size_t)m * L.n + i);
 #pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] += w * C.x[(size_t)c * K + q];
+                for (int q = 0; q < K; ++q) acc[q] += w * gld(C.x, (size_t)c * K + q);
             }
 #pragma unroll
-            for (int q = 0; q < K; ++q) L.x[(size_t)i * K + q] += acc[q];
+            for (int q = 0; q < K; ++q) gst(L.x, (size_t)i * K + q, gld(L.x, (size_t)i * K + q) + acc[q]);
         }
         team_sync(tm);
         wg_relax<K, T>(tm, L, mu_post);
@@ -755,14 +766,6 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
 // read from the level descriptors are marked global explicitly (the compiler
 // cannot infer it) so loads need not wait on LDS traffic, and every load of a
 // chunk is unconditional (clamped index, masked value) so all are in flight.
-template <typename T>
-__device__ __forceinline__ T gld(const T *p, size_t i) {
-    return ((const __attribute__((address_space(1))) T *)p)[i];
-}
-template <typename T>
-__device__ __forceinline__ void gst(T *p, size_t i, T v) {
-    ((__attribute__((address_space(1))) T *)p)[i] = v;
-}
 
 template <typename T, int K, int KP>
 __device__ __forceinline__ void lds_get(const T *xs, int c, T (&v)[K]) {
@@ -1073,16 +1076,16 @@ __device__ void batch_mesh(Team &tm, const BatchMesh &M) {
     // b (caller order) -> level-0 color-major order; x = 0; r = b
     for (int t = tm.tid; t < n * K; t += nt) {
         const int r = t / K, q = t % K;
-        const double v = M.b_user[(size_t)M.perm0[r] * K + q];
-        L0.b[t] = v;
-        L0.r[t] = v;
-        L0.x[t] = 0.0;
+        const double v = gld(M.b_user, (size_t)gld(M.perm0, r) * K + q);
+        gst(L0.b, t, v);
+        gst(L0.r, t, v);
+        gst(L0.x, t, 0.0);
     }
     double bn[K], sq[K], mx[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
     for (int t = tm.tid; t < n * K; t += nt) {
-        const double v = M.b_user[(size_t)M.perm0[t / K] * K + t % K];
+        const double v = gld(M.b_user, (size_t)gld(M.perm0, t / K) * K + t % K);
 #pragma unroll
         for (int q = 0; q < K; ++q)
             if (t % K == q) { sq[q] += v * v; mx[q] = fmax(mx[q], fabs(v)); }
@@ -1108,8 +1111,8 @@ __device__ void batch_mesh(Team &tm, const BatchMesh &M) {
                 double s = 0.0;
 #pragma unroll
                 for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
-                F0.b[t] = (float)(s > 0.0 ? L0.r[t] / s : 0.0);
-                F0.x[t] = 0.0f;
+                gst(F0.b, t, (float)(s > 0.0 ? gld(L0.r, t) / s : 0.0));
+                gst(F0.x, t, 0.0f);
             }
             team_sync(tm);
             wg_vcycle<K, float>(tm, M.lv32, 0, M.nlev, M.mu_pre, M.mu_post, M.Ainv);
@@ -1118,7 +1121,7 @@ __device__ void batch_mesh(Team &tm, const BatchMesh &M) {
                 double s = 0.0;
 #pragma unroll
                 for (int qq = 0; qq < K; ++qq) if (qq == q) s = mx[qq];
-                L0.x[t] += s * (double)F0.x[t];
+                gst(L0.x, t, gld(L0.x, t) + s * (double)gld(F0.x, t));
             }
             team_sync(tm);
         }
@@ -1137,17 +1140,20 @@ __device__ void batch_mesh(Team &tm, const BatchMesh &M) {
     }
     for (int t = tm.tid; t < n * K; t += nt) {
         const int r = t / K, q = t % K;
-        M.x_user[(size_t)M.perm0[r] * K + q] = L0.x[t];
+        gst(M.x_user, (size_t)gld(M.perm0, r) * K + q, gld(L0.x, t));
     }
     if (tm.tid == 0) {
-        M.out[0] = (double)cycles;
+        gst(M.out, 0, (double)cycles);
 #pragma unroll
-        for (int q = 0; q < K; ++q) M.out[1 + q] = rho[q];
+        for (int q = 0; q < K; ++q) gst(M.out, 1 + q, rho[q]);
     }
 }
 
-// block b works for mesh team_mesh[b] as member team_rank[b] of team_size[mesh]
-__global__ __launch_bounds__(1024) void k_batch_solve(const BatchMesh *__restrict__ meshes,
+// block b works for mesh team_mesh[b] as member team_rank[b] of team_size[mesh];
+// one instantiation per workgroup size, so smaller workgroups get the larger
+// register budget instead of spilling
+template <int BS>
+__global__ __launch_bounds__(BS) void k_batch_solve(const BatchMesh *__restrict__ meshes,
                                                       const int32_t *__restrict__ team_mesh,
                                                       const int32_t *__restrict__ team_rank,
                                                       unsigned *__restrict__ ctrs,
@@ -1560,14 +1566,19 @@ hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
     if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
     k_fill<unsigned><<<nblocks(count), kBlock, 0, st>>>(ctrs, 0u, count);
     k_fill<int><<<nblocks(count), kBlock, 0, st>>>(aborts, 0, count);
-    k_batch_solve<<<nblocks_total, threads, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
+    if (threads == 256) k_batch_solve<256><<<nblocks_total, 256, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
+    else if (threads == 512) k_batch_solve<512><<<nblocks_total, 512, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
+    else k_batch_solve<1024><<<nblocks_total, 1024, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
     return hipGetLastError();
 }
 
 int batch_blocks_per_cu(int threads) {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_solve, threads, 0) != hipSuccess) return 0;
-    return occ;
+    hipError_t e = hipErrorInvalidValue;
+    if (threads == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_solve<256>, 256, 0);
+    else if (threads == 512) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_solve<512>, 512, 0);
+    else if (threads == 1024) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_solve<1024>, 1024, 0);
+    return e == hipSuccess ? occ : 0;
 }
 
 hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_t nnz,
