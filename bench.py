@@ -264,8 +264,8 @@ def bench_frames(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, nargs=2, default=(1000, 1000))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
@@ -336,7 +336,7 @@ def main():
     per_launch_bytes = prof["bytes"] / max(1, prof["launches"])
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic_all,
-                "kernel": "k_gs_color<3, float> (multicolor Gauss-Seidel, FP32 cycles, every level)"
+                "kernel": "k_gs_color_w<3, float> / k_gs_color<3, float> (multicolor Gauss-Seidel, FP32 cycles, every level)"
                           if args.profile_kind == "gs" else f"{args.profile_kind} (every level)",
                 "launches": prof["launches"], "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"]),
                 "algorithmic_bytes_per_launch": per_launch_bytes,

@@ -213,7 +213,11 @@ typedef struct {
 /* x = A^{-1} b from x0 = 0.  SMG_FP32_IR runs relaxation, residual and
  * transfers of every cycle in FP32 (FP32 accumulation) inside an FP64
  * iterative-refinement loop: FP64 outer residual, FP64 coarsest Cholesky,
- * FP64 update.  info may be NULL.  Errors: STATE, NONFINITE, NO_CONVERGENCE. */
+ * FP64 update.  info may be NULL.  Errors: STATE, NONFINITE, NO_CONVERGENCE.
+ * The calling thread polls (busy-waits) for each cycle's residual norms; with
+ * SMG_FP32_IR and no graph the next cycle's first part is already queued
+ * while it does, and its result is discarded when the stop test ends the
+ * solve (x is always the iterate of info->cycles cycles). */
 smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                      const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
 

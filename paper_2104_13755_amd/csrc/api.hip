@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -313,6 +314,9 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
                 D.offdiag_nnz += z;
             }
             D.color_slice = Sl.color_slice;
+            D.color_row_h = Sl.color_row;
+            D.color_w = Sl.color_w;
+            for (int c = 0; c < L.ncolors; ++c) D.color_off.push_back(Sl.slice_off[Sl.color_slice[c]]);
             D.slots = Sl.slots();
             std::vector<int32_t> row0 = Sl.slice_row0;
             row0.push_back(L.n);
@@ -441,7 +445,8 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     CHK(dalloc(&S->partial, (size_t)S->npartial, S->owned));
     CHK(dalloc(&S->norms, 16, S->owned));
     CHK(dalloc(&S->flag, 4, S->owned));
-    HIPCHK(hipHostMalloc((void **)&S->h_norms, 16 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&S->h_norms, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&S->d_hnorms, S->h_norms, 0));
     HIPCHK(hipHostMalloc((void **)&S->h_flag, 4 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
@@ -685,7 +690,9 @@ smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
         for (int c = 0; c < D.ncolors; ++c) {
             const int pi = prof_begin(s, SMG_PROF_GS, l,
                                       D.color_nnz[c] * (sb + 4) + D.color_rows[c] * sb * (1 + 3 * k), st);
-            HIPCHK(launch_gs_color<T>(A, D.color_slice[c], D.color_slice[c + 1], bbuf<T>(D), xbuf<T>(D), k, st,
+            const ColorSpan span{D.color_slice[c], D.color_slice[c + 1], D.color_row_h[c], D.color_row_h[c + 1],
+                                 D.color_off[c], D.color_w[c]};
+            HIPCHK(launch_gs_color<T>(A, span, bbuf<T>(D), xbuf<T>(D), k, st,
                                       prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
         }
     return SMG_OK;
@@ -699,27 +706,32 @@ smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t
     const int pi = prof_begin(s, SMG_PROF_RESIDUAL, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
     HIPCHK(launch_residual<T>(sell_view<T>(D), D.nslices, bbuf<T>(D), xbuf<T>(D), rbuf<T>(D), k,
                               norms ? s->partial : nullptr, &nblk, st, prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
-    if (norms) HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st));
+    if (norms) HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st, s->d_hnorms, s->norm_seq));
     return SMG_OK;
 }
 
 // Alg. "V-cycle" from level l with b_l, x_l in the level buffers (x_l in/out).
+// `part` splits off level l's pre-relaxation (empty when level l is the
+// coarsest or runs in the LDS tail).
 template <typename T>
-smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st) {
+smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part) {
     DevLevel &D = s->lev[l];
     if (D.coarsest) {
-        HIPCHK((launch_coarse_solve<T, T>(D.dense_inv, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
+        if (part != kCyclePre)
+            HIPCHK((launch_coarse_solve<T, T>(D.dense_inv, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
         return SMG_OK;
     }
     const int pr = sizeof(T) == 8 ? 0 : 1;
     if (l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
-        HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
-                                  s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st));
+        if (part != kCyclePre)
+            HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
+                                      s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st));
         return SMG_OK;
     }
     DevLevel &C = s->lev[l + 1];
     const TransferView P = transfer_view(D, C);
-    CHK(smooth_level<T>(s, l, k, s->mu_pre, st));                  // pre-relaxation
+    if (part != kCycleAfterPre) CHK(smooth_level<T>(s, l, k, s->mu_pre, st));   // pre-relaxation
+    if (part == kCyclePre) return SMG_OK;
     CHK(residual_level<T>(s, l, k, false, st));                    // r = b - A x'
     // P^T r; the coarse iterate starts from zero
     HIPCHK(launch_restrict<T>(P, rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st, C.coarsest ? nullptr : xbuf<T>(C)));
@@ -729,8 +741,8 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st) {
     return SMG_OK;
 }
 
-template smg_status vcycle_from<double>(smg_solver_s *, int, int, hipStream_t);
-template smg_status vcycle_from<float>(smg_solver_s *, int, int, hipStream_t);
+template smg_status vcycle_from<double>(smg_solver_s *, int, int, hipStream_t, int);
+template smg_status vcycle_from<float>(smg_solver_s *, int, int, hipStream_t, int);
 template smg_status residual_level<double>(smg_solver_s *, int, int, bool, hipStream_t);
 template smg_status residual_level<float>(smg_solver_s *, int, int, bool, hipStream_t);
 
@@ -830,23 +842,56 @@ extern "C" smg_status smg_vcycle(smg_solver s, const double *d_b, double *d_x, i
 // ------------------------------------------------------------------ solve
 namespace smg {
 
-// read back the column norms (sum of squares, max) reduced into s->norms
+// Wait for the column norms (sum of squares, max) of the last reduction: the
+// reduction kernel writes them to h_norms itself (no copy back), so this only
+// waits, polling, for the stream to drain.
 static smg_status fetch_norms(smg_solver_s *s, int k, hipStream_t st) {
-    HIPCHK(hipMemcpyAsync(s->h_norms, s->norms, 2 * k * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    (void)k;
+    for (;;) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) return fail(SMG_ERR_HIP, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+    }
     return SMG_OK;
 }
 
-// one refinement or plain cycle, enqueued; ends with the FP64 level-0
-// residual and its column norms in s->norms
-smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st) {
+// Wait until the norm reduction tagged `seq` has written its k column norms to
+// h_norms; work enqueued after it keeps the device busy meanwhile.  The wait
+// ends with the stream at the latest: a drained stream without the tag is an
+// error.
+static smg_status wait_norms(smg_solver_s *s, int k, double seq, hipStream_t st) {
+    volatile double *tag = s->h_norms + 2 * k;
+    for (unsigned it = 1;; ++it) {
+        if (*tag == seq) break;
+        if ((it & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess) {
+                if (*tag == seq) break;
+                return fail(SMG_ERR_HIP, "residual norms were not reported");
+            }
+            if (e != hipErrorNotReady) return fail(SMG_ERR_HIP, std::string("hipStreamQuery: ") + hipGetErrorString(e));
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return SMG_OK;
+}
+
+// One refinement or plain cycle, enqueued; ends with the FP64 level-0
+// residual and its column norms in s->norms (and in h_norms, tagged with
+// s->norm_seq).  A refinement cycle can be enqueued in two parts: kCyclePre
+// (the correction's right-hand side and the level-0 pre-relaxation) writes
+// FP32 buffers only, so x still holds the previous iterate until the
+// kCycleAfterPre part has run.
+smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st, int part) {
     DevLevel &D = s->lev[0];
     if (precision == SMG_FP64) {
+        if (part != kCycleWhole) return fail(SMG_ERR_INVALID_ARG, "FP64 cycles are enqueued whole");
         CHK(vcycle_from<double>(s, 0, k, st));
     } else {
         // x32 is zero here: cleared at the start of the solve and by every ir_up
-        HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
-        CHK(vcycle_from<float>(s, 0, k, st));
+        if (part != kCycleAfterPre) HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
+        CHK(vcycle_from<float>(s, 0, k, st, part));
+        if (part == kCyclePre) return SMG_OK;
         HIPCHK(launch_ir_up(D.x32, s->norms, D.x, D.n, k, st));
     }
     if (D.coarsest) {
@@ -888,7 +933,7 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
     int nblk = 0;
     HIPCHK(hipMemcpyAsync(D.r, D.b, (size_t)D.n * k * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_colnorm_partial(D.b, D.n, k, s->partial, &nblk, st));
-    HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st));
+    HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st, s->d_hnorms));
     HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     CHK(fetch_norms(s, k, st));
     if (s->h_flag[0]) return fail(SMG_ERR_NONFINITE, "non-finite right-hand side");
@@ -901,6 +946,12 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
     smg_status status = SMG_OK;
     hipGraphExec_t gexec = nullptr;
     if (graphs) CHK(get_cycle_graph(s, k, p->precision, st, &gexec));
+    // Refinement cycles run one part ahead: the next cycle's first part (FP32
+    // buffers only) is enqueued before the host waits for this cycle's
+    // residual norms, so the device does not idle on the convergence test;
+    // when the test ends the solve, that part's result is left unused.
+    const bool ahead = !gexec && p->fixed_cycles <= 0 && p->precision == SMG_FP32_IR;
+    bool pre_queued = false;
     for (;;) {
         double worst = 0.0;
         for (int q = 0; q < k; ++q) worst = std::max(worst, rho[q]);
@@ -912,11 +963,25 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
             status = SMG_ERR_NO_CONVERGENCE;
             break;
         }
-        if (gexec) HIPCHK(hipGraphLaunch(gexec, st));
-        else CHK(cycle_enqueue(s, k, p->precision, st));
+        if (gexec) {
+            HIPCHK(hipGraphLaunch(gexec, st));
+        } else if (ahead) {
+            if (!pre_queued) CHK(cycle_enqueue(s, k, p->precision, st, kCyclePre));
+            s->norm_seq += 1.0;
+            s->h_norms[2 * k] = -1.0;
+            CHK(cycle_enqueue(s, k, p->precision, st, kCycleAfterPre));
+        } else {
+            CHK(cycle_enqueue(s, k, p->precision, st));
+        }
         ++cycles;
         if (p->fixed_cycles > 0 && cycles < p->fixed_cycles) continue;
-        CHK(fetch_norms(s, k, st));
+        if (ahead) {
+            pre_queued = cycles < p->max_cycles;
+            if (pre_queued) CHK(cycle_enqueue(s, k, p->precision, st, kCyclePre));
+            CHK(wait_norms(s, k, s->norm_seq, st));
+        } else {
+            CHK(fetch_norms(s, k, st));
+        }
         for (int q = 0; q < k; ++q) {
             const double rn = std::sqrt(s->h_norms[q]);
             rho[q] = bn[q] > 0.0 ? rn / bn[q] : rn;
@@ -993,7 +1058,7 @@ extern "C" smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const d
     int nblk = 0;
     HIPCHK(launch_spmv_dot(s->mesh.rowptr, s->mesh.cols, d_l_vals, d_lambda, d_u, s->lev[0].n,
                            s->partial, &nblk, st));
-    HIPCHK(launch_reduce_partial(s->partial, nblk, 1, s->norms, st));
+    HIPCHK(launch_reduce_partial(s->partial, nblk, 1, s->norms, st, s->d_hnorms));
     CHK(fetch_norms(s, 1, st));
     *h_out = s->h_norms[0];
     return SMG_OK;

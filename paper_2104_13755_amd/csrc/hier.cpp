@@ -114,13 +114,33 @@ static void build_sell(LevelHost &L, int lpr) {
     S.slice_off.assign(1, 0);
     S.color_slice.assign(1, 0);
     S.row_slice.assign(n, 0);
+    S.color_w.assign(L.ncolors, 0);
+    std::vector<int> ws;
     for (int c = 0; c < L.ncolors; ++c) {
+        // a color whose slices all take its widest slice's rounds costs at
+        // most a quarter more slots; then every slice's offset follows from
+        // its index and a relaxation needs no slice table
+        ws.clear();
+        int64_t sum = 0;
+        int wmax = 0;
         for (int r0 = S.color_row[c]; r0 < S.color_row[c + 1]; r0 += rps) {
             const int r1 = std::min(r0 + rps, S.color_row[c + 1]);
             int w = 0;
-            for (int r = r0; r < r1; ++r) { w = std::max(w, (S.rowlen[r] + lpr - 1) / lpr); S.row_slice[r] = (int)S.slice_row0.size(); }
+            for (int r = r0; r < r1; ++r) w = std::max(w, (S.rowlen[r] + lpr - 1) / lpr);
+            ws.push_back(w);
+            sum += w;
+            wmax = std::max(wmax, w);
+        }
+        if (4 * (int64_t)wmax * (int64_t)ws.size() <= 5 * sum) {
+            S.color_w[c] = wmax;
+            std::fill(ws.begin(), ws.end(), wmax);
+        }
+        int q = 0;
+        for (int r0 = S.color_row[c]; r0 < S.color_row[c + 1]; r0 += rps, ++q) {
+            const int r1 = std::min(r0 + rps, S.color_row[c + 1]);
+            for (int r = r0; r < r1; ++r) S.row_slice[r] = (int)S.slice_row0.size();
             S.slice_row0.push_back(r0);
-            S.slice_off.push_back(S.slice_off.back() + 64 * w);
+            S.slice_off.push_back(S.slice_off.back() + 64 * ws[q]);
         }
         S.color_slice.push_back((int)S.slice_row0.size());
     }

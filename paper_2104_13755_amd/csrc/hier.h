@@ -47,6 +47,7 @@ struct SellLayout {
     std::vector<int32_t> rowlen;     // off-diagonal entries per permuted row
     std::vector<int32_t> color_row;  // ncolors + 1 row boundaries (permuted)
     std::vector<int32_t> color_slice;// ncolors + 1 slice boundaries
+    std::vector<int32_t> color_w;    // per color: rounds of every slice, 0 = per-slice widths
     std::vector<int32_t> row_slice;  // slice index of each permuted row
     std::vector<int32_t> pptr, pidx; // permuted rows' off-diagonal columns, ascending
     int64_t slots() const { return slice_off.empty() ? 0 : slice_off.back(); }

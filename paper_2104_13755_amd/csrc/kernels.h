@@ -27,8 +27,14 @@ struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (sliced EL
 // --- relaxation / residual / transfers (K right-hand sides, 1..4) ---
 // ev0/ev1 (optional): events stamped by the dispatch itself when the kernel
 // starts and ends (hipExtLaunchKernelGGL), for per-launch timing.
+struct ColorSpan {
+    int s_begin, s_end;          // the color's slices
+    int row0, row_end;           // its permuted rows
+    int off0;                    // slot offset of its first slice
+    int w;                       // rounds of every slice when all are equal, else 0 (slice table)
+};
 template <typename T>
-hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T *b, T *x, int k,
+hipError_t launch_gs_color(const SellView<T> &A, const ColorSpan &c, const T *b, T *x, int k,
                            hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // r = b - A x over `nslices` slices; if partial != nullptr also writes
 // per-block (sum r^2, max |r|) per column into partial[blk * 2k ..]; the
@@ -49,8 +55,11 @@ hipError_t launch_prolong_add(const TransferView &P, const T *pw, const T *e, T 
 // column sums of squares and max-abs of a dense n x k array (FP64)
 hipError_t launch_colnorm_partial(const double *v, int n, int k, double *partial, int *nblk,
                                   hipStream_t st);
+// out[0..k) = column sums, out[k..2k) = column maxima; the same values also go
+// to host_out (device address of mapped, coherent host memory) when given,
+// followed by host_out[2k] = seq once they are visible to the host.
 hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double *out,
-                                 hipStream_t st);
+                                 hipStream_t st, double *host_out = nullptr, double seq = 0.0);
 
 // --- coarsest level ---
 hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st);

@@ -126,6 +126,35 @@ __global__ __launch_bounds__(kGsBlock) void k_gs_color(int s_begin, int s_end, i
     }
 }
 
+// The same update for a color whose slices all hold w rounds: a slice's rows
+// and slots follow from its index, so the matrix, diagonal and b loads are
+// issued together (one round trip fewer than through the slice table).
+template <int K, typename T>
+__global__ __launch_bounds__(kGsBlock) void k_gs_color_w(int nsl, int row0, int row_end, int off0, int w,
+                                                       int lpr, const int32_t *__restrict__ cols,
+                                                       const T *__restrict__ vals,
+                                                       const T *__restrict__ diag,
+                                                       const T *__restrict__ b, T *__restrict__ x) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk * (kGsBlock / 64) + (threadIdx.x >> 6);
+    if (s >= nsl) return;
+    const int lane = threadIdx.x & 63;
+    const int lg = __builtin_ctz(lpr);
+    const int r0 = row0 + (s << (6 - lg));
+    const int row = r0 + (lane >> lg);
+    const bool valid = row < row_end;
+    const int rw = valid ? row : r0;
+    const T d = diag[rw];
+    T bq[K], acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { bq[q] = b[(size_t)rw * K + q]; acc[q] = T(0); }
+    row_gather<K, T>(off0 + s * 64 * w + lane, w, lpr, cols, vals, x, acc);
+    if (valid && (lane & (lpr - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) x[(size_t)row * K + q] = (bq[q] - acc[q]) / d;
+    }
+}
+
 // ------------------------------------------------------------------ residual
 // r = b - A x over all slices; optional per-block column (sum r^2, max |r|).
 template <int K, typename T, bool NORM>
@@ -286,7 +315,8 @@ __global__ __launch_bounds__(kBlock) void k_colnorm_partial(const double *__rest
 
 // one block: out[q] = sum_b partial[b][q], out[K+q] = max_b partial[b][K+q]
 __global__ __launch_bounds__(1024) void k_reduce_partial(const double *__restrict__ partial,
-                                                         int nblk, int k, double *__restrict__ out) {
+                                                         int nblk, int k, double *__restrict__ out,
+                                                         double *__restrict__ host_out, double seq) {
     __shared__ double s_sum[1024], s_max[1024];
     for (int q = 0; q < k; ++q) {
         double a = 0.0, m = 0.0;
@@ -304,8 +334,16 @@ __global__ __launch_bounds__(1024) void k_reduce_partial(const double *__restric
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) { out[q] = s_sum[0]; out[k + q] = s_max[0]; }
+        if (threadIdx.x == 0) {
+            out[q] = s_sum[0];
+            out[k + q] = s_max[0];
+            if (host_out) { host_out[q] = s_sum[0]; host_out[k + q] = s_max[0]; }
+        }
         __syncthreads();
+    }
+    if (host_out && threadIdx.x == 0) {   // the host reads the norms once it sees seq
+        __threadfence_system();
+        host_out[2 * k] = seq;
     }
 }
 
@@ -1413,11 +1451,23 @@ inline int nblocks(int64_t n, int per = kBlock) { return (int)((n + per - 1) / p
     default: return hipErrorInvalidValue; }
 
 template <typename T>
-hipError_t launch_gs_color(const SellView<T> &A, int s_begin, int s_end, const T *b, T *x, int k,
+hipError_t launch_gs_color(const SellView<T> &A, const ColorSpan &c, const T *b, T *x, int k,
                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    const int s_begin = c.s_begin, s_end = c.s_end;
     const int ns = s_end - s_begin;
     if (ns <= 0) return hipSuccess;
     const int g = nblocks(ns, kGsBlock / 64);
+    if (c.w > 0) {
+        if (ev0) {
+            SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_gs_color_w<KK, T>, dim3(g), dim3(kGsBlock), 0, st, ev0, ev1, 0,
+                                                   ns, c.row0, c.row_end, c.off0, c.w, A.lpr, A.cols, A.vals,
+                                                   A.diag, b, x)));
+        } else {
+            SMG_K_SWITCH(k, (k_gs_color_w<KK, T><<<g, kGsBlock, 0, st>>>(ns, c.row0, c.row_end, c.off0, c.w, A.lpr,
+                                                                       A.cols, A.vals, A.diag, b, x)));
+        }
+        return hipGetLastError();
+    }
     if (ev0) {
         SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_gs_color<KK, T>, dim3(g), dim3(kGsBlock), 0, st, ev0, ev1, 0,
                                                s_begin, s_end, A.lpr, A.slice_row0, A.slice_off, A.cols,
@@ -1486,8 +1536,8 @@ hipError_t launch_colnorm_partial(const double *v, int n, int k, double *partial
 }
 
 hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double *out,
-                                 hipStream_t st) {
-    k_reduce_partial<<<1, 1024, 0, st>>>(partial, nblk, k, out);
+                                 hipStream_t st, double *host_out, double seq) {
+    k_reduce_partial<<<1, 1024, 0, st>>>(partial, nblk, k, out, host_out, seq);
     return hipGetLastError();
 }
 
@@ -1698,9 +1748,9 @@ hipError_t launch_mass_grad(const double *lam, const double *m, const double *u,
     return hipGetLastError();
 }
 
-template hipError_t launch_gs_color<double>(const SellView<double> &, int, int, const double *,
+template hipError_t launch_gs_color<double>(const SellView<double> &, const ColorSpan &, const double *,
                                             double *, int, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_gs_color<float>(const SellView<float> &, int, int, const float *,
+template hipError_t launch_gs_color<float>(const SellView<float> &, const ColorSpan &, const float *,
                                            float *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_residual<double>(const SellView<double> &, int, const double *,
                                             const double *, double *, int, double *, int *,

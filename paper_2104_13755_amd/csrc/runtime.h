@@ -20,6 +20,8 @@ struct DevLevel {
     bool coarsest = false;
     int64_t slots = 0, nnz_nat = 0;
     std::vector<int32_t> color_slice;      // host copy of slice boundaries per color
+    std::vector<int32_t> color_row_h;      // host copy of row boundaries per color
+    std::vector<int32_t> color_w, color_off;  // per color: uniform rounds (0: none), first slot
     std::vector<int32_t> pat_ptr, pat_idx; // natural CSR pattern (host)
     std::vector<int32_t> store_h;          // natural entry -> storage (host)
     std::vector<int32_t> color_h;          // natural color ids (host)
@@ -92,7 +94,9 @@ struct smg_solver_s {
     int64_t npartial = 0;
     double *norms = nullptr;       // reduced (sum r^2, max |r|) per column
     int *flag = nullptr;           // [0] non-finite, [1] not SPD
-    double *h_norms = nullptr;     // pinned
+    double *h_norms = nullptr;     // pinned, coherent: written by the norm reduction itself
+    double *d_hnorms = nullptr;    // device address of h_norms
+    double norm_seq = 0.0;         // tag the next norm reduction writes after its norms
     int *h_flag = nullptr;         // pinned
     std::vector<void *> owned;
     std::vector<smg::CycleGraph> graphs;
@@ -110,11 +114,14 @@ struct smg_solver_s {
 
 namespace smg {
 smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st);
+// parts of one cycle: all of it, only the first level's pre-relaxation, or
+// everything after that pre-relaxation
+enum CyclePart { kCycleWhole = 0, kCyclePre = 1, kCycleAfterPre = 2 };
 template <typename T>
-smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st);
+smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part = kCycleWhole);
 template <typename T>
 smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t st);
-smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st);
+smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st, int part = kCycleWhole);
 smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st,
                            hipGraphExec_t *out);
 // profiling helpers: begin returns the event pair index or -1; prof_ev gives

@@ -113,6 +113,25 @@ def test_solve_mixed_precision(prob):
     assert err < 1e-6
 
 
+def test_refinement_run_ahead_is_exact(prob):
+    """The mixed-precision solve queues each next cycle's first part before
+    its stop test; the iterate returned is still that of the reported cycle
+    count (bitwise equal to a fixed-count solve, which runs no stop test), and
+    a cycle cap stops it with exactly the capped count."""
+    S = prob.gpu
+    rng = np.random.default_rng(5)
+    b = _t(prob.m[:, None] * rng.uniform(-1, 1, (prob.sizes[0], 3)))
+    x1, i1 = S.solve(b, rtol=1e-9, precision="fp32ir")
+    x2, i2 = S.solve(b, fixed_cycles=i1["cycles"], precision="fp32ir")
+    assert np.array_equal(_np(x1), _np(x2))
+    assert i2["rel_res"] == i1["rel_res"]
+    cap = i1["cycles"] - 1
+    x3, i3 = S.solve(b, rtol=1e-9, max_cycles=cap, precision="fp32ir", raise_on_error=False)
+    x4, _ = S.solve(b, fixed_cycles=cap, precision="fp32ir")
+    assert i3["status"] != 0 and i3["cycles"] == cap
+    assert np.array_equal(_np(x3), _np(x4))
+
+
 def test_graph_replay_and_determinism(prob):
     S = prob.gpu
     rng = np.random.default_rng(4)
