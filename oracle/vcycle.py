@@ -75,12 +75,16 @@ class Solver:
         self.A = As
 
     # --- building blocks -------------------------------------------------
-    def relax(self, l, x, b, sweeps):
-        """Multicolor Gauss-Seidel: for each color in ascending order, every
-        row i of that color becomes (b_i - sum_{j != i} A_ij x_j) / A_ii."""
+    def relax(self, l, x, b, sweeps, descending=False):
+        """Multicolor Gauss-Seidel: for each color in ascending order (or
+        descending), every row i of that color becomes
+        (b_i - sum_{j != i} A_ij x_j) / A_ii."""
         lv = self.levels[l]
+        order = list(zip(lv.rows, lv.off_rows))
+        if descending:
+            order = order[::-1]
         for _ in range(sweeps):
-            for rows, offr in zip(lv.rows, lv.off_rows):
+            for rows, offr in order:
                 x[rows] = (b[rows] - offr @ x) / lv.diag[rows, None]
         return x
 
@@ -97,14 +101,17 @@ class Solver:
         y = sla.solve_triangular(self.G, b, lower=True)
         return sla.solve_triangular(self.G.T, y, lower=False)
 
-    def vcycle(self, l, x, b):
+    def vcycle(self, l, x, b, symmetric=False):
+        """symmetric: post-relaxation visits the colors in descending order,
+        the adjoint of the pre-relaxation (with mu_pre == mu_post the cycle
+        from x = 0 is then a symmetric operator in b)."""
         if l == self.nlev - 1:
             return self.coarse_solve(b)
         x = self.relax(l, x, b, self.mu_pre)
         r = self.restrict(l, self.residual(l, x, b))
-        c = self.vcycle(l + 1, np.zeros_like(r), r)
+        c = self.vcycle(l + 1, np.zeros_like(r), r, symmetric)
         x = x + self.prolong(l, c)
-        return self.relax(l, x, b, self.mu_post)
+        return self.relax(l, x, b, self.mu_post, descending=symmetric)
 
     def solve(self, b, rtol, max_cycles=100, x0=None, fixed_cycles=None):
         """Returns (x, cycles, history of per-column relative residuals)."""
