@@ -221,6 +221,23 @@ typedef struct {
 smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                      const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
 
+/* --- conjugate gradients preconditioned by one V-cycle (the combination
+ * proposed in Sec. "Limitations & Future Work") ---
+ * x = A^{-1} b from x0 = 0, one CG run per column (textbook preconditioned
+ * CG).  The preconditioner is one V-cycle from zero whose post-relaxation
+ * visits the colors in descending order, the adjoint of the pre-relaxation,
+ * so that it is symmetric positive definite (needs mu_pre == mu_post).
+ * Stops when max_c ||r_c|| / ||b_c|| <= p->rtol for the recurrence residual
+ * r; p->max_cycles caps the iterations (one V-cycle each), p->fixed_cycles
+ * > 0 runs exactly that many.  p->precision: SMG_FP64, or SMG_FP32_IR for
+ * an FP32 V-cycle on r scaled by max |r| per column (vectors, dot products
+ * and updates stay FP64).  p->use_graph must be 0.  info->cycles =
+ * iterations, info->rel_res = final recurrence residuals.  The first call
+ * allocates three n x 4 FP64 work vectors.  Errors: INVALID_ARG, STATE,
+ * NONFINITE, NO_CONVERGENCE, OOM. */
+smg_status smg_pcg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                         const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
+
 /* --- adjoint helpers for A = diag(s.*m) + t L (differentiation) --- */
 /* *h_out = lambda^T L u over the level-0 pattern (d_l_vals in CSR order), k = 1 */
 smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const double *d_lambda,

@@ -682,12 +682,13 @@ template <> const double *rwbuf<double>(const DevLevel &D) { return D.rs_w; }
 template <> const float *rwbuf<float>(const DevLevel &D) { return D.rs_w32; }
 
 template <typename T>
-smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st) {
+smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool descending = false) {
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
     for (int sw = 0; sw < sweeps; ++sw)
-        for (int c = 0; c < D.ncolors; ++c) {
+        for (int cc = 0; cc < D.ncolors; ++cc) {
+            const int c = descending ? D.ncolors - 1 - cc : cc;
             const int pi = prof_begin(s, SMG_PROF_GS, l,
                                       D.color_nnz[c] * (sb + 4) + D.color_rows[c] * sb * (1 + 3 * k), st);
             const ColorSpan span{D.color_slice[c], D.color_slice[c + 1], D.color_row_h[c], D.color_row_h[c + 1],
@@ -712,9 +713,10 @@ smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t
 
 // Alg. "V-cycle" from level l with b_l, x_l in the level buffers (x_l in/out).
 // `part` splits off level l's pre-relaxation (empty when level l is the
-// coarsest or runs in the LDS tail).
+// coarsest or runs in the LDS tail); `sym` runs the post-relaxation's colors
+// in descending order (the cycle is then symmetric, for CG).
 template <typename T>
-smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part) {
+smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part, bool sym) {
     DevLevel &D = s->lev[l];
     if (D.coarsest) {
         if (part != kCyclePre)
@@ -725,7 +727,7 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part) 
     if (l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
         if (part != kCyclePre)
             HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
-                                      s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st));
+                                      s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st, sym));
         return SMG_OK;
     }
     DevLevel &C = s->lev[l + 1];
@@ -735,14 +737,14 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part) 
     CHK(residual_level<T>(s, l, k, false, st));                    // r = b - A x'
     // P^T r; the coarse iterate starts from zero
     HIPCHK(launch_restrict<T>(P, rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st, C.coarsest ? nullptr : xbuf<T>(C)));
-    CHK(vcycle_from<T>(s, l + 1, k, st));                           // coarse correction
+    CHK(vcycle_from<T>(s, l + 1, k, st, kCycleWhole, sym));        // coarse correction
     HIPCHK(launch_prolong_add<T>(P, pwbuf<T>(D), xbuf<T>(C), xbuf<T>(D), k, st));  // x' + P c
-    CHK(smooth_level<T>(s, l, k, s->mu_post, st));                 // post-relaxation
+    CHK(smooth_level<T>(s, l, k, s->mu_post, st, sym));            // post-relaxation
     return SMG_OK;
 }
 
-template smg_status vcycle_from<double>(smg_solver_s *, int, int, hipStream_t, int);
-template smg_status vcycle_from<float>(smg_solver_s *, int, int, hipStream_t, int);
+template smg_status vcycle_from<double>(smg_solver_s *, int, int, hipStream_t, int, bool);
+template smg_status vcycle_from<float>(smg_solver_s *, int, int, hipStream_t, int, bool);
 template smg_status residual_level<double>(smg_solver_s *, int, int, bool, hipStream_t);
 template smg_status residual_level<float>(smg_solver_s *, int, int, bool, hipStream_t);
 
@@ -1047,6 +1049,133 @@ smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st
 }
 
 }  // namespace smg
+
+// ------------------------------------------- V-cycle-preconditioned CG
+namespace smg {
+
+// z = B r, B one symmetric V-cycle from zero.  FP64: r in D.b, z in D.x.
+// FP32: r in D.r, scaled by max |r| per column into D.b32 (the scale is
+// s->norms[k + q], left there by the update's reduction), z in D.x32.  The
+// iterate is zero on entry (cleared by the last direction update).
+static smg_status cg_precond(smg_solver_s *s, int k, int precision, hipStream_t st) {
+    DevLevel &D = s->lev[0];
+    if (precision == SMG_FP64) return vcycle_from<double>(s, 0, k, st, kCycleWhole, true);
+    HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
+    return vcycle_from<float>(s, 0, k, st, kCycleWhole, true);
+}
+
+// r.z reduced into out[0..k); then p = z + (out / rz_old) p and z cleared
+static smg_status cg_direction(smg_solver_s *s, int k, int precision, double *out, const double *rz_old,
+                               hipStream_t st) {
+    DevLevel &D = s->lev[0];
+    const bool f32 = precision != SMG_FP64;
+    const double *r = f32 ? D.r : D.b;
+    int nblk = 0;
+    HIPCHK(launch_cg_dot(D.n, r, D.x, f32 ? D.x32 : nullptr, s->norms, k, s->partial, &nblk, st));
+    HIPCHK(launch_reduce_partial(s->partial, nblk, k, out, st));
+    HIPCHK(launch_cg_direction(D.n, out, rz_old, D.x, f32 ? D.x32 : nullptr, s->norms, s->cg_p, k, st));
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+extern "C" smg_status smg_pcg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+                                    const smg_solve_params *p, smg_solve_info *info, smg_stream stream) {
+    CHK(check_level(s, 0, k));
+    if (!d_b || !d_x || !p) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    if (p->precision != SMG_FP64 && p->precision != SMG_FP32_IR) return fail(SMG_ERR_INVALID_ARG, "bad precision");
+    if (p->use_graph) return fail(SMG_ERR_INVALID_ARG, "graph replay is not offered for CG");
+    if (s->mu_pre != s->mu_post) return fail(SMG_ERR_INVALID_ARG, "a symmetric V-cycle needs mu_pre == mu_post");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[0];
+    if (D.coarsest) return smg_solve_single_level(s, d_b, d_x, k, p, info, st);
+    if (!s->cg_x) {
+        const size_t nv = (size_t)D.n * 4;
+        CHK(dalloc(&s->cg_x, nv, s->owned));
+        CHK(dalloc(&s->cg_p, nv, s->owned));
+        CHK(dalloc(&s->cg_ap, nv, s->owned));
+        CHK(dalloc(&s->cg_s, 32, s->owned));
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const int prec = p->precision;
+    const bool f32 = prec != SMG_FP64;
+    double *r = f32 ? D.r : D.b;
+    const int64_t nk = (int64_t)D.n * k;
+    HIPCHK(launch_fill<int>(s->flag, 0, 1, st));
+    HIPCHK(launch_check_finite(d_b, nk, s->flag, st));
+    HIPCHK(launch_gather_rows(D.perm, d_b, r, D.n, k, st));
+    HIPCHK(launch_fill<double>(D.x, 0.0, nk, st));
+    HIPCHK(launch_fill<float>(D.x32, 0.0f, nk, st));
+    HIPCHK(launch_fill<double>(s->cg_x, 0.0, nk, st));
+    int nblk = 0;
+    HIPCHK(launch_colnorm_partial(r, D.n, k, s->partial, &nblk, st));
+    HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st, s->d_hnorms, s->norm_seq));
+    HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(fetch_norms(s, k, st));
+    if (s->h_flag[0]) return fail(SMG_ERR_NONFINITE, "non-finite right-hand side");
+    double bn[4], rho[4];
+    for (int q = 0; q < k; ++q) {
+        bn[q] = std::sqrt(s->h_norms[q]);
+        rho[q] = bn[q] > 0.0 ? 1.0 : 0.0;
+    }
+    // first direction: z = B b, p = z, r.z into slot 0
+    CHK(cg_precond(s, k, prec, st));
+    CHK(cg_direction(s, k, prec, s->cg_s, nullptr, st));
+    int it = 0, cur = 0;
+    smg_status status = SMG_OK;
+    for (;;) {
+        double worst = 0.0;
+        for (int q = 0; q < k; ++q) worst = std::max(worst, rho[q]);
+        if (p->fixed_cycles > 0) {
+            if (it >= p->fixed_cycles) break;
+        } else if (worst <= p->rtol) {
+            break;
+        } else if (it >= p->max_cycles) {
+            status = SMG_ERR_NO_CONVERGENCE;
+            break;
+        }
+        double *rz = s->cg_s + 8 * cur, *rz_next = s->cg_s + 8 * (1 - cur), *pap = s->cg_s + 16;
+        HIPCHK(launch_cg_spmv(sell_view<double>(D), D.nslices, s->cg_p, s->cg_ap, k, s->partial, &nblk, st));
+        HIPCHK(launch_reduce_partial(s->partial, nblk, k, pap, st));
+        s->norm_seq += 1.0;
+        s->h_norms[2 * k] = -1.0;
+        HIPCHK(launch_cg_update(D.n, rz, pap, s->cg_p, s->cg_ap, s->cg_x, r, k, s->partial, &nblk, st));
+        HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st, s->d_hnorms, s->norm_seq));
+        ++it;
+        const bool more = p->fixed_cycles > 0 ? it < p->fixed_cycles : it < p->max_cycles;
+        // the preconditioner leaves x alone: it runs while the host tests r
+        if (more) CHK(cg_precond(s, k, prec, st));
+        if (p->fixed_cycles <= 0 || !more) {
+            CHK(wait_norms(s, k, s->norm_seq, st));
+            for (int q = 0; q < k; ++q) {
+                const double rn = std::sqrt(s->h_norms[q]);
+                rho[q] = bn[q] > 0.0 ? rn / bn[q] : rn;
+                if (!std::isfinite(rho[q])) status = SMG_ERR_NONFINITE;
+            }
+            if (status == SMG_ERR_NONFINITE) break;
+        }
+        if (!more) continue;   // the loop head ends the solve
+        if (p->fixed_cycles <= 0) {
+            double w2 = 0.0;
+            for (int q = 0; q < k; ++q) w2 = std::max(w2, rho[q]);
+            if (w2 <= p->rtol) break;   // the queued preconditioner's result is unused
+        }
+        CHK(cg_direction(s, k, prec, rz_next, rz, st));
+        cur = 1 - cur;
+    }
+    HIPCHK(launch_scatter_rows(D.perm, s->cg_x, d_x, D.n, k, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) {
+        info->cycles = it;
+        info->k = k;
+        for (int q = 0; q < 4; ++q) info->rel_res[q] = q < k ? rho[q] : 0.0;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status == SMG_ERR_NO_CONVERGENCE) return fail(status, "iteration cap reached");
+    if (status == SMG_ERR_NONFINITE) return fail(status, "non-finite residual");
+    return SMG_OK;
+}
 
 // ------------------------------------------------- adjoint helper kernels
 extern "C" smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const double *d_lambda,

@@ -61,6 +61,21 @@ hipError_t launch_colnorm_partial(const double *v, int n, int k, double *partial
 hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double *out,
                                  hipStream_t st, double *host_out = nullptr, double seq = 0.0);
 
+// --- conjugate gradients preconditioned by a V-cycle (level 0, FP64) ---
+// ap = A p; per-block partials of p . ap (sums at [blk][q]) into partial
+hipError_t launch_cg_spmv(const SellView<double> &A, int nslices, const double *p, double *ap, int k,
+                          double *partial, int *nblk, hipStream_t st);
+// alpha = rz / pap per column (0 if pap is 0): x += alpha p, r -= alpha ap;
+// partials of r . r and max |r|
+hipError_t launch_cg_update(int n, const double *rz, const double *pap, const double *p, const double *ap,
+                            double *x, double *r, int k, double *partial, int *nblk, hipStream_t st);
+// partials of r . z; z = z64, or z32 * zscale[k + q] when z32 is given
+hipError_t launch_cg_dot(int n, const double *r, const double *z64, const float *z32, const double *zscale,
+                         int k, double *partial, int *nblk, hipStream_t st);
+// p = z + (rz_new / rz_old) p (p = z when rz_old is null); clears z
+hipError_t launch_cg_direction(int n, const double *rz_new, const double *rz_old, double *z64, float *z32,
+                               const double *zscale, double *p, int k, hipStream_t st);
+
 // --- coarsest level ---
 hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st);
 // Ainv = (G G^T)^{-1} from the Cholesky factor G (W: n x n scratch)
@@ -117,7 +132,8 @@ struct LdsLevel {
 template <typename T>
 hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves,
                            int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
-                           size_t lds_bytes, hipStream_t st);
+                           size_t lds_bytes, hipStream_t st,
+                           bool post_desc = false);
 // grant k_tail_lds<*, T> `bytes` of dynamic LDS
 template <typename T>
 hipError_t tail_lds_allow(size_t bytes);

@@ -220,6 +220,145 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
     }
 }
 
+// -------------------------------------- preconditioned CG on level 0
+// Per-block column partials: partial[blk][q] = sum of v[q], [K + q] = max of m[q].
+template <int K>
+__device__ __forceinline__ void block_partials(const double (&v)[K], const double (&m)[K],
+                                               double *__restrict__ partial) {
+    __shared__ double red[2 * K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double a = wave_sum(v[q]), b = wave_max(m[q]);
+        if (lane == 0) { red[q][wv] = a; red[K + q][wv] = b; }
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i) { a += red[q][i]; b = fmax(b, red[K + q][i]); }
+        partial[(size_t)blockIdx.x * 2 * K + q] = a;
+        partial[(size_t)blockIdx.x * 2 * K + K + q] = b;
+    }
+}
+
+// ap = A p over every slice (diagonal + sliced ELL); partials of p . ap.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(int nslices, int lpr, const int32_t *__restrict__ slice_row0,
+                                                    const int32_t *__restrict__ slice_off,
+                                                    const int32_t *__restrict__ cols,
+                                                    const double *__restrict__ vals,
+                                                    const double *__restrict__ diag,
+                                                    const double *__restrict__ p, double *__restrict__ ap,
+                                                    double *__restrict__ partial) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double pq[K], zero[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { pq[q] = 0.0; zero[q] = 0.0; }
+    if (s < nslices) {
+        const int r0 = slice_row0[s], r1 = slice_row0[s + 1];
+        const int o0 = slice_off[s], o1 = slice_off[s + 1];
+        const int row = r0 + (lane >> __builtin_ctz(lpr));
+        const bool valid = row < r1;
+        const int rw = valid ? row : r0;
+        const int w = (o1 - o0) >> 6;
+        const double d = diag[rw];
+        double pi[K], acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) { pi[q] = p[(size_t)rw * K + q]; acc[q] = 0.0; }
+        row_gather<K, double>(o0 + lane, w, lpr, cols, vals, p, acc);
+        if (valid && (lane & (lpr - 1)) == 0) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const double v = acc[q] + d * pi[q];
+                ap[(size_t)row * K + q] = v;
+                pq[q] = pi[q] * v;
+            }
+        }
+    }
+    block_partials<K>(pq, zero, partial);
+}
+
+// alpha = (r.z) / (p.Ap) per column (0 when p.Ap is 0); x += alpha p,
+// r -= alpha Ap; partials of r.r and max |r|.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int n, const double *__restrict__ rz,
+                                                      const double *__restrict__ pap,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ ap, double *__restrict__ x,
+                                                      double *__restrict__ r, double *__restrict__ partial) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double sq[K], mx[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { sq[q] = 0.0; mx[q] = 0.0; }
+    if (i < n) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double den = pap[q];
+            const double al = den != 0.0 ? rz[q] / den : 0.0;
+            const size_t t = (size_t)i * K + q;
+            x[t] += al * p[t];
+            const double rv = r[t] - al * ap[t];
+            r[t] = rv;
+            sq[q] = rv * rv;
+            mx[q] = fabs(rv);
+        }
+    }
+    block_partials<K>(sq, mx, partial);
+}
+
+// z as the preconditioner left it: FP64 iterate, or the FP32 iterate of the
+// scaled system times the scale (max |r| per column, as in refinement)
+template <int K, bool Z32>
+__device__ __forceinline__ double cg_z(size_t t, int q, const double *z64, const float *z32,
+                                       const double *zscale) {
+    if constexpr (Z32) return (double)z32[t] * zscale[K + q];
+    else return z64[t];
+}
+
+// partials of r . z
+template <int K, bool Z32>
+__global__ __launch_bounds__(kBlock) void k_cg_dot(int n, const double *__restrict__ r,
+                                                   const double *__restrict__ z64, const float *__restrict__ z32,
+                                                   const double *__restrict__ zscale, double *__restrict__ partial) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double v[K], zero[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { v[q] = 0.0; zero[q] = 0.0; }
+    if (i < n)
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const size_t t = (size_t)i * K + q;
+            v[q] = r[t] * cg_z<K, Z32>(t, q, z64, z32, zscale);
+        }
+    block_partials<K>(v, zero, partial);
+}
+
+// p = z + beta p with beta = rz_new / rz_old (0 when rz_old is 0; p = z when
+// rz_old is null); the preconditioner's iterate is cleared for its next use.
+template <int K, bool Z32>
+__global__ __launch_bounds__(kBlock) void k_cg_direction(int n, const double *__restrict__ rz_new,
+                                                         const double *__restrict__ rz_old,
+                                                         double *__restrict__ z64, float *__restrict__ z32,
+                                                         const double *__restrict__ zscale,
+                                                         double *__restrict__ p) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * K) return;
+    const int q = (int)(t % K);
+    const double z = cg_z<K, Z32>((size_t)t, q, z64, z32, zscale);
+    if (rz_old) {
+        const double den = rz_old[q];
+        const double beta = den != 0.0 ? rz_new[q] / den : 0.0;
+        p[t] = z + beta * p[t];
+    } else {
+        p[t] = z;
+    }
+    if constexpr (Z32) z32[t] = 0.0f;
+    else z64[t] = 0.0;
+}
+
 // --------------------------------------------------------------- transfers
 // rc_a = sum_{i} R_ai r_i with R = P^T (gather; deterministic order)
 template <int K, typename T>
@@ -889,14 +1028,16 @@ __device__ __forceinline__ void tail_row(const LdsLevel<T> &L, const int2 *wv, i
         for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
 }
 
-// Multicolor Gauss-Seidel on one tail level (App. A): passes in color order,
-// a barrier after the last pass of every color.
+// Multicolor Gauss-Seidel on one tail level (App. A): passes in color order
+// (descending: colors last to first), a barrier after every color.
 template <int K, int KP, typename T>
-__device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, T *xs, int sweeps) {
+__device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, T *xs, int sweeps,
+                           bool descending = false) {
     const int tid = threadIdx.x, lg = L.lg_grp, G = 1 << lg;
     const int g = tid >> lg, j = tid & (G - 1);
     for (int sw = 0; sw < sweeps; ++sw)
-        for (int p = 0; p < L.npass; ++p) {
+        for (int pp = 0; pp < L.npass; ++pp) {
+            const int p = descending ? L.npass - 1 - pp : pp;
             const int4 P = sp[p];
             const int nta = P.y << lg;
             if (tid < nta) {
@@ -907,7 +1048,8 @@ __device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv
 #pragma unroll
                     for (int q = 0; q < K; ++q) xs[(size_t)row * KP + q] = (bq[q] - acc[q]) / d;
             }
-            if (P.z >> 16) __syncthreads();
+            // a color ends after its last pass, or, going down, its first one
+            if (descending ? (p == 0 || (sp[p - 1].z >> 16)) : (P.z >> 16)) __syncthreads();
         }
 }
 
@@ -1040,7 +1182,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__
                                                            const int4 *__restrict__ passes,
                                                            const int2 *__restrict__ waves, int first,
                                                            int nlev, int mu_pre, int mu_post,
-                                                           const double *__restrict__ Ainv) {
+                                                           const double *__restrict__ Ainv, int post_desc) {
     constexpr int KP = K == 3 ? 4 : K;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nt = blockDim.x, last = nlev - 1;
@@ -1081,7 +1223,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__
         T *xs = xall + (size_t)(L.nsum - base) * KP;
         tail_prolong<K, KP, T>(L, xs, xall + (size_t)(L.nsum + L.n - base) * KP);
         __syncthreads();
-        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_post);
+        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_post, post_desc != 0);
     }
     {
         const int n0 = lv[first].n;
@@ -1581,10 +1723,54 @@ hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv
 template <typename T>
 hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves,
                            int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
-                           size_t lds_bytes, hipStream_t st) {
+                           size_t lds_bytes, hipStream_t st, bool post_desc) {
     SMG_K_SWITCH(k, (k_tail_lds<KK, T><<<1, kTailThreads, lds_bytes, st>>>(
                         lv, reinterpret_cast<const int4 *>(passes), reinterpret_cast<const int2 *>(waves),
-                        first, nlev, mu_pre, mu_post, Ainv)));
+                        first, nlev, mu_pre, mu_post, Ainv, post_desc ? 1 : 0)));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_spmv(const SellView<double> &A, int nslices, const double *p, double *ap, int k,
+                          double *partial, int *nblk, hipStream_t st) {
+    const int g = nblocks(nslices, kBlock / 64);
+    *nblk = g;
+    if (nslices <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_cg_spmv<KK><<<g, kBlock, 0, st>>>(nslices, A.lpr, A.slice_row0, A.slice_off, A.cols,
+                                                         A.vals, A.diag, p, ap, partial)));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(int n, const double *rz, const double *pap, const double *p, const double *ap,
+                            double *x, double *r, int k, double *partial, int *nblk, hipStream_t st) {
+    const int g = nblocks(n);
+    *nblk = g;
+    if (n <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_cg_update<KK><<<g, kBlock, 0, st>>>(n, rz, pap, p, ap, x, r, partial)));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_dot(int n, const double *r, const double *z64, const float *z32, const double *zscale,
+                         int k, double *partial, int *nblk, hipStream_t st) {
+    const int g = nblocks(n);
+    *nblk = g;
+    if (n <= 0) return hipSuccess;
+    if (z32) {
+        SMG_K_SWITCH(k, (k_cg_dot<KK, true><<<g, kBlock, 0, st>>>(n, r, z64, z32, zscale, partial)));
+    } else {
+        SMG_K_SWITCH(k, (k_cg_dot<KK, false><<<g, kBlock, 0, st>>>(n, r, z64, z32, zscale, partial)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(int n, const double *rz_new, const double *rz_old, double *z64, float *z32,
+                               const double *zscale, double *p, int k, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int g = nblocks((int64_t)n * k);
+    if (z32) {
+        SMG_K_SWITCH(k, (k_cg_direction<KK, true><<<g, kBlock, 0, st>>>(n, rz_new, rz_old, z64, z32, zscale, p)));
+    } else {
+        SMG_K_SWITCH(k, (k_cg_direction<KK, false><<<g, kBlock, 0, st>>>(n, rz_new, rz_old, z64, z32, zscale, p)));
+    }
     return hipGetLastError();
 }
 
@@ -1771,9 +1957,9 @@ template hipError_t launch_coarse_solve<double, double>(const double *, int, con
 template hipError_t launch_coarse_solve<float, float>(const double *, int, const float *, float *,
                                                       int, hipStream_t);
 template hipError_t launch_tail_lds<double>(const LdsLevel<double> *, const int32_t *, const int32_t *,
-                                            int, int, int, int, const double *, int, size_t, hipStream_t);
+                                            int, int, int, int, const double *, int, size_t, hipStream_t, bool);
 template hipError_t launch_tail_lds<float>(const LdsLevel<float> *, const int32_t *, const int32_t *,
-                                           int, int, int, int, const double *, int, size_t, hipStream_t);
+                                           int, int, int, int, const double *, int, size_t, hipStream_t, bool);
 template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
 template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);

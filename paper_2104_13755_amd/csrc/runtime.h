@@ -97,6 +97,9 @@ struct smg_solver_s {
     double *h_norms = nullptr;     // pinned, coherent: written by the norm reduction itself
     double *d_hnorms = nullptr;    // device address of h_norms
     double norm_seq = 0.0;         // tag the next norm reduction writes after its norms
+    // preconditioned CG (allocated at its first use): x, p, A p on level 0
+    // (n x 4 each) and column scalars: r.z at [0] / [8] (alternating), p.Ap at [16]
+    double *cg_x = nullptr, *cg_p = nullptr, *cg_ap = nullptr, *cg_s = nullptr;
     int *h_flag = nullptr;         // pinned
     std::vector<void *> owned;
     std::vector<smg::CycleGraph> graphs;
@@ -118,7 +121,8 @@ smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t 
 // everything after that pre-relaxation
 enum CyclePart { kCycleWhole = 0, kCyclePre = 1, kCycleAfterPre = 2 };
 template <typename T>
-smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part = kCycleWhole);
+smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part = kCycleWhole,
+                       bool sym = false);
 template <typename T>
 smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t st);
 smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st, int part = kCycleWhole);

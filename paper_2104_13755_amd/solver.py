@@ -209,6 +209,21 @@ class Solver:
         out = dict(status=st, cycles=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
         return (x if b.dim() == 2 else x[:, 0]), out
 
+    def pcg(self, b, rtol=1e-8, max_iters=100, precision="fp64", fixed_iters=0, raise_on_error=True):
+        """Conjugate gradients preconditioned by one symmetric V-cycle
+        (smg_pcg_solve); returns (x, info) with info["iterations"]."""
+        b2 = b if b.dim() == 2 else b.unsqueeze(1)
+        b2 = _dev_f64(b2.contiguous())
+        k = b2.shape[1]
+        x = torch.empty_like(b2)
+        p = L.SolveParams(float(rtol), int(max_iters), PRECISION[precision], int(fixed_iters), 0)
+        info = L.SolveInfo()
+        st = self._lib.smg_pcg_solve(self._s, _t_ptr(b2), _t_ptr(x), k, ctypes.byref(p), ctypes.byref(info), _stream())
+        if raise_on_error:
+            L.check(st, "pcg")
+        out = dict(status=st, iterations=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
+        return (x if b.dim() == 2 else x[:, 0]), out
+
     def vcycle(self, b, x):
         k = b.shape[1]
         L.check(self._lib.smg_vcycle(self._s, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), k, _stream()), "vcycle")

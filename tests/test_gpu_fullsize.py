@@ -79,3 +79,11 @@ def test_torus_1m_bench_configuration():
         print(f"[full] {prec}: cycles={info['cycles']} oracle residual={res.max():.3e}", flush=True)
         assert res.max() <= 1e-8 * 1.0001
         assert info["cycles"] == 44
+    # V-cycle-preconditioned CG on the same system (FP64 vectors; the stop
+    # test is on the recurrence residual, checked here with the oracle's A)
+    for prec in ("fp64", "fp32ir"):
+        x, info = S.pcg(bd, rtol=1e-8, precision=prec)
+        x = x.cpu().numpy()
+        res = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+        print(f"[full] pcg {prec}: iterations={info['iterations']} oracle residual={res.max():.3e}", flush=True)
+        assert max(info["rel_res"]) <= 1e-8 and res.max() <= 2e-8
