@@ -453,36 +453,43 @@ __global__ __launch_bounds__(kBlock) void k_colnorm_partial(const double *__rest
 }
 
 // one block: out[q] = sum_b partial[b][q], out[K+q] = max_b partial[b][K+q]
-__global__ __launch_bounds__(1024) void k_reduce_partial(const double *__restrict__ partial,
-                                                         int nblk, int k, double *__restrict__ out,
-                                                         double *__restrict__ host_out, double seq) {
-    __shared__ double s_sum[1024], s_max[1024];
-    for (int q = 0; q < k; ++q) {
-        double a = 0.0, m = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            a += partial[(size_t)b * 2 * k + q];
-            m = fmax(m, partial[(size_t)b * 2 * k + k + q]);
-        }
-        s_sum[threadIdx.x] = a;
-        s_max[threadIdx.x] = m;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
-                s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + w]);
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            out[q] = s_sum[0];
-            out[k + q] = s_max[0];
-            if (host_out) { host_out[q] = s_sum[0]; host_out[k + q] = s_max[0]; }
-        }
-        __syncthreads();
+// (each thread folds every 1024th block, then wavefront shuffles, then the
+// 16 wavefronts in order: a fixed summation order, one barrier)
+template <int K>
+__global__ __launch_bounds__(1024) void k_reduce_partial(const double *__restrict__ partial, int nblk,
+                                                         double *__restrict__ out, double *__restrict__ host_out,
+                                                         double seq) {
+    __shared__ double red[2 * K][16];
+    __shared__ double fin[2 * K];
+    double a[K], m[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { a[q] = 0.0; m[q] = 0.0; }
+    for (int b = threadIdx.x; b < nblk; b += 1024) {
+        const double *pb = partial + (size_t)b * 2 * K;
+#pragma unroll
+        for (int q = 0; q < K; ++q) { a[q] += pb[q]; m[q] = fmax(m[q], pb[K + q]); }
     }
-    if (host_out && threadIdx.x == 0) {   // the host reads the norms once it sees seq
-        __threadfence_system();
-        host_out[2 * k] = seq;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double sa = wave_sum(a[q]), sm = wave_max(m[q]);
+        if (lane == 0) { red[q][wv] = sa; red[K + q][wv] = sm; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * K) {
+        const int j = threadIdx.x;
+        double v = 0.0;
+        for (int w = 0; w < 16; ++w) v = j < K ? v + red[j][w] : fmax(v, red[j][w]);
+        fin[j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < 2 * K; ++j) out[j] = fin[j];
+        if (host_out) {   // the host reads the norms once it sees seq
+            for (int j = 0; j < 2 * K; ++j) host_out[j] = fin[j];
+            __threadfence_system();
+            host_out[2 * K] = seq;
+        }
     }
 }
 
@@ -1679,7 +1686,7 @@ hipError_t launch_colnorm_partial(const double *v, int n, int k, double *partial
 
 hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double *out,
                                  hipStream_t st, double *host_out, double seq) {
-    k_reduce_partial<<<1, 1024, 0, st>>>(partial, nblk, k, out, host_out, seq);
+    SMG_K_SWITCH(k, (k_reduce_partial<KK><<<1, 1024, 0, st>>>(partial, nblk, out, host_out, seq)));
     return hipGetLastError();
 }
 
