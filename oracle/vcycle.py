@@ -14,6 +14,10 @@ Follows Alg. "V-cycle" and Alg. "Galerkin Surface Multigrid Solver" (Sec. 5):
   Solve: x = 0; while max_c ||b_c - A x_c|| / ||b_c|| > eps: x = Vcycle(0, x, b)
 
 Readings (the paper is silent or inconsistent):
+  * damped Jacobi (named as an alternative in App. "Ablation Study", no
+    factor given) uses omega = 2/3 unless set: of {0.5, 0.6, 2/3, 0.7,
+    0.75, 0.8} it needed the fewest V-cycles on a jittered 200x80 torus
+    (5 levels; 0.7 took half as many again, 0.75 and above diverged);
   * the correction is added to the pre-relaxed iterate x' (the update line of
     the listing names the un-relaxed iterate; the residual was taken at x');
   * relaxation is multicolor Gauss-Seidel (App. A), colors in ascending
@@ -53,11 +57,15 @@ class Level:
 
 
 class Solver:
-    """Hierarchy (P_l, coloring) fixed at construction; values via set_values."""
+    """Hierarchy (P_l, coloring) fixed at construction; values via set_values.
+    smoother: "gs" (multicolor Gauss-Seidel, the paper's default) or
+    "jacobi" (damped Jacobi with factor omega, the alternative App.
+    "Ablation Study" names)."""
 
-    def __init__(self, Ps, A0, mu_pre=2, mu_post=2):
+    def __init__(self, Ps, A0, mu_pre=2, mu_post=2, smoother="gs", omega=2.0 / 3.0):
         self.P = [P.tocsr() for P in Ps]
         self.mu_pre, self.mu_post = mu_pre, mu_post
+        self.smoother, self.omega = smoother, omega
         self.nlev = len(Ps) + 1
         self.colors = []
         self.set_values(A0, recolor=True)
@@ -78,8 +86,14 @@ class Solver:
     def relax(self, l, x, b, sweeps, descending=False):
         """Multicolor Gauss-Seidel: for each color in ascending order (or
         descending), every row i of that color becomes
-        (b_i - sum_{j != i} A_ij x_j) / A_ii."""
+        (b_i - sum_{j != i} A_ij x_j) / A_ii.
+        Damped Jacobi: every row at once, x <- x + omega D^{-1} (b - A x)
+        (the color order plays no part)."""
         lv = self.levels[l]
+        if self.smoother == "jacobi":
+            for _ in range(sweeps):
+                x = x + self.omega * (b - self.A[l] @ x) / lv.diag[:, None]
+            return x
         order = list(zip(lv.rows, lv.off_rows))
         if descending:
             order = order[::-1]
