@@ -53,6 +53,7 @@ enum {
 };
 
 enum { SMG_FP64 = 0, SMG_FP32_IR = 1 };   /* precision of smg_solve / smg_vcycle */
+enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_JACOBI = 1 };   /* relaxation, smg_set_smoother */
 
 typedef struct smg_hier_s *smg_hier;       /* host-side hierarchy (prolongations) */
 typedef struct smg_solver_s *smg_solver;   /* device-resident solver of one mesh */
@@ -220,6 +221,25 @@ typedef struct {
  * solve (x is always the iterate of info->cycles cycles). */
 smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                      const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
+
+/* --- relaxation method (App. "Ablation Study") ---
+ * SMG_SMOOTH_GS (default): multicolor Gauss-Seidel (App. A), one launch per
+ * color, the small levels in one workgroup.  SMG_SMOOTH_JACOBI: damped
+ * Jacobi x <- x + omega_l D^{-1} (b - A x), one launch per sweep on every
+ * level.  omega in (0, 2) sets omega_l = omega on every level; omega <= 0
+ * (the paper gives no factor) sets omega_l = 2 / (1 + lambda_l) with
+ * lambda_l the Rayleigh quotient of A_l after 20 power steps
+ * v <- D_l^{-1} A_l v from v_i = frac(0.6180339887498949 (i + 1)) - 1/2
+ * (i the natural row index), recomputed whenever the values change.
+ * Applies to every later smooth, V-cycle, solve and PCG call of s (the
+ * Jacobi V-cycle is symmetric as it is); the first Jacobi selection
+ * allocates a second n x 4 iterate per level (FP64 and FP32).  Waits for the
+ * device and drops captured cycle graphs.  Batches take GS solvers only.
+ * Errors: INVALID_ARG (omega >= 2 or NaN, unknown kind), OOM. */
+smg_status smg_set_smoother(smg_solver s, int32_t kind, double omega);
+/* *omega = the Jacobi factor of a smoothed level (host; waits for the
+ * device).  Errors: INVALID_ARG, STATE (GS selected or values not set). */
+smg_status smg_get_jacobi_omega(smg_solver s, int32_t level, double *omega);
 
 /* --- conjugate gradients preconditioned by one V-cycle (the combination
  * proposed in Sec. "Limitations & Future Work") ---

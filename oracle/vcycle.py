@@ -15,9 +15,13 @@ Follows Alg. "V-cycle" and Alg. "Galerkin Surface Multigrid Solver" (Sec. 5):
 
 Readings (the paper is silent or inconsistent):
   * damped Jacobi (named as an alternative in App. "Ablation Study", no
-    factor given) uses omega = 2/3 unless set: of {0.5, 0.6, 2/3, 0.7,
-    0.75, 0.8} it needed the fewest V-cycles on a jittered 200x80 torus
-    (5 levels; 0.7 took half as many again, 0.75 and above diverged);
+    factor given) uses per level omega_l = 2 / (1 + lambda_l), lambda_l an
+    estimate of the largest eigenvalue of D_l^{-1} A_l (power steps, see
+    jacobi_lambda), unless one factor is set.  A single factor is not
+    robust: on a jittered 200x80 torus lambda is 2.8 on levels 0-1 and 1.9
+    below, 2/3 needed 39 cycles, 0.75 diverged, while the per-level rule
+    needs 43 (and omega_l lambda_l < 2 even for estimates well below
+    lambda_l);
   * the correction is added to the pre-relaxed iterate x' (the update line of
     the listing names the un-relaxed iterate; the residual was taken at x');
   * relaxation is multicolor Gauss-Seidel (App. A), colors in ascending
@@ -56,13 +60,37 @@ class Level:
                 self.off_rows.append(off[rows])
 
 
+JACOBI_POWER_STEPS = 20
+
+
+def power_start(n):
+    """Deterministic start vector: v_i = frac(0.6180339887498949 * (i + 1))
+    - 1/2 (the golden-ratio sequence), for natural row index i."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.mod(0.6180339887498949 * i, 1.0) - 0.5
+
+
+def jacobi_lambda(A):
+    """Estimate of the largest eigenvalue of D^{-1} A: JACOBI_POWER_STEPS
+    power steps v <- D^{-1} A v from power_start (no normalization: the
+    growth stays far inside FP64 range), then the Rayleigh quotient
+    (v . A v) / (v . D v)."""
+    d = A.diagonal()
+    v = power_start(A.shape[0])
+    for _ in range(JACOBI_POWER_STEPS):
+        v = (A @ v) / d
+    return float((v @ (A @ v)) / (v @ (d * v)))
+
+
 class Solver:
     """Hierarchy (P_l, coloring) fixed at construction; values via set_values.
     smoother: "gs" (multicolor Gauss-Seidel, the paper's default) or
     "jacobi" (damped Jacobi with factor omega, the alternative App.
     "Ablation Study" names)."""
 
-    def __init__(self, Ps, A0, mu_pre=2, mu_post=2, smoother="gs", omega=2.0 / 3.0):
+    def __init__(self, Ps, A0, mu_pre=2, mu_post=2, smoother="gs", omega=0.0):
+        """omega > 0: that Jacobi factor on every level; omega <= 0: per
+        level 2 / (1 + lambda_l), lambda_l estimated by jacobi_lambda."""
         self.P = [P.tocsr() for P in Ps]
         self.mu_pre, self.mu_post = mu_pre, mu_post
         self.smoother, self.omega = smoother, omega
@@ -78,6 +106,7 @@ class Solver:
             self.colors = [H.coloring(A) for A in As[:-1]]
         self.levels = [Level(A, *self.colors[l]) for l, A in enumerate(As[:-1])]
         self.levels.append(Level(As[-1]))
+        self.omegas = [self.omega if self.omega > 0 else 2.0 / (1.0 + jacobi_lambda(A)) for A in As]
         dense = As[-1].toarray()
         self.G = np.linalg.cholesky(dense)          # lower, A_H = G G^T
         self.A = As
@@ -92,7 +121,7 @@ class Solver:
         lv = self.levels[l]
         if self.smoother == "jacobi":
             for _ in range(sweeps):
-                x = x + self.omega * (b - self.A[l] @ x) / lv.diag[:, None]
+                x = x + self.omegas[l] * (b - self.A[l] @ x) / lv.diag[:, None]
             return x
         order = list(zip(lv.rows, lv.off_rows))
         if descending:

@@ -608,6 +608,21 @@ smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t 
                           hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_cholesky(Lc.dense, Lc.n, s->flag + 1, st));
     HIPCHK(launch_coarse_inverse(Lc.dense, Lc.n, Lc.dense_w, Lc.dense_inv, st));
+    if (s->smoother == SMG_SMOOTH_JACOBI) CHK(jacobi_factors(s, st));
+    return SMG_OK;
+}
+
+// Jacobi factor of every smoothed level into d_omega: the set factor, or
+// 2 / (1 + lambda_l) from the power-step estimate of lambda_max(D^{-1} A_l).
+smg_status jacobi_factors(smg_solver_s *s, hipStream_t st) {
+    for (int l = 0; l < s->nlev; ++l) {
+        DevLevel &D = s->lev[l];
+        if (D.coarsest) continue;
+        if (s->omega > 0.0) HIPCHK(launch_fill<double>(s->d_omega + l, s->omega, 1, st));
+        else HIPCHK(launch_jacobi_factor(SellView<double>{D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals, D.diag},
+                                         D.n, D.nslices, D.perm, s->jac_v, s->jac_u,
+                                         s->partial, s->jac_sums, s->d_omega + l, st));
+    }
     return SMG_OK;
 }
 
@@ -681,8 +696,29 @@ template <typename T> static const T *rwbuf(const DevLevel &D);
 template <> const double *rwbuf<double>(const DevLevel &D) { return D.rs_w; }
 template <> const float *rwbuf<float>(const DevLevel &D) { return D.rs_w32; }
 
+template <typename T> T *xjbuf(DevLevel &D);
+template <> double *xjbuf<double>(DevLevel &D) { return D.xj; }
+template <> float *xjbuf<float>(DevLevel &D) { return D.xj32; }
+
+// damped Jacobi sweeps: x -> xj -> x ...; an odd count copies the result back
+template <typename T>
+smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    const SellView<T> A = sell_view<T>(D);
+    const double sb = sizeof(T);
+    T *x = xbuf<T>(D), *y = xjbuf<T>(D);
+    for (int sw = 0; sw < sweeps; ++sw) {
+        const int pi = prof_begin(s, SMG_PROF_GS, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
+        HIPCHK(launch_jacobi<T>(A, D.nslices, bbuf<T>(D), sw % 2 ? y : x, sw % 2 ? x : y, s->d_omega + l, k, st,
+                                prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
+    }
+    if (sweeps % 2) HIPCHK(hipMemcpyAsync(x, y, (size_t)D.n * k * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return SMG_OK;
+}
+
 template <typename T>
 smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool descending = false) {
+    if (s->smoother == SMG_SMOOTH_JACOBI) return jacobi_level<T>(s, l, k, sweeps, st);
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
@@ -724,7 +760,7 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part, 
         return SMG_OK;
     }
     const int pr = sizeof(T) == 8 ? 0 : 1;
-    if (l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
+    if (s->smoother == SMG_SMOOTH_GS && l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
         if (part != kCyclePre)
             HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
                                       s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st, sym));
@@ -1049,6 +1085,49 @@ smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st
 }
 
 }  // namespace smg
+
+extern "C" smg_status smg_set_smoother(smg_solver s, int32_t kind, double omega) {
+    if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
+    if (kind != SMG_SMOOTH_GS && kind != SMG_SMOOTH_JACOBI) return fail(SMG_ERR_INVALID_ARG, "unknown smoother");
+    if (kind == SMG_SMOOTH_JACOBI && !(omega < 2.0)) return fail(SMG_ERR_INVALID_ARG, "Jacobi damping must be below 2");
+    HIPCHK(hipSetDevice(s->device));
+    if (kind == SMG_SMOOTH_JACOBI && !s->d_omega) {
+        int64_t nmax = 1;
+        for (smg::DevLevel &D : s->lev)
+            if (!D.coarsest) {
+                nmax = std::max<int64_t>(nmax, D.n);
+                CHK(smg::dalloc(&D.xj, (size_t)D.n * 4, s->owned));
+                CHK(smg::dalloc(&D.xj32, (size_t)D.n * 4, s->owned));
+            }
+        CHK(smg::dalloc(&s->jac_v, (size_t)nmax, s->owned));
+        CHK(smg::dalloc(&s->jac_u, (size_t)nmax, s->owned));
+        CHK(smg::dalloc(&s->jac_sums, 4, s->owned));
+        CHK(smg::dalloc(&s->d_omega, (size_t)s->nlev, s->owned));
+    }
+    // captured cycles hold the previous smoother's launches
+    HIPCHK(hipDeviceSynchronize());
+    for (auto &g : s->graphs) if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+    s->smoother = kind;
+    if (kind == SMG_SMOOTH_JACOBI) {
+        s->omega = omega > 0.0 ? omega : 0.0;
+        if (s->values_set) {
+            CHK(smg::jacobi_factors(s, nullptr));
+            HIPCHK(hipDeviceSynchronize());
+        }
+    }
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_get_jacobi_omega(smg_solver s, int32_t level, double *omega) {
+    if (!s || !omega) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    if (level < 0 || level >= s->nlev || s->lev[level].coarsest) return fail(SMG_ERR_INVALID_ARG, "level out of range");
+    if (s->smoother != SMG_SMOOTH_JACOBI || !s->values_set) return fail(SMG_ERR_STATE, "no Jacobi factors (smoother or values not set)");
+    HIPCHK(hipSetDevice(s->device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(omega, s->d_omega + level, sizeof(double), hipMemcpyDeviceToHost));
+    return SMG_OK;
+}
 
 // ------------------------------------------- V-cycle-preconditioned CG
 namespace smg {

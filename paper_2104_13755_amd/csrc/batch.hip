@@ -172,6 +172,7 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
         if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver in batch");
         if (s->device != b->device) return fail(SMG_ERR_INVALID_ARG, "batched solvers must share a device");
         if (s->nlev < 2) return fail(SMG_ERR_INVALID_ARG, "batched solvers need at least two levels");
+        if (s->smoother != SMG_SMOOTH_GS) return fail(SMG_ERR_INVALID_ARG, "batched solvers relax with Gauss-Seidel");
         b->off.push_back((int)b->h64.size());
         for (int l = 0; l < s->nlev; ++l) {
             const DevLevel &D = s->lev[l];

@@ -36,6 +36,18 @@ struct ColorSpan {
 template <typename T>
 hipError_t launch_gs_color(const SellView<T> &A, const ColorSpan &c, const T *b, T *x, int k,
                            hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// damped Jacobi sweep over `nslices` slices: xo = x + omega D^{-1} (b - A x),
+// omega read from device memory (the level's factor)
+template <typename T>
+hipError_t launch_jacobi(const SellView<T> &A, int nslices, const T *b, const T *x, T *xo, const double *omega,
+                         int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// *omega_l = 2 / (1 + lambda), lambda the Rayleigh quotient after
+// kJacobiPowerSteps power steps v <- D^{-1} A v from the golden-ratio start
+// vector of the natural row indices (perm: permuted -> natural); v, u are n
+// scratch doubles, sums two doubles (FP64 level matrix)
+constexpr int kJacobiPowerSteps = 20;
+hipError_t launch_jacobi_factor(const SellView<double> &A, int n, int nslices, const int32_t *perm, double *v,
+                                double *u, double *partial, double *sums, double *omega_l, hipStream_t st);
 // r = b - A x over `nslices` slices; if partial != nullptr also writes
 // per-block (sum r^2, max |r|) per column into partial[blk * 2k ..]; the
 // block count is returned in *nblk.

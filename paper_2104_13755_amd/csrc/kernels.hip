@@ -155,6 +155,111 @@ __global__ __launch_bounds__(kGsBlock) void k_gs_color_w(int nsl, int row0, int 
     }
 }
 
+// Per-block column partials: partial[blk][q] = sum of v[q], [K + q] = max of m[q].
+template <int K>
+__device__ __forceinline__ void block_partials(const double (&v)[K], const double (&m)[K],
+                                               double *__restrict__ partial) {
+    __shared__ double red[2 * K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double a = wave_sum(v[q]), b = wave_max(m[q]);
+        if (lane == 0) { red[q][wv] = a; red[K + q][wv] = b; }
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        const int q = threadIdx.x;
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i) { a += red[q][i]; b = fmax(b, red[K + q][i]); }
+        partial[(size_t)blockIdx.x * 2 * K + q] = a;
+        partial[(size_t)blockIdx.x * 2 * K + K + q] = b;
+    }
+}
+
+// Damped Jacobi (the alternative relaxation of App. "Ablation Study"):
+// xo_i = x_i + omega (b_i - sum_j A_ij x_j) / A_ii for every row at once.
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(int nslices, int lpr, const int32_t *__restrict__ slice_row0,
+                                                   const int32_t *__restrict__ slice_off,
+                                                   const int32_t *__restrict__ cols,
+                                                   const T *__restrict__ vals, const T *__restrict__ diag,
+                                                   const T *__restrict__ b, const T *__restrict__ x,
+                                                   T *__restrict__ xo, const double *__restrict__ omega_l) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    if (s >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int r0 = slice_row0[s], r1 = slice_row0[s + 1];
+    const int o0 = slice_off[s], o1 = slice_off[s + 1];
+    const int row = r0 + (lane >> __builtin_ctz(lpr));
+    const bool valid = row < r1;
+    const int rw = valid ? row : r0;
+    const int w = (o1 - o0) >> 6;
+    const T d = diag[rw];
+    const T omega = (T)*omega_l;
+    T bq[K], xi[K], acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        bq[q] = b[(size_t)rw * K + q];
+        xi[q] = x[(size_t)rw * K + q];
+        acc[q] = T(0);
+    }
+    row_gather<K, T>(o0 + lane, w, lpr, cols, vals, x, acc);
+    if (valid && (lane & (lpr - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) xo[(size_t)row * K + q] = xi[q] + omega * (bq[q] - (acc[q] + d * xi[q])) / d;
+    }
+}
+
+// Estimate of the largest eigenvalue of D^{-1} A for the Jacobi factor:
+// v_r = frac(phi^-1 (natural index + 1)) - 1/2, then power steps
+// v <- D^{-1} A v (FINAL = false), then partials of v . A v and v . D v
+// (FINAL = true, two sums per block).
+__global__ __launch_bounds__(kBlock) void k_power_start(int n, const int32_t *__restrict__ perm,
+                                                        double *__restrict__ v) {
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n) return;
+    const double i = (double)perm[r] + 1.0;
+    const double t = 0.6180339887498949 * i;
+    v[r] = (t - floor(t)) - 0.5;
+}
+
+template <bool FINAL>
+__global__ __launch_bounds__(kBlock) void k_power_step(int nslices, int lpr, const int32_t *__restrict__ slice_row0,
+                                                       const int32_t *__restrict__ slice_off,
+                                                       const int32_t *__restrict__ cols,
+                                                       const double *__restrict__ vals,
+                                                       const double *__restrict__ diag,
+                                                       const double *__restrict__ v, double *__restrict__ vo,
+                                                       double *__restrict__ partial) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double sums[2] = {0.0, 0.0}, zero[2] = {0.0, 0.0};
+    if (s < nslices) {
+        const int r0 = slice_row0[s], r1 = slice_row0[s + 1];
+        const int o0 = slice_off[s], o1 = slice_off[s + 1];
+        const int row = r0 + (lane >> __builtin_ctz(lpr));
+        const bool valid = row < r1;
+        const int rw = valid ? row : r0;
+        const int w = (o1 - o0) >> 6;
+        const double d = diag[rw], vi = v[rw];
+        double acc[1] = {0.0};
+        row_gather<1, double>(o0 + lane, w, lpr, cols, vals, v, acc);
+        if (valid && (lane & (lpr - 1)) == 0) {
+            const double av = acc[0] + d * vi;
+            if (FINAL) { sums[0] = vi * av; sums[1] = vi * d * vi; }
+            else vo[row] = av / d;
+        }
+    }
+    if (FINAL) block_partials<2>(sums, zero, partial);
+}
+
+// omega_l = 2 / (1 + lambda), lambda = (v . A v) / (v . D v)
+__global__ void k_power_omega(const double *__restrict__ sums, double *__restrict__ omega_l) {
+    if (threadIdx.x == 0) *omega_l = 2.0 / (1.0 + sums[0] / sums[1]);
+}
+
 // ------------------------------------------------------------------ residual
 // r = b - A x over all slices; optional per-block column (sum r^2, max |r|).
 template <int K, typename T, bool NORM>
@@ -221,27 +326,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
 }
 
 // -------------------------------------- preconditioned CG on level 0
-// Per-block column partials: partial[blk][q] = sum of v[q], [K + q] = max of m[q].
-template <int K>
-__device__ __forceinline__ void block_partials(const double (&v)[K], const double (&m)[K],
-                                               double *__restrict__ partial) {
-    __shared__ double red[2 * K][kBlock / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        const double a = wave_sum(v[q]), b = wave_max(m[q]);
-        if (lane == 0) { red[q][wv] = a; red[K + q][wv] = b; }
-    }
-    __syncthreads();
-    if (threadIdx.x < K) {
-        const int q = threadIdx.x;
-        double a = 0.0, b = 0.0;
-        for (int i = 0; i < kBlock / 64; ++i) { a += red[q][i]; b = fmax(b, red[K + q][i]); }
-        partial[(size_t)blockIdx.x * 2 * K + q] = a;
-        partial[(size_t)blockIdx.x * 2 * K + K + q] = b;
-    }
-}
-
 // ap = A p over every slice (diagonal + sliced ELL); partials of p . ap.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(int nslices, int lpr, const int32_t *__restrict__ slice_row0,
@@ -1629,6 +1713,39 @@ hipError_t launch_gs_color(const SellView<T> &A, const ColorSpan &c, const T *b,
 }
 
 template <typename T>
+hipError_t launch_jacobi(const SellView<T> &A, int nslices, const T *b, const T *x, T *xo, const double *omega,
+                         int k, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+    if (nslices <= 0) return hipSuccess;
+    const int g = nblocks(nslices, kBlock / 64);
+    if (ev0) {
+        SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_jacobi<KK, T>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
+                                               nslices, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals,
+                                               A.diag, b, x, xo, omega)));
+    } else {
+        SMG_K_SWITCH(k, (k_jacobi<KK, T><<<g, kBlock, 0, st>>>(nslices, A.lpr, A.slice_row0, A.slice_off, A.cols,
+                                                               A.vals, A.diag, b, x, xo, omega)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_factor(const SellView<double> &A, int n, int nslices, const int32_t *perm, double *v,
+                                double *u, double *partial, double *sums, double *omega_l, hipStream_t st) {
+    if (n <= 0 || nslices <= 0) return hipSuccess;
+    const int g = nblocks(nslices, kBlock / 64);
+    k_power_start<<<nblocks(n), kBlock, 0, st>>>(n, perm, v);
+    for (int i = 0; i < kJacobiPowerSteps; ++i) {
+        k_power_step<false><<<g, kBlock, 0, st>>>(nslices, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
+                                                  v, u, nullptr);
+        double *t = v; v = u; u = t;
+    }
+    k_power_step<true><<<g, kBlock, 0, st>>>(nslices, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
+                                             v, nullptr, partial);
+    k_reduce_partial<2><<<1, 1024, 0, st>>>(partial, g, sums, nullptr, 0.0);
+    k_power_omega<<<1, 64, 0, st>>>(sums, omega_l);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const T *x, T *r,
                            int k, double *partial, int *nblk, hipStream_t st, hipEvent_t ev0,
                            hipEvent_t ev1) {
@@ -1945,6 +2062,10 @@ template hipError_t launch_gs_color<double>(const SellView<double> &, const Colo
                                             double *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_gs_color<float>(const SellView<float> &, const ColorSpan &, const float *,
                                            float *, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_jacobi<double>(const SellView<double> &, int, const double *, const double *,
+                                          double *, const double *, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_jacobi<float>(const SellView<float> &, int, const float *, const float *, float *,
+                                         const double *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_residual<double>(const SellView<double> &, int, const double *,
                                             const double *, double *, int, double *, int *,
                                             hipStream_t, hipEvent_t, hipEvent_t);

@@ -209,6 +209,17 @@ class Solver:
         out = dict(status=st, cycles=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
         return (x if b.dim() == 2 else x[:, 0]), out
 
+    def set_smoother(self, kind="gs", omega=0.0):
+        """Relaxation for every later call: "gs" (multicolor Gauss-Seidel)
+        or "jacobi" (damped Jacobi; omega > 0 on every level, omega <= 0 per
+        level from the largest eigenvalue estimate of D^{-1} A)."""
+        L.check(self._lib.smg_set_smoother(self._s, {"gs": 0, "jacobi": 1}[kind], float(omega)), "set_smoother")
+
+    def jacobi_omega(self, level):
+        w = ctypes.c_double()
+        L.check(self._lib.smg_get_jacobi_omega(self._s, int(level), ctypes.byref(w)), "jacobi_omega")
+        return w.value
+
     def pcg(self, b, rtol=1e-8, max_iters=100, precision="fp64", fixed_iters=0, raise_on_error=True):
         """Conjugate gradients preconditioned by one symmetric V-cycle
         (smg_pcg_solve); returns (x, info) with info["iterations"]."""

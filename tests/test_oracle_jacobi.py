@@ -60,3 +60,23 @@ def test_jacobi_cycle_is_spd_and_converges(ico3):
     assert np.all(np.diff(hist.max(axis=1)) < 0)       # residual falls every cycle
     xp, its, _ = PCG.pcg(A, b, lambda r: S.vcycle(0, np.zeros_like(r), r), 1e-12)
     assert np.abs(xp - xs).max() < 1e-10 * np.abs(xs).max() and its < cyc
+
+
+def test_lambda_estimate_and_level_factors(ico3):
+    """The power-step estimate of lambda_max(D^{-1} A) is a Rayleigh quotient
+    (never above the largest eigenvalue, computed densely here) and within 10%
+    of it on every level (the factor 2 / (1 + lambda) keeps omega lambda < 2
+    for any estimate above lambda - 1); a diagonal matrix gives exactly 1."""
+    V, F, A, L, m, Ps = ico3
+    S = VC.Solver(Ps, A, smoother="jacobi")
+    for l, Al in enumerate(S.A[:-1]):
+        d = Al.diagonal()
+        Ad = Al.toarray() / np.sqrt(np.outer(d, d))
+        lam = np.linalg.eigvalsh(Ad).max()
+        est = VC.jacobi_lambda(Al)
+        assert est <= lam * (1 + 1e-12) and est >= 0.9 * lam, (l, est, lam)
+        assert abs(S.omegas[l] - 2.0 / (1.0 + est)) < 1e-15
+    M = AS.system(V, F, 0.0)[0]
+    assert VC.jacobi_lambda(M) == 1.0
+    assert VC.Solver([], M, smoother="jacobi").omegas == [1.0]
+    assert VC.Solver(Ps, A, smoother="jacobi", omega=0.7).omegas == [0.7] * (len(Ps) + 1)
