@@ -700,14 +700,20 @@ template <typename T> T *xjbuf(DevLevel &D);
 template <> double *xjbuf<double>(DevLevel &D) { return D.xj; }
 template <> float *xjbuf<float>(DevLevel &D) { return D.xj32; }
 
-// damped Jacobi sweeps: x -> xj -> x ...; an odd count copies the result back
+// damped Jacobi sweeps: x -> xj -> x ...; an odd count copies the result back.
+// x_zero: the iterate is zero on entry (a coarse level's pre-relaxation), so
+// the first sweep needs no matrix.
 template <typename T>
-smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st) {
+smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool x_zero) {
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
     T *x = xbuf<T>(D), *y = xjbuf<T>(D);
     for (int sw = 0; sw < sweeps; ++sw) {
+        if (sw == 0 && x_zero) {
+            HIPCHK(launch_jacobi_first<T>(D.n, k, A.diag, bbuf<T>(D), y, s->d_omega + l, st));
+            continue;
+        }
         const int pi = prof_begin(s, SMG_PROF_GS, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
         HIPCHK(launch_jacobi<T>(A, D.nslices, bbuf<T>(D), sw % 2 ? y : x, sw % 2 ? x : y, s->d_omega + l, k, st,
                                 prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
@@ -717,8 +723,9 @@ smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
 }
 
 template <typename T>
-smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool descending = false) {
-    if (s->smoother == SMG_SMOOTH_JACOBI) return jacobi_level<T>(s, l, k, sweeps, st);
+smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool descending = false,
+                        bool x_zero = false) {
+    if (s->smoother == SMG_SMOOTH_JACOBI) return jacobi_level<T>(s, l, k, sweeps, st, x_zero);
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
@@ -768,7 +775,8 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part, 
     }
     DevLevel &C = s->lev[l + 1];
     const TransferView P = transfer_view(D, C);
-    if (part != kCycleAfterPre) CHK(smooth_level<T>(s, l, k, s->mu_pre, st));   // pre-relaxation
+    // pre-relaxation; below level 0 the iterate starts at zero (cleared by the restriction)
+    if (part != kCycleAfterPre) CHK(smooth_level<T>(s, l, k, s->mu_pre, st, false, l > 0));
     if (part == kCyclePre) return SMG_OK;
     CHK(residual_level<T>(s, l, k, false, st));                    // r = b - A x'
     // P^T r; the coarse iterate starts from zero

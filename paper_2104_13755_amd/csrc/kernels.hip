@@ -211,6 +211,18 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int nslices, int lpr, const i
     }
 }
 
+// The first Jacobi sweep from a zero iterate: xo = omega b / A_ii (no
+// gathers; the same operations as a sweep with x = 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_first(int64_t nk, int k, const T *__restrict__ diag,
+                                                         const T *__restrict__ b, T *__restrict__ xo,
+                                                         const double *__restrict__ omega_l) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nk) return;
+    const T omega = (T)*omega_l;
+    xo[t] = omega * (b[t] - T(0)) / diag[t / k];
+}
+
 // Estimate of the largest eigenvalue of D^{-1} A for the Jacobi factor:
 // v_r = frac(phi^-1 (natural index + 1)) - 1/2, then power steps
 // v <- D^{-1} A v (FINAL = false), then partials of v . A v and v . D v
@@ -733,29 +745,37 @@ __global__ __launch_bounds__(kBlock) void k_inverse_product(const double *__rest
     Ainv[(size_t)j * n + i] = s;
 }
 
-// x = A_H^{-1} b (the coarsest direct solve), 4 lanes per row, FP64
-// accumulation; Ainv symmetric so column i is row i.
+// x = A_H^{-1} b (the coarsest direct solve), one wavefront per row, FP64
+// accumulation; A_H^{-1} is exactly symmetric (each entry is the same sum of
+// the same products for (i, j) and (j, i)), so row i is read contiguously.
 template <int K, typename Tin, typename Tout>
 __global__ __launch_bounds__(kBlock) void k_coarse_apply(const double *__restrict__ Ainv, int n,
                                                          const Tin *__restrict__ b,
                                                          Tout *__restrict__ x) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int i = t >> 2, j = t & 3;
+    constexpr int CH = 4;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= n) return;   // whole wavefronts leave together
+    const double *row = Ainv + (size_t)i * n;
     double acc[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.0;
-    if (i < n)
-        for (int jj = j; jj < n; jj += 4) {
-            const double a = Ainv[(size_t)jj * n + i];
+    for (int j0 = lane; j0 < n; j0 += 64 * CH) {
+        double a[CH], bv[CH][K];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(size_t)jj * K + q];
+        for (int u = 0; u < CH; ++u) {   // all loads of a chunk in flight; columns past n weigh 0
+            const int j = min(j0 + 64 * u, n - 1);
+            a[u] = j0 + 64 * u < n ? row[j] : 0.0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) bv[u][q] = (double)b[(size_t)j * K + q];
         }
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-        acc[q] += __shfl_xor(acc[q], 1, 64);
-        acc[q] += __shfl_xor(acc[q], 2, 64);
+        for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] += a[u] * bv[u][q];
     }
-    if (i < n && j == 0) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < K; ++q) x[(size_t)i * K + q] = (Tout)acc[q];
     }
@@ -1728,6 +1748,18 @@ hipError_t launch_jacobi(const SellView<T> &A, int nslices, const T *b, const T 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_jacobi_first(int n, int k, const T *diag, const T *b, T *xo, const double *omega, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nk = (int64_t)n * k;
+    k_jacobi_first<T><<<nblocks(nk), kBlock, 0, st>>>(nk, k, diag, b, xo, omega);
+    return hipGetLastError();
+}
+template hipError_t launch_jacobi_first<double>(int, int, const double *, const double *, double *, const double *,
+                                                hipStream_t);
+template hipError_t launch_jacobi_first<float>(int, int, const float *, const float *, float *, const double *,
+                                               hipStream_t);
+
 hipError_t launch_jacobi_factor(const SellView<double> &A, int n, int nslices, const int32_t *perm, double *v,
                                 double *u, double *partial, double *sums, double *omega_l, hipStream_t st) {
     if (n <= 0 || nslices <= 0) return hipSuccess;
@@ -1826,7 +1858,7 @@ template <typename Tin, typename Tout>
 hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x, int k,
                                hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    SMG_K_SWITCH(k, (k_coarse_apply<KK, Tin, Tout><<<nblocks(4 * (int64_t)n), kBlock, 0, st>>>(Ainv, n, b, x)));
+    SMG_K_SWITCH(k, (k_coarse_apply<KK, Tin, Tout><<<nblocks(n, kBlock / 64), kBlock, 0, st>>>(Ainv, n, b, x)));
     return hipGetLastError();
 }
 
