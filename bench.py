@@ -312,6 +312,70 @@ def bench_jacobi(args):
         "cycles": res["cycles"], "pcg": res["pcg"]}), flush=True)
 
 
+def bench_split(args):
+    """Split Galerkin (App. E) on the benchmark mesh: a sweep of t over 10
+    values in [1e-3, 1e-1] (A = M + t L), each solved to 1e-8 with FP32
+    cycles; the levels of L and M are kept once, so a new t costs one axpby
+    per level plus the coarsest factorization, against re-assembly and the
+    Galerkin products."""
+    import torch
+    import synth
+    rtol = 1e-8
+    w = synth.workload_c2(*args.size)
+    S, h, Vd, b, setup = gpu_setup(w, 7)
+    _, lv, m = S.assemble(Vd, w["t"], want_l=True, want_mass=True)
+    rp = torch.tensor(S.rowptr, dtype=torch.int64, device="cuda")
+    ci = torch.tensor(S.cols, dtype=torch.int64, device="cuda")
+    rows = torch.repeat_interleave(torch.arange(len(rp) - 1, device="cuda"), rp[1:] - rp[:-1])
+    mv = torch.where(rows == ci, m[rows], torch.zeros_like(lv))
+    S.split_prepare(lv, mv)
+    ts = [float(x) for x in np.logspace(-3, -1, 10)]
+
+    def sweep(split):
+        cyc = 0
+        for t in ts:
+            if split:
+                S.split_combine(t, 1.0)
+            else:
+                a, _, _ = S.assemble(Vd, t)
+                S.set_values(a)
+            x, info = S.solve(b, rtol=rtol, precision="fp32ir")
+            cyc += info["cycles"]
+        return cyc
+    res = {}
+    for split in (True, False):
+        for _ in range(max(1, args.warmup // 5)):
+            sweep(split)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(1, args.steps // 10)
+        for _ in range(reps):
+            cyc = sweep(split)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (reps * len(ts))
+        res["split" if split else "full"] = dict(value=1.0 / dt, ms_per_step=dt * 1e3, cycles_per_sweep=cyc)
+        log(f"split={split}: {dt * 1e3:.2f} ms per t, {cyc} cycles per sweep")
+    # refresh cost alone
+    torch.cuda.synchronize(); t0 = time.perf_counter()
+    for t in ts:
+        S.split_combine(t, 1.0)
+    torch.cuda.synchronize(); t_comb = (time.perf_counter() - t0) / len(ts)
+    t0 = time.perf_counter()
+    for t in ts:
+        a, _, _ = S.assemble(Vd, t)
+        S.set_values(a)
+    torch.cuda.synchronize(); t_full = (time.perf_counter() - t0) / len(ts)
+    print(json.dumps({
+        "metric": "parameter sweep solves/s at 1M verts (A = M + t L, 10 values of t, rel residual 1e-8, split Galerkin)",
+        "value": res["split"]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["split"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']} torus, 3 RHS b=M X, 7 levels, t in logspace(-3,-1,10), FP32 cycles",
+                   "vertices": len(w["V"]), "levels": h.sizes, "rhs": 3},
+        "split": res["split"], "full_refresh": res["full"],
+        "refresh_ms": {"split_combine": t_comb * 1e3, "assemble_and_galerkin": t_full * 1e3}}), flush=True)
+
+
 def bench_frames(args):
     """Time-varying A: 2M-vertex height-field disc, per-frame edge weights and
     t, on-device re-assembly + Galerkin over 8 levels + Cholesky + FP32/FP64-IR
@@ -359,7 +423,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--profile-kind", default="gs")
-    ap.add_argument("--workload", default="torus", choices=["torus", "batch", "grad", "frames", "pcg", "jacobi"])
+    ap.add_argument("--workload", default="torus", choices=["torus", "batch", "grad", "frames", "pcg", "jacobi", "split"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--tune-cache", default=None)
@@ -385,6 +449,8 @@ def main():
         return bench_pcg(args)
     if args.workload == "jacobi":
         return bench_jacobi(args)
+    if args.workload == "split":
+        return bench_split(args)
     rtol = 1e-8
     n_levels = 7
     w = synth.workload_c2(*args.size)

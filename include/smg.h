@@ -222,6 +222,20 @@ typedef struct {
 smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                      const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
 
+/* --- split Galerkin (App. E): P^T (a Q + b M) P = a P^T Q P + b P^T M P ---
+ * smg_split_prepare runs the Galerkin products of two level-0 matrices on
+ * the solver's pattern (device CSR values in smg_set_values order; e.g. the
+ * cotan Laplacian and the lumped mass) and keeps every level of both (two
+ * extra copies of the level values).  smg_split_combine then sets the
+ * values to a Q + b M on every level with one a x + b y per level plus the
+ * FP32 copies, LDS-tail records, coarsest Cholesky/inverse (and Jacobi
+ * factors), i.e. a change of a and b needs no assembly and no Galerkin
+ * product.  prepare leaves no values set; combine waits for the device.
+ * Errors: INVALID_ARG, STATE (combine before prepare), NONFINITE (prepare),
+ * NOT_SPD (combine), OOM. */
+smg_status smg_split_prepare(smg_solver s, const double *d_q_vals, const double *d_m_vals, smg_stream stream);
+smg_status smg_split_combine(smg_solver s, double a, double b, smg_stream stream);
+
 /* --- relaxation method (App. "Ablation Study") ---
  * SMG_SMOOTH_GS (default): multicolor Gauss-Seidel (App. A), one launch per
  * color, the small levels in one workgroup.  SMG_SMOOTH_JACOBI: damped

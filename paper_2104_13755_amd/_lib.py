@@ -76,6 +76,8 @@ SIGNATURES = {
     "smg_vcycle": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "smg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_set_smoother": (c_int32, [c_void_p, c_int32, ctypes.c_double]),
+    "smg_split_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "smg_split_combine": (c_int32, [c_void_p, ctypes.c_double, ctypes.c_double, c_void_p]),
     "smg_get_jacobi_omega": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_double)]),
     "smg_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_spmv_dot": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, P_f64, c_void_p]),

@@ -570,9 +570,88 @@ extern "C" smg_status smg_set_values(smg_solver s, const double *d_a0_vals, smg_
     return SMG_OK;
 }
 
+// ------------------------------------------- split Galerkin (App. E)
+// Galerkin products are linear in A: P^T (a Q + b M) P = a P^T Q P + b P^T M P.
+// smg_split_prepare keeps every level of Q and of M; smg_split_combine forms
+// the levels of a Q + b M with one axpby per level.
+static smg_status split_keep(smg_solver_s *s, int which, hipStream_t st) {
+    for (DevLevel &D : s->lev) {
+        double *v = which ? D.sm_vals : D.sq_vals, *d = which ? D.sm_diag : D.sq_diag;
+        if (D.coarsest) {
+            HIPCHK(hipMemcpyAsync(v, D.dense_a, (size_t)D.n * D.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        } else {
+            HIPCHK(hipMemcpyAsync(v, D.vals, (size_t)D.slots * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(d, D.diag, (size_t)D.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+    }
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_split_prepare(smg_solver s, const double *d_q_vals, const double *d_m_vals,
+                                        smg_stream stream) {
+    if (!s || !d_q_vals || !d_m_vals) return fail(SMG_ERR_INVALID_ARG, "smg_split_prepare: null argument");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (!s->split_ready_alloc) {
+        for (DevLevel &D : s->lev) {
+            const size_t nv = D.coarsest ? (size_t)D.n * D.n : (size_t)D.slots;
+            CHK(dalloc(&D.sq_vals, nv, s->owned));
+            CHK(dalloc(&D.sm_vals, nv, s->owned));
+            if (!D.coarsest) {
+                CHK(dalloc(&D.sq_diag, (size_t)D.n, s->owned));
+                CHK(dalloc(&D.sm_diag, (size_t)D.n, s->owned));
+            }
+        }
+        s->split_ready_alloc = true;
+    }
+    s->values_set = false;
+    s->split_ready = false;
+    int bad = 0;
+    for (int which = 0; which < 2; ++which) {
+        CHK(galerkin_values(s, which ? d_m_vals : d_q_vals, st));
+        CHK(split_keep(s, which, st));
+        HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bad |= s->h_flag[0];
+    }
+    if (bad) return fail(SMG_ERR_NONFINITE, "non-finite matrix value");
+    s->split_ready = true;
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_split_combine(smg_solver s, double a, double b, smg_stream stream) {
+    if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
+    if (!s->split_ready) return fail(SMG_ERR_STATE, "smg_split_prepare has not run");
+    if (!std::isfinite(a) || !std::isfinite(b)) return fail(SMG_ERR_INVALID_ARG, "non-finite coefficient");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(launch_fill<int>(s->flag, 0, 2, st));
+    for (DevLevel &D : s->lev) {
+        if (D.coarsest) {
+            HIPCHK(launch_axpby((int64_t)D.n * D.n, a, D.sq_vals, b, D.sm_vals, D.dense_a, st));
+        } else {
+            HIPCHK(launch_axpby(D.slots, a, D.sq_vals, b, D.sm_vals, D.vals, st));
+            HIPCHK(launch_axpby(D.n, a, D.sq_diag, b, D.sm_diag, D.diag, st));
+        }
+    }
+    CHK(finish_values(s, st));
+    HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (s->h_flag[1]) { s->values_set = false; return fail(SMG_ERR_NOT_SPD, "coarsest Cholesky: non-positive pivot"); }
+    s->values_set = true;
+    return SMG_OK;
+}
+
 namespace smg {
 
 smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st) {
+    CHK(galerkin_values(s, d_a0_vals, st));
+    return finish_values(s, st);
+}
+
+// A_0 values into level 0 and every Galerkin product A_{l+1} = P_l^T A_l P_l
+// (FP64 values and diagonals, dense A_H on the coarsest level)
+smg_status galerkin_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st) {
     HIPCHK(launch_fill<int>(s->flag, 0, 2, st));
     for (int l = 0; l < s->nlev; ++l) {
         DevLevel &D = s->lev[l];
@@ -593,6 +672,12 @@ smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t 
         HIPCHK(launch_galerkin_c(C.n, D.cmax, D.plan2ptr, D.plan2, D.rptr, D.ridx, D.rw, D.tptr, s->tbuf,
                                  D.optr, D.opos, C.coarsest ? C.dense_a : C.vals, C.coarsest ? nullptr : C.diag, st));
     }
+    return SMG_OK;
+}
+
+// everything derived from the FP64 level values: FP32 copies, LDS-tail
+// records, the coarsest factor and inverse, Jacobi factors
+smg_status finish_values(smg_solver_s *s, hipStream_t st) {
     for (int l = 0; l < s->nlev; ++l) {
         DevLevel &D = s->lev[l];
         if (D.coarsest) continue;

@@ -41,6 +41,9 @@ hipError_t launch_gs_color(const SellView<T> &A, const ColorSpan &c, const T *b,
 template <typename T>
 hipError_t launch_jacobi(const SellView<T> &A, int nslices, const T *b, const T *x, T *xo, const double *omega,
                          int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// out = a x + b y over n doubles
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
+                        hipStream_t st);
 // first sweep from x = 0: xo = omega b / A_ii
 template <typename T>
 hipError_t launch_jacobi_first(int n, int k, const T *diag, const T *b, T *xo, const double *omega, hipStream_t st);

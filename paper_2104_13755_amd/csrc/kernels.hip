@@ -211,6 +211,13 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int nslices, int lpr, const i
     }
 }
 
+// out = a x + b y (split Galerkin levels, App. E)
+__global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, double a, const double *__restrict__ x, double b,
+                                                  const double *__restrict__ y, double *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) out[t] = a * x[t] + b * y[t];
+}
+
 // The first Jacobi sweep from a zero iterate: xo = omega b / A_ii (no
 // gathers; the same operations as a sweep with x = 0).
 template <typename T>
@@ -1759,6 +1766,13 @@ template hipError_t launch_jacobi_first<double>(int, int, const double *, const 
                                                 hipStream_t);
 template hipError_t launch_jacobi_first<float>(int, int, const float *, const float *, float *, const double *,
                                                hipStream_t);
+
+hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
+                        hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_axpby<<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_jacobi_factor(const SellView<double> &A, int n, int nslices, const int32_t *perm, double *v,
                                 double *u, double *partial, double *sums, double *omega_l, hipStream_t st) {

@@ -57,6 +57,8 @@ struct DevLevel {
     double *x = nullptr, *b = nullptr, *r = nullptr;
     float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
     double *xj = nullptr;                  // Jacobi's second iterate (allocated when selected)
+    double *sq_vals = nullptr, *sq_diag = nullptr;   // split Galerkin: levels of Q (dense on the coarsest)
+    double *sm_vals = nullptr, *sm_diag = nullptr;   // and of M
     float *xj32 = nullptr;
 };
 
@@ -83,6 +85,7 @@ struct smg_solver_s {
     int smoother = 0;              // SMG_SMOOTH_GS or SMG_SMOOTH_JACOBI
     double omega = 0.0;            // Jacobi factor for every level; <= 0: per level from lambda estimates
     double *d_omega = nullptr;     // per level factor (device), set by jacobi_factors
+    bool split_ready = false, split_ready_alloc = false;   // split Galerkin levels kept
     double *jac_v = nullptr, *jac_u = nullptr, *jac_sums = nullptr;   // power-step scratch
     // first level run by the one-workgroup LDS tail, per precision (0 FP64,
     // 1 FP32) and right-hand-side count k (index k); nlev - 1 = no tail
@@ -124,6 +127,8 @@ struct smg_solver_s {
 namespace smg {
 smg_status refresh_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st);
 smg_status jacobi_factors(smg_solver_s *s, hipStream_t st);
+smg_status galerkin_values(smg_solver_s *s, const double *d_a0_vals, hipStream_t st);
+smg_status finish_values(smg_solver_s *s, hipStream_t st);
 // parts of one cycle: all of it, only the first level's pre-relaxation, or
 // everything after that pre-relaxation
 enum CyclePart { kCycleWhole = 0, kCyclePre = 1, kCycleAfterPre = 2 };

@@ -209,6 +209,16 @@ class Solver:
         out = dict(status=st, cycles=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
         return (x if b.dim() == 2 else x[:, 0]), out
 
+    def split_prepare(self, q_vals, m_vals):
+        """Keep the Galerkin levels of two level-0 matrices (values on the
+        solver's pattern) for split_combine (App. E linearity)."""
+        L.check(self._lib.smg_split_prepare(self._s, _t_ptr(_dev_f64(q_vals)), _t_ptr(_dev_f64(m_vals)), _stream()),
+                "split_prepare")
+
+    def split_combine(self, a, b):
+        """Values a Q + b M on every level without assembly or Galerkin products."""
+        L.check(self._lib.smg_split_combine(self._s, float(a), float(b), _stream()), "split_combine")
+
     def set_smoother(self, kind="gs", omega=0.0):
         """Relaxation for every later call: "gs" (multicolor Gauss-Seidel)
         or "jacobi" (damped Jacobi; omega > 0 on every level, omega <= 0 per
