@@ -222,6 +222,33 @@ typedef struct {
 smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                      const smg_solve_params *p, smg_solve_info *info, smg_stream stream);
 
+/* --- Dirichlet conditions (App. B) ---
+ * x_k = c on the known vertices: solve A_uu x_u = b_u - A_uk c.  The
+ * multigrid hierarchy of the reduced system keeps every level except the
+ * finest transfer, whose rows become P_{u:} (the rows of P_0 of the
+ * unknowns); coarse vertices that then receive no weight are removed with
+ * the matching rows of the next prolongation (level by level).
+ * smg_hier_dirichlet: known = n_0 flags (natural order, nonzero = known);
+ * unknown_idx (n_0 capacity) receives the unknowns' natural indices in
+ * ascending order, *n_unknown their count; *out a new hierarchy (free with
+ * smg_hier_free).  Errors: INVALID_ARG (null, all known).
+ * smg_dirichlet_pattern (host): the CSR pattern of A_uu from A's pattern
+ * (rows/columns of the unknowns, order kept); u_rowptr needs n + 1 and
+ * u_cols nnz(A) capacity.  Errors: INVALID_ARG.
+ * smg_dirichlet_reduce (device, on `stream`): A_uu values in that pattern
+ * (d_u_rowptr = the pattern's row pointers on the device) and
+ * rhs = b_u - A_uk x_k for k columns (d_x, d_b: n_0 x k, the known entries
+ * of d_x used).  All pointers device, inputs from the same known mask.
+ * Errors: INVALID_ARG. */
+smg_status smg_hier_dirichlet(smg_hier h, const uint8_t *known, smg_hier *out, int32_t *unknown_idx,
+                              int32_t *n_unknown);
+smg_status smg_dirichlet_pattern(int32_t n, const int32_t *rowptr, const int32_t *cols, const uint8_t *known,
+                                 int32_t *u_rowptr, int32_t *u_cols, int32_t *n_unknown, int32_t *nnz_unknown);
+smg_status smg_dirichlet_reduce(int32_t n_unknown, const int32_t *d_unknown_idx, const int32_t *d_rowptr,
+                                const int32_t *d_cols, const double *d_vals, const uint8_t *d_known,
+                                const double *d_x, const double *d_b, int32_t k, const int32_t *d_u_rowptr,
+                                double *d_u_vals, double *d_rhs, smg_stream stream);
+
 /* --- split Galerkin (App. E): P^T (a Q + b M) P = a P^T Q P + b P^T M P ---
  * smg_split_prepare runs the Galerkin products of two level-0 matrices on
  * the solver's pattern (device CSR values in smg_set_values order; e.g. the

@@ -77,6 +77,9 @@ SIGNATURES = {
     "smg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_set_smoother": (c_int32, [c_void_p, c_int32, ctypes.c_double]),
     "smg_split_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "smg_hier_dirichlet": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_void_p), c_void_p, ctypes.POINTER(c_int32)]),
+    "smg_dirichlet_pattern": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "smg_dirichlet_reduce": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "smg_split_combine": (c_int32, [c_void_p, ctypes.c_double, ctypes.c_double, c_void_p]),
     "smg_get_jacobi_omega": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_double)]),
     "smg_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),

@@ -62,6 +62,39 @@ struct smg_hier_s {
     HierHost H;
 };
 
+// Zero-column removal (App. B): drop coarse vertices that receive no weight
+// from the level above, and the matching rows of the next prolongation (a
+// removal can leave further zero columns below, so levels go in order).
+static void compact_zero_columns(HierHost &H) {
+    for (int l = 0; l + 1 < H.nlev; ++l) {
+        const int nc = H.sizes[l + 1];
+        std::vector<char> used(nc, 0);
+        for (size_t e = 0; e < H.pcols[l].size(); ++e)
+            if (H.pcols[l][e] >= 0 && H.pw[l][e] > 0.0) used[H.pcols[l][e]] = 1;
+        std::vector<int32_t> newid(nc, -1);
+        int cnt = 0;
+        for (int a = 0; a < nc; ++a) if (used[a]) newid[a] = cnt++;
+        if (cnt == nc) continue;
+        for (auto &c : H.pcols[l]) if (c >= 0) c = newid[c];
+        if (l + 1 < (int)H.X.size() && H.X[l + 1].size() == 3 * (size_t)nc) {
+            std::vector<double> Xc;
+            for (int a = 0; a < nc; ++a)
+                if (used[a]) Xc.insert(Xc.end(), H.X[l + 1].begin() + 3 * a, H.X[l + 1].begin() + 3 * a + 3);
+            H.X[l + 1] = std::move(Xc);
+        }
+        if (l + 2 < H.nlev) {
+            std::vector<int32_t> pc2;
+            std::vector<double> pw2;
+            for (int a = 0; a < nc; ++a)
+                if (used[a])
+                    for (int q = 0; q < 3; ++q) { pc2.push_back(H.pcols[l + 1][3 * a + q]); pw2.push_back(H.pw[l + 1][3 * a + q]); }
+            H.pcols[l + 1] = std::move(pc2);
+            H.pw[l + 1] = std::move(pw2);
+        }
+        H.sizes[l + 1] = cnt;
+    }
+}
+
 extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F, int32_t m,
                                     const smg_pre_opts *opts, smg_hier *out) {
     if (!V || !F || !out || n < 3 || m < 1) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: bad arguments");
@@ -95,35 +128,7 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
         h->H.sizes.push_back((int)(X.size() / 3));
         h->H.X.push_back(X);
     }
-    // zero-column removal (App. B): drop coarse vertices that receive no
-    // weight, and the matching rows of the next prolongation.
-    for (int l = 0; l + 1 < nlev; ++l) {
-        const int nc = h->H.sizes[l + 1];
-        std::vector<char> used(nc, 0);
-        for (size_t e = 0; e < h->H.pcols[l].size(); ++e)
-            if (h->H.pcols[l][e] >= 0 && h->H.pw[l][e] > 0.0) used[h->H.pcols[l][e]] = 1;
-        std::vector<int32_t> newid(nc, -1);
-        int cnt = 0;
-        for (int a = 0; a < nc; ++a) if (used[a]) newid[a] = cnt++;
-        if (cnt == nc) continue;
-        for (auto &c : h->H.pcols[l]) if (c >= 0) c = newid[c];
-        {
-            std::vector<double> Xc;
-            for (int a = 0; a < nc; ++a)
-                if (used[a]) Xc.insert(Xc.end(), h->H.X[l + 1].begin() + 3 * a, h->H.X[l + 1].begin() + 3 * a + 3);
-            h->H.X[l + 1] = std::move(Xc);
-        }
-        if (l + 2 < nlev) {
-            std::vector<int32_t> pc2;
-            std::vector<double> pw2;
-            for (int a = 0; a < nc; ++a)
-                if (used[a])
-                    for (int q = 0; q < 3; ++q) { pc2.push_back(h->H.pcols[l + 1][3 * a + q]); pw2.push_back(h->H.pw[l + 1][3 * a + q]); }
-            h->H.pcols[l + 1] = std::move(pc2);
-            h->H.pw[l + 1] = std::move(pw2);
-        }
-        h->H.sizes[l + 1] = cnt;
-    }
+    compact_zero_columns(h->H);
     *out = h.release();
     return SMG_OK;
 }
@@ -171,6 +176,78 @@ extern "C" smg_status smg_hier_stats(smg_hier h, int32_t l, double *s8) {
     return SMG_OK;
 }
 extern "C" void smg_hier_free(smg_hier h) { delete h; }
+
+// ------------------------------------------ Dirichlet conditions (App. B)
+extern "C" smg_status smg_hier_dirichlet(smg_hier h, const uint8_t *known, smg_hier *out, int32_t *unknown_idx,
+                                         int32_t *n_unknown) {
+    if (!h || !known || !out || !unknown_idx || !n_unknown) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    const HierHost &H = h->H;
+    const int n = H.sizes[0];
+    int nu = 0;
+    for (int i = 0; i < n; ++i) if (!known[i]) unknown_idx[nu++] = i;
+    if (nu == 0) return fail(SMG_ERR_INVALID_ARG, "every value is known");
+    auto r = std::make_unique<smg_hier_s>();
+    HierHost &R = r->H;
+    R = H;
+    R.sizes[0] = nu;
+    if (!H.X.empty() && H.X[0].size() == 3 * (size_t)n) {
+        std::vector<double> X0;
+        for (int q = 0; q < nu; ++q) X0.insert(X0.end(), H.X[0].begin() + 3 * unknown_idx[q], H.X[0].begin() + 3 * unknown_idx[q] + 3);
+        R.X[0] = std::move(X0);
+    }
+    if (H.nlev > 1) {   // P_{u:}: the rows of P_0 of the unknowns
+        std::vector<int32_t> pc;
+        std::vector<double> pw;
+        for (int q = 0; q < nu; ++q)
+            for (int m = 0; m < 3; ++m) {
+                pc.push_back(H.pcols[0][3 * (size_t)unknown_idx[q] + m]);
+                pw.push_back(H.pw[0][3 * (size_t)unknown_idx[q] + m]);
+            }
+        R.pcols[0] = std::move(pc);
+        R.pw[0] = std::move(pw);
+        compact_zero_columns(R);
+    }
+    *n_unknown = nu;
+    *out = r.release();
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_dirichlet_pattern(int32_t n, const int32_t *rowptr, const int32_t *cols,
+                                            const uint8_t *known, int32_t *u_rowptr, int32_t *u_cols,
+                                            int32_t *n_unknown, int32_t *nnz_unknown) {
+    if (n < 1 || !rowptr || !cols || !known || !u_rowptr || !u_cols || !n_unknown || !nnz_unknown)
+        return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    std::vector<int32_t> umap(n, -1);
+    int nu = 0;
+    for (int i = 0; i < n; ++i) if (!known[i]) umap[i] = nu++;
+    int64_t z = 0;
+    u_rowptr[0] = 0;
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+        if (known[i]) continue;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (cols[p] < 0 || cols[p] >= n) return fail(SMG_ERR_INVALID_ARG, "column out of range");
+            if (umap[cols[p]] >= 0) u_cols[z++] = umap[cols[p]];
+        }
+        u_rowptr[++r] = (int32_t)z;
+    }
+    *n_unknown = nu;
+    *nnz_unknown = (int32_t)z;
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_dirichlet_reduce(int32_t n_unknown, const int32_t *d_unknown_idx, const int32_t *d_rowptr,
+                                           const int32_t *d_cols, const double *d_vals, const uint8_t *d_known,
+                                           const double *d_x, const double *d_b, int32_t k,
+                                           const int32_t *d_u_rowptr, double *d_u_vals, double *d_rhs,
+                                           smg_stream stream) {
+    if (n_unknown < 1 || !d_unknown_idx || !d_rowptr || !d_cols || !d_vals || !d_known || !d_x || !d_b ||
+        !d_u_rowptr || !d_u_vals || !d_rhs || k < 1 || k > 4)
+        return fail(SMG_ERR_INVALID_ARG, "bad arguments");
+    HIPCHK(launch_dirichlet_reduce(n_unknown, d_unknown_idx, d_rowptr, d_cols, d_vals, d_known, d_x, d_b, k,
+                                   d_u_rowptr, d_u_vals, d_rhs, (hipStream_t)stream));
+    return SMG_OK;
+}
 
 extern "C" int32_t smg_color_pattern(int32_t n, const int32_t *rowptr, const int32_t *cols,
                                      int32_t *color) {

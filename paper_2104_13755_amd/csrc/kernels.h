@@ -41,6 +41,12 @@ hipError_t launch_gs_color(const SellView<T> &A, const ColorSpan &c, const T *b,
 template <typename T>
 hipError_t launch_jacobi(const SellView<T> &A, int nslices, const T *b, const T *x, T *xo, const double *omega,
                          int k, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Dirichlet reduced system (App. B): for each unknown row r (natural index
+// uidx[r]) the values of its unknown columns into uvals[uptr[r]..] in row
+// order, and rhs[r] = b_i - sum over known j of A_ij x_j (k columns)
+hipError_t launch_dirichlet_reduce(int nu, const int32_t *uidx, const int32_t *rowptr, const int32_t *cols,
+                                   const double *vals, const uint8_t *known, const double *x, const double *b, int k,
+                                   const int32_t *uptr, double *uvals, double *rhs, hipStream_t st);
 // out = a x + b y over n doubles
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
                         hipStream_t st);

@@ -218,6 +218,41 @@ __global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, double a, const dou
     if (t < n) out[t] = a * x[t] + b * y[t];
 }
 
+// Reduced system of Dirichlet conditions (App. B), one thread per unknown
+// row i: A_uu values in row order (the full row's entries whose column is
+// unknown) and rhs = b_i - sum over known columns j of A_ij x_j.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_dirichlet_reduce(int nu, const int32_t *__restrict__ uidx,
+                                                             const int32_t *__restrict__ rowptr,
+                                                             const int32_t *__restrict__ cols,
+                                                             const double *__restrict__ vals,
+                                                             const uint8_t *__restrict__ known,
+                                                             const double *__restrict__ x,
+                                                             const double *__restrict__ b,
+                                                             const int32_t *__restrict__ uptr,
+                                                             double *__restrict__ uvals, double *__restrict__ rhs) {
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nu) return;
+    const int i = uidx[r];
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = b[(size_t)i * K + q];
+    int o = uptr[r];
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        const int j = cols[p];
+        const double a = vals[p];
+        if (known[j]) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] -= a * x[(size_t)j * K + q];
+        } else {
+            if (o < uptr[r + 1]) uvals[o] = a;   // a pattern from another mask writes nothing past the row
+            ++o;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) rhs[(size_t)r * K + q] = acc[q];
+}
+
 // The first Jacobi sweep from a zero iterate: xo = omega b / A_ii (no
 // gathers; the same operations as a sweep with x = 0).
 template <typename T>
@@ -1766,6 +1801,15 @@ template hipError_t launch_jacobi_first<double>(int, int, const double *, const 
                                                 hipStream_t);
 template hipError_t launch_jacobi_first<float>(int, int, const float *, const float *, float *, const double *,
                                                hipStream_t);
+
+hipError_t launch_dirichlet_reduce(int nu, const int32_t *uidx, const int32_t *rowptr, const int32_t *cols,
+                                   const double *vals, const uint8_t *known, const double *x, const double *b, int k,
+                                   const int32_t *uptr, double *uvals, double *rhs, hipStream_t st) {
+    if (nu <= 0) return hipSuccess;
+    SMG_K_SWITCH(k, (k_dirichlet_reduce<KK><<<nblocks(nu), kBlock, 0, st>>>(nu, uidx, rowptr, cols, vals, known, x, b,
+                                                                         uptr, uvals, rhs)));
+    return hipGetLastError();
+}
 
 hipError_t launch_axpby(int64_t n, double a, const double *x, double b, const double *y, double *out,
                         hipStream_t st) {

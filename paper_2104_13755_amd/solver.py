@@ -116,6 +116,54 @@ class Hierarchy:
             self._h = None
 
 
+class DirichletSystem:
+    """Dirichlet conditions (App. B): the reduced system A_uu x_u = b_u - A_uk x_k
+    on the unknowns, with its hierarchy (P_{u:} at the finest transfer, zero
+    columns removed).  `known`: boolean per vertex (natural order)."""
+
+    def __init__(self, hier, rowptr, cols, known):
+        lib = L.load()
+        self._lib = lib
+        n = len(rowptr) - 1
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        kn = np.ascontiguousarray(np.asarray(known, dtype=bool).astype(np.uint8))
+        if len(kn) != n:
+            raise ValueError("known must have one flag per row")
+        uidx = np.zeros(n, dtype=np.int32)
+        nu = ctypes.c_int32()
+        h = _c()
+        L.check(lib.smg_hier_dirichlet(hier._h, _np_ptr(kn), ctypes.byref(h), _np_ptr(uidx), ctypes.byref(nu)),
+                "hier_dirichlet")
+        self.hier = Hierarchy(h)
+        self.unknown = uidx[:nu.value].copy()
+        urp = np.zeros(n + 1, dtype=np.int32)
+        uci = np.zeros(max(1, len(cols)), dtype=np.int32)
+        nu2, nnz = ctypes.c_int32(), ctypes.c_int32()
+        L.check(lib.smg_dirichlet_pattern(n, _np_ptr(rowptr), _np_ptr(cols), _np_ptr(kn), _np_ptr(urp), _np_ptr(uci),
+                                          ctypes.byref(nu2), ctypes.byref(nnz)), "dirichlet_pattern")
+        self.u_rowptr = urp[:nu2.value + 1].copy()
+        self.u_cols = uci[:nnz.value].copy()
+        dev = "cuda"
+        self._d = [torch.tensor(a, device=dev) for a in (self.unknown, rowptr, cols, kn, self.u_rowptr)]
+        self.n = n
+
+    def reduce(self, a_vals, x, b):
+        """(A_uu values on (u_rowptr, u_cols), b_u - A_uk x_k); x and b are n x k
+        (the known entries of x are the prescribed values)."""
+        x2 = x if x.dim() == 2 else x.unsqueeze(1)
+        b2 = b if b.dim() == 2 else b.unsqueeze(1)
+        k = b2.shape[1]
+        uv = torch.empty(len(self.u_cols), dtype=torch.float64, device=a_vals.device)
+        rhs = torch.empty((len(self.unknown), k), dtype=torch.float64, device=a_vals.device)
+        ui, rp, ci, kn, urp = self._d
+        L.check(self._lib.smg_dirichlet_reduce(len(self.unknown), _t_ptr(ui), _t_ptr(rp), _t_ptr(ci),
+                                               _t_ptr(_dev_f64(a_vals)), _t_ptr(kn), _t_ptr(_dev_f64(x2.contiguous())),
+                                               _t_ptr(_dev_f64(b2.contiguous())), k, _t_ptr(urp), _t_ptr(uv),
+                                               _t_ptr(rhs), _stream()), "dirichlet_reduce")
+        return uv, (rhs if b.dim() == 2 else rhs[:, 0])
+
+
 PRECISION = {"fp64": L.SMG_FP64, "fp32ir": L.SMG_FP32_IR}
 
 
