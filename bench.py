@@ -376,6 +376,82 @@ def bench_split(args):
         "refresh_ms": {"split_combine": t_comb * 1e3, "assemble_and_galerkin": t_full * 1e3}}), flush=True)
 
 
+def bench_smooth(args):
+    """Data smoothing with the squared Laplacian energy (Sec. Applications):
+    A(alpha) = alpha L M^{-1} L + (1 - alpha) M (2-ring pattern) on the
+    benchmark mesh, b = (1 - alpha) M f, a sweep over 5 values of alpha in
+    [1e-4, 1e-2] with split Galerkin levels (App. E), each solved to 1e-8
+    with V-cycle-preconditioned CG, and with plain FP32 cycles (capped at 200;
+    the paper notes slow convergence of its prolongation on higher-order
+    problems, Sec. "Limitations & Future Work").  L comes from
+    the device assembly; L M^{-1} L is formed once on the host (setup)."""
+    import torch
+    import scipy.sparse as sp
+    import synth
+    from paper_2104_13755_amd.solver import Hierarchy, Solver, mesh_pattern
+    rtol = 1e-8
+    w = synth.workload_c2(*args.size)
+    n = len(w["V"])
+    t0 = time.perf_counter()
+    h = Hierarchy.build(w["V"], w["F"], n_levels=7)
+    rp, ci = mesh_pattern(n, w["F"])
+    S1 = Solver(h, rp, ci, faces=w["F"])
+    Vd = torch.tensor(w["V"], dtype=torch.float64, device="cuda")
+    _, lv, m = S1.assemble(Vd, 1.0, want_l=True, want_mass=True)
+    L = sp.csr_matrix((lv.cpu().numpy(), ci, rp), shape=(n, n))
+    mh = m.cpu().numpy()
+    Q = (L @ sp.diags(1.0 / mh) @ L).tocsr()
+    Q.sort_indices()
+    del S1
+    rows = np.repeat(np.arange(n), np.diff(Q.indptr))
+    Mv = np.where(rows == Q.indices, mh[rows], 0.0)
+    S = Solver(h, Q.indptr, Q.indices)
+    t_setup = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.split_prepare(torch.tensor(Q.data, device="cuda"), torch.tensor(Mv, device="cuda"))
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    log(f"smooth: setup {t_setup:.1f}s, 2-ring nnz/row {Q.nnz / n:.1f}, split prepare {t_prep * 1e3:.1f} ms")
+    f = torch.tensor(np.random.default_rng(5).uniform(-1, 1, (n, 1)), device="cuda")
+    md = m[:, None]
+    alphas = [float(a) for a in np.logspace(-4, -2, 5)]
+
+    def sweep(kind):
+        its = []
+        for a in alphas:
+            S.split_combine(a, 1.0 - a)
+            b = ((1.0 - a) * md * f).contiguous()
+            if kind == "cycles":
+                info = S.solve(b, rtol=rtol, precision="fp32ir", max_cycles=200, raise_on_error=False)[1]
+                its.append((info["cycles"], max(info["rel_res"])))
+            else:
+                info = S.pcg(b, rtol=rtol, precision="fp32ir", max_iters=400)[1]
+                its.append((info["iterations"], max(info["rel_res"])))
+        return its
+    res = {}
+    for kind in ("pcg", "cycles"):
+        sweep(kind)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(1, args.steps // 10)
+        for _ in range(reps):
+            its = sweep(kind)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (reps * len(alphas))
+        res[kind] = dict(value=1.0 / dt, ms_per_step=dt * 1e3, iterations=its)
+        log(f"smooth {kind}: {dt * 1e3:.2f} ms per alpha, iterations {its}")
+    print(json.dumps({
+        "metric": "Bilaplacian data smoothing solves/s at 1M verts (5 values of alpha, rel residual 1e-8, V-cycle-preconditioned CG)",
+        "value": res["pcg"]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["pcg"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']} torus, A = alpha L M^-1 L + (1-alpha) M (2-ring), b = (1-alpha) M f, "
+                               "alpha in logspace(-4,-2,5), 1 RHS, FP32 cycles",
+                   "vertices": n, "levels": h.sizes, "nnz_per_row": Q.nnz / n},
+        "pcg": res["pcg"], "cycles": res["cycles"], "split_prepare_ms": t_prep * 1e3}), flush=True)
+
+
 def bench_frames(args):
     """Time-varying A: 2M-vertex height-field disc, per-frame edge weights and
     t, on-device re-assembly + Galerkin over 8 levels + Cholesky + FP32/FP64-IR
@@ -423,7 +499,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--profile-kind", default="gs")
-    ap.add_argument("--workload", default="torus", choices=["torus", "batch", "grad", "frames", "pcg", "jacobi", "split"])
+    ap.add_argument("--workload", default="torus", choices=["torus", "batch", "grad", "frames", "pcg", "jacobi", "split", "smooth"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--tune-cache", default=None)
@@ -451,6 +527,8 @@ def main():
         return bench_jacobi(args)
     if args.workload == "split":
         return bench_split(args)
+    if args.workload == "smooth":
+        return bench_smooth(args)
     rtol = 1e-8
     n_levels = 7
     w = synth.workload_c2(*args.size)

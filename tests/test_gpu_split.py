@@ -3,6 +3,7 @@
 Galerkin level 1e-13 relative, coarsest factor 1e-12, identical cycle
 counts), for several coefficient pairs, and the errors of the entry points."""
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from helpers import Problem, gpu_available, rel
@@ -57,3 +58,44 @@ def test_combine_equals_direct_values(prob):
         assert np.linalg.norm(_np(xs) - _np(xd)) / np.linalg.norm(_np(xd)) < 1e-9
     with pytest.raises(SmgError):
         S.split_combine(float("nan"), 1.0)
+
+
+def test_bilaplacian_smoothing_levels():
+    """Data smoothing with the squared Laplacian energy (Sec. Applications):
+    A(alpha) = alpha L M^{-1} L + (1 - alpha) M on the 2-ring pattern, levels
+    by split_combine; the solve matches the oracle's V-cycle solve of the same
+    matrix (cycle counts equal) and PCG reaches the tolerance."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import synth
+    from oracle import assemble as AS, hierarchy as OH, vcycle as OV
+    from paper_2104_13755_amd.solver import Hierarchy, Solver
+    from helpers import ell3
+    V, F = synth.small_icosphere(4, seed=21, sigma=0.01)
+    _, L, m = AS.system(V, F, 1e-2)
+    L = L.tocsr()
+    Q = (L @ sp.diags(1.0 / m) @ L).tocsr()
+    Q.sort_indices()
+    n = Q.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(Q.indptr))
+    Mv = np.where(rows == Q.indices, m[rows], 0.0)
+    Ps, _, _ = OH.prolongations(V, F, n_levels=3)
+    ells = [ell3(P) for P in Ps]
+    sizes = [n] + [P.shape[1] for P in Ps]
+    h = Hierarchy.from_prolongations(sizes, [e[0] for e in ells], [e[1] for e in ells])
+    S = Solver(h, Q.indptr, Q.indices)
+    S.split_prepare(_t(Q.data), _t(Mv))
+    f = np.random.default_rng(63).uniform(-1, 1, (n, 1))
+    for alpha in (1e-3, 1e-2):
+        S.split_combine(alpha, 1.0 - alpha)
+        A = sp.csr_matrix((alpha * Q.data + (1.0 - alpha) * Mv, Q.indices, Q.indptr), shape=Q.shape)
+        b = (1.0 - alpha) * m[:, None] * f
+        O = OV.Solver(Ps, A)
+        xo, co, _ = O.solve(b, 1e-10)
+        xg, info = S.solve(_t(b), rtol=1e-10, precision="fp64")
+        assert info["cycles"] == co
+        assert np.linalg.norm(_np(xg) - xo) / np.linalg.norm(xo) < 1e-9
+        xp, ip = S.pcg(_t(b), rtol=1e-8, precision="fp32ir")
+        res = np.linalg.norm(b - A @ _np(xp)) / np.linalg.norm(b)
+        assert res <= 2e-8
+        print(f"[bilaplacian] alpha={alpha}: {co} cycles, pcg {ip['iterations']}", flush=True)
