@@ -79,3 +79,24 @@ def test_dirichlet_reduction_and_solve(disc, which):
     xm, im = S.solve(rg, rtol=1e-8, precision="fp32ir")
     res = np.linalg.norm(rhs - Auu @ _np(xm), axis=0) / np.linalg.norm(rhs, axis=0)
     assert res.max() <= 1e-8 * 1.0001
+
+
+def test_dirichlet_edges(disc):
+    """No known value: the reduced hierarchy is the original one; every value
+    known: an error."""
+    from paper_2104_13755_amd.solver import DirichletSystem, Hierarchy
+    from paper_2104_13755_amd._lib import SmgError
+    p = disc
+    n = p.sizes[0]
+    ells = [ell3(P) for P in p.Ps]
+    h = Hierarchy.from_prolongations(p.sizes, [e[0] for e in ells], [e[1] for e in ells])
+    A = p.A.tocsr()
+    ds = DirichletSystem(h, A.indptr, A.indices, np.zeros(n, bool))
+    assert ds.hier.sizes == p.sizes and np.array_equal(ds.unknown, np.arange(n))
+    assert np.array_equal(ds.u_rowptr, A.indptr) and np.array_equal(ds.u_cols, A.indices)
+    for l in range(len(p.Ps)):
+        c0, w0 = h.prolongation(l)
+        c1, w1 = ds.hier.prolongation(l)
+        assert np.array_equal(c0, c1) and np.array_equal(w0, w1)
+    with pytest.raises(SmgError):
+        DirichletSystem(h, A.indptr, A.indices, np.ones(n, bool))

@@ -110,3 +110,21 @@ def test_switch_back_and_errors(prob):
                 S.set_smoother("jacobi", bad)
     finally:
         S.set_smoother("jacobi")
+
+
+def test_odd_sweep_counts():
+    """mu_pre = 1, mu_post = 3: odd Jacobi sweep counts end in the second
+    iterate and are copied back; the cycle matches the oracle's."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    p = Problem("disc-41x37")
+    S = p.gpu_solver(mu_pre=1, mu_post=3)
+    S.set_smoother("jacobi")
+    O = OV.Solver(p.Ps, p.A, mu_pre=1, mu_post=3, smoother="jacobi")
+    rng = np.random.default_rng(54)
+    b = rng.uniform(-1, 1, (p.sizes[0], 2))
+    x0 = rng.uniform(-1, 1, (p.sizes[0], 2))
+    assert rel(_np(S.vcycle(_t(b), _t(x0))), O.vcycle(0, x0.copy(), b)) < 1e-12
+    xo, co, _ = O.solve(b, 1e-10, max_cycles=300)
+    xg, info = S.solve(_t(b), rtol=1e-10, precision="fp64", max_cycles=300)
+    assert info["cycles"] == co and rel(_np(xg), xo) < 1e-9

@@ -112,3 +112,24 @@ def test_edges(prob):
     _, i2 = S2.pcg(_t(b), raise_on_error=False)
     assert i2["status"] != 0
     torch.cuda.synchronize()
+
+
+def test_rhs_counts_and_single_level():
+    """2 and 4 right-hand sides against the oracle; a one-level hierarchy is
+    the direct solve."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    p = Problem("disc-41x37")
+    S = p.gpu_solver()
+    B = OP.vcycle_preconditioner(p.oracle)
+    for k in (2, 4):
+        b = _rhs(p, k, 90 + k)
+        xg, info = S.pcg(_t(b), fixed_iters=4, precision="fp64")
+        xo, _, _ = OP.pcg(p.A, b, B, 0.0, fixed_iters=4)
+        assert rel(_np(xg), xo) < 1e-10, k
+    one = Problem("disc-41x37", n_levels=1)
+    S1 = one.gpu_solver()
+    b = _rhs(one, 2, 95)
+    x1, i1 = S1.pcg(_t(b), rtol=1e-10)
+    xs = np.linalg.solve(one.A.toarray(), b)
+    assert i1["iterations"] == 1 and rel(_np(x1), xs) < 1e-12
