@@ -507,7 +507,7 @@ def main():
                     help="short run for hardware counters: a 256 MiB copy (calibration), then 3 mixed cycles")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
