@@ -25,6 +25,10 @@ static thread_local std::string g_last_error;
 // levels with at most this many rows (and all coarser ones) form the
 // one-workgroup LDS tail unless the caller chooses otherwise
 static constexpr int kTailRowsDefault = 4096;
+// The LDS tail runs one workgroup per right-hand side (columns are
+// independent solves): each holds one value per row in LDS and the columns
+// proceed on different compute units at once.
+constexpr bool kTailPerColumn = true;
 
 namespace smg {
 smg_status fail(smg_status st, const std::string &msg) {
@@ -488,7 +492,7 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
                 for (int l = last - 1; l >= 0 && S->lev[l].tl; --l) {
                     const size_t bytes = tail_lds_bytes(npass_before - S->lev[l].tl_pass0,
                                                         nwave_before - S->lev[l].tl_wave0, nsum[last + 1] - nsum[l],
-                                                        S->lev[last].n, k, pr == 0 ? 8 : 4);
+                                                        S->lev[last].n, kTailPerColumn ? 1 : k, pr == 0 ? 8 : 4);
                     if (bytes > (size_t)dev_lds) break;
                     S->tail_first[pr][k] = l;
                     S->tail_lds[pr][k][l] = bytes;
@@ -932,7 +936,8 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part, 
     if (s->smoother == SMG_SMOOTH_GS && l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
         if (part != kCyclePre)
             HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
-                                      s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st, sym));
+                                      s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st, sym,
+                                      kTailPerColumn));
         return SMG_OK;
     }
     DevLevel &C = s->lev[l + 1];

@@ -157,7 +157,7 @@ template <typename T>
 hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves,
                            int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
                            size_t lds_bytes, hipStream_t st,
-                           bool post_desc = false);
+                           bool post_desc = false, bool per_column = false);
 // grant k_tail_lds<*, T> `bytes` of dynamic LDS
 template <typename T>
 hipError_t tail_lds_allow(size_t bytes);

@@ -1169,12 +1169,12 @@ __device__ __forceinline__ void tail_gather(const TailRec<T> *rp, int np, const 
 // (the wavefront's record offset and rounds come from the LDS table)
 template <int K, int KP, typename T>
 __device__ __forceinline__ void tail_row(const LdsLevel<T> &L, const int2 *wv, int tid, int row, int G,
-                                         const T *xs, T &d, T (&bq)[K], T (&acc)[K]) {
+                                         const T *xs, T &d, T (&bq)[K], T (&acc)[K], int vs, int vc) {
     const int2 W = wv[tid >> 6];
     const int off = __builtin_amdgcn_readfirstlane(W.x), kmax = __builtin_amdgcn_readfirstlane(W.y);
     d = gld(L.diag, row);
 #pragma unroll
-    for (int q = 0; q < K; ++q) { bq[q] = gld(L.b, (size_t)row * K + q); acc[q] = T(0); }
+    for (int q = 0; q < K; ++q) { bq[q] = gld(L.b, (size_t)row * vs + vc + q); acc[q] = T(0); }
     tail_gather<K, KP, T>(L.rec + off + 2 * (tid & 63), kmax, xs, acc);
     for (int m = G >> 1; m > 0; m >>= 1)
 #pragma unroll
@@ -1185,7 +1185,7 @@ __device__ __forceinline__ void tail_row(const LdsLevel<T> &L, const int2 *wv, i
 // (descending: colors last to first), a barrier after every color.
 template <int K, int KP, typename T>
 __device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, T *xs, int sweeps,
-                           bool descending = false) {
+                           bool descending, int vs, int vc) {
     const int tid = threadIdx.x, lg = L.lg_grp, G = 1 << lg;
     const int g = tid >> lg, j = tid & (G - 1);
     for (int sw = 0; sw < sweeps; ++sw)
@@ -1196,7 +1196,7 @@ __device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv
             if (tid < nta) {
                 const int row = P.x + g;
                 T d, bq[K], acc[K];
-                tail_row<K, KP, T>(L, swv + P.w, tid, row, G, xs, d, bq, acc);
+                tail_row<K, KP, T>(L, swv + P.w, tid, row, G, xs, d, bq, acc, vs, vc);
                 if (j == 0)
 #pragma unroll
                     for (int q = 0; q < K; ++q) xs[(size_t)row * KP + q] = (bq[q] - acc[q]) / d;
@@ -1208,7 +1208,7 @@ __device__ void tail_relax(const LdsLevel<T> &L, const int4 *sp, const int2 *swv
 
 // r = b - A x on one tail level (r in global memory); no barrier inside
 template <int K, int KP, typename T>
-__device__ void tail_residual(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, const T *xs) {
+__device__ void tail_residual(const LdsLevel<T> &L, const int4 *sp, const int2 *swv, const T *xs, int vs, int vc) {
     const int tid = threadIdx.x, lg = L.lg_grp, G = 1 << lg;
     const int g = tid >> lg, j = tid & (G - 1);
     for (int p = 0; p < L.npass; ++p) {
@@ -1217,12 +1217,12 @@ __device__ void tail_residual(const LdsLevel<T> &L, const int4 *sp, const int2 *
         if (tid < nta) {
             const int row = P.x + g;
             T d, bq[K], acc[K];
-            tail_row<K, KP, T>(L, swv + P.w, tid, row, G, xs, d, bq, acc);
+            tail_row<K, KP, T>(L, swv + P.w, tid, row, G, xs, d, bq, acc, vs, vc);
             if (j == 0) {
                 T xv[K];
                 lds_get<T, K, KP>(xs, row, xv);
 #pragma unroll
-                for (int q = 0; q < K; ++q) gst(L.r, (size_t)row * K + q, bq[q] - (acc[q] + d * xv[q]));
+                for (int q = 0; q < K; ++q) gst(L.r, (size_t)row * vs + vc + q, bq[q] - (acc[q] + d * xv[q]));
             }
         }
     }
@@ -1231,7 +1231,7 @@ __device__ void tail_residual(const LdsLevel<T> &L, const int4 *sp, const int2 *
 // b_{l+1} = R r (R = P^T as ELL); into LDS (bl) for the coarsest level, else
 // into the next level's global b, whose x is then cleared in LDS
 template <int K, int KP, typename T>
-__device__ void tail_restrict(const LdsLevel<T> &L, T *bc_global, T *bl, T *xc) {
+__device__ void tail_restrict(const LdsLevel<T> &L, T *bc_global, T *bl, T *xc, int vs, int vc) {
     constexpr int CH = 8;
     const int tid = threadIdx.x, nt = blockDim.x, nc = L.nc, rk = L.rk;
     for (int a = tid; a < nc; a += nt) {
@@ -1251,7 +1251,7 @@ __device__ void tail_restrict(const LdsLevel<T> &L, T *bc_global, T *bl, T *xc) 
 #pragma unroll
             for (int u = 0; u < CH; ++u)
 #pragma unroll
-                for (int q = 0; q < K; ++q) rv[u][q] = gld((const T *)L.r, (size_t)c[u] * K + q);
+                for (int q = 0; q < K; ++q) rv[u][q] = gld((const T *)L.r, (size_t)c[u] * vs + vc + q);
 #pragma unroll
             for (int u = 0; u < CH; ++u)
 #pragma unroll
@@ -1262,7 +1262,7 @@ __device__ void tail_restrict(const LdsLevel<T> &L, T *bc_global, T *bl, T *xc) 
             for (int q = 0; q < K; ++q) bl[(size_t)a * KP + q] = acc[q];
         } else {
 #pragma unroll
-            for (int q = 0; q < K; ++q) gst(bc_global, (size_t)a * K + q, acc[q]);
+            for (int q = 0; q < K; ++q) gst(bc_global, (size_t)a * vs + vc + q, acc[q]);
         }
     }
     if (!bl)
@@ -1335,10 +1335,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__
                                                            const int4 *__restrict__ passes,
                                                            const int2 *__restrict__ waves, int first,
                                                            int nlev, int mu_pre, int mu_post,
-                                                           const double *__restrict__ Ainv, int post_desc) {
+                                                           const double *__restrict__ Ainv, int post_desc,
+                                                           int vs) {
     constexpr int KP = K == 3 ? 4 : K;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nt = blockDim.x, last = nlev - 1;
+    // global vectors are n x vs; this workgroup owns columns [vc, vc + K)
+    const int vc = blockIdx.x * K;
     const int pbeg = lv[first].pass0, pend = lv[last].pass0;
     const int wbeg = lv[first].wave0, wend = lv[last].wave0;
     int4 *sp = reinterpret_cast<int4 *>(smem);
@@ -1356,17 +1359,17 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__
     {
         const int n0 = lv[first].n;
         const T *xg = lv[first].x;
-        for (int t = tid; t < n0 * K; t += nt) xall[(size_t)(t / K) * KP + t % K] = gld(xg, t);
+        for (int t = tid; t < n0 * K; t += nt) xall[(size_t)(t / K) * KP + t % K] = gld(xg, (size_t)(t / K) * vs + vc + t % K);
     }
     __syncthreads();
     for (int l = first; l < last; ++l) {
         const LdsLevel<T> L = lv[l];
         T *xs = xall + (size_t)(L.nsum - base) * KP;
         T *xc = xall + (size_t)(L.nsum + L.n - base) * KP;
-        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_pre);
-        tail_residual<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs);
+        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_pre, false, vs, vc);
+        tail_residual<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, vs, vc);
         __syncthreads();
-        tail_restrict<K, KP, T>(L, lv[l + 1].b, l + 1 == last ? bl : nullptr, xc);
+        tail_restrict<K, KP, T>(L, lv[l + 1].b, l + 1 == last ? bl : nullptr, xc, vs, vc);
         __syncthreads();
     }
     tail_coarse<K, KP, T>(lv[last].n, Ainv, bl, xall + (size_t)(lv[last].nsum - base) * KP);
@@ -1376,12 +1379,12 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__
         T *xs = xall + (size_t)(L.nsum - base) * KP;
         tail_prolong<K, KP, T>(L, xs, xall + (size_t)(L.nsum + L.n - base) * KP);
         __syncthreads();
-        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_post, post_desc != 0);
+        tail_relax<K, KP, T>(L, sp + (L.pass0 - pbeg), swv, xs, mu_post, post_desc != 0, vs, vc);
     }
     {
         const int n0 = lv[first].n;
         T *xg = lv[first].x;
-        for (int t = tid; t < n0 * K; t += nt) gst(xg, t, xall[(size_t)(t / K) * KP + t % K]);
+        for (int t = tid; t < n0 * K; t += nt) gst(xg, (size_t)(t / K) * vs + vc + t % K, xall[(size_t)(t / K) * KP + t % K]);
     }
 }
 
@@ -1937,10 +1940,16 @@ hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv
 template <typename T>
 hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves,
                            int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
-                           size_t lds_bytes, hipStream_t st, bool post_desc) {
+                           size_t lds_bytes, hipStream_t st, bool post_desc, bool per_column) {
+    if (per_column) {   // one workgroup per right-hand side, all in parallel
+        k_tail_lds<1, T><<<k, kTailThreads, lds_bytes, st>>>(
+            lv, reinterpret_cast<const int4 *>(passes), reinterpret_cast<const int2 *>(waves), first, nlev, mu_pre,
+            mu_post, Ainv, post_desc ? 1 : 0, k);
+        return hipGetLastError();
+    }
     SMG_K_SWITCH(k, (k_tail_lds<KK, T><<<1, kTailThreads, lds_bytes, st>>>(
                         lv, reinterpret_cast<const int4 *>(passes), reinterpret_cast<const int2 *>(waves),
-                        first, nlev, mu_pre, mu_post, Ainv, post_desc ? 1 : 0)));
+                        first, nlev, mu_pre, mu_post, Ainv, post_desc ? 1 : 0, k)));
     return hipGetLastError();
 }
 
@@ -2175,9 +2184,11 @@ template hipError_t launch_coarse_solve<double, double>(const double *, int, con
 template hipError_t launch_coarse_solve<float, float>(const double *, int, const float *, float *,
                                                       int, hipStream_t);
 template hipError_t launch_tail_lds<double>(const LdsLevel<double> *, const int32_t *, const int32_t *,
-                                            int, int, int, int, const double *, int, size_t, hipStream_t, bool);
+                                            int, int, int, int, const double *, int, size_t, hipStream_t, bool,
+                                            bool);
 template hipError_t launch_tail_lds<float>(const LdsLevel<float> *, const int32_t *, const int32_t *,
-                                           int, int, int, int, const double *, int, size_t, hipStream_t, bool);
+                                           int, int, int, int, const double *, int, size_t, hipStream_t, bool,
+                                           bool);
 template hipError_t launch_fill<double>(double *, double, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float *, float, int64_t, hipStream_t);
 template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);
