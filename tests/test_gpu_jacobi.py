@@ -128,3 +128,16 @@ def test_odd_sweep_counts():
     xo, co, _ = O.solve(b, 1e-10, max_cycles=300)
     xg, info = S.solve(_t(b), rtol=1e-10, precision="fp64", max_cycles=300)
     assert info["cycles"] == co and rel(_np(xg), xo) < 1e-9
+
+
+def test_graph_replay_with_jacobi(prob):
+    """Cycles captured into a graph with the Jacobi smoother replay to the
+    same iterates as eager launches (several replays in a row)."""
+    S = prob.gpu
+    rng = np.random.default_rng(55)
+    b = _t(prob.m[:, None] * rng.uniform(-1, 1, (prob.sizes[0], 2)))
+    for precision in ("fp64", "fp32ir"):
+        x1, i1 = S.solve(b, rtol=1e-9, precision=precision, max_cycles=300)
+        for _ in range(3):
+            x2, i2 = S.solve(b, rtol=1e-9, precision=precision, max_cycles=300, use_graph=True)
+            assert i1["cycles"] == i2["cycles"] and np.array_equal(_np(x1), _np(x2)), precision
