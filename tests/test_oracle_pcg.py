@@ -83,3 +83,16 @@ def test_pcg_converges_to_dense_solution_faster_than_cycles(ico3):
     assert true_res.max() < 1e-11
     _, cycles, _ = S.solve(b, 1e-12)
     assert its < cycles
+
+
+def test_columns_are_independent_runs(ico3):
+    """PCG on several right-hand sides at once runs one CG per column: each
+    column's iterate equals a run on that column alone."""
+    A, m, S, Bsym, Bns = ico3
+    rng = np.random.default_rng(6)
+    b = m[:, None] * rng.uniform(-1, 1, (A.shape[0], 3))
+    b[:, 2] *= 1e-3                                    # different scales, same directions
+    X, _, _ = PCG.pcg(A, b, lambda r: Bsym @ r, 0.0, fixed_iters=5)
+    for c in range(3):
+        x1, _, _ = PCG.pcg(A, b[:, c], lambda r: Bsym @ r, 0.0, fixed_iters=5)
+        assert np.abs(X[:, c] - x1[:, 0]).max() <= 1e-14 * np.abs(x1).max()
