@@ -49,6 +49,53 @@ def test_flat_closed_form_interior_collapses():
         assert abs(D[v] - ref).max() < 1e-10, v
 
 
+def test_flat_closed_form_in_a_tilted_plane():
+    """The parameterization is intrinsic (Sec. 4 flattens by edge lengths and
+    angles), so the flat-disc closed form must hold unchanged once the disc is
+    moved rigidly into a general plane of R^3: dropping the z coordinate, or
+    any other use of raw coordinates, breaks it."""
+    V, F = synth.flat_disc(32, seed=11, jitter=0.1)
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    off = np.array([0.3, -1.7, 2.2])
+    n = len(V)
+    Vc, Fc, Pc, Pw, st = native.ssp_level(V @ Q.T + off, F, H.next_target(n), interior_only=True)
+    assert st["collapses"] > 0
+    D = _dense_rows(Pc, Pw, len(Vc))
+    Uc = ((Vc - off) @ Q)[:, :2]          # coarse vertices back in the disc's plane
+    U = V[:, :2]
+    assert abs(D @ Uc - U).max() < 1e-13
+    for v in range(n):
+        best = -np.inf
+        for f in Fc:
+            lam = _planar_bary(U[v], Uc[f[0]], Uc[f[1]], Uc[f[2]])
+            if lam.min() > best:
+                best, bb, bf = lam.min(), lam, f
+        assert best > -1e-12
+        ref = np.zeros(len(Vc))
+        ref[bf] = np.clip(bb, 0, None) / np.clip(bb, 0, None).sum()
+        assert abs(D[v] - ref).max() < 1e-10, v
+
+
+def test_similarity_invariance():
+    """Every quantity the hierarchy depends on (quadric costs, edge lengths,
+    angles) is invariant under rigid motion, and a power-of-two scale changes
+    them by exact factors: scaling gives bitwise the same operators, a rigid
+    motion the same sparsity with values equal to rounding."""
+    rng = np.random.default_rng(5)
+    V, F = synth.torus_grid(60, 24, 1.0, 0.3, rng, jitter=0.2)
+    Ps, _, _ = H.prolongations(V, F, n_levels=3)
+    Ps_scaled, _, _ = H.prolongations(4.0 * V, F, n_levels=3)
+    for a, b in zip(Ps, Ps_scaled):
+        assert a.shape == b.shape and (a != b).nnz == 0
+    Q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    Ps_moved, _, _ = H.prolongations(V @ Q.T + np.array([0.5, -0.25, 1.0]), F, n_levels=3)
+    for a, b in zip(Ps, Ps_moved):
+        assert a.shape == b.shape
+        assert (a.indptr == b.indptr).all() and (a.indices == b.indices).all()
+        assert abs(a - b).max() < 1e-12
+
+
 @pytest.mark.parametrize("mesh", ["icosphere", "torus", "disc", "heightfield"])
 def test_prolongation_invariants(mesh):
     rng = np.random.default_rng(5)
