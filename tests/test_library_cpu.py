@@ -111,6 +111,86 @@ def test_precompute_rejects_bad_input():
         Hierarchy.build(V, Fb, n_levels=2)
 
 
+def _host_dirichlet(h, A, known):
+    """smg_hier_dirichlet + smg_dirichlet_pattern, called straight through the
+    C ABI (both are host-only)."""
+    import ctypes
+    from paper_2104_13755_amd import _lib as L
+    from paper_2104_13755_amd.solver import Hierarchy
+    lib = L.load()
+    n = A.shape[0]
+    kn = np.ascontiguousarray(known, dtype=np.uint8)
+    uidx = np.zeros(n, dtype=np.int32)
+    nu = ctypes.c_int32()
+    hh = ctypes.c_void_p()
+    L.check(lib.smg_hier_dirichlet(h._h, kn.ctypes.data, ctypes.byref(hh), uidx.ctypes.data, ctypes.byref(nu)),
+            "hier_dirichlet")
+    rp = np.ascontiguousarray(A.indptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.indices, dtype=np.int32)
+    urp = np.zeros(n + 1, dtype=np.int32)
+    uci = np.zeros(len(ci), dtype=np.int32)
+    nu2, nnz = ctypes.c_int32(), ctypes.c_int32()
+    L.check(lib.smg_dirichlet_pattern(n, rp.ctypes.data, ci.ctypes.data, kn.ctypes.data, urp.ctypes.data,
+                                      uci.ctypes.data, ctypes.byref(nu2), ctypes.byref(nnz)), "dirichlet_pattern")
+    assert nu2.value == nu.value
+    return Hierarchy(hh), uidx[:nu.value], urp[:nu.value + 1], uci[:nnz.value]
+
+
+@pytest.mark.parametrize("which", ["none", "rim", "random60", "random85"])
+def test_dirichlet_host_reduction_matches_oracle(which):
+    """App. B on the host: the unknowns, the reduced hierarchy (P_{u:}, zero
+    columns removed level by level) and the A_uu pattern equal the oracle's,
+    bitwise."""
+    from oracle import dirichlet as DR
+    from paper_2104_13755_amd.solver import Hierarchy
+    V, F = synth.flat_disc(31, 27, seed=5, jitter=0.1)
+    n = len(V)
+    A, _, _ = AS.system(V, F, 1e-2)
+    A = A.tocsr()
+    Ps, _, _ = OH.prolongations(V, F, n_levels=4)
+    cols, ws = [], []
+    for P in Ps:
+        P = P.tocsr()
+        c = -np.ones((P.shape[0], 3), dtype=np.int32)
+        w = np.zeros((P.shape[0], 3))
+        cnt = np.diff(P.indptr)
+        for s in range(3):
+            m = cnt > s
+            c[m, s] = P.indices[P.indptr[:-1][m] + s]
+            w[m, s] = P.data[P.indptr[:-1][m] + s]
+        cols.append(c)
+        ws.append(w)
+    h = Hierarchy.from_prolongations([n] + [P.shape[1] for P in Ps], cols, ws)
+    rng = np.random.default_rng(17)
+    if which == "none":
+        known = np.zeros(n, bool)
+    elif which == "rim":
+        known = np.zeros(n, bool)
+        known[np.argsort(np.linalg.norm(V[:, :2], axis=1))[-n // 8:]] = True
+    else:
+        known = rng.uniform(size=n) < (0.6 if which == "random60" else 0.85)
+    hr, u, urp, uci = _host_dirichlet(h, A, known)
+    Auu, _, u_ref = DR.reduce(A, np.zeros(n), known, np.zeros(n))
+    Pr = DR.prolongations(Ps, known)
+    assert np.array_equal(u, u_ref)
+    assert np.array_equal(urp, Auu.indptr) and np.array_equal(uci, Auu.indices)
+    assert hr.sizes == [len(u)] + [P.shape[1] for P in Pr]
+    for l, P in enumerate(Pr):
+        Pp = _p_matrix(*hr.prolongation(l), P.shape)
+        assert ((Pp != 0) != (P != 0)).nnz == 0, l
+        assert abs(Pp - P).max() == 0.0, l
+
+
+def test_dirichlet_all_known_is_an_error():
+    from paper_2104_13755_amd._lib import SmgError
+    from paper_2104_13755_amd.solver import Hierarchy
+    V, F = synth.flat_disc(12, seed=2)
+    A, _, _ = AS.system(V, F, 1e-2)
+    h = Hierarchy.build(V, F, n_levels=2)
+    with pytest.raises(SmgError):
+        _host_dirichlet(h, A.tocsr(), np.ones(len(V), bool))
+
+
 def test_bench_refuses_more_than_one_gpu():
     """bench.py measures one GPU: --gpus above 1 exits with a message (before
     touching any GPU)."""
