@@ -45,6 +45,8 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_SPD",
           -5: "NO_CONVERGENCE", -6: "NONFINITE", -7: "STATE", -8: "PRECOMPUTE"}
 SMG_FP64 = 0
 SMG_FP32_IR = 1
+SMG_SMOOTH_GS = 0
+SMG_SMOOTH_JACOBI = 1
 
 # name -> (restype, argtypes)
 SIGNATURES = {

@@ -165,6 +165,7 @@ class DirichletSystem:
 
 
 PRECISION = {"fp64": L.SMG_FP64, "fp32ir": L.SMG_FP32_IR}
+SMOOTHER = {"gs": L.SMG_SMOOTH_GS, "jacobi": L.SMG_SMOOTH_JACOBI}
 
 
 class Solver:
@@ -271,7 +272,7 @@ class Solver:
         """Relaxation for every later call: "gs" (multicolor Gauss-Seidel)
         or "jacobi" (damped Jacobi; omega > 0 on every level, omega <= 0 per
         level from the largest eigenvalue estimate of D^{-1} A)."""
-        L.check(self._lib.smg_set_smoother(self._s, {"gs": 0, "jacobi": 1}[kind], float(omega)), "set_smoother")
+        L.check(self._lib.smg_set_smoother(self._s, SMOOTHER[kind], float(omega)), "set_smoother")
 
     def jacobi_omega(self, level):
         w = ctypes.c_double()
