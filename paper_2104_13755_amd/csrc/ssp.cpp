@@ -69,16 +69,6 @@ struct Surface {
                 if (!found) out.push_back({w, 1});
             }
     }
-    bool on_boundary(int v, std::vector<std::pair<int, int>> &scratch) const {
-        link(v, scratch);
-        for (auto &pr : scratch) if (pr.second == 1) return true;
-        return false;
-    }
-    int boundary_neighbour_except(int v, int other, std::vector<std::pair<int, int>> &scratch) const {
-        link(v, scratch);
-        for (auto &pr : scratch) if (pr.second == 1 && pr.first != other) return pr.first;
-        return -1;
-    }
 };
 
 struct Cand {
@@ -130,16 +120,25 @@ static inline double orient2(const double *a, const double *b, const double *c) 
     return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
 }
 
+// Buffers of flatten(), reused across collapses.
+struct FlatWork {
+    std::vector<int> slot;
+    std::vector<double> N, g;
+};
+
 // Minimise the summed conformal energy of both patches with some coordinates
 // fixed.  Normal equations N z_free = -J_free^T J_fixed z_fixed, solved by a
 // dense Cholesky factorisation.
 static bool flatten(const Surface &S, Joint &J, const std::vector<int> &fixed,
-                    const std::vector<double> &fixval) {
+                    const std::vector<double> &fixval, FlatWork &w) {
     const int ncol = 2 * J.ndof;
-    std::vector<int> slot(ncol, -1);
+    std::vector<int> &slot = w.slot;
+    slot.assign(ncol, -1);
     int nfree = 0;
     for (int c = 0; c < ncol; ++c) if (!fixed[c]) slot[c] = nfree++;
-    std::vector<double> N((size_t)nfree * nfree, 0.0), g(nfree, 0.0);
+    std::vector<double> &N = w.N, &g = w.g;
+    N.assign((size_t)nfree * nfree, 0.0);
+    g.assign(nfree, 0.0);
     auto accumulate = [&](const std::array<int, 3> &v, const std::array<int, 3> &d) -> bool {
         double re[6], im[6];
         if (!conformal_rows(&S.X[3 * v[0]], &S.X[3 * v[1]], &S.X[3 * v[2]], re, im)) return false;
@@ -244,12 +243,35 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
         for (int c = 0; c < 3; ++c) bary[v][c] = S.tri[t][c] == v ? 1.0 : 0.0;
         bucket[t].push_back(v);
     }
-    std::priority_queue<Cand, std::vector<Cand>, CandAfter> pq;
+    // Candidates in priority order.  An edge of the input keeps its length
+    // for the whole level (a collapse creates a new vertex id), so the input
+    // edges are sorted once and read in order; edges created by collapses and
+    // re-enabled edges go through a heap, and each pop takes the smaller head
+    // of the two under the same total order.
+    std::vector<Cand> init;
+    init.reserve(3 * (size_t)m);
     for (int t = 0; t < m; ++t)
         for (int c = 0; c < 3; ++c) {
             const int a = S.tri[t][c], b = S.tri[t][(c + 1) % 3];
-            pq.push({S.sqdist(a, b), std::min(a, b), std::max(a, b)});
+            init.push_back({S.sqdist(a, b), std::min(a, b), std::max(a, b)});
         }
+    std::sort(init.begin(), init.end(), [](const Cand &x, const Cand &y) { return CandAfter()(y, x); });
+    init.erase(std::unique(init.begin(), init.end(),
+                           [](const Cand &x, const Cand &y) { return x.lo == y.lo && x.hi == y.hi; }),
+               init.end());
+    size_t cursor = 0;
+    std::priority_queue<Cand, std::vector<Cand>, CandAfter> pq;
+    auto next_cand = [&](Cand &out) {
+        const bool from_init = cursor < init.size() && (pq.empty() || CandAfter()(pq.top(), init[cursor]));
+        if (from_init) {
+            out = init[cursor++];
+        } else {
+            if (pq.empty()) return false;
+            out = pq.top();
+            pq.pop();
+        }
+        return true;
+    };
 
     double st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int alive = n;
@@ -257,15 +279,22 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
     // only when a collapse changes their neighbourhood; every other edge keeps
     // its single queue entry (its length never changes: new vertices get new
     // ids), so re-inserting it would only add an equal-key duplicate.
+    // nfailed[v] counts the failed edges at v, so the re-enable scan skips
+    // vertices that have none.
     std::unordered_set<uint64_t> failed;
+    std::vector<int> nfailed(n, 0);
     auto ekey = [](int lo, int hi) { return ((uint64_t)(uint32_t)lo << 32) | (uint32_t)hi; };
-    auto fail_edge = [&](int lo, int hi) { failed.insert(ekey(lo, hi)); st[1]++; };
-    std::vector<std::pair<int, int> > la, lb, tmp;
-    std::vector<int> before, ring, moved;
+    auto fail_edge = [&](int lo, int hi) {
+        if (failed.insert(ekey(lo, hi)).second) { nfailed[lo]++; nfailed[hi]++; }
+        st[1]++;
+    };
+    std::vector<std::pair<int, int> > la, lb;
+    std::vector<int> before, ring, moved, opp, opps, na, nb, common, fixed;
+    std::vector<double> val;
+    FlatWork work;
     Joint cur, best;
-    while (alive > target && !pq.empty()) {
-        const Cand cd = pq.top();
-        pq.pop();
+    Cand cd;
+    while (alive > target && next_cand(cd)) {
         const int a = cd.lo, b = cd.hi;
         if (!S.vert_alive[a] || !S.vert_alive[b]) continue;
         int shared_tris[3], nshared = 0;
@@ -274,26 +303,33 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
             if (f[0] == b || f[1] == b || f[2] == b) { if (nshared < 3) shared_tris[nshared] = t; ++nshared; }
         }
         if (nshared < 1 || nshared > 2) { fail_edge(a, b); continue; }
-        const bool ba = S.on_boundary(a, tmp), bb = S.on_boundary(b, tmp);
+        // a vertex is on the boundary iff an edge at it has one triangle
+        S.link(a, la);
+        S.link(b, lb);
+        auto boundary_of = [](const std::vector<std::pair<int, int> > &l) {
+            for (auto &pr : l) if (pr.second == 1) return true;
+            return false;
+        };
+        const bool ba = boundary_of(la), bb = boundary_of(lb);
         const bool boundary_edge = nshared == 1;
         if (interior_only && (ba || bb)) { fail_edge(a, b); continue; }
         if (!boundary_edge && ba && bb) { fail_edge(a, b); continue; }
         // link condition: common neighbours == opposite corners of the shared triangles
-        S.link(a, la);
-        S.link(b, lb);
-        std::vector<int> opp;
+        opp.clear();
         for (int q = 0; q < nshared; ++q)
             for (int c = 0; c < 3; ++c) {
                 const int w = S.tri[shared_tris[q]][c];
                 if (w != a && w != b) opp.push_back(w);
             }
-        std::vector<int> na, nb, common;
+        na.clear();
+        nb.clear();
+        common.clear();
         for (auto &pr : la) if (pr.first != b) na.push_back(pr.first);
         for (auto &pr : lb) if (pr.first != a) nb.push_back(pr.first);
         std::sort(na.begin(), na.end());
         std::sort(nb.begin(), nb.end());
         std::set_intersection(na.begin(), na.end(), nb.begin(), nb.end(), std::back_inserter(common));
-        std::vector<int> opps = opp;
+        opps = opp;
         std::sort(opps.begin(), opps.end());
         if (common != opps) { fail_edge(a, b); continue; }
         bool ear = false;
@@ -308,8 +344,12 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
                 if (f[c] == a && f[(c + 1) % 3] == b) { i = a; j = b; }
                 else if (f[c] == b && f[(c + 1) % 3] == a) { i = b; j = a; }
             }
-            p = S.boundary_neighbour_except(i, j, tmp);
-            q = S.boundary_neighbour_except(j, i, tmp);
+            auto boundary_neighbour_except = [](const std::vector<std::pair<int, int> > &l, int other) {
+                for (auto &pr : l) if (pr.second == 1 && pr.first != other) return pr.first;
+                return -1;
+            };
+            p = boundary_neighbour_except(i == a ? la : lb, j);
+            q = boundary_neighbour_except(j == a ? la : lb, i);
             if (p < 0 || q < 0 || p == q || p == j || q == i) { fail_edge(a, b); continue; }
         } else if (ba || bb) {
             kind = 1;
@@ -364,8 +404,8 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
                 if (has_i && has_j) continue;
                 cur.after_id.push_back(t); cur.after_v.push_back(av); cur.after_d.push_back(ad);
             }
-            std::vector<int> fixed(2 * cur.ndof, 0);
-            std::vector<double> val(2 * cur.ndof, 0.0);
+            fixed.assign(2 * cur.ndof, 0);
+            val.assign(2 * cur.ndof, 0.0);
             if (kind != 2) {
                 int pa = -1, pb = -1;
                 double far2 = -1.0;
@@ -383,19 +423,22 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
                 const int dp = ring_dof(p), dq = ring_dof(q);
                 const double lpi = std::sqrt(S.sqdist(p, i)), lij = std::sqrt(S.sqdist(i, j)),
                              ljq = std::sqrt(S.sqdist(j, q));
-                int first, last;
+                int first, last, nline;
                 double span;
-                std::vector<int> line;
-                if (cs == 0) { line = {di, dj, dq}; first = di; last = dq; span = lij + ljq; }
-                else if (cs == 1) { line = {dp, di, dj}; first = dp; last = dj; span = lpi + lij; }
-                else { line = {dp, di, dk, dj, dq}; first = dp; last = dq; span = lpi + lij + ljq; }
-                for (int d : line) fixed[2 * d + 1] = 1;
+                int line[5];
+                if (cs == 0) { line[0] = di; line[1] = dj; line[2] = dq; nline = 3; first = di; last = dq; span = lij + ljq; }
+                else if (cs == 1) { line[0] = dp; line[1] = di; line[2] = dj; nline = 3; first = dp; last = dj; span = lpi + lij; }
+                else {
+                    line[0] = dp; line[1] = di; line[2] = dk; line[3] = dj; line[4] = dq;
+                    nline = 5; first = dp; last = dq; span = lpi + lij + ljq;
+                }
+                for (int s = 0; s < nline; ++s) fixed[2 * line[s] + 1] = 1;
                 fixed[2 * first] = 1; val[2 * first] = 0.0;
                 fixed[2 * last] = 1; val[2 * last] = span;
                 cur.scale = span;
             }
-            if (!flatten(S, cur, fixed, val)) continue;
-            if (chosen < 0 || cur.energy < best.energy) { chosen = cs; best = cur; }
+            if (!flatten(S, cur, fixed, val, work)) continue;
+            if (chosen < 0 || cur.energy < best.energy) { chosen = cs; std::swap(best, cur); }
         }
         if (chosen < 0) { S.X.resize(3 * (size_t)k); fail_edge(a, b); continue; }
 
@@ -456,6 +499,7 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
         S.star[i].clear();
         S.star[j].clear();
         S.vert_alive.push_back(1);
+        nfailed.push_back(0);
         S.star.push_back(best.after_id);
         --alive;
         st[0]++;
@@ -469,12 +513,15 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
         if (!failed.empty())
             for (auto &pr : la) {
                 const int x = pr.first;
+                if (nfailed[x] == 0) continue;
                 S.link(x, lb);
                 for (auto &qr : lb) {
                     const int y = qr.first;
                     auto it = failed.find(ekey(std::min(x, y), std::max(x, y)));
                     if (it != failed.end()) {
                         failed.erase(it);
+                        nfailed[x]--;
+                        nfailed[y]--;
                         pq.push({S.sqdist(x, y), std::min(x, y), std::max(x, y)});
                     }
                 }
