@@ -104,6 +104,24 @@ class Hierarchy:
         L.check(self._lib.smg_hier_get_prolongation(self._h, l, _np_ptr(cols), _np_ptr(w)), "get_prolongation")
         return cols, w
 
+    def save(self, path):
+        """Write the prolongations to an .npz file (no pickled objects): the
+        precompute depends on the geometry only, so a saved hierarchy serves
+        every later system on the same mesh."""
+        arrays = {"sizes": np.asarray(self.sizes, dtype=np.int32)}
+        for l in range(self.num_levels - 1):
+            arrays[f"pcols{l}"], arrays[f"pw{l}"] = self.prolongation(l)
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load(cls, path):
+        """Hierarchy from a file written by save() (statistics are not kept)."""
+        with np.load(path, allow_pickle=False) as z:
+            sizes = z["sizes"]
+            nl = len(sizes)
+            return cls.from_prolongations(sizes, [z[f"pcols{l}"] for l in range(nl - 1)],
+                                          [z[f"pw{l}"] for l in range(nl - 1)])
+
     def stats(self, l):
         s = np.zeros(8)
         L.check(self._lib.smg_hier_stats(self._h, l, _np_ptr(s)), "hier_stats")

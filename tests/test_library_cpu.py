@@ -81,6 +81,21 @@ def test_flat_interior_closed_form_product():
     assert abs(P @ Vc_ref[:, :2] - V[:, :2]).max() < 1e-13
 
 
+def test_hierarchy_save_load_round_trip(tmp_path):
+    from paper_2104_13755_amd.solver import Hierarchy
+    rng = np.random.default_rng(4)
+    V, F = synth.disc_grid(40, 37, rng, 0.1, height=lambda x, y: 0.1 * np.sin(3 * x))
+    h = Hierarchy.build(V, F, n_levels=4)
+    path = tmp_path / "hier.npz"
+    h.save(path)
+    g = Hierarchy.load(path)
+    assert g.sizes == h.sizes
+    for l in range(h.num_levels - 1):
+        c0, w0 = h.prolongation(l)
+        c1, w1 = g.prolongation(l)
+        assert np.array_equal(c0, c1) and np.array_equal(w0, w1)
+
+
 def test_coloring_matches_oracle():
     from paper_2104_13755_amd.solver import color_pattern
     V, F = synth.small_icosphere(4, seed=2)
