@@ -5,6 +5,7 @@
 #include "hier.h"
 
 #include <algorithm>
+#include <array>
 #include <numeric>
 
 namespace smg {
@@ -310,29 +311,35 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, 
         // T = A P pattern per permuted fine row; plan1 maps (source, slot) -> T offset
         L.tptr.assign(n + 1, 0);
         L.plan1ptr.assign(n + 1, 0);
+        L.plan1.reserve(3 * ((size_t)n + L.sell.pidx.size()));
+        // the prolongation row by row (-1: unused slot), one cache line per source
+        std::vector<std::array<int32_t, 3>> prow(n);
+        for (int r = 0; r < n; ++r)
+            for (int m = 0; m < 3; ++m) prow[r][m] = L.pw[(size_t)m * n + r] > 0.0 ? L.pc[(size_t)m * n + r] : -1;
         std::vector<int32_t> tcols;
         std::vector<int32_t> row;
+        // mark[b] == r: coarse column b already in T row r, at offset pos[b]
+        std::vector<int32_t> mark(nc, -1), pos(nc, 0);
         for (int r = 0; r < n; ++r) {
             row.clear();
             auto add_src = [&](int src) {
-                for (int m = 0; m < 3; ++m)
-                    if (L.pw[(size_t)m * n + src] > 0.0) row.push_back(L.pc[(size_t)m * n + src]);
+                for (int m = 0; m < 3; ++m) {
+                    const int b = prow[src][m];
+                    if (b >= 0 && mark[b] != r) { mark[b] = r; row.push_back(b); }
+                }
             };
             add_src(r);
             for (int e = 0; e < L.sell.rowlen[r]; ++e) add_src(L.sell.pidx[L.sell.pptr[r] + e]);
             std::sort(row.begin(), row.end());
-            row.erase(std::unique(row.begin(), row.end()), row.end());
+            for (size_t k = 0; k < row.size(); ++k) pos[row[k]] = (int32_t)k;
             if (row.size() > 65535) { err = "Galerkin row too long"; return -1; }
             tcols.insert(tcols.end(), row.begin(), row.end());
             L.tptr[r + 1] = (int32_t)tcols.size();
             L.tmax = std::max(L.tmax, (int)row.size());
             auto emit = [&](int src) {
                 for (int m = 0; m < 3; ++m) {
-                    const int b = L.pc[(size_t)m * n + src];
-                    const bool used = L.pw[(size_t)m * n + src] > 0.0;
-                    int off = 0;
-                    if (used) off = (int)(std::lower_bound(row.begin(), row.end(), b) - row.begin());
-                    L.plan1.push_back((uint16_t)off);
+                    const int b = prow[src][m];
+                    L.plan1.push_back((uint16_t)(b >= 0 ? pos[b] : 0));
                 }
             };
             emit(r);
@@ -360,14 +367,20 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, 
         }
         // plan2: for coarse row a, for R entry (r, w), for T entry (r, b): local slot of (a, b)
         L.plan2ptr.assign(nc + 1, 0);
+        {
+            size_t total = 0;
+            for (int a = 0; a < nc; ++a)
+                for (int q = L.rptr[a]; q < L.rptr[a + 1]; ++q) total += L.tptr[L.ridx[q] + 1] - L.tptr[L.ridx[q]];
+            L.plan2.reserve(total);
+        }
+        std::fill(mark.begin(), mark.end(), -1);
         for (int a = 0; a < nc; ++a) {
-            const int32_t *ob = ocol.data() + L.optr[a], *oe = ocol.data() + L.optr[a + 1];
+            for (int k = L.optr[a]; k < L.optr[a + 1]; ++k) { mark[ocol[k]] = a; pos[ocol[k]] = k - L.optr[a]; }
             for (int q = L.rptr[a]; q < L.rptr[a + 1]; ++q) {
                 const int r = L.ridx[q];
                 for (int t = L.tptr[r]; t < L.tptr[r + 1]; ++t) {
-                    const int32_t *it = std::lower_bound(ob, oe, tcols[t]);
-                    if (it == oe || *it != tcols[t]) { err = "Galerkin plan outside the symbolic pattern"; return -1; }
-                    L.plan2.push_back((uint16_t)(it - ob));
+                    if (mark[tcols[t]] != a) { err = "Galerkin plan outside the symbolic pattern"; return -1; }
+                    L.plan2.push_back((uint16_t)pos[tcols[t]]);
                 }
             }
             if (L.plan2.size() > (size_t)INT32_MAX) { err = "Galerkin plan too large"; return -1; }

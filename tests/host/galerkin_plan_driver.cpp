@@ -1,0 +1,117 @@
+// Test driver (host only): builds the device-side level data of a hierarchy
+// with build_levels() and replays the two Galerkin plans on the CPU, row by
+// row in the order the device kernels use them (T = A P per permuted fine
+// row, then A_{l+1} = P^T T per permuted coarse row), starting from A_0 in the
+// library's storage (sliced ELL + diagonal; dense on the coarsest level).
+// Every level's values are decoded back to natural CSR through `store`.
+//
+// Input (binary, little endian): int32 nlev, lpr, sort_rows; int32 sizes[nlev];
+// per level l < nlev-1: int32 pcols[3 n_l], double pw[3 n_l]; int32 nnz;
+// int32 ptr[n_0 + 1], idx[nnz]; double a[nnz].
+// Output (binary): per level: int32 nnz, ncolors; int32 ptr[n_l + 1],
+// idx[nnz]; double a[nnz]; int32 color[n_l] (all -1 on the coarsest level).
+#include "hier.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+using namespace smg;
+
+template <class T> static bool rd(FILE *f, T *p, size_t n) { return fread(p, sizeof(T), n, f) == n; }
+template <class T> static void wr(FILE *f, const T *p, size_t n) { fwrite(p, sizeof(T), n, f); }
+
+int main(int argc, char **argv) {
+    if (argc != 3) return 2;
+    FILE *f = fopen(argv[1], "rb");
+    if (!f) return 2;
+    int32_t hdr[3];
+    if (!rd(f, hdr, 3)) return 3;
+    const int nlev = hdr[0];
+    HierHost H;
+    H.nlev = nlev;
+    H.sizes.resize(nlev);
+    if (!rd(f, H.sizes.data(), nlev)) return 3;
+    for (int l = 0; l + 1 < nlev; ++l) {
+        std::vector<int32_t> c(3 * (size_t)H.sizes[l]);
+        std::vector<double> w(3 * (size_t)H.sizes[l]);
+        if (!rd(f, c.data(), c.size()) || !rd(f, w.data(), w.size())) return 3;
+        H.pcols.push_back(c);
+        H.pw.push_back(w);
+    }
+    int32_t nnz;
+    if (!rd(f, &nnz, 1)) return 3;
+    Csr A0;
+    A0.n = A0.m = H.sizes[0];
+    A0.ptr.resize(A0.n + 1);
+    A0.idx.resize(nnz);
+    std::vector<double> a0(nnz);
+    if (!rd(f, A0.ptr.data(), A0.ptr.size()) || !rd(f, A0.idx.data(), nnz) || !rd(f, a0.data(), nnz)) return 3;
+    fclose(f);
+
+    std::vector<LevelHost> lev;
+    std::string err;
+    if (build_levels(H, A0, std::vector<int>(nlev, hdr[1]), hdr[2], lev, err) != 0) {
+        fprintf(stderr, "build_levels: %s\n", err.c_str());
+        return 4;
+    }
+    // storage of every level: vals (SELL slots, or dense n x n on the coarsest) + diag
+    std::vector<std::vector<double>> vals(nlev), diag(nlev);
+    for (int l = 0; l < nlev; ++l) {
+        const LevelHost &L = lev[l];
+        vals[l].assign(L.coarsest ? (size_t)L.n * L.n : (size_t)L.sell.slots(), 0.0);
+        diag[l].assign(L.n, 0.0);
+    }
+    auto put = [&](int l, int32_t pos, double v) {
+        if (pos >= 0) vals[l][pos] = v; else diag[l][-1 - pos] = v;
+    };
+    for (int p = 0; p < nnz; ++p) put(0, lev[0].store[p], a0[p]);
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const LevelHost &L = lev[l];
+        const SellLayout &S = L.sell;
+        const int n = L.n, nc = lev[l + 1].n;
+        std::vector<double> T(L.tptr[n], 0.0);
+        for (int r = 0; r < n; ++r) {
+            const uint16_t *pl = L.plan1.data() + L.plan1ptr[r];
+            double *acc = T.data() + L.tptr[r];
+            for (int m = 0; m < 3; ++m) acc[pl[m]] += diag[l][r] * L.pw[(size_t)m * n + r];
+            const int s = S.row_slice[r];
+            const int base = S.slice_off[s] + (r - S.slice_row0[s]) * S.lpr;
+            for (int e = 0; e < S.rowlen[r]; ++e) {
+                const int slot = base + (e / S.lpr) * 64 + (e % S.lpr);
+                const int c = S.cols[slot];
+                for (int m = 0; m < 3; ++m) acc[pl[3 * (e + 1) + m]] += vals[l][slot] * L.pw[(size_t)m * n + c];
+            }
+        }
+        for (int a = 0; a < nc; ++a) {
+            std::vector<double> acc(L.optr[a + 1] - L.optr[a], 0.0);
+            int idx = L.plan2ptr[a];
+            for (int p = L.rptr[a]; p < L.rptr[a + 1]; ++p) {
+                const int r = L.ridx[p];
+                for (int t = L.tptr[r]; t < L.tptr[r + 1]; ++t) acc[L.plan2[idx++]] += L.rw[p] * T[t];
+            }
+            if (idx != L.plan2ptr[a + 1]) return 5;
+            for (size_t k = 0; k < acc.size(); ++k) put(l + 1, L.opos[L.optr[a] + k], acc[k]);
+        }
+    }
+    FILE *o = fopen(argv[2], "wb");
+    if (!o) return 2;
+    for (int l = 0; l < nlev; ++l) {
+        const LevelHost &L = lev[l];
+        const int32_t hd[2] = {(int32_t)L.pat.idx.size(), L.ncolors};
+        wr(o, hd, 2);
+        wr(o, L.pat.ptr.data(), L.pat.ptr.size());
+        wr(o, L.pat.idx.data(), L.pat.idx.size());
+        std::vector<double> av(L.pat.idx.size());
+        for (size_t p = 0; p < av.size(); ++p) {
+            const int32_t pos = L.store[p];
+            av[p] = pos >= 0 ? vals[l][pos] : diag[l][-1 - pos];
+        }
+        wr(o, av.data(), av.size());
+        std::vector<int32_t> col(L.n, -1);
+        if (!L.coarsest) col = L.color;
+        wr(o, col.data(), col.size());
+    }
+    fclose(o);
+    return 0;
+}
