@@ -241,12 +241,22 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, 
         }
         if (l + 1 < nlev) pat = galerkin_pattern(pat, H.sizes[l + 1], H.pcols[l]);
     }
+    // epos[c]: index of permuted column c in the current row's ascending
+    // off-diagonal list (every column looked up is in that row's pattern)
+    std::vector<int32_t> epos;
     for (int l = 0; l < nlev; ++l) {
         LevelHost &L = levels[l];
         L.store.resize(L.pat.idx.size());
-        for (int i = 0; i < L.n; ++i)
-            for (int p = L.pat.ptr[i]; p < L.pat.ptr[i + 1]; ++p)
-                L.store[p] = store_pos(L, L.iperm[i], L.iperm[L.pat.idx[p]]);
+        epos.assign(L.n, 0);
+        for (int i = 0; i < L.n; ++i) {
+            const int r = L.iperm[i];
+            if (!L.coarsest)
+                for (int e = L.sell.pptr[r]; e < L.sell.pptr[r + 1]; ++e) epos[L.sell.pidx[e]] = e - L.sell.pptr[r];
+            for (int p = L.pat.ptr[i]; p < L.pat.ptr[i + 1]; ++p) {
+                const int c = L.iperm[L.pat.idx[p]];
+                L.store[p] = (L.coarsest || c == r) ? store_pos(L, r, c) : L.sell.slot(r, epos[c]);
+            }
+        }
         if (l + 1 == nlev) break;
         const LevelHost &C = levels[l + 1];
         const int n = L.n, nc = C.n;
@@ -351,13 +361,17 @@ int build_levels(const HierHost &H, const Csr &A0, const std::vector<int> &lpr, 
         L.optr.assign(nc + 1, 0);
         L.opos.clear();
         std::vector<int32_t> ocol;   // permuted column of each local slot
+        epos.assign(nc, 0);
         for (int a = 0; a < nc; ++a) {
             const int i = C.perm[a];
             const size_t o0 = ocol.size();
             for (int p = C.pat.ptr[i]; p < C.pat.ptr[i + 1]; ++p) ocol.push_back(C.iperm[C.pat.idx[p]]);
             std::sort(ocol.begin() + o0, ocol.end());
+            if (!C.coarsest)
+                for (int e = C.sell.pptr[a]; e < C.sell.pptr[a + 1]; ++e) epos[C.sell.pidx[e]] = e - C.sell.pptr[a];
             for (size_t k = o0; k < ocol.size(); ++k) {
-                const int32_t pos = store_pos(C, a, ocol[k]);
+                const int c = ocol[k];
+                const int32_t pos = (C.coarsest || c == a) ? store_pos(C, a, c) : C.sell.slot(a, epos[c]);
                 if (pos == INT32_MIN) { err = "coarse pattern without storage"; return -1; }
                 L.opos.push_back(pos);
             }
