@@ -292,6 +292,8 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
     std::vector<int> before, ring, moved, opp, opps, na, nb, common, fixed;
     std::vector<double> val;
     FlatWork work;
+    struct AfterTri { const double *A, *B, *C; double area; };
+    std::vector<AfterTri> after_uv;   // corners and signed area of each after triangle
     Joint cur, best;
     Cand cd;
     while (alive > target && next_cand(cd)) {
@@ -444,6 +446,13 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
 
         // move the query points of the before patch into the after patch
         moved.clear();
+        after_uv.clear();
+        for (size_t r = 0; r < best.after_id.size(); ++r) {
+            const double *A = best.uv[best.after_d[r][0]].data();
+            const double *B = best.uv[best.after_d[r][1]].data();
+            const double *C = best.uv[best.after_d[r][2]].data();
+            after_uv.push_back({A, B, C, orient2(A, B, C)});
+        }
         for (size_t s = 0; s < best.before_id.size(); ++s) {
             const int t = best.before_id[s];
             for (int v : bucket[t]) {
@@ -455,11 +464,9 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
                 const double pt[2] = {u0, u1};
                 int win = -1;
                 double win_min = 0.0, wl[3] = {0, 0, 0};
-                for (size_t r = 0; r < best.after_id.size(); ++r) {
-                    const double *A = best.uv[best.after_d[r][0]].data();
-                    const double *B = best.uv[best.after_d[r][1]].data();
-                    const double *C = best.uv[best.after_d[r][2]].data();
-                    const double area = orient2(A, B, C);
+                for (size_t r = 0; r < after_uv.size(); ++r) {
+                    const double *A = after_uv[r].A, *B = after_uv[r].B, *C = after_uv[r].C;
+                    const double area = after_uv[r].area;
                     const double l0 = orient2(pt, B, C) / area;
                     const double l1 = orient2(A, pt, C) / area;
                     const double l2 = orient2(A, B, pt) / area;
