@@ -4,12 +4,17 @@
 // row, then A_{l+1} = P^T T per permuted coarse row), starting from A_0 in the
 // library's storage (sliced ELL + diagonal; dense on the coarsest level).
 // Every level's values are decoded back to natural CSR through `store`.
+// Then, on every smoothed level, the one-workgroup tail's record layout is
+// built and one Gauss-Seidel sweep is replayed from it (records read per
+// wavefront lane as the device reads them), ascending and descending.
 //
 // Input (binary, little endian): int32 nlev, lpr, sort_rows; int32 sizes[nlev];
 // per level l < nlev-1: int32 pcols[3 n_l], double pw[3 n_l]; int32 nnz;
-// int32 ptr[n_0 + 1], idx[nnz]; double a[nnz].
+// int32 ptr[n_0 + 1], idx[nnz]; double a[nnz]; per smoothed level (natural
+// order): double x0[n_l], b[n_l].
 // Output (binary): per level: int32 nnz, ncolors; int32 ptr[n_l + 1],
-// idx[nnz]; double a[nnz]; int32 color[n_l] (all -1 on the coarsest level).
+// idx[nnz]; double a[nnz]; int32 color[n_l] (all -1 on the coarsest level);
+// then per smoothed level: int32 grp; double x_asc[n_l], x_desc[n_l] (natural).
 #include "hier.h"
 
 #include <cstdio>
@@ -47,6 +52,12 @@ int main(int argc, char **argv) {
     A0.idx.resize(nnz);
     std::vector<double> a0(nnz);
     if (!rd(f, A0.ptr.data(), A0.ptr.size()) || !rd(f, A0.idx.data(), nnz) || !rd(f, a0.data(), nnz)) return 3;
+    std::vector<std::vector<double>> x0(nlev), b0(nlev);
+    for (int l = 0; l + 1 < nlev; ++l) {
+        x0[l].resize(H.sizes[l]);
+        b0[l].resize(H.sizes[l]);
+        if (!rd(f, x0[l].data(), x0[l].size()) || !rd(f, b0[l].data(), b0[l].size())) return 3;
+    }
     fclose(f);
 
     std::vector<LevelHost> lev;
@@ -111,6 +122,43 @@ int main(int argc, char **argv) {
         std::vector<int32_t> col(L.n, -1);
         if (!L.coarsest) col = L.color;
         wr(o, col.data(), col.size());
+    }
+    const int threads = 1024;
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const LevelHost &L = lev[l];
+        TailLayout T;
+        build_tail_layout(L, lev[l + 1].n, threads, 0, T);
+        if (!check_tail_layout(T, L.n, threads, err)) {
+            fprintf(stderr, "level %d: %s\n", l, err.c_str());
+            return 6;
+        }
+        const int G = T.grp, npass = (int)T.pass.size() / 4;
+        wr(o, &G, 1);
+        for (int dir = 0; dir < 2; ++dir) {
+            std::vector<double> x(L.n), b(L.n);
+            for (int r = 0; r < L.n; ++r) { x[r] = x0[l][L.perm[r]]; b[r] = b0[l][L.perm[r]]; }
+            for (int pp = 0; pp < npass; ++pp) {
+                const int p = dir ? npass - 1 - pp : pp;
+                const int row0 = T.pass[4 * p], nrows = T.pass[4 * p + 1], w0 = T.pass[4 * p + 3];
+                for (int g = 0; g < nrows; ++g) {
+                    double acc = 0.0;
+                    for (int j = 0; j < G; ++j) {
+                        const int t = g * G + j, w = w0 + t / 64, lane = t % 64;
+                        const int off = T.wave[2 * w], npair = T.wave[2 * w + 1];
+                        for (int k = 0; k < 2 * npair; ++k) {
+                            const int rec = off + 128 * (k / 2) + 2 * lane + k % 2;
+                            const double v = T.src[rec] >= 0 ? vals[l][T.src[rec]] : 0.0;
+                            acc += v * x[T.cols[rec]];
+                        }
+                    }
+                    const int r = row0 + g;
+                    x[r] = (b[r] - acc) / diag[l][r];
+                }
+            }
+            std::vector<double> xn(L.n);
+            for (int r = 0; r < L.n; ++r) xn[L.perm[r]] = x[r];
+            wr(o, xn.data(), xn.size());
+        }
     }
     fclose(o);
     return 0;

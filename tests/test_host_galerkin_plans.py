@@ -4,7 +4,10 @@ two symbolic Galerkin plans of Eq. gca) is compiled with a small driver that
 replays both plans row by row as the device does, from A_0 in the library's
 storage, and decodes every level back to natural CSR.  Each level must equal
 the oracle's P_l^T A_l P_l (all of its nonzeros inside the symbolic pattern,
-values to rounding), and each color class must be an independent set."""
+values to rounding), and each color class must be an independent set.  The
+one-workgroup tail's record layout is checked the same way: one
+Gauss-Seidel sweep replayed from the records (ascending and descending color
+order) must equal the oracle's multicolor sweep on that level."""
 import os
 import shutil
 import subprocess
@@ -15,7 +18,7 @@ import scipy.sparse as sp
 
 from conftest import ROOT
 import synth
-from oracle import assemble as AS, hierarchy as OH
+from oracle import assemble as AS, hierarchy as OH, vcycle as OV
 
 CSRC = os.path.join(ROOT, "paper_2104_13755_amd", "csrc")
 DRIVER = os.path.join(ROOT, "tests", "host", "galerkin_plan_driver.cpp")
@@ -45,7 +48,7 @@ def _ell3(P):
     return cols, w
 
 
-def _run(driver, tmp_path, A, Ps, lpr, sort_rows):
+def _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb):
     sizes = [A.shape[0]] + [P.shape[1] for P in Ps]
     A = A.tocsr()
     A.sort_indices()
@@ -61,6 +64,9 @@ def _run(driver, tmp_path, A, Ps, lpr, sort_rows):
         A.indptr.astype(np.int32).tofile(f)
         A.indices.astype(np.int32).tofile(f)
         A.data.astype(np.float64).tofile(f)
+        for x0, b in xb:
+            x0.astype(np.float64).tofile(f)
+            b.astype(np.float64).tofile(f)
     r = subprocess.run([driver, str(inp), str(out)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     raw = open(out, "rb").read()
@@ -73,8 +79,15 @@ def _run(driver, tmp_path, A, Ps, lpr, sort_rows):
         val = np.frombuffer(raw, np.float64, nnz, o); o += 8 * nnz
         col = np.frombuffer(raw, np.int32, n, o); o += 4 * n
         levels.append((sp.csr_matrix((val, idx, ptr), shape=(n, n)), int(ncol), col))
+    sweeps = []
+    for n in sizes[:-1]:
+        grp = int(np.frombuffer(raw, np.int32, 1, o)[0])
+        o += 4
+        xa = np.frombuffer(raw, np.float64, n, o); o += 8 * n
+        xd = np.frombuffer(raw, np.float64, n, o); o += 8 * n
+        sweeps.append((grp, xa, xd))
     assert o == len(raw)
-    return levels
+    return levels, sweeps
 
 
 def _meshes():
@@ -89,7 +102,15 @@ def test_plans_replay_to_the_oracle_galerkin(driver, tmp_path, lpr, sort_rows):
     for name, (V, F), nl in _meshes():
         A, _, _ = AS.system(V, F, 1e-2)
         Ps, _, _ = OH.prolongations(V, F, n_levels=nl)
-        levels = _run(driver, tmp_path, A, Ps, lpr, sort_rows)
+        rng = np.random.default_rng(77)
+        xb = [(rng.uniform(-1, 1, P.shape[0]), rng.uniform(-1, 1, P.shape[0])) for P in Ps]
+        levels, sweeps = _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb)
+        O = OV.Solver(Ps, A)
+        for l, (grp, xa, xd) in enumerate(sweeps):
+            assert grp in (1, 2, 4)
+            for desc, xg in ((False, xa), (True, xd)):
+                xo = O.relax(l, xb[l][0][:, None].copy(), xb[l][1][:, None], 1, descending=desc)[:, 0]
+                assert abs(xg - xo).max() <= 1e-12 * abs(xo).max(), (name, l, desc)
         Al = A.tocsr()
         for l, (G, ncol, col) in enumerate(levels):
             if l > 0:
