@@ -4,9 +4,11 @@
 // row, then A_{l+1} = P^T T per permuted coarse row), starting from A_0 in the
 // library's storage (sliced ELL + diagonal; dense on the coarsest level).
 // Every level's values are decoded back to natural CSR through `store`.
-// Then, on every smoothed level, the one-workgroup tail's record layout is
-// built and one Gauss-Seidel sweep is replayed from it (records read per
-// wavefront lane as the device reads them), ascending and descending.
+// Then, on every smoothed level, one Gauss-Seidel sweep is replayed, in
+// ascending and in descending color order, from the sliced-ELL layout the
+// way the per-color launches read it (slice table, or for a color of uniform
+// width its offset from the slice index), and from the one-workgroup tail's
+// record layout (records read per wavefront lane as the device reads them).
 //
 // Input (binary, little endian): int32 nlev, lpr, sort_rows; int32 sizes[nlev];
 // per level l < nlev-1: int32 pcols[3 n_l], double pw[3 n_l]; int32 nnz;
@@ -14,7 +16,8 @@
 // order): double x0[n_l], b[n_l].
 // Output (binary): per level: int32 nnz, ncolors; int32 ptr[n_l + 1],
 // idx[nnz]; double a[nnz]; int32 color[n_l] (all -1 on the coarsest level);
-// then per smoothed level: int32 grp; double x_asc[n_l], x_desc[n_l] (natural).
+// then per smoothed level: int32 grp, uniform-width colors; double x_asc[n_l], x_desc[n_l] from the
+// tail records, then x_asc[n_l], x_desc[n_l] from the sliced ELL (natural).
 #include "hier.h"
 
 #include <cstdio>
@@ -133,7 +136,10 @@ int main(int argc, char **argv) {
             return 6;
         }
         const int G = T.grp, npass = (int)T.pass.size() / 4;
+        int nuniform = 0;
+        for (int c = 0; c < L.ncolors; ++c) nuniform += L.sell.color_w[c] > 0;
         wr(o, &G, 1);
+        wr(o, &nuniform, 1);
         for (int dir = 0; dir < 2; ++dir) {
             std::vector<double> x(L.n), b(L.n);
             for (int r = 0; r < L.n; ++r) { x[r] = x0[l][L.perm[r]]; b[r] = b0[l][L.perm[r]]; }
@@ -153,6 +159,42 @@ int main(int argc, char **argv) {
                     }
                     const int r = row0 + g;
                     x[r] = (b[r] - acc) / diag[l][r];
+                }
+            }
+            std::vector<double> xn(L.n);
+            for (int r = 0; r < L.n; ++r) xn[L.perm[r]] = x[r];
+            wr(o, xn.data(), xn.size());
+        }
+        const SellLayout &S = L.sell;
+        for (int dir = 0; dir < 2; ++dir) {
+            std::vector<double> x(L.n), b(L.n);
+            for (int r = 0; r < L.n; ++r) { x[r] = x0[l][L.perm[r]]; b[r] = b0[l][L.perm[r]]; }
+            for (int cc = 0; cc < L.ncolors; ++cc) {
+                const int c = dir ? L.ncolors - 1 - cc : cc;
+                const int s0 = S.color_slice[c], s1 = S.color_slice[c + 1];
+                for (int s = s0; s < s1; ++s) {
+                    int r0, r1, off, w;
+                    if (S.color_w[c] > 0) {   // uniform width: offsets from the slice index
+                        w = S.color_w[c];
+                        r0 = S.color_row[c] + (s - s0) * (64 / S.lpr);
+                        r1 = S.color_row[c + 1];
+                        off = S.slice_off[s0] + (s - s0) * 64 * w;
+                    } else {
+                        r0 = S.slice_row0[s];
+                        r1 = S.slice_row0[s + 1];
+                        off = S.slice_off[s];
+                        w = (S.slice_off[s + 1] - off) / 64;
+                    }
+                    std::vector<double> acc(64 / S.lpr, 0.0);
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int k = 0; k < w; ++k) {
+                            const int at = off + lane + 64 * k;
+                            acc[lane / S.lpr] += vals[l][at] * x[S.cols[at]];
+                        }
+                    for (int g = 0; g < 64 / S.lpr && r0 + g < r1; ++g) {
+                        const int r = r0 + g;
+                        x[r] = (b[r] - acc[g]) / diag[l][r];
+                    }
                 }
             }
             std::vector<double> xn(L.n);

@@ -5,9 +5,10 @@ replays both plans row by row as the device does, from A_0 in the library's
 storage, and decodes every level back to natural CSR.  Each level must equal
 the oracle's P_l^T A_l P_l (all of its nonzeros inside the symbolic pattern,
 values to rounding), and each color class must be an independent set.  The
-one-workgroup tail's record layout is checked the same way: one
-Gauss-Seidel sweep replayed from the records (ascending and descending color
-order) must equal the oracle's multicolor sweep on that level."""
+sliced-ELL layout of the per-color launches and the one-workgroup tail's
+record layout are checked the same way: one Gauss-Seidel sweep replayed from
+each (ascending and descending color order) must equal the oracle's
+multicolor sweep on that level."""
 import os
 import shutil
 import subprocess
@@ -81,11 +82,13 @@ def _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb):
         levels.append((sp.csr_matrix((val, idx, ptr), shape=(n, n)), int(ncol), col))
     sweeps = []
     for n in sizes[:-1]:
-        grp = int(np.frombuffer(raw, np.int32, 1, o)[0])
-        o += 4
+        grp, nuni = (int(v) for v in np.frombuffer(raw, np.int32, 2, o))
+        o += 8
         xa = np.frombuffer(raw, np.float64, n, o); o += 8 * n
         xd = np.frombuffer(raw, np.float64, n, o); o += 8 * n
-        sweeps.append((grp, xa, xd))
+        ya = np.frombuffer(raw, np.float64, n, o); o += 8 * n
+        yd = np.frombuffer(raw, np.float64, n, o); o += 8 * n
+        sweeps.append((grp, nuni, xa, xd, ya, yd))
     assert o == len(raw)
     return levels, sweeps
 
@@ -99,6 +102,7 @@ def _meshes():
 
 @pytest.mark.parametrize("lpr,sort_rows", [(0, 4096), (1, 0), (8, 100000), (2, 4096)])
 def test_plans_replay_to_the_oracle_galerkin(driver, tmp_path, lpr, sort_rows):
+    uniform = 0
     for name, (V, F), nl in _meshes():
         A, _, _ = AS.system(V, F, 1e-2)
         Ps, _, _ = OH.prolongations(V, F, n_levels=nl)
@@ -106,9 +110,10 @@ def test_plans_replay_to_the_oracle_galerkin(driver, tmp_path, lpr, sort_rows):
         xb = [(rng.uniform(-1, 1, P.shape[0]), rng.uniform(-1, 1, P.shape[0])) for P in Ps]
         levels, sweeps = _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb)
         O = OV.Solver(Ps, A)
-        for l, (grp, xa, xd) in enumerate(sweeps):
+        uniform += sum(sw[1] for sw in sweeps)
+        for l, (grp, _, xa, xd, ya, yd) in enumerate(sweeps):
             assert grp in (1, 2, 4)
-            for desc, xg in ((False, xa), (True, xd)):
+            for desc, xg in ((False, xa), (True, xd), (False, ya), (True, yd)):
                 xo = O.relax(l, xb[l][0][:, None].copy(), xb[l][1][:, None], 1, descending=desc)[:, 0]
                 assert abs(xg - xo).max() <= 1e-12 * abs(xo).max(), (name, l, desc)
         Al = A.tocsr()
@@ -130,3 +135,4 @@ def test_plans_replay_to_the_oracle_galerkin(driver, tmp_path, lpr, sort_rows):
                 assert not np.any(col[rows[off]] == col[G.indices[off]]), (name, l)
             else:
                 assert (col == -1).all()
+    assert uniform > 0   # colors of uniform width were replayed through their own offsets
