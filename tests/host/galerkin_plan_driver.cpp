@@ -9,15 +9,18 @@
 // way the per-color launches read it (slice table, or for a color of uniform
 // width its offset from the slice index), and from the one-workgroup tail's
 // record layout (records read per wavefront lane as the device reads them).
+// Last, per transfer, the restriction from its sliced-ELL form (P^T r) and
+// the prolongation from its permuted ELL-3 form (x + P e).
 //
 // Input (binary, little endian): int32 nlev, lpr, sort_rows; int32 sizes[nlev];
 // per level l < nlev-1: int32 pcols[3 n_l], double pw[3 n_l]; int32 nnz;
 // int32 ptr[n_0 + 1], idx[nnz]; double a[nnz]; per smoothed level (natural
-// order): double x0[n_l], b[n_l].
+// order): double x0[n_l], b[n_l]; per level l < nlev-1: double e[n_{l+1}].
 // Output (binary): per level: int32 nnz, ncolors; int32 ptr[n_l + 1],
 // idx[nnz]; double a[nnz]; int32 color[n_l] (all -1 on the coarsest level);
 // then per smoothed level: int32 grp, uniform-width colors; double x_asc[n_l], x_desc[n_l] from the
-// tail records, then x_asc[n_l], x_desc[n_l] from the sliced ELL (natural).
+// tail records, then x_asc[n_l], x_desc[n_l] from the sliced ELL (natural);
+// then per level l < nlev-1: double P^T x0[n_{l+1}], x0 + P e[n_l] (natural).
 #include "hier.h"
 
 #include <cstdio>
@@ -60,6 +63,11 @@ int main(int argc, char **argv) {
         x0[l].resize(H.sizes[l]);
         b0[l].resize(H.sizes[l]);
         if (!rd(f, x0[l].data(), x0[l].size()) || !rd(f, b0[l].data(), b0[l].size())) return 3;
+    }
+    std::vector<std::vector<double>> ec(nlev);
+    for (int l = 0; l + 1 < nlev; ++l) {
+        ec[l].resize(H.sizes[l + 1]);
+        if (!rd(f, ec[l].data(), ec[l].size())) return 3;
     }
     fclose(f);
 
@@ -201,6 +209,34 @@ int main(int argc, char **argv) {
             for (int r = 0; r < L.n; ++r) xn[L.perm[r]] = x[r];
             wr(o, xn.data(), xn.size());
         }
+    }
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const LevelHost &L = lev[l], &C = lev[l + 1];
+        const int n = L.n, nc = C.n, lr = L.rs_lanes, rps = 64 / lr;
+        std::vector<double> r(n), rc(nc, 0.0);
+        for (int i = 0; i < n; ++i) r[i] = x0[l][L.perm[i]];
+        for (int s = 0; s * rps < nc; ++s) {
+            const int w = (L.rs_off[s + 1] - L.rs_off[s]) / 64;
+            for (int lane = 0; lane < 64; ++lane) {
+                const int a = s * rps + lane / lr;
+                if (a >= nc) continue;
+                for (int k = 0; k < w; ++k) {
+                    const int at = L.rs_off[s] + lane + 64 * k;
+                    rc[a] += L.rs_w[at] * r[L.rs_idx[at]];
+                }
+            }
+        }
+        std::vector<double> rcn(nc);
+        for (int a = 0; a < nc; ++a) rcn[C.perm[a]] = rc[a];
+        wr(o, rcn.data(), rcn.size());
+        std::vector<double> x(n);
+        for (int i = 0; i < n; ++i) {
+            const int rr = L.iperm[i];
+            double v = r[rr];
+            for (int m = 0; m < 3; ++m) v += L.pw[(size_t)m * n + rr] * ec[l][C.perm[L.pc[(size_t)m * n + rr]]];
+            x[i] = v;
+        }
+        wr(o, x.data(), x.size());
     }
     fclose(o);
     return 0;

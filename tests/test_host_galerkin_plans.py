@@ -8,7 +8,8 @@ values to rounding), and each color class must be an independent set.  The
 sliced-ELL layout of the per-color launches and the one-workgroup tail's
 record layout are checked the same way: one Gauss-Seidel sweep replayed from
 each (ascending and descending color order) must equal the oracle's
-multicolor sweep on that level."""
+multicolor sweep on that level; the restriction and prolongation layouts
+must give P^T r and x + P e."""
 import os
 import shutil
 import subprocess
@@ -49,7 +50,7 @@ def _ell3(P):
     return cols, w
 
 
-def _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb):
+def _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb, ecs):
     sizes = [A.shape[0]] + [P.shape[1] for P in Ps]
     A = A.tocsr()
     A.sort_indices()
@@ -68,6 +69,8 @@ def _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb):
         for x0, b in xb:
             x0.astype(np.float64).tofile(f)
             b.astype(np.float64).tofile(f)
+        for e in ecs:
+            e.astype(np.float64).tofile(f)
     r = subprocess.run([driver, str(inp), str(out)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     raw = open(out, "rb").read()
@@ -89,8 +92,13 @@ def _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb):
         ya = np.frombuffer(raw, np.float64, n, o); o += 8 * n
         yd = np.frombuffer(raw, np.float64, n, o); o += 8 * n
         sweeps.append((grp, nuni, xa, xd, ya, yd))
+    transfers = []
+    for n, nc in zip(sizes[:-1], sizes[1:]):
+        rc = np.frombuffer(raw, np.float64, nc, o); o += 8 * nc
+        xp = np.frombuffer(raw, np.float64, n, o); o += 8 * n
+        transfers.append((rc, xp))
     assert o == len(raw)
-    return levels, sweeps
+    return levels, sweeps, transfers
 
 
 def _meshes():
@@ -108,7 +116,13 @@ def test_plans_replay_to_the_oracle_galerkin(driver, tmp_path, lpr, sort_rows):
         Ps, _, _ = OH.prolongations(V, F, n_levels=nl)
         rng = np.random.default_rng(77)
         xb = [(rng.uniform(-1, 1, P.shape[0]), rng.uniform(-1, 1, P.shape[0])) for P in Ps]
-        levels, sweeps = _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb)
+        ecs = [rng.uniform(-1, 1, P.shape[1]) for P in Ps]
+        levels, sweeps, transfers = _run(driver, tmp_path, A, Ps, lpr, sort_rows, xb, ecs)
+        for l, (rc, xp) in enumerate(transfers):
+            ro = Ps[l].T @ xb[l][0]
+            assert abs(rc - ro).max() <= 1e-14 * abs(ro).max(), (name, l)
+            xo = xb[l][0] + Ps[l] @ ecs[l]
+            assert abs(xp - xo).max() <= 1e-14 * abs(xo).max(), (name, l)
         O = OV.Solver(Ps, A)
         uniform += sum(sw[1] for sw in sweeps)
         for l, (grp, _, xa, xd, ya, yd) in enumerate(sweeps):
