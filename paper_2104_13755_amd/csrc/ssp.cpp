@@ -37,7 +37,6 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
-#include <queue>
 #include <unordered_set>
 #include <vector>
 
@@ -75,12 +74,50 @@ struct Cand {
     double key;
     int lo, hi;
 };
-struct CandAfter {   // min-heap order for std::priority_queue
+struct CandAfter {   // a comes after b in the collapse order
     bool operator()(const Cand &a, const Cand &b) const {
         if (a.key != b.key) return a.key > b.key;
         if (a.lo != b.lo) return a.lo > b.lo;
         return a.hi > b.hi;
     }
+};
+
+// Min-heap with four children per node (fewer levels, children in one cache line).
+class Heap4 {
+  public:
+    bool empty() const { return h_.empty(); }
+    const Cand &top() const { return h_[0]; }
+    void push(const Cand &c) {
+        size_t i = h_.size();
+        h_.push_back(c);
+        while (i > 0) {
+            const size_t p = (i - 1) / 4;
+            if (!CandAfter()(h_[p], c)) break;
+            h_[i] = h_[p];
+            i = p;
+        }
+        h_[i] = c;
+    }
+    void pop() {
+        const Cand last = h_.back();
+        h_.pop_back();
+        const size_t n = h_.size();
+        if (n == 0) return;
+        size_t i = 0;
+        for (;;) {
+            const size_t c0 = 4 * i + 1;
+            if (c0 >= n) break;
+            size_t m = c0;
+            const size_t ce = std::min(n, c0 + 4);
+            for (size_t c = c0 + 1; c < ce; ++c) if (CandAfter()(h_[m], h_[c])) m = c;
+            if (!CandAfter()(last, h_[m])) break;
+            h_[i] = h_[m];
+            i = m;
+        }
+        h_[i] = last;
+    }
+  private:
+    std::vector<Cand> h_;
 };
 
 // One patch pair sharing a joint UV variable.
@@ -260,7 +297,7 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
                            [](const Cand &x, const Cand &y) { return x.lo == y.lo && x.hi == y.hi; }),
                init.end());
     size_t cursor = 0;
-    std::priority_queue<Cand, std::vector<Cand>, CandAfter> pq;
+    Heap4 pq;
     auto next_cand = [&](Cand &out) {
         const bool from_init = cursor < init.size() && (pq.empty() || CandAfter()(pq.top(), init[cursor]));
         if (from_init) {
