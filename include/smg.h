@@ -76,13 +76,15 @@ typedef struct {
  * V: n x 3 double, F: m x 3 int32, a consistently oriented manifold mesh with
  * or without boundary.  opts may be NULL (n_levels 0, min_coarse 500).
  * *out is owned by the caller and released with smg_hier_free.
- * Errors: INVALID_ARG (bad sizes/indices), PRECOMPUTE (non-manifold input). */
+ * Errors: INVALID_ARG (bad sizes or indices, a face repeating a vertex, a
+ * non-finite coordinate), PRECOMPUTE (non-manifold input). */
 smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F, int32_t m,
                          const smg_pre_opts *opts, smg_hier *out);
 
 /* Wrap externally computed prolongations: level l has sizes[l] vertices,
  * P_l is sizes[l] x 3 in ELL form (p_cols[l], p_w[l]); a slot with weight 0
- * or column < 0 is unused.  Weights must be >= 0.  Data are copied. */
+ * or column < 0 is unused.  Weights must be finite and >= 0, and every row
+ * needs one positive weight (else INVALID_ARG).  Data are copied. */
 smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_t *sizes,
                                        const int32_t *const *p_cols,
                                        const double *const *p_w, smg_hier *out);

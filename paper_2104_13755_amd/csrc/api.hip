@@ -104,6 +104,11 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
     if (!V || !F || !out || n < 3 || m < 1) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: bad arguments");
     for (int64_t i = 0; i < 3 * (int64_t)m; ++i)
         if (F[i] < 0 || F[i] >= n) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: face index out of range");
+    for (int64_t f = 0; f < m; ++f)
+        if (F[3 * f] == F[3 * f + 1] || F[3 * f + 1] == F[3 * f + 2] || F[3 * f] == F[3 * f + 2])
+            return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: face " + std::to_string(f) + " repeats a vertex");
+    for (int64_t i = 0; i < 3 * (int64_t)n; ++i)
+        if (!std::isfinite(V[i])) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: non-finite vertex coordinate");
     const int min_coarse = (opts && opts->min_coarse > 0) ? opts->min_coarse : 500;
     const bool interior_only = opts && opts->interior_only;
     int nlev = opts ? opts->n_levels : 0;
@@ -142,6 +147,7 @@ extern "C" smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_
                                                   const double *const *p_w, smg_hier *out) {
     if (n_levels < 1 || !sizes || !out || (n_levels > 1 && (!p_cols || !p_w)))
         return fail(SMG_ERR_INVALID_ARG, "smg_hier_from_prolongations: bad arguments");
+    if (sizes[0] < 1) return fail(SMG_ERR_INVALID_ARG, "empty level");
     auto h = std::make_unique<smg_hier_s>();
     h->H.nlev = n_levels;
     h->H.sizes.assign(sizes, sizes + n_levels);
@@ -155,11 +161,14 @@ extern "C" smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_
                 return fail(SMG_ERR_INVALID_ARG, "prolongation entry out of range");
             if (pc[e] < 0 || pw[e] == 0.0) { pc[e] = -1; pw[e] = 0.0; }
         }
+        for (int i = 0; i < n; ++i)
+            if (pc[3 * (size_t)i] < 0 && pc[3 * (size_t)i + 1] < 0 && pc[3 * (size_t)i + 2] < 0)
+                return fail(SMG_ERR_INVALID_ARG, "prolongation row " + std::to_string(i) + " of level " +
+                                                     std::to_string(l) + " has no positive weight");
         h->H.pcols.push_back(std::move(pc));
         h->H.pw.push_back(std::move(pw));
         h->H.stats.push_back({0, 0, 0, 0, 0, 0, 0, 0});
     }
-    if (n_levels > 1 && sizes[0] < 1) return fail(SMG_ERR_INVALID_ARG, "empty level");
     *out = h.release();
     return SMG_OK;
 }

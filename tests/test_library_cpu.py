@@ -122,8 +122,36 @@ def test_precompute_rejects_bad_input():
     V, F = synth.flat_disc(8, seed=0)
     Fb = F.copy()
     Fb[0, 0] = len(V) + 5
-    with pytest.raises(SmgError):
+    with pytest.raises(SmgError, match="out of range"):
         Hierarchy.build(V, Fb, n_levels=2)
+    Fd = F.copy()
+    Fd[3, 2] = Fd[3, 0]
+    with pytest.raises(SmgError, match="repeats a vertex"):
+        Hierarchy.build(V, Fd, n_levels=2)
+    Vn = V.copy()
+    Vn[5, 1] = np.nan
+    with pytest.raises(SmgError, match="non-finite"):
+        Hierarchy.build(Vn, F, n_levels=2)
+
+
+def test_external_prolongations_are_validated():
+    from paper_2104_13755_amd.solver import Hierarchy
+    from paper_2104_13755_amd._lib import SmgError
+    cols = np.array([[0, 1, -1], [1, -1, -1], [0, 1, -1], [1, 0, -1]], dtype=np.int32)
+    w = np.array([[0.5, 0.5, 0], [1, 0, 0], [0.25, 0.75, 0], [0.6, 0.4, 0]])
+    h = Hierarchy.from_prolongations([4, 2], [cols], [w])
+    c, ww = h.prolongation(0)
+    assert np.array_equal(c, cols) and np.array_equal(ww, w)
+    for bad_c, bad_w, msg in [(cols, np.where(cols >= 0, -0.5, 0.0), "out of range"),
+                              (np.where(cols == 1, 2, cols).astype(np.int32), w, "out of range"),
+                              (cols, np.where(cols >= 0, np.inf, 0.0), "out of range"),
+                              (cols, np.vstack([w[:3], np.zeros(3)]), "no positive weight")]:
+        with pytest.raises(SmgError, match=msg):
+            Hierarchy.from_prolongations([4, 2], [bad_c], [bad_w])
+    with pytest.raises(SmgError, match="empty level"):
+        Hierarchy.from_prolongations([0], [], [])
+    with pytest.raises(SmgError, match="bad level"):
+        h.prolongation(1)
 
 
 def _host_dirichlet(h, A, known):
