@@ -58,20 +58,31 @@ Csr galerkin_pattern(const Csr &A, int nc, const std::vector<int32_t> &pcols) {
     std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
     for (int i = 0; i < n; ++i)
         for (int m = 0; m < 3; ++m) if (pcols[3 * i + m] >= 0) ridx[fill[pcols[3 * i + m]]++] = i;
+    // columns of T = A P per fine row (each fine row feeds up to three coarse rows)
+    std::vector<int32_t> tptr(n + 1, 0), tidx, mark(nc, -1);
+    tidx.reserve((size_t)A.ptr[n] * 2);
+    for (int i = 0; i < n; ++i) {
+        for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+            const int j = A.idx[p];
+            for (int m = 0; m < 3; ++m) {
+                const int b = pcols[3 * j + m];
+                if (b >= 0 && mark[b] != i) { mark[b] = i; tidx.push_back(b); }
+            }
+        }
+        tptr[i + 1] = (int32_t)tidx.size();
+    }
     Csr C;
     C.n = C.m = nc;
     C.ptr.assign(nc + 1, 0);
-    std::vector<int32_t> mark(nc, -1), row;
+    std::fill(mark.begin(), mark.end(), -1);
+    std::vector<int32_t> row;
     for (int a = 0; a < nc; ++a) {
         row.clear();
         for (int q = rptr[a]; q < rptr[a + 1]; ++q) {
             const int i = ridx[q];
-            for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
-                const int j = A.idx[p];
-                for (int m = 0; m < 3; ++m) {
-                    const int b = pcols[3 * j + m];
-                    if (b >= 0 && mark[b] != a) { mark[b] = a; row.push_back(b); }
-                }
+            for (int t = tptr[i]; t < tptr[i + 1]; ++t) {
+                const int b = tidx[t];
+                if (mark[b] != a) { mark[b] = a; row.push_back(b); }
             }
         }
         std::sort(row.begin(), row.end());
