@@ -134,6 +134,30 @@ def test_precompute_rejects_bad_input():
         Hierarchy.build(Vn, F, n_levels=2)
 
 
+def test_solver_create_rejects_bad_pattern_before_any_device_call():
+    """The level-0 pattern is checked on the host first (these calls never
+    reach the HIP runtime)."""
+    import ctypes
+    from paper_2104_13755_amd import _lib as L
+    from paper_2104_13755_amd.solver import Hierarchy, mesh_pattern
+    V, F = synth.flat_disc(10, seed=1)
+    h = Hierarchy.build(V, F, n_levels=2)
+    rp, ci = mesh_pattern(len(V), F)
+    lib = L.load()
+    cases = []
+    r = rp.copy(); r[0] = 1; cases.append((r, ci, "rowptr"))
+    r = rp.copy(); r[3] = r[2] - 1; cases.append((r, ci, "monotone"))
+    c = ci.copy(); c[5] = len(V); cases.append((rp, c, "out of range"))
+    c = ci.copy(); c[rp[4]], c[rp[4] + 1] = c[rp[4] + 1], c[rp[4]]; cases.append((rp, c, "ascending"))
+    for r, c, msg in cases:
+        r = np.ascontiguousarray(r, dtype=np.int32)
+        c = np.ascontiguousarray(c, dtype=np.int32)
+        out = ctypes.c_void_p()
+        st = lib.smg_solver_create(0, h._h, r.ctypes.data, c.ctypes.data, None, ctypes.byref(out))
+        assert st == -1 and not out.value, msg
+        assert msg in lib.smg_last_error().decode()
+
+
 def test_external_prolongations_are_validated():
     from paper_2104_13755_amd.solver import Hierarchy
     from paper_2104_13755_amd._lib import SmgError
