@@ -26,6 +26,15 @@
  *    barycentric coordinate (ties: lowest face id); negative coordinates are
  *    clamped to 0 and the row renormalized; at the end weights < 1e-12 are
  *    dropped and the row renormalized.
+ * What pins this file: on a flat disc with interior collapses every row must
+ * be the planar barycentric coordinates of the fine vertex in the coarse
+ * triangle that contains it, in the xy plane and after a rigid motion into a
+ * tilted plane; on any mesh, rows are nonnegative, sum to 1, have at most
+ * three entries, leave no coarse column empty, keep the Euler characteristic,
+ * and are bitwise unchanged by a power-of-two scale and unchanged to
+ * rounding by a rigid motion.  The rows on curved meshes have no closed form
+ * or printed values to compare with: parity unpinned there beyond these
+ * invariants.
  * Compile with -ffp-contract=off.
  */
 #include <math.h>
