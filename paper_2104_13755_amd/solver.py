@@ -68,6 +68,10 @@ class Hierarchy:
 
     @classmethod
     def build(cls, V, F, n_levels=0, min_coarse=500, interior_only=False):
+        """Precompute P_1..P_H from the mesh alone (Sec. 4, successive
+        self-parameterization; host).  V: n x 3 float64, F: m x 3 int32.
+        n_levels = 0 keeps decimating by 1/4 while the next level has at
+        least min_coarse vertices (Sec. 5 defaults)."""
         lib = L.load()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
@@ -78,6 +82,8 @@ class Hierarchy:
 
     @classmethod
     def from_prolongations(cls, sizes, pcols, pws):
+        """Wrap prolongations computed elsewhere: level l is sizes[l] x 3 ELL
+        (pcols[l] int32 with -1 for unused slots, pws[l] float64 >= 0)."""
         lib = L.load()
         sizes = np.ascontiguousarray(sizes, dtype=np.int32)
         pcols = [np.ascontiguousarray(p, dtype=np.int32) for p in pcols]
@@ -191,6 +197,10 @@ class Solver:
 
     def __init__(self, hier, rowptr, cols, device=0, mu_pre=2, mu_post=2, faces=None,
                  tail_rows=0, lanes_per_row=None):
+        """Upload a hierarchy for the level-0 CSR pattern (rowptr, cols: host
+        int32, diagonal present, columns ascending).  Builds colorings,
+        layouts and the symbolic Galerkin plans; `faces` enables assemble().
+        tail_rows / lanes_per_row are launch shapes (0 = defaults)."""
         self._lib = L.load()
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -247,6 +257,10 @@ class Solver:
 
     # ---- values ---------------------------------------------------------
     def assemble(self, V, t, mass_scale=None, edge_w=None, want_l=False, want_mass=False):
+        """A = M + t L on the device from vertex positions V (n x 3 float64):
+        cotangent Laplacian and lumped mass (optional per-vertex mass scales
+        and per-edge float32 weights).  Returns (a, l, m): values of A on the
+        solver's pattern, of L if want_l, the lumped mass if want_mass."""
         dev = V.device
         a = torch.empty(self.nnz, dtype=torch.float64, device=dev)
         lv = torch.empty(self.nnz, dtype=torch.float64, device=dev) if want_l else None
@@ -259,11 +273,18 @@ class Solver:
         return a, lv, m
 
     def set_values(self, a_vals):
+        """New values of A_0 on the pattern: every Galerkin level
+        A_{l+1} = P_l^T A_l P_l and the coarsest factor are recomputed on the
+        device (Alg. "Galerkin Surface Multigrid Solver")."""
         L.check(self._lib.smg_set_values(self._s, _t_ptr(_dev_f64(a_vals, (self.nnz,))), _stream()), "set_values")
 
     # ---- solve ----------------------------------------------------------
     def solve(self, b, rtol=1e-8, max_cycles=100, precision="fp64", fixed_cycles=0,
               use_graph=False, raise_on_error=True):
+        """V-cycles from x = 0 until every column's relative residual is at most
+        rtol (or exactly fixed_cycles).  b: n or n x k (k <= 4) float64 on the
+        device.  precision "fp32ir" runs FP32 cycles inside FP64 iterative
+        refinement.  Returns (x, info) with info cycles, rel_res, ms."""
         b2 = b if b.dim() == 2 else b.unsqueeze(1)
         b2 = _dev_f64(b2.contiguous())
         k = b2.shape[1]
@@ -313,30 +334,36 @@ class Solver:
         return (x if b.dim() == 2 else x[:, 0]), out
 
     def vcycle(self, b, x):
+        """One V-cycle (Alg. "V-cycle") updating x in place."""
         k = b.shape[1]
         L.check(self._lib.smg_vcycle(self._s, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), k, _stream()), "vcycle")
         return x
 
     # ---- single steps (level-natural numbering) ------------------------
     def residual(self, l, b, x):
+        """r = b - A_l x on level l."""
         r = torch.empty_like(b)
         L.check(self._lib.smg_residual(self._s, l, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), _t_ptr(r), b.shape[1], _stream()), "residual")
         return r
 
     def smooth(self, l, b, x, sweeps):
+        """`sweeps` relaxation sweeps of the current smoother on level l, in place."""
         L.check(self._lib.smg_smooth(self._s, l, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), b.shape[1], sweeps, _stream()), "smooth")
         return x
 
     def restrict(self, l, r):
+        """P_l^T r: level l to level l + 1."""
         rc = torch.empty((self.level_size(l + 1), r.shape[1]), dtype=torch.float64, device=r.device)
         L.check(self._lib.smg_restrict(self._s, l, _t_ptr(_dev_f64(r)), _t_ptr(rc), r.shape[1], _stream()), "restrict")
         return rc
 
     def prolong_add(self, l, e, x):
+        """x += P_l e: level l + 1 to level l, in place."""
         L.check(self._lib.smg_prolong_add(self._s, l, _t_ptr(_dev_f64(e)), _t_ptr(_dev_f64(x)), x.shape[1], _stream()), "prolong_add")
         return x
 
     def coarse_solve(self, b):
+        """x = A_H^{-1} b on the coarsest level (dense Cholesky factor)."""
         x = torch.empty_like(b)
         L.check(self._lib.smg_coarse_solve(self._s, _t_ptr(_dev_f64(b)), _t_ptr(x), b.shape[1], _stream()), "coarse_solve")
         return x
