@@ -161,6 +161,7 @@ static inline double orient2(const double *a, const double *b, const double *c) 
 struct FlatWork {
     std::vector<int> slot;
     std::vector<double> N, g;
+    std::vector<std::array<double, 12>> rows;   // conformal rows (re, im) per triangle, in accumulation order
 };
 
 // Minimise the summed conformal energy of both patches with some coordinates
@@ -176,8 +177,10 @@ static bool flatten(const Surface &S, Joint &J, const std::vector<int> &fixed,
     std::vector<double> &N = w.N, &g = w.g;
     N.assign((size_t)nfree * nfree, 0.0);
     g.assign(nfree, 0.0);
+    w.rows.clear();
     auto accumulate = [&](const std::array<int, 3> &v, const std::array<int, 3> &d) -> bool {
-        double re[6], im[6];
+        w.rows.emplace_back();
+        double *re = w.rows.back().data(), *im = re + 6;
         if (!conformal_rows(&S.X[3 * v[0]], &S.X[3 * v[1]], &S.X[3 * v[2]], re, im)) return false;
         int col[6];
         for (int c = 0; c < 3; ++c) { col[2 * c] = 2 * d[c]; col[2 * c + 1] = 2 * d[c] + 1; }
@@ -227,9 +230,10 @@ static bool flatten(const Surface &S, Joint &J, const std::vector<int> &fixed,
     for (int c = 0; c < ncol; ++c) J.uv[c / 2][c % 2] = fixed[c] ? fixval[c] : g[slot[c]];
     // energy of the solution, and the orientation test of every UV triangle
     double e = 0.0;
-    auto add_energy = [&](const std::array<int, 3> &v, const std::array<int, 3> &d) {
-        double re[6], im[6];
-        conformal_rows(&S.X[3 * v[0]], &S.X[3 * v[1]], &S.X[3 * v[2]], re, im);
+    size_t tri = 0;
+    auto add_energy = [&](const std::array<int, 3> &d) {
+        const double *re = w.rows[tri].data(), *im = re + 6;
+        ++tri;
         double sr = 0.0, si = 0.0;
         for (int c = 0; c < 3; ++c) {
             sr += re[2 * c] * J.uv[d[c]][0] + re[2 * c + 1] * J.uv[d[c]][1];
@@ -237,8 +241,8 @@ static bool flatten(const Surface &S, Joint &J, const std::vector<int> &fixed,
         }
         e += sr * sr + si * si;
     };
-    for (size_t t = 0; t < J.before_v.size(); ++t) add_energy(J.before_v[t], J.before_d[t]);
-    for (size_t t = 0; t < J.after_v.size(); ++t) add_energy(J.after_v[t], J.after_d[t]);
+    for (size_t t = 0; t < J.before_v.size(); ++t) add_energy(J.before_d[t]);
+    for (size_t t = 0; t < J.after_v.size(); ++t) add_energy(J.after_d[t]);
     J.energy = e;
     const double min_area = 1e-12 * J.scale * J.scale;
     for (const auto *dl : {&J.before_d, &J.after_d})
