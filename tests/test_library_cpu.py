@@ -44,7 +44,7 @@ def _p_matrix(cols, w, shape):
     return sp.csr_matrix((w[m], (np.repeat(np.arange(n), 3).reshape(n, 3)[m], cols[m])), shape=shape)
 
 
-@pytest.mark.parametrize("mesh", ["icosphere", "torus", "disc", "heightfield"])
+@pytest.mark.parametrize("mesh", ["icosphere", "torus", "disc", "heightfield", "torus-100k"])
 def test_precompute_matches_oracle(mesh):
     from paper_2104_13755_amd.solver import Hierarchy
     rng = np.random.default_rng(8)
@@ -52,6 +52,8 @@ def test_precompute_matches_oracle(mesh):
         V, F = synth.small_icosphere(4, seed=12, sigma=0.01)
     elif mesh == "torus":
         V, F = synth.torus_grid(80, 30, 1.0, 0.3, rng, jitter=0.2)
+    elif mesh == "torus-100k":
+        V, F = synth.torus_grid(400, 250, 1.0, 0.3, rng, jitter=0.2)
     elif mesh == "disc":
         V, F = synth.flat_disc(45, 39, seed=6, jitter=0.1)
     else:
