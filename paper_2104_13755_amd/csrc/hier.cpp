@@ -20,9 +20,13 @@ int greedy_coloring(int n, const int32_t *rowptr, const int32_t *cols, std::vect
         for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) d += cols[p] != i;
         degree[i] = d;
     }
-    std::vector<int32_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return degree[a] > degree[b]; });
+    // descending degree, ties ascending index: a counting sort by degree
+    int maxd = 0;
+    for (int i = 0; i < n; ++i) maxd = std::max(maxd, degree[i]);
+    std::vector<int32_t> start(maxd + 2, 0), order(n);
+    for (int i = 0; i < n; ++i) start[maxd - degree[i] + 1]++;
+    for (int d = 0; d <= maxd; ++d) start[d + 1] += start[d];
+    for (int i = 0; i < n; ++i) order[start[maxd - degree[i]]++] = i;
     color.assign(n, -1);
     std::vector<int32_t> palette;
     std::vector<int32_t> taken;   // taken[c] == node + 1 marks color c as used around node
