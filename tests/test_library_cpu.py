@@ -110,6 +110,26 @@ def test_coloring_matches_oracle():
         assert nc_o == nc_p and np.array_equal(col_o, col_p)
 
 
+def test_coloring_matches_hand_worked_cases():
+    """The library's greedy coloring against the colorings worked out by hand
+    from App. A's algorithm (the same fixtures that pin the oracle)."""
+    import json
+    from conftest import GOLDEN
+    from paper_2104_13755_amd.solver import color_pattern
+    with open(os.path.join(GOLDEN, "coloring_greedy.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        n = case["n"]
+        e = np.array(case["edges"]).reshape(-1, 2)
+        r = np.concatenate([np.arange(n), e[:, 0], e[:, 1]])
+        c = np.concatenate([np.arange(n), e[:, 1], e[:, 0]])
+        S = sp.csr_matrix((np.ones(len(r)), (r, c)), shape=(n, n))
+        S.sort_indices()
+        col, nc = color_pattern(S.indptr, S.indices)
+        assert np.asarray(col).tolist() == case["colors"], case["name"]
+        assert nc == max(case["colors"]) + 1
+
+
 def test_mesh_pattern_matches_oracle():
     from paper_2104_13755_amd.solver import mesh_pattern
     V, F = synth.flat_disc(17, 23, seed=1)
