@@ -130,6 +130,30 @@ def test_coloring_matches_hand_worked_cases():
         assert nc == max(case["colors"]) + 1
 
 
+def test_pattern_helpers_reject_bad_input():
+    import ctypes
+    from paper_2104_13755_amd import _lib as L
+    from paper_2104_13755_amd._lib import SmgError
+    from paper_2104_13755_amd.solver import color_pattern, mesh_pattern
+    V, F = synth.flat_disc(6, seed=1)
+    Fb = F.copy()
+    Fb[2, 1] = -1
+    with pytest.raises(SmgError, match="out of range"):
+        mesh_pattern(len(V), Fb)
+    rp, ci = mesh_pattern(len(V), F)
+    lib = L.load()
+    small = np.zeros(len(ci) - 1, dtype=np.int32)
+    nnz = ctypes.c_int32(len(small))
+    r = np.zeros(len(V) + 1, dtype=np.int32)
+    F32 = np.ascontiguousarray(F, dtype=np.int32)
+    st = lib.smg_mesh_pattern(len(V), F32.ctypes.data, len(F), r.ctypes.data, small.ctypes.data, ctypes.byref(nnz))
+    assert st == -1 and "capacity" in lib.smg_last_error().decode()
+    cb = ci.copy()
+    cb[3] = len(V)
+    with pytest.raises(SmgError, match="out of range"):
+        color_pattern(rp, cb)
+
+
 def test_mesh_pattern_matches_oracle():
     from paper_2104_13755_amd.solver import mesh_pattern
     V, F = synth.flat_disc(17, 23, seed=1)
