@@ -68,8 +68,17 @@ typedef struct {
     int32_t n_levels;      /* total levels incl. the finest; 0 = rule below      */
     int32_t min_coarse;    /* rule: decimate while floor(n/4 + 1/2) >= min_coarse
                               (Sec. 5 defaults: ratio 0.25, coarsest >= 500)     */
-    int32_t interior_only; /* 1: only collapse edges with both ends interior     */
+    int32_t collapses;     /* which edges may collapse: SMG_COLLAPSE_ALL (the
+                              method); SMG_COLLAPSE_INTERIOR (both endpoints
+                              interior) and SMG_COLLAPSE_STRAIGHT (those plus
+                              boundary edges whose previous, own and next
+                              boundary vertices lie on one line; no collapse
+                              with exactly one boundary endpoint) restrict it
+                              to collapses whose flattening of a flat disc is
+                              the planar embedding (used by tests)             */
 } smg_pre_opts;
+
+enum { SMG_COLLAPSE_ALL = 0, SMG_COLLAPSE_INTERIOR = 1, SMG_COLLAPSE_STRAIGHT = 2 };
 
 /* Build P_1..P_H by mid-point edge collapse with joint LSCM flattening
  * (Sec. 4.1-4.4) and the barycentric query (App. C, Fig. baryQuery).

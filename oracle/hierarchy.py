@@ -31,7 +31,7 @@ def level_count(n0, min_coarse=500):
     return nl
 
 
-def prolongations(V, F, n_levels=0, min_coarse=500, interior_only=False):
+def prolongations(V, F, n_levels=0, min_coarse=500, collapses="all"):
     """Returns (P list of scipy CSR n_l x n_{l+1}, meshes list, stats list)."""
     if n_levels <= 0:
         n_levels = level_count(len(V), min_coarse)
@@ -39,7 +39,7 @@ def prolongations(V, F, n_levels=0, min_coarse=500, interior_only=False):
     Ps, stats = [], []
     for _ in range(n_levels - 1):
         Vl, Fl = meshes[-1]
-        Vc, Fc, Pc, Pw, st = native.ssp_level(Vl, Fl, next_target(len(Vl)), interior_only)
+        Vc, Fc, Pc, Pw, st = native.ssp_level(Vl, Fl, next_target(len(Vl)), collapses)
         n = len(Vl)
         mask = Pw > 0
         rows = np.repeat(np.arange(n), 3).reshape(n, 3)[mask]

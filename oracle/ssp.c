@@ -29,12 +29,19 @@
  * What pins this file: on a flat disc with interior collapses every row must
  * be the planar barycentric coordinates of the fine vertex in the coarse
  * triangle that contains it, in the xy plane and after a rigid motion into a
- * tilted plane; on any mesh, rows are nonnegative, sum to 1, have at most
- * three entries, leave no coarse column empty, keep the Euler characteristic,
- * and are bitwise unchanged by a power-of-two scale and unchanged to
- * rounding by a rigid motion.  The rows on curved meshes have no closed form
- * or printed values to compare with: parity unpinned there beyond these
- * invariants.
+ * tilted plane; the same holds when boundary-edge collapses on straight
+ * boundary runs are allowed too (there the third boundary case, the new
+ * vertex on the line through i and j, meets every constraint with zero
+ * energy, so it must win); every collapse of a curved disc (interior,
+ * one-boundary and all three boundary-edge cases) is re-solved from the 3D
+ * triangles by an independent least-squares formulation of the conformal
+ * energy, which must give the same per-case energies, the same winning case
+ * and the same UV positions; on any mesh, rows are nonnegative, sum to 1,
+ * have at most three entries, leave no coarse column empty, keep the Euler
+ * characteristic, and are bitwise unchanged by a power-of-two scale and
+ * unchanged to rounding by a rigid motion.  The rows on curved meshes have
+ * no closed form or printed values to compare with: parity unpinned there
+ * beyond these checks.
  * Compile with -ffp-contract=off.
  */
 #include <math.h>
@@ -286,6 +293,44 @@ static int joint_solve(const mesh *M, jpatch *jp, const int *fixed, const double
 }
 
 /* ---------- level driver ---------- */
+
+/* Which edges may collapse.  ALL is the method; the other two are test
+ * options that restrict it to collapses with a closed-form result on a flat
+ * disc: INTERIOR keeps edges with both endpoints interior; STRAIGHT keeps
+ * those plus boundary edges whose previous, own and next boundary vertices
+ * (p, i, j, q) lie on one straight line, and no one-boundary collapse. */
+enum { COLLAPSE_ALL = 0, COLLAPSE_INTERIOR = 1, COLLAPSE_STRAIGHT = 2 };
+
+/* Probe record of one committed collapse (test infrastructure): doubles
+ *   [0..9]   kind (0 interior, 1 one-boundary, 2 boundary edge), chosen case,
+ *            i, j, p, q, k, ring size nr, before-face count nfb, case count
+ *   ring     PR_RING: ring vertex ids (ascending)
+ *   faces    PR_FACE: 3 vertex ids per before face (ascending face id)
+ *   per case PR_CASE: flatten status (0 ok), energy, UV of each ring vertex,
+ *            UV of i and j in the before patch, UV of k in the after patch. */
+#define PR_HDR 10
+#define PR_RING PR_HDR
+#define PR_FACE (PR_RING + MAXD)
+#define PR_CASE0 (PR_FACE + 3 * MAXF)
+#define PR_CASE_SIZE (2 + 2 * MAXD + 6)
+#define PR_SIZE (PR_CASE0 + 3 * PR_CASE_SIZE)
+
+/* p, i, j, q on one line in this order: consecutive segments parallel (sine
+ * of their angle below 1e-9) and pointing the same way. */
+static int straight_run(const mesh *M, int p, int i, int j, int q) {
+    int pts[4] = {p, i, j, q};
+    for (int s = 0; s < 2; ++s) {
+        const double *A = &M->X[3 * pts[s]], *B = &M->X[3 * pts[s + 1]], *C = &M->X[3 * pts[s + 2]];
+        double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+        double w[3] = {C[0] - B[0], C[1] - B[1], C[2] - B[2]};
+        double cx = u[1] * w[2] - u[2] * w[1], cy = u[2] * w[0] - u[0] * w[2], cz = u[0] * w[1] - u[1] * w[0];
+        double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double nw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (!(sqrt(cx * cx + cy * cy + cz * cz) <= 1e-9 * nu * nw)) return 0;
+        if (!(u[0] * w[0] + u[1] * w[1] + u[2] * w[2] > 0.0)) return 0;
+    }
+    return 1;
+}
 typedef struct {
     long collapses, fails, case_int, case_one, case_b1, case_b2, case_b3;
     double max_clamp;
@@ -298,11 +343,16 @@ static double dist3(const mesh *M, int a, int b) { return sqrt(len2(M, a, b)); }
  * Outputs: *nc coarse vertices (Xc, 3*nc), *mc coarse faces (Fc), and for each
  * fine vertex v three coarse columns Pc[3v..] and weights Pw[3v..] (weight 0
  * marks an unused slot, column then -1).  stats (7 longs + 1 double) optional.
- * interior_only != 0 restricts collapses to edges with both endpoints interior.
+ * mode is one of the COLLAPSE_* sets above.
+ * probe (optional, test infrastructure): room for probe_cap records of
+ * PR_SIZE doubles; the first committed collapses are recorded there, their
+ * count in *probe_n, and every vertex position created (3 * (2n + 8)
+ * doubles, new vertex ids continue after n) in Xall.
  * Returns 0, or <0 on failure.
  */
-int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, int interior_only,
-                     int *nc, double *Xc, int *mc, int *Fc, int *Pc, double *Pw, double *stats_out) {
+int oracle_ssp_level_probe(int n, const double *X, int m, const int *F, int target, int mode,
+                           int *nc, double *Xc, int *mc, int *Fc, int *Pc, double *Pw, double *stats_out,
+                           double *probe, int probe_cap, int *probe_n, double *Xall) {
     mesh M;
     M.nv = n; M.capv = 2 * n + 8;
     M.X = (double *)malloc(sizeof(double) * 3 * (size_t)M.capv);
@@ -363,7 +413,8 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
         if (nfab == 0 || nfab > 2) { st.fails++; continue; }
         int bnd_a = is_boundary_vertex(&M, a), bnd_b = is_boundary_vertex(&M, b);
         int edge_bnd = (nfab == 1);
-        if (interior_only && (bnd_a || bnd_b)) { st.fails++; continue; }
+        if (mode == COLLAPSE_INTERIOR && (bnd_a || bnd_b)) { st.fails++; continue; }
+        if (mode == COLLAPSE_STRAIGHT && !edge_bnd && (bnd_a || bnd_b)) { st.fails++; continue; }
         if (!edge_bnd && bnd_a && bnd_b) { st.fails++; continue; }
         /* link condition */
         int ida[256], cna[256], idb[256], cnb[256];
@@ -402,6 +453,7 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
             p = other_boundary_neighbour(&M, i, j);
             q = other_boundary_neighbour(&M, j, i);
             if (p < 0 || q < 0 || p == q || p == j || q == i) { st.fails++; continue; }
+            if (mode == COLLAPSE_STRAIGHT && !straight_run(&M, p, i, j, q)) { st.fails++; continue; }
         } else if (bnd_a || bnd_b) {
             kind = 1;
             if (bnd_a) { j = a; i = b; } else { i = a; j = b; }
@@ -442,6 +494,15 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
 
         int ncase = (kind == 2) ? 3 : 1;
         int chosen = -1;
+        double *rec = (probe && *probe_n < probe_cap) ? &probe[(size_t)(*probe_n) * PR_SIZE] : NULL;
+        if (rec) {
+            for (int s = 0; s < PR_SIZE; ++s) rec[s] = NAN;
+            rec[0] = kind; rec[2] = i; rec[3] = j; rec[4] = p; rec[5] = q; rec[6] = k;
+            rec[7] = nr; rec[8] = nfb; rec[9] = ncase;
+            for (int s = 0; s < nr; ++s) rec[PR_RING + s] = ring[s];
+            for (int s = 0; s < nfb; ++s)
+                for (int c = 0; c < 3; ++c) rec[PR_FACE + 3 * s + c] = M.F[3 * fb[s] + c];
+        }
         for (int cs = 0; cs < ncase; ++cs) {
             /* DOFs: ring 0..nr-1, i = nr, j = nr+1, k = nr+2 unless aliased */
             int di = nr, dj = nr + 1, dk;
@@ -518,6 +579,16 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
                 jp->scale = span;
             }
             int rc = joint_solve(&M, jp, fixed, val);
+            if (rec) {
+                double *cr = &rec[PR_CASE0 + cs * PR_CASE_SIZE];
+                cr[0] = rc;
+                cr[1] = jp->energy;
+                for (int s = 0; s < nr; ++s) { cr[2 + 2 * s] = jp->U[s][0]; cr[3 + 2 * s] = jp->U[s][1]; }
+                double *tail = &cr[2 + 2 * MAXD];
+                tail[0] = jp->U[di][0]; tail[1] = jp->U[di][1];
+                tail[2] = jp->U[dj][0]; tail[3] = jp->U[dj][1];
+                tail[4] = jp->U[dk][0]; tail[5] = jp->U[dk][1];
+            }
             if (rc != 0) continue;
             if (chosen < 0 || jp->energy < jbest->energy) {
                 chosen = cs;
@@ -594,6 +665,7 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
         M.nv++;
         alive--;
         st.collapses++;
+        if (rec) { rec[1] = chosen; (*probe_n)++; }
         if (kind == 0) st.case_int++;
         else if (kind == 1) st.case_one++;
         else if (chosen == 0) st.case_b1++;
@@ -648,6 +720,7 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
         stats_out[4] = (double)st.case_b1; stats_out[5] = (double)st.case_b2;
         stats_out[6] = (double)st.case_b3; stats_out[7] = st.max_clamp;
     }
+    if (Xall) memcpy(Xall, M.X, sizeof(double) * 3 * (size_t)M.nv);
     free(newid); free(moved);
     free(jp); free(jbest);
     free(H.e);
@@ -655,4 +728,10 @@ int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, in
     for (int v = 0; v < M.capv; ++v) free(M.vf[v].a);
     free(M.vf); free(M.X); free(M.valive); free(M.F); free(M.falive);
     return 0;
+}
+
+int oracle_ssp_level(int n, const double *X, int m, const int *F, int target, int mode,
+                     int *nc, double *Xc, int *mc, int *Fc, int *Pc, double *Pw, double *stats_out) {
+    return oracle_ssp_level_probe(n, X, m, F, target, mode, nc, Xc, mc, Fc, Pc, Pw, stats_out,
+                                  NULL, 0, NULL, NULL);
 }

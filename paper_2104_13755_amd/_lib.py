@@ -18,7 +18,7 @@ P_f64 = ctypes.POINTER(c_double)
 
 
 class PreOpts(ctypes.Structure):
-    _fields_ = [("n_levels", c_int32), ("min_coarse", c_int32), ("interior_only", c_int32)]
+    _fields_ = [("n_levels", c_int32), ("min_coarse", c_int32), ("collapses", c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -47,6 +47,9 @@ SMG_FP64 = 0
 SMG_FP32_IR = 1
 SMG_SMOOTH_GS = 0
 SMG_SMOOTH_JACOBI = 1
+SMG_COLLAPSE_ALL = 0
+SMG_COLLAPSE_INTERIOR = 1
+SMG_COLLAPSE_STRAIGHT = 2
 
 # name -> (restype, argtypes)
 SIGNATURES = {

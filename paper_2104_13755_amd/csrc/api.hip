@@ -110,7 +110,9 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
     for (int64_t i = 0; i < 3 * (int64_t)n; ++i)
         if (!std::isfinite(V[i])) return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: non-finite vertex coordinate");
     const int min_coarse = (opts && opts->min_coarse > 0) ? opts->min_coarse : 500;
-    const bool interior_only = opts && opts->interior_only;
+    const int collapses = opts ? opts->collapses : SMG_COLLAPSE_ALL;
+    if (collapses < SMG_COLLAPSE_ALL || collapses > SMG_COLLAPSE_STRAIGHT)
+        return fail(SMG_ERR_INVALID_ARG, "smg_pre_build: unknown collapse set");
     int nlev = opts ? opts->n_levels : 0;
     auto target = [](int nn) { return (int)std::floor(nn / 4.0 + 0.5); };
     if (nlev <= 0) {
@@ -125,7 +127,7 @@ extern "C" smg_status smg_pre_build(const double *V, int32_t n, const int32_t *F
     std::vector<int32_t> Fv(F, F + 3 * (size_t)m);
     for (int l = 0; l + 1 < nlev; ++l) {
         LevelOut lo;
-        const int rc = ssp_decimate_level(X, Fv, target((int)(X.size() / 3)), interior_only, lo);
+        const int rc = ssp_decimate_level(X, Fv, target((int)(X.size() / 3)), collapses, lo);
         if (rc != 0) return fail(SMG_ERR_PRECOMPUTE, "successive self-parameterization failed at level " + std::to_string(l));
         h->H.pcols.push_back(std::move(lo.pcols));
         h->H.pw.push_back(std::move(lo.pw));

@@ -17,8 +17,10 @@ struct LevelOut {
     double stats[8];
 };
 
+// collapses: 0 every edge, 1 edges with both endpoints interior, 2 those plus
+// boundary edges on straight boundary runs (no one-boundary collapse).
 int ssp_decimate_level(const std::vector<double> &X, const std::vector<int32_t> &F, int target,
-                       bool interior_only, LevelOut &out);
+                       int collapses, LevelOut &out);
 
 // Greedy coloring of a CSR pattern's off-diagonal graph (Alg. "Graph Coloring").
 int greedy_coloring(int n, const int32_t *rowptr, const int32_t *cols, std::vector<int32_t> &color);

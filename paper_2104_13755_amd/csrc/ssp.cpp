@@ -55,6 +55,13 @@ struct Surface {
         const double dz = X[3 * a + 2] - X[3 * b + 2];
         return dx * dx + dy * dy + dz * dz;
     }
+    // a, b, c, d in this order on one straight line: the polyline is as long
+    // as the segment from a to d (to 1e-12 relative; a bend by an angle t
+    // lengthens it by about t^2 / 2 of the shorter side)
+    bool on_one_line(int a, int b, int c, int d) const {
+        const double chain = std::sqrt(sqdist(a, b)) + std::sqrt(sqdist(b, c)) + std::sqrt(sqdist(c, d));
+        return chain - std::sqrt(sqdist(a, d)) <= 1e-12 * chain;
+    }
     // neighbour -> number of incident triangles shared with v
     void link(int v, std::vector<std::pair<int, int>> &out) const {
         out.clear();
@@ -255,7 +262,7 @@ static bool flatten(const Surface &S, Joint &J, const std::vector<int> &fixed,
 }  // namespace
 
 int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t> &Fin, int target,
-                       bool interior_only, LevelOut &out) {
+                       int collapses, LevelOut &out) {
     const int n = (int)(Xin.size() / 3);
     const int m = (int)(Fin.size() / 3);
     Surface S;
@@ -355,7 +362,8 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
         };
         const bool ba = boundary_of(la), bb = boundary_of(lb);
         const bool boundary_edge = nshared == 1;
-        if (interior_only && (ba || bb)) { fail_edge(a, b); continue; }
+        if (collapses == 1 && (ba || bb)) { fail_edge(a, b); continue; }
+        if (collapses == 2 && !boundary_edge && (ba || bb)) { fail_edge(a, b); continue; }
         if (!boundary_edge && ba && bb) { fail_edge(a, b); continue; }
         // link condition: common neighbours == opposite corners of the shared triangles
         opp.clear();
@@ -394,6 +402,7 @@ int ssp_decimate_level(const std::vector<double> &Xin, const std::vector<int32_t
             p = boundary_neighbour_except(i == a ? la : lb, j);
             q = boundary_neighbour_except(j == a ? la : lb, i);
             if (p < 0 || q < 0 || p == q || p == j || q == i) { fail_edge(a, b); continue; }
+            if (collapses == 2 && !S.on_one_line(p, i, j, q)) { fail_edge(a, b); continue; }
         } else if (ba || bb) {
             kind = 1;
             if (ba) { j = a; i = b; } else { i = a; j = b; }

@@ -59,6 +59,10 @@ def color_pattern(rowptr, cols):
     return out[:n], nc
 
 
+_COLLAPSES = {"all": L.SMG_COLLAPSE_ALL, "interior": L.SMG_COLLAPSE_INTERIOR,
+              "straight": L.SMG_COLLAPSE_STRAIGHT}
+
+
 class Hierarchy:
     """Host-side prolongations P_1..P_H (owned by libsmg)."""
 
@@ -67,15 +71,18 @@ class Hierarchy:
         self._lib = L.load()
 
     @classmethod
-    def build(cls, V, F, n_levels=0, min_coarse=500, interior_only=False):
+    def build(cls, V, F, n_levels=0, min_coarse=500, collapses="all"):
         """Precompute P_1..P_H from the mesh alone (Sec. 4, successive
         self-parameterization; host).  V: n x 3 float64, F: m x 3 int32.
         n_levels = 0 keeps decimating by 1/4 while the next level has at
-        least min_coarse vertices (Sec. 5 defaults)."""
+        least min_coarse vertices (Sec. 5 defaults).  collapses: "all" (the
+        method), or the test restrictions "interior" (both endpoints
+        interior) and "straight" (those plus boundary edges on straight
+        boundary runs)."""
         lib = L.load()
         V = np.ascontiguousarray(V, dtype=np.float64)
         F = np.ascontiguousarray(F, dtype=np.int32)
-        o = L.PreOpts(int(n_levels), int(min_coarse), int(bool(interior_only)))
+        o = L.PreOpts(int(n_levels), int(min_coarse), _COLLAPSES[collapses])
         h = _c()
         L.check(lib.smg_pre_build(_np_ptr(V), len(V), _np_ptr(F), len(F), ctypes.byref(o), ctypes.byref(h)), "pre_build")
         return cls(h)

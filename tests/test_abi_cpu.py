@@ -16,13 +16,14 @@ from conftest import ROOT
 HEADER = os.path.join(ROOT, "include", "smg.h")
 
 STRUCTS = {
-    "smg_pre_opts": ("PreOpts", ["n_levels", "min_coarse", "interior_only"]),
+    "smg_pre_opts": ("PreOpts", ["n_levels", "min_coarse", "collapses"]),
     "smg_opts": ("Opts", ["mu_pre", "mu_post", "tail_rows", "lanes_per_row"]),
     "smg_solve_params": ("SolveParams", ["rtol", "max_cycles", "precision", "fixed_cycles", "use_graph"]),
     "smg_solve_info": ("SolveInfo", ["cycles", "k", "rel_res", "ms"]),
     "smg_batch_opts": ("BatchOpts", ["threads", "lanes_level0", "lanes_coarse", "team_max", "cache_file"]),
 }
 CONSTANTS = ["SMG_OK", "SMG_FP64", "SMG_FP32_IR", "SMG_SMOOTH_GS", "SMG_SMOOTH_JACOBI",
+             "SMG_COLLAPSE_ALL", "SMG_COLLAPSE_INTERIOR", "SMG_COLLAPSE_STRAIGHT",
              "SMG_ERR_INVALID_ARG", "SMG_ERR_OOM", "SMG_ERR_HIP", "SMG_ERR_NOT_SPD",
              "SMG_ERR_NO_CONVERGENCE", "SMG_ERR_NONFINITE", "SMG_ERR_STATE", "SMG_ERR_PRECOMPUTE"]
 
@@ -66,7 +67,8 @@ def test_struct_layouts_match(c_layout):
 
 def test_constants_match(c_layout):
     from paper_2104_13755_amd import _lib as L
-    for k in ("SMG_OK", "SMG_FP64", "SMG_FP32_IR", "SMG_SMOOTH_GS", "SMG_SMOOTH_JACOBI"):
+    for k in ("SMG_OK", "SMG_FP64", "SMG_FP32_IR", "SMG_SMOOTH_GS", "SMG_SMOOTH_JACOBI",
+              "SMG_COLLAPSE_ALL", "SMG_COLLAPSE_INTERIOR", "SMG_COLLAPSE_STRAIGHT"):
         assert getattr(L, k) == c_layout[("const", k)]
     for k in CONSTANTS:
         if k.startswith("SMG_ERR_"):

@@ -71,16 +71,29 @@ def test_precompute_matches_oracle(mesh):
             assert s[key] == st[l][key]
 
 
-def test_flat_interior_closed_form_product():
-    """Product SSP on the flat disc with interior-only collapses reproduces
-    linear functions exactly (the planar closed form)."""
+@pytest.mark.parametrize("collapses", ["interior", "straight"])
+def test_flat_closed_form_product(collapses):
+    """Product SSP on the flat disc with interior-only collapses, and with
+    boundary-edge collapses on the straight sides too, reproduces linear
+    functions exactly (the planar closed form), picks the third boundary case
+    for every boundary collapse, and equals the oracle's P under the same
+    restriction (structure, values to 1e-12)."""
     from paper_2104_13755_amd.solver import Hierarchy
     V, F = synth.flat_disc(32, seed=11, jitter=0.1)
-    h = Hierarchy.build(V, F, n_levels=2, interior_only=True)
+    h = Hierarchy.build(V, F, n_levels=2, collapses=collapses)
     c, w = h.prolongation(0)
-    Vc_ref = OH.native.ssp_level(V, F, OH.next_target(len(V)), interior_only=True)[0]
+    Vc_ref, _, Pc, Pw, st = OH.native.ssp_level(V, F, OH.next_target(len(V)), collapses)
     P = _p_matrix(c, w, (len(V), h.sizes[1]))
     assert abs(P @ Vc_ref[:, :2] - V[:, :2]).max() < 1e-13
+    s = h.stats(0)
+    assert s["b_case1"] == s["b_case2"] == s["one_boundary"] == 0
+    assert (s["b_case3"] > 20) == (collapses == "straight")
+    for key in ("collapses", "interior", "b_case3"):
+        assert s[key] == st[key]
+    mask = Pw > 0
+    rows = np.repeat(np.arange(len(V)), 3).reshape(-1, 3)[mask]
+    Po = sp.csr_matrix((Pw[mask], (rows, Pc[mask])), shape=P.shape)
+    assert ((P != 0) != (Po != 0)).nnz == 0 and abs(P - Po).max() < 1e-12
 
 
 def test_hierarchy_save_load_round_trip(tmp_path):
