@@ -29,8 +29,9 @@ HBM_PEAK_GBS = 8000.0
 
 
 def measured_traffic():
-    """Traffic per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+    """HBM traffic per launch of the dominant kernel (every launch level, and
+    per level) from the committed counter summary, or (None, {}) when the
+    kernel source changed since the counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "traffic_gs_color_f32_torus1M.md")
@@ -39,13 +40,13 @@ def measured_traffic():
         txt = open(path).read()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
-        return None, None
+        return None, {}
     m = re.search(r"kernels_hip_sha256: ([0-9a-f]+)", txt)
     if not m or m.group(1) != sha:
-        return None, None
+        return None, {}
     a = re.search(r"traffic_bytes_per_launch_every_level: (\d+)", txt)
-    z = re.search(r"traffic_bytes_per_launch_level0: (\d+)", txt)
-    return (float(a.group(1)) if a else None), (float(z.group(1)) if z else None)
+    per = {int(l): float(v) for l, v in re.findall(r"traffic_bytes_per_launch_level(\d+): (\d+)", txt)}
+    return (float(a.group(1)) if a else None), per
 
 
 def log(*a):
@@ -95,29 +96,58 @@ def time_solve_only(S, b, rtol, precision, steps, use_graph):
     return (time.perf_counter() - t0) / steps, info
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads():
+    """Threads this process may use: its CPU affinity, at most 16 (the share
+    of one GPU's host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(w, n_levels, rtol):
     """The oracle, untouched, on the same workload: its own hierarchy (untimed
     setup, as the paper excludes precompute), then one timed step = assembly +
-    Galerkin refresh + coarsest Cholesky + FP64 solve to rtol."""
+    Galerkin refresh + coarsest Cholesky + FP64 solve to rtol, once with the
+    host's threads available to its numerical libraries and once with one."""
     from threadpoolctl import threadpool_limits
     from oracle import assemble as AS, vcycle as OV, hierarchy as OH
+    nthr = host_threads()
     t0 = time.perf_counter()
     with threadpool_limits(limits=1):
         Ps, _, _ = OH.prolongations(w["V"], w["F"], n_levels=n_levels)
         A, L, m = AS.system(w["V"], w["F"], w["t"])
         S = OV.Solver(Ps, A)
         b = m[:, None] * w["u"]
-        log(f"oracle setup {time.perf_counter() - t0:.1f}s")
-        t1 = time.perf_counter()
-        A, L, m = AS.system(w["V"], w["F"], w["t"])
-        S.set_values(A)
-        x, cycles, hist = S.solve(b, rtol, max_cycles=500)
-        dt = time.perf_counter() - t1
-    log(f"oracle step {dt:.1f}s cycles={cycles}")
-    return dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
-                sample="one full step (assembly, Galerkin refresh, Cholesky, FP64 solve of the "
-                       "3-RHS system to 1e-8) on the full 1M-vertex workload; single thread",
-                step_s=dt, cycles=int(cycles))
+    log(f"oracle setup {time.perf_counter() - t0:.1f}s")
+    runs = {}
+    for threads in (nthr, 1):
+        with threadpool_limits(limits=threads):
+            t1 = time.perf_counter()
+            A, L, m = AS.system(w["V"], w["F"], w["t"])
+            S.set_values(A)
+            x, cycles, hist = S.solve(b, rtol, max_cycles=500)
+            runs[threads] = (time.perf_counter() - t1, int(cycles))
+        log(f"oracle step with {threads} thread(s): {runs[threads][0]:.1f}s cycles={cycles}")
+    dt, cycles = runs[nthr]
+    return dict(value=1.0 / dt, unit="solves/s", cores=nthr, kind="oracle",
+                sample="one full step (assembly, Galerkin refresh, Cholesky, FP64 solve of the 3-RHS system to "
+                       "1e-8) on the full 1M-vertex workload",
+                threads_note=f"{nthr} threads allowed to the oracle's BLAS/LAPACK calls (the dense coarsest "
+                             "factor and solves); its sparse products and Gauss-Seidel sweeps (scipy) run on one",
+                cpu_model=cpu_model(), host_threads=nthr, step_s=dt, cycles=cycles,
+                single_thread={"value": 1.0 / runs[1][0], "step_s": runs[1][0], "cycles": runs[1][1]})
 
 
 def build_solvers(meshes, threads=16):
@@ -558,9 +588,13 @@ def main():
     S.profile_enable(args.profile_kind, -1)
     t_prof, _, _ = run_steps(S, Vd, w["t"], b, rtol, "fp32ir", args.steps, use_graph)
     prof = S.profile_read()
-    S.profile_enable(args.profile_kind, 0)
-    run_steps(S, Vd, w["t"], b, rtol, "fp32ir", 1, use_graph)
-    prof0 = S.profile_read()
+    # per level: every level relaxed by per-color launches (above the tail)
+    launch_levels = list(range(S.tail_first(3, "fp32ir")))
+    prof_lv = {}
+    for l in launch_levels:
+        S.profile_enable(args.profile_kind, l)
+        run_steps(S, Vd, w["t"], b, rtol, "fp32ir", 2, use_graph)
+        prof_lv[l] = S.profile_read()
     S.profile_enable(None)
     t_fp64, infos_d, x_d = run_steps(S, Vd, w["t"], b, rtol, "fp64", args.steps, use_graph)
     log(f"fp64: {t_fp64 / args.steps * 1e3:.2f} ms/step cycles={infos_d[-1]['cycles']} res={max(infos_d[-1]['rel_res']):.2e}")
@@ -568,23 +602,26 @@ def main():
     so_d, _ = time_solve_only(S, b, rtol, "fp64", args.steps, use_graph)
     diff = float(torch.linalg.norm(x_m - x_d) / torch.linalg.norm(x_d))
 
-    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else None
-    traffic_all, traffic_l0 = measured_traffic() if args.profile_kind == "gs" else (None, None)
-    per_launch_bytes = prof["bytes"] / max(1, prof["launches"])
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic_all,
-                "kernel": "k_gs_color_w<3, float> / k_gs_color<3, float> (multicolor Gauss-Seidel, FP32 cycles, every level)"
+    def summary(p):
+        ach = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else None
+        return {"achieved": ach, "frac": ach / HBM_PEAK_GBS if ach else None, "launches": p["launches"],
+                "avg_launch_us": p["ms"] * 1e3 / max(1, p["launches"]),
+                "algorithmic_bytes_per_launch": p["bytes"] / max(1, p["launches"])}
+    traffic_all, traffic_lv = measured_traffic() if args.profile_kind == "gs" else (None, {})
+    top = summary(prof)
+    roofline = {"bound": "hbm", "achieved": top["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": top["frac"], "traffic": traffic_all,
+                "kernel": "k_gs_color_w<3, float> / k_gs_color<3, float> (multicolor Gauss-Seidel, FP32 cycles, "
+                          "every level relaxed by per-color launches)"
                           if args.profile_kind == "gs" else f"{args.profile_kind} (every level)",
-                "launches": prof["launches"], "avg_launch_us": prof["ms"] * 1e3 / max(1, prof["launches"]),
-                "algorithmic_bytes_per_launch": per_launch_bytes,
+                "launches": top["launches"], "avg_launch_us": top["avg_launch_us"],
+                "algorithmic_bytes_per_launch": top["algorithmic_bytes_per_launch"],
+                "bytes_rule": "per sweep z(s+4) + 4(n+1) + 3kns: z matrix entries incl. diagonal, n rows, "
+                              "s = 4 B values, k = 3 right-hand sides, x gathers counted once; "
+                              "a color launch counts its rows' share",
                 "measured": "dispatch-stamped HIP events on the launch stream, every launch of the kernel "
                             "in a second pass of the same timed steps",
-                "level0": {"achieved": prof0["bytes"] / (prof0["ms"] * 1e-3) / 1e9 if prof0["ms"] > 0 else None,
-                           "frac": prof0["bytes"] / (prof0["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS if prof0["ms"] > 0 else None,
-                           "launches": prof0["launches"],
-                           "avg_launch_us": prof0["ms"] * 1e3 / max(1, prof0["launches"]),
-                           "algorithmic_bytes_per_launch": prof0["bytes"] / max(1, prof0["launches"]),
-                           "traffic": traffic_l0}}
+                "levels": {str(l): dict(summary(p), traffic=traffic_lv.get(l)) for l, p in prof_lv.items()}}
     value = args.steps / t_mixed
     out = {
         "metric": "V-cycle solves/s + HBM GB/s at 1M verts to rel residual 1e-8, mixed vs FP64",

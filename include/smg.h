@@ -146,7 +146,9 @@ typedef struct {
  * Builds on the host: R_l = P_l^T, the symbolic Galerkin patterns and their
  * numeric plans, the coloring of every smoothed level (App. A) and the
  * color-major layout; then copies everything to device `device`.
- * opts may be NULL (2/2).  Errors: INVALID_ARG, OOM, HIP. */
+ * opts may be NULL (2/2).  The coarsest level is factored densely and may
+ * have at most 16384 rows (INVALID_ARG beyond).  Errors: INVALID_ARG, OOM,
+ * HIP. */
 smg_status smg_solver_create(int32_t device, smg_hier h, const int32_t *a0_rowptr,
                              const int32_t *a0_cols, const smg_opts *opts, smg_solver *out);
 void smg_solver_destroy(smg_solver s);
@@ -185,26 +187,63 @@ smg_status smg_get_level_matrix(smg_solver s, int32_t level, int32_t *rowptr, in
  * upper part zero. */
 smg_status smg_get_coarse_factor(smg_solver s, double *G);
 
-/* --- one step of the V-cycle on level l (FP64; for parity checks) --- */
+/* --- one step of the V-cycle on level l (for parity checks) ---
+ * precision SMG_FP64 runs the step on the FP64 level matrices.  SMG_FP32_IR
+ * runs the kernels of the FP32 inner cycles: the FP64 input vectors are
+ * rounded to FP32, the step reads the FP32 copies of the level matrices and
+ * of P_l, accumulates in FP32, and its FP32 result is returned widened to
+ * FP64 (exactly).  Vectors stay FP64 at the ABI. */
 /* r = b - A_l x  (Alg. "V-cycle", restriction line, inner term) */
-smg_status smg_residual(smg_solver s, int32_t level, const double *d_b, const double *d_x,
+smg_status smg_residual(smg_solver s, int32_t level, int32_t precision, const double *d_b, const double *d_x,
                         double *d_r, int32_t k, smg_stream stream);
-/* `sweeps` multicolor Gauss-Seidel sweeps in place on x (App. A) */
-smg_status smg_smooth(smg_solver s, int32_t level, const double *d_b, double *d_x, int32_t k,
+/* `sweeps` multicolor Gauss-Seidel sweeps in place on x (App. A); the
+ * per-color launches on every level (the one-workgroup tail of the cycle
+ * runs only inside smg_vcycle / smg_solve) */
+smg_status smg_smooth(smg_solver s, int32_t level, int32_t precision, const double *d_b, double *d_x, int32_t k,
                       int32_t sweeps, smg_stream stream);
 /* rc = P_l^T r  (restriction, R = P^T, Eq. gca) */
-smg_status smg_restrict(smg_solver s, int32_t level, const double *d_r, double *d_rc,
+smg_status smg_restrict(smg_solver s, int32_t level, int32_t precision, const double *d_r, double *d_rc,
                         int32_t k, smg_stream stream);
 /* x += P_l e  (prolong correction and update) */
-smg_status smg_prolong_add(smg_solver s, int32_t level, const double *d_e, double *d_x,
+smg_status smg_prolong_add(smg_solver s, int32_t level, int32_t precision, const double *d_e, double *d_x,
                            int32_t k, smg_stream stream);
 /* x = A_H^{-1} b, the coarsest direct solve: A_H^{-1} is formed once per
  * smg_set_values from the Cholesky factor G (A_H^{-1} = G^{-T} G^{-1}) and
- * applied as a dense FP64 product */
-smg_status smg_coarse_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+ * applied as a dense product with FP64 accumulation (SMG_FP32_IR: b rounded
+ * to FP32 on entry and x to FP32 on exit, as inside the FP32 cycles) */
+smg_status smg_coarse_solve(smg_solver s, int32_t precision, const double *d_b, double *d_x, int32_t k,
                             smg_stream stream);
-/* One V-cycle at level 0 in place on x (precision SMG_FP64 only). */
-smg_status smg_vcycle(smg_solver s, const double *d_b, double *d_x, int32_t k, smg_stream stream);
+/* One step of the one-workgroup tail: the device code that smg_solve and
+ * smg_vcycle run, in one workgroup per right-hand side with the iterates in
+ * LDS, for the levels with at most tail_rows rows (those from which every
+ * coarser level fits one workgroup's LDS for the precision and k; else
+ * INVALID_ARG).  It runs one step alone on one level with the same thread
+ * mapping and summation order as inside the tail, so chaining these calls
+ * in the order of Alg. "V-cycle" reproduces the tail's result exactly.
+ *   SMG_TAIL_RELAX     d_in = b, d_out = x (in/out): |sweeps| multicolor
+ *                      Gauss-Seidel sweeps, colors descending if sweeps < 0
+ *   SMG_TAIL_RESIDUAL  d_in = b, d_in2 = x, d_out = r = b - A_l x
+ *   SMG_TAIL_RESTRICT  d_in = r (level l), d_out = P_l^T r (level l + 1)
+ *   SMG_TAIL_PROLONG   d_in = e (level l + 1), d_out = x (in/out) += P_l e
+ *   SMG_TAIL_COARSE    level = coarsest: d_in = b, d_out = A_H^{-1} b
+ * Vectors are n_level x k FP64 at the ABI, rounded to FP32 on entry for
+ * SMG_FP32_IR as in smg_residual.  Errors: INVALID_ARG, STATE. */
+/* The finest level of the one-workgroup tail for this precision and k
+ * (num_levels - 1 when no smoothed level is in it); -1 on a bad argument. */
+int32_t smg_tail_first_level(smg_solver s, int32_t precision, int32_t k);
+enum { SMG_TAIL_RELAX = 0, SMG_TAIL_RESIDUAL = 1, SMG_TAIL_RESTRICT = 2, SMG_TAIL_PROLONG = 3,
+       SMG_TAIL_COARSE = 4 };
+smg_status smg_tail_step(smg_solver s, int32_t level, int32_t step, int32_t precision, const double *d_in,
+                         const double *d_in2, double *d_out, int32_t k, int32_t sweeps, smg_stream stream);
+/* One cycle at level 0 in place on x, in the launch shape smg_solve uses.
+ * SMG_FP64: one V-cycle (Alg. "V-cycle").  SMG_FP32_IR: one refinement step
+ * of the mixed solve: r = b - A x and sigma_q = max_i |r_iq| in FP64, one
+ * FP32 V-cycle from zero on fp32(r / sigma) (FP32 relaxation, residuals,
+ * transfers and tail, FP64 coarsest product), then x += sigma * d in FP64
+ * (a column with sigma = 0 is left unchanged).  A one-level hierarchy takes
+ * SMG_FP64 only (its cycle is the direct solve). */
+smg_status smg_vcycle(smg_solver s, int32_t precision, const double *d_b, double *d_x, int32_t k,
+                      smg_stream stream);
 
 /* --- the solve (Alg. "Galerkin Surface Multigrid Solver") --- */
 typedef struct {
@@ -327,10 +366,12 @@ enum { SMG_PROF_GS = 0, SMG_PROF_RESIDUAL = 1, SMG_PROF_RESTRICT = 2, SMG_PROF_P
  * profiling is on. */
 smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level);
 /* Totals since enable: summed launch durations (ms), launch count, and the
- * algorithmic bytes of those launches (matrix entries and vector traffic the
- * method must move: z (s + 4) + n s + 3 k n s for a relaxation color or a
- * residual, s = 8 or 4 bytes per value, z off-diagonal entries, n rows, k
- * right-hand sides; x gathers counted once).  Synchronizes the device. */
+ * algorithmic bytes of those launches (what a CSR sweep must move: z (s + 4)
+ * + 4 (n + 1) + 3 k n s for a relaxation sweep or a residual over n rows
+ * with z matrix entries, diagonal included, s = 8 or 4 bytes per value, k
+ * right-hand sides, neighbour values of x counted once; a color of a sweep
+ * counts its own rows' share, the first color the extra row pointer).
+ * Synchronizes the device. */
 smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches, double *bytes);
 
 /* ------------------------------------------------------------------------ */

@@ -50,6 +50,7 @@ SMG_SMOOTH_JACOBI = 1
 SMG_COLLAPSE_ALL = 0
 SMG_COLLAPSE_INTERIOR = 1
 SMG_COLLAPSE_STRAIGHT = 2
+SMG_TAIL_RELAX, SMG_TAIL_RESIDUAL, SMG_TAIL_RESTRICT, SMG_TAIL_PROLONG, SMG_TAIL_COARSE = range(5)
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -73,12 +74,15 @@ SIGNATURES = {
     "smg_level_colors": (c_int32, [c_void_p, c_int32, c_void_p]),
     "smg_get_level_matrix": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "smg_get_coarse_factor": (c_int32, [c_void_p, c_void_p]),
-    "smg_residual": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
-    "smg_smooth": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
-    "smg_restrict": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
-    "smg_prolong_add": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
-    "smg_coarse_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
-    "smg_vcycle": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "smg_residual": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "smg_smooth": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
+    "smg_restrict": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "smg_prolong_add": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "smg_coarse_solve": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
+    "smg_tail_first_level": (c_int32, [c_void_p, c_int32, c_int32]),
+    "smg_tail_step": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                c_void_p]),
+    "smg_vcycle": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p]),
     "smg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_set_smoother": (c_int32, [c_void_p, c_int32, ctypes.c_double]),
     "smg_split_prepare": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -25,6 +25,8 @@ static thread_local std::string g_last_error;
 // levels with at most this many rows (and all coarser ones) form the
 // one-workgroup LDS tail unless the caller chooses otherwise
 static constexpr int kTailRowsDefault = 4096;
+// largest coarsest level factored densely: 16384^2 doubles = 2 GiB per copy
+static constexpr int kCoarsestMax = 16384;
 // The LDS tail runs one workgroup per right-hand side (columns are
 // independent solves): each holds one value per row in LDS and the columns
 // proceed on different compute units at once.
@@ -352,6 +354,13 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
             if (A0.idx[p] < 0 || A0.idx[p] >= n0) return fail(SMG_ERR_INVALID_ARG, "column out of range");
             if (p > A0.ptr[i] && A0.idx[p] <= A0.idx[p - 1]) return fail(SMG_ERR_INVALID_ARG, "columns not strictly ascending");
         }
+    // the coarsest level is factored densely (n_H^2 doubles, four copies,
+    // 32-bit element indices in the factor kernels)
+    const int n_coarse = h->H.sizes[h->H.nlev - 1];
+    if (n_coarse > kCoarsestMax)
+        return fail(SMG_ERR_INVALID_ARG, "smg_solver_create: coarsest level has " + std::to_string(n_coarse) +
+                                             " rows; the dense factorization takes at most " +
+                                             std::to_string(kCoarsestMax));
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(SMG_ERR_INVALID_ARG, "bad device");
@@ -880,6 +889,16 @@ template <> float *xjbuf<float>(DevLevel &D) { return D.xj32; }
 // damped Jacobi sweeps: x -> xj -> x ...; an odd count copies the result back.
 // x_zero: the iterate is zero on entry (a coarse level's pre-relaxation), so
 // the first sweep needs no matrix.
+// Algorithmic bytes of a relaxation sweep or residual over rows holding z
+// matrix entries (diagonal included) and n rows: what a CSR sweep must move,
+// z (s + 4) for values and column indices, 4 (n + 1) for row pointers, and
+// 3 k n s for b, x read and x (or r) written, with s bytes per value and
+// neighbour values of x counted once.  A color of a sweep gets its own rows'
+// share and the first color the one extra row pointer.
+static double sweep_bytes(int64_t z, int64_t n, int k, double sb, bool first) {
+    return (double)z * (sb + 4) + 4.0 * (double)(n + (first ? 1 : 0)) + 3.0 * k * (double)n * sb;
+}
+
 template <typename T>
 smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool x_zero) {
     DevLevel &D = s->lev[l];
@@ -891,7 +910,7 @@ smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
             HIPCHK(launch_jacobi_first<T>(D.n, k, A.diag, bbuf<T>(D), y, s->d_omega + l, st));
             continue;
         }
-        const int pi = prof_begin(s, SMG_PROF_GS, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
+        const int pi = prof_begin(s, SMG_PROF_GS, l, sweep_bytes(D.offdiag_nnz + D.n, D.n, k, sb, true), st);
         HIPCHK(launch_jacobi<T>(A, D.nslices, bbuf<T>(D), sw % 2 ? y : x, sw % 2 ? x : y, s->d_omega + l, k, st,
                                 prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
     }
@@ -910,7 +929,8 @@ smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
         for (int cc = 0; cc < D.ncolors; ++cc) {
             const int c = descending ? D.ncolors - 1 - cc : cc;
             const int pi = prof_begin(s, SMG_PROF_GS, l,
-                                      D.color_nnz[c] * (sb + 4) + D.color_rows[c] * sb * (1 + 3 * k), st);
+                                      sweep_bytes(D.color_nnz[c] + D.color_rows[c], D.color_rows[c], k, sb, cc == 0),
+                                      st);
             const ColorSpan span{D.color_slice[c], D.color_slice[c + 1], D.color_row_h[c], D.color_row_h[c + 1],
                                  D.color_off[c], D.color_w[c]};
             HIPCHK(launch_gs_color<T>(A, span, bbuf<T>(D), xbuf<T>(D), k, st,
@@ -924,7 +944,7 @@ smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t
     DevLevel &D = s->lev[l];
     int nblk = 0;
     const double sb = sizeof(T);
-    const int pi = prof_begin(s, SMG_PROF_RESIDUAL, l, D.offdiag_nnz * (sb + 4) + D.n * sb * (1 + 3 * k), st);
+    const int pi = prof_begin(s, SMG_PROF_RESIDUAL, l, sweep_bytes(D.offdiag_nnz + D.n, D.n, k, sb, true), st);
     HIPCHK(launch_residual<T>(sell_view<T>(D), D.nslices, bbuf<T>(D), xbuf<T>(D), rbuf<T>(D), k,
                               norms ? s->partial : nullptr, &nblk, st, prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
     if (norms) HIPCHK(launch_reduce_partial(s->partial, nblk, k, s->norms, st, s->d_hnorms, s->norm_seq));
@@ -981,85 +1001,223 @@ static smg_status check_level(smg_solver s, int l, int k) {
     return SMG_OK;
 }
 
-extern "C" smg_status smg_residual(smg_solver s, int32_t l, const double *d_b, const double *d_x,
-                                   double *d_r, int32_t k, smg_stream stream) {
+static smg_status check_precision(int precision) {
+    if (precision != SMG_FP64 && precision != SMG_FP32_IR) return fail(SMG_ERR_INVALID_ARG, "bad precision");
+    return SMG_OK;
+}
+
+namespace smg {
+
+// The per-step entry points in one value type: caller vectors (FP64, natural
+// order) are gathered into the level's permuted buffers of type T (rounded to
+// FP32 for T = float), the step runs on them, and the result is scattered back.
+template <typename T>
+static smg_status step_residual(smg_solver_s *s, int l, const double *d_b, const double *d_x, double *d_r, int k,
+                                hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    HIPCHK(launch_gather_rows(D.perm, d_b, bbuf<T>(D), D.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, d_x, xbuf<T>(D), D.n, k, st));
+    CHK(residual_level<T>(s, l, k, false, st));
+    HIPCHK(launch_scatter_rows(D.perm, (const T *)rbuf<T>(D), d_r, D.n, k, st));
+    return SMG_OK;
+}
+template <typename T>
+static smg_status step_smooth(smg_solver_s *s, int l, const double *d_b, double *d_x, int k, int sweeps,
+                              hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    HIPCHK(launch_gather_rows(D.perm, d_b, bbuf<T>(D), D.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, (const double *)d_x, xbuf<T>(D), D.n, k, st));
+    CHK(smooth_level<T>(s, l, k, sweeps, st));
+    HIPCHK(launch_scatter_rows(D.perm, (const T *)xbuf<T>(D), d_x, D.n, k, st));
+    return SMG_OK;
+}
+template <typename T>
+static smg_status step_restrict(smg_solver_s *s, int l, const double *d_r, double *d_rc, int k, hipStream_t st) {
+    DevLevel &D = s->lev[l], &C = s->lev[l + 1];
+    HIPCHK(launch_gather_rows(D.perm, d_r, rbuf<T>(D), D.n, k, st));
+    HIPCHK(launch_restrict<T>(transfer_view(D, C), rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st));
+    HIPCHK(launch_scatter_rows(C.perm, (const T *)bbuf<T>(C), d_rc, C.n, k, st));
+    return SMG_OK;
+}
+template <typename T>
+static smg_status step_prolong_add(smg_solver_s *s, int l, const double *d_e, double *d_x, int k, hipStream_t st) {
+    DevLevel &D = s->lev[l], &C = s->lev[l + 1];
+    HIPCHK(launch_gather_rows(C.perm, d_e, xbuf<T>(C), C.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, (const double *)d_x, xbuf<T>(D), D.n, k, st));
+    HIPCHK(launch_prolong_add<T>(transfer_view(D, C), pwbuf<T>(D), xbuf<T>(C), xbuf<T>(D), k, st));
+    HIPCHK(launch_scatter_rows(D.perm, (const T *)xbuf<T>(D), d_x, D.n, k, st));
+    return SMG_OK;
+}
+
+}  // namespace smg
+
+extern "C" smg_status smg_residual(smg_solver s, int32_t l, int32_t precision, const double *d_b,
+                                   const double *d_x, double *d_r, int32_t k, smg_stream stream) {
     CHK(check_level(s, l, k));
+    CHK(check_precision(precision));
     if (!d_b || !d_x || !d_r) return fail(SMG_ERR_INVALID_ARG, "null vector");
     if (s->lev[l].coarsest) return fail(SMG_ERR_INVALID_ARG, "residual on the coarsest level is not part of the cycle");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
-    DevLevel &D = s->lev[l];
-    HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
-    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
-    CHK(residual_level<double>(s, l, k, false, st));
-    HIPCHK(launch_scatter_rows(D.perm, D.r, d_r, D.n, k, st));
-    return SMG_OK;
+    return precision == SMG_FP64 ? step_residual<double>(s, l, d_b, d_x, d_r, k, st)
+                                 : step_residual<float>(s, l, d_b, d_x, d_r, k, st);
 }
 
-extern "C" smg_status smg_smooth(smg_solver s, int32_t l, const double *d_b, double *d_x,
+extern "C" smg_status smg_smooth(smg_solver s, int32_t l, int32_t precision, const double *d_b, double *d_x,
                                  int32_t k, int32_t sweeps, smg_stream stream) {
     CHK(check_level(s, l, k));
+    CHK(check_precision(precision));
     if (!d_b || !d_x || sweeps < 0) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
     if (s->lev[l].coarsest) return fail(SMG_ERR_INVALID_ARG, "the coarsest level is not smoothed");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
-    DevLevel &D = s->lev[l];
-    HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
-    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
-    CHK(smooth_level<double>(s, l, k, sweeps, st));
-    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
-    return SMG_OK;
+    return precision == SMG_FP64 ? step_smooth<double>(s, l, d_b, d_x, k, sweeps, st)
+                                 : step_smooth<float>(s, l, d_b, d_x, k, sweeps, st);
 }
 
-extern "C" smg_status smg_restrict(smg_solver s, int32_t l, const double *d_r, double *d_rc,
+extern "C" smg_status smg_restrict(smg_solver s, int32_t l, int32_t precision, const double *d_r, double *d_rc,
                                    int32_t k, smg_stream stream) {
     CHK(check_level(s, l, k));
+    CHK(check_precision(precision));
     if (l + 1 >= s->nlev || !d_r || !d_rc) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
-    DevLevel &D = s->lev[l], &C = s->lev[l + 1];
-    HIPCHK(launch_gather_rows(D.perm, d_r, D.r, D.n, k, st));
-    HIPCHK(launch_restrict<double>(transfer_view(D, C), D.rs_w, D.r, C.b, k, st));
-    HIPCHK(launch_scatter_rows(C.perm, C.b, d_rc, C.n, k, st));
-    return SMG_OK;
+    return precision == SMG_FP64 ? step_restrict<double>(s, l, d_r, d_rc, k, st)
+                                 : step_restrict<float>(s, l, d_r, d_rc, k, st);
 }
 
-extern "C" smg_status smg_prolong_add(smg_solver s, int32_t l, const double *d_e, double *d_x,
+extern "C" smg_status smg_prolong_add(smg_solver s, int32_t l, int32_t precision, const double *d_e, double *d_x,
                                       int32_t k, smg_stream stream) {
     CHK(check_level(s, l, k));
+    CHK(check_precision(precision));
     if (l + 1 >= s->nlev || !d_e || !d_x) return fail(SMG_ERR_INVALID_ARG, "bad arguments");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
-    DevLevel &D = s->lev[l], &C = s->lev[l + 1];
-    HIPCHK(launch_gather_rows(C.perm, d_e, C.x, C.n, k, st));
-    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
-    HIPCHK(launch_prolong_add<double>(transfer_view(D, C), D.pw, C.x, D.x, k, st));
-    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
+    return precision == SMG_FP64 ? step_prolong_add<double>(s, l, d_e, d_x, k, st)
+                                 : step_prolong_add<float>(s, l, d_e, d_x, k, st);
+}
+
+static_assert(SMG_TAIL_RELAX == kTailStepRelax && SMG_TAIL_RESIDUAL == kTailStepResidual &&
+                  SMG_TAIL_RESTRICT == kTailStepRestrict && SMG_TAIL_PROLONG == kTailStepProlong &&
+                  SMG_TAIL_COARSE == kTailStepCoarse,
+              "tail step codes of the ABI and the kernels");
+
+namespace smg {
+
+// One step of the one-workgroup tail (see smg_tail_step) in value type T.
+template <typename T>
+static smg_status tail_step(smg_solver_s *s, int l, int step, const double *d_in, const double *d_in2,
+                            double *d_out, int k, int sweeps, bool desc, hipStream_t st) {
+    DevLevel &D = s->lev[l];
+    const int last = s->nlev - 1;
+    const int nc = l < last ? s->lev[l + 1].n : 0;
+    int np = 0, nw = 0;
+    if (l < last) { np = D.tl_npass; nw = s->lev[l + 1].tl_wave0 - D.tl_wave0; }
+    const size_t bytes = tail_step_lds_bytes(np, nw, D.n, step == kTailStepCoarse ? D.n : nc, sizeof(T));
+    switch (step) {
+    case kTailStepRelax:
+        HIPCHK(launch_gather_rows(D.perm, d_in, bbuf<T>(D), D.n, k, st));
+        HIPCHK(launch_gather_rows(D.perm, (const double *)d_out, xbuf<T>(D), D.n, k, st));
+        break;
+    case kTailStepResidual:
+        HIPCHK(launch_gather_rows(D.perm, d_in, bbuf<T>(D), D.n, k, st));
+        HIPCHK(launch_gather_rows(D.perm, d_in2, xbuf<T>(D), D.n, k, st));
+        break;
+    case kTailStepRestrict:
+        HIPCHK(launch_gather_rows(D.perm, d_in, rbuf<T>(D), D.n, k, st));
+        break;
+    case kTailStepProlong:
+        HIPCHK(launch_gather_rows(s->lev[l + 1].perm, d_in, xbuf<T>(s->lev[l + 1]), nc, k, st));
+        HIPCHK(launch_gather_rows(D.perm, (const double *)d_out, xbuf<T>(D), D.n, k, st));
+        break;
+    default:
+        HIPCHK(launch_gather_rows(D.perm, d_in, bbuf<T>(D), D.n, k, st));
+    }
+    HIPCHK(launch_tail_step<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, step, sweeps, desc,
+                               s->lev[last].dense_inv, k, bytes, st));
+    switch (step) {
+    case kTailStepResidual: HIPCHK(launch_scatter_rows(D.perm, (const T *)rbuf<T>(D), d_out, D.n, k, st)); break;
+    case kTailStepRestrict:
+        HIPCHK(launch_scatter_rows(s->lev[l + 1].perm, (const T *)bbuf<T>(s->lev[l + 1]), d_out, nc, k, st));
+        break;
+    default: HIPCHK(launch_scatter_rows(D.perm, (const T *)xbuf<T>(D), d_out, D.n, k, st));
+    }
     return SMG_OK;
 }
 
-extern "C" smg_status smg_coarse_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
+}  // namespace smg
+
+extern "C" int32_t smg_tail_first_level(smg_solver s, int32_t precision, int32_t k) {
+    if (!s || (precision != SMG_FP64 && precision != SMG_FP32_IR) || k < 1 || k > 4) return -1;
+    if (s->smoother != SMG_SMOOTH_GS) return s->nlev - 1;   // Jacobi cycles use no tail
+    return s->tail_first[precision == SMG_FP64 ? 0 : 1][k];
+}
+
+extern "C" smg_status smg_tail_step(smg_solver s, int32_t level, int32_t step, int32_t precision,
+                                    const double *d_in, const double *d_in2, double *d_out, int32_t k,
+                                    int32_t sweeps, smg_stream stream) {
+    CHK(check_level(s, level, k));
+    CHK(check_precision(precision));
+    if (step < SMG_TAIL_RELAX || step > SMG_TAIL_COARSE) return fail(SMG_ERR_INVALID_ARG, "unknown tail step");
+    const int last = s->nlev - 1;
+    const int pr = precision == SMG_FP64 ? 0 : 1;
+    if ((step == SMG_TAIL_COARSE) != (level == last))
+        return fail(SMG_ERR_INVALID_ARG, "the coarsest solve is the only step on the coarsest level");
+    if (level < last && level < s->tail_first[pr][k])
+        return fail(SMG_ERR_INVALID_ARG, "level is not in the one-workgroup tail for this precision and k");
+    if (!d_in || !d_out || (step == SMG_TAIL_RESIDUAL && !d_in2)) return fail(SMG_ERR_INVALID_ARG, "null vector");
+    if (step == SMG_TAIL_RELAX && sweeps == 0) return SMG_OK;
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    const bool desc = sweeps < 0;
+    const int sw = sweeps < 0 ? -sweeps : sweeps;
+    return pr == 0 ? tail_step<double>(s, level, step, d_in, d_in2, d_out, k, sw, desc, st)
+                   : tail_step<float>(s, level, step, d_in, d_in2, d_out, k, sw, desc, st);
+}
+
+extern "C" smg_status smg_coarse_solve(smg_solver s, int32_t precision, const double *d_b, double *d_x, int32_t k,
                                        smg_stream stream) {
     if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
     CHK(check_level(s, s->nlev - 1, k));
+    CHK(check_precision(precision));
     if (!d_b || !d_x) return fail(SMG_ERR_INVALID_ARG, "null vector");
     HIPCHK(hipSetDevice(s->device));
-    const DevLevel &D = s->lev[s->nlev - 1];
-    HIPCHK((launch_coarse_solve<double, double>(D.dense_inv, D.n, d_b, d_x, k, (hipStream_t)stream)));
+    hipStream_t st = (hipStream_t)stream;
+    DevLevel &D = s->lev[s->nlev - 1];
+    if (precision == SMG_FP64) {
+        HIPCHK((launch_coarse_solve<double, double>(D.dense_inv, D.n, d_b, d_x, k, st)));
+    } else {
+        HIPCHK(launch_gather_rows(D.perm, d_b, D.b32, D.n, k, st));
+        HIPCHK((launch_coarse_solve<float, float>(D.dense_inv, D.n, D.b32, D.x32, k, st)));
+        HIPCHK(launch_scatter_rows(D.perm, (const float *)D.x32, d_x, D.n, k, st));
+    }
     return SMG_OK;
 }
 
-extern "C" smg_status smg_vcycle(smg_solver s, const double *d_b, double *d_x, int32_t k,
+extern "C" smg_status smg_vcycle(smg_solver s, int32_t precision, const double *d_b, double *d_x, int32_t k,
                                  smg_stream stream) {
     CHK(check_level(s, 0, k));
+    CHK(check_precision(precision));
     if (!d_b || !d_x) return fail(SMG_ERR_INVALID_ARG, "null vector");
+    if (s->lev[0].coarsest && precision != SMG_FP64)
+        return fail(SMG_ERR_INVALID_ARG, "a one-level hierarchy has no refinement cycle (its cycle is the FP64 direct solve)");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
     DevLevel &D = s->lev[0];
     HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
-    HIPCHK(launch_gather_rows(D.perm, d_x, D.x, D.n, k, st));
-    CHK(vcycle_from<double>(s, 0, k, st));
-    HIPCHK(launch_scatter_rows(D.perm, D.x, d_x, D.n, k, st));
+    HIPCHK(launch_gather_rows(D.perm, (const double *)d_x, D.x, D.n, k, st));
+    if (precision == SMG_FP64) {
+        CHK(vcycle_from<double>(s, 0, k, st));
+    } else {
+        // one refinement step: r = b - A x and max |r| per column (FP64), then
+        // the FP32 cycle on r / max|r| from zero and x += max|r| * d (FP64)
+        CHK(residual_level<double>(s, 0, k, true, st));
+        HIPCHK(launch_fill<float>(D.x32, 0.0f, (int64_t)D.n * k, st));
+        HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
+        CHK(vcycle_from<float>(s, 0, k, st));
+        HIPCHK(launch_ir_up(D.x32, s->norms, D.x, D.n, k, st));
+    }
+    HIPCHK(launch_scatter_rows(D.perm, (const double *)D.x, d_x, D.n, k, st));
     return SMG_OK;
 }
 

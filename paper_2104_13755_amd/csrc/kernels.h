@@ -158,6 +158,22 @@ hipError_t launch_tail_lds(const LdsLevel<T> *lv, const int32_t *passes, const i
                            int first, int nlev, int mu_pre, int mu_post, const double *Ainv, int k,
                            size_t lds_bytes, hipStream_t st,
                            bool post_desc = false, bool per_column = false);
+// One step of the tail on level l alone (same device code and thread mapping
+// as launch_tail_lds with per_column, one workgroup per right-hand side):
+// relax `sweeps` sweeps of lv[l].x (desc: colors descending), the residual
+// into lv[l].r, the restriction into lv[l + 1].b, the prolongation
+// lv[l].x += P lv[l + 1].x, or on the coarsest level lv[l].x = Ainv lv[l].b.
+// lds_bytes from tail_step_lds_bytes().
+enum { kTailStepRelax = 0, kTailStepResidual = 1, kTailStepRestrict = 2, kTailStepProlong = 3,
+       kTailStepCoarse = 4 };
+template <typename T>
+hipError_t launch_tail_step(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves, int l, int nlev,
+                            int op, int sweeps, bool desc, const double *Ainv, int k, size_t lds_bytes,
+                            hipStream_t st);
+inline size_t tail_step_lds_bytes(int npass, int nwave, int n, int nc, size_t value_bytes) {
+    const size_t tables = ((size_t)npass * 16 + (size_t)nwave * 8 + 15) / 16 * 16;
+    return tables + ((size_t)n + (size_t)nc) * value_bytes;   // one column per workgroup
+}
 // grant k_tail_lds<*, T> `bytes` of dynamic LDS
 template <typename T>
 hipError_t tail_lds_allow(size_t bytes);
@@ -219,11 +235,12 @@ hipError_t launch_galerkin_c(int nc, int cmax, const int32_t *plan2ptr, const ui
 template <typename T>
 hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t st);
 hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
-// dst[r*k + q] = src[perm[r]*k + q]  (gather into permuted order) and inverse
-hipError_t launch_gather_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
-                              hipStream_t st);
-hipError_t launch_scatter_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
-                               hipStream_t st);
+// dst[r*k + q] = src[perm[r]*k + q]  (gather into permuted order) and inverse,
+// converting the value type on the way (double -> double / float, and back)
+template <typename Ts, typename Td>
+hipError_t launch_gather_rows(const int32_t *perm, const Ts *src, Td *dst, int n, int k, hipStream_t st);
+template <typename Ts, typename Td>
+hipError_t launch_scatter_rows(const int32_t *perm, const Ts *src, Td *dst, int n, int k, hipStream_t st);
 hipError_t launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st);
 // FP64 iterative-refinement glue
 hipError_t launch_ir_down(const double *r64, const double *norms, float *r32, int n, int k,

@@ -1388,6 +1388,70 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_lds(const LdsLevel<T> *__
     }
 }
 
+// One step of the tail on level l alone, with the device code of k_tail_lds
+// and its thread-to-row mapping (so its results equal that kernel's, pass
+// for pass): the level's iterate is loaded into LDS from lv[l].x (and the
+// next level's from lv[l + 1].x), the step runs, and what it changed is
+// stored back.  op: kTailStepRelax `sweeps` sweeps (desc: colors
+// descending), kTailStepResidual into lv[l].r, kTailStepRestrict into
+// lv[l + 1].b, kTailStepProlong x_l += P_l x_{l+1}, kTailStepCoarse
+// x_l = A_H^{-1} b_l on the coarsest level.
+template <int K, typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail_step(const LdsLevel<T> *__restrict__ lv,
+                                                            const int4 *__restrict__ passes,
+                                                            const int2 *__restrict__ waves, int l, int nlev,
+                                                            int op, int sweeps, int desc,
+                                                            const double *__restrict__ Ainv, int vs) {
+    constexpr int KP = K == 3 ? 4 : K;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, nt = blockDim.x, last = nlev - 1;
+    const int vc = blockIdx.x * K;
+    const LdsLevel<T> L = lv[l];
+    const int np = l < last ? L.npass : 0;
+    const int wbeg = L.wave0, nw = l < last ? lv[l + 1].wave0 - wbeg : 0;
+    int4 *sp = reinterpret_cast<int4 *>(smem);
+    int2 *swv = reinterpret_cast<int2 *>(smem + (size_t)np * sizeof(int4));
+    for (int i = tid; i < np; i += nt) {
+        int4 P = passes[L.pass0 + i];
+        P.w -= wbeg;
+        sp[i] = P;
+    }
+    for (int i = tid; i < nw; i += nt) swv[i] = waves[wbeg + i];
+    const size_t tables = ((size_t)np * 16 + (size_t)nw * 8 + 15) / 16 * 16;
+    T *xs = reinterpret_cast<T *>(smem + tables);
+    const int nc = l < last ? lv[l + 1].n : 0;
+    T *xc = xs + (size_t)L.n * KP;
+    const bool coarse_next = l + 1 == last;
+    // load the iterate of this level (the coarsest solve reads b instead)
+    const T *src = op == kTailStepCoarse ? L.b : L.x;
+    for (int t = tid; t < L.n * K; t += nt) xs[(size_t)(t / K) * KP + t % K] = gld(src, (size_t)(t / K) * vs + vc + t % K);
+    if (op == kTailStepProlong)
+        for (int t = tid; t < nc * K; t += nt)
+            xc[(size_t)(t / K) * KP + t % K] = gld((const T *)lv[l + 1].x, (size_t)(t / K) * vs + vc + t % K);
+    __syncthreads();
+    if (op == kTailStepRelax) {
+        tail_relax<K, KP, T>(L, sp, swv, xs, sweeps, desc != 0, vs, vc);
+    } else if (op == kTailStepResidual) {
+        tail_residual<K, KP, T>(L, sp, swv, xs, vs, vc);
+        return;
+    } else if (op == kTailStepRestrict) {
+        tail_restrict<K, KP, T>(L, lv[l + 1].b, coarse_next ? xc : nullptr, xc, vs, vc);
+        if (!coarse_next) return;
+        __syncthreads();
+        for (int t = tid; t < nc * K; t += nt) gst(lv[l + 1].b, (size_t)(t / K) * vs + vc + t % K, xc[(size_t)(t / K) * KP + t % K]);
+        return;
+    } else if (op == kTailStepProlong) {
+        tail_prolong<K, KP, T>(L, xs, xc);
+    } else {
+        tail_coarse<K, KP, T>(L.n, Ainv, xs, xc);
+        __syncthreads();
+        for (int t = tid; t < L.n * K; t += nt) gst(L.x, (size_t)(t / K) * vs + vc + t % K, xc[(size_t)(t / K) * KP + t % K]);
+        return;
+    }
+    __syncthreads();
+    for (int t = tid; t < L.n * K; t += nt) gst(L.x, (size_t)(t / K) * vs + vc + t % K, xs[(size_t)(t / K) * KP + t % K]);
+}
+
 __global__ void k_gather_records(const int32_t *__restrict__ src, const int32_t *__restrict__ cols,
                                  int64_t n, const double *__restrict__ vals,
                                  const float *__restrict__ vals32, TailRec<double> *__restrict__ rec64,
@@ -1607,21 +1671,23 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ s,
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) d[i] = (float)s[i];
 }
+template <typename Ts, typename Td>
 __global__ __launch_bounds__(kBlock) void k_gather_rows(const int32_t *__restrict__ perm,
-                                                        const double *__restrict__ src,
-                                                        double *__restrict__ dst, int n, int k) {
+                                                        const Ts *__restrict__ src,
+                                                        Td *__restrict__ dst, int n, int k) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (int64_t)n * k) return;
     const int r = (int)(t / k), q = (int)(t % k);
-    dst[t] = src[(size_t)perm[r] * k + q];
+    dst[t] = (Td)src[(size_t)perm[r] * k + q];
 }
+template <typename Ts, typename Td>
 __global__ __launch_bounds__(kBlock) void k_scatter_rows(const int32_t *__restrict__ perm,
-                                                         const double *__restrict__ src,
-                                                         double *__restrict__ dst, int n, int k) {
+                                                         const Ts *__restrict__ src,
+                                                         Td *__restrict__ dst, int n, int k) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (int64_t)n * k) return;
     const int r = (int)(t / k), q = (int)(t % k);
-    dst[(size_t)perm[r] * k + q] = src[t];
+    dst[(size_t)perm[r] * k + q] = (Td)src[t];
 }
 __global__ __launch_bounds__(kBlock) void k_check_finite(const double *__restrict__ v, int64_t n,
                                                          int *__restrict__ flag) {
@@ -1997,6 +2063,24 @@ hipError_t launch_cg_direction(int n, const double *rz_new, const double *rz_old
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_tail_step(const LdsLevel<T> *lv, const int32_t *passes, const int32_t *waves, int l, int nlev,
+                            int op, int sweeps, bool desc, const double *Ainv, int k, size_t lds_bytes,
+                            hipStream_t st) {
+    // one workgroup per right-hand side, as k_tail_lds runs them
+    const void *f = (const void *)k_tail_step<1, T>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    k_tail_step<1, T><<<k, kTailThreads, lds_bytes, st>>>(lv, reinterpret_cast<const int4 *>(passes),
+                                                         reinterpret_cast<const int2 *>(waves), l, nlev, op,
+                                                         sweeps, desc ? 1 : 0, Ainv, k);
+    return hipGetLastError();
+}
+template hipError_t launch_tail_step<double>(const LdsLevel<double> *, const int32_t *, const int32_t *, int, int,
+                                             int, int, bool, const double *, int, size_t, hipStream_t);
+template hipError_t launch_tail_step<float>(const LdsLevel<float> *, const int32_t *, const int32_t *, int, int,
+                                            int, int, bool, const double *, int, size_t, hipStream_t);
+
 // Dynamic LDS above the default limit must be granted per kernel once.
 template <typename T>
 hipError_t tail_lds_allow(size_t bytes) {
@@ -2098,19 +2182,27 @@ hipError_t launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
-                              hipStream_t st) {
+template <typename Ts, typename Td>
+hipError_t launch_gather_rows(const int32_t *perm, const Ts *src, Td *dst, int n, int k, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_gather_rows<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(perm, src, dst, n, k);
+    k_gather_rows<Ts, Td><<<nblocks((int64_t)n * k), kBlock, 0, st>>>(perm, src, dst, n, k);
     return hipGetLastError();
 }
+template hipError_t launch_gather_rows<double, double>(const int32_t *, const double *, double *, int, int,
+                                                       hipStream_t);
+template hipError_t launch_gather_rows<double, float>(const int32_t *, const double *, float *, int, int,
+                                                      hipStream_t);
 
-hipError_t launch_scatter_rows(const int32_t *perm, const double *src, double *dst, int n, int k,
-                               hipStream_t st) {
+template <typename Ts, typename Td>
+hipError_t launch_scatter_rows(const int32_t *perm, const Ts *src, Td *dst, int n, int k, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_scatter_rows<<<nblocks((int64_t)n * k), kBlock, 0, st>>>(perm, src, dst, n, k);
+    k_scatter_rows<Ts, Td><<<nblocks((int64_t)n * k), kBlock, 0, st>>>(perm, src, dst, n, k);
     return hipGetLastError();
 }
+template hipError_t launch_scatter_rows<double, double>(const int32_t *, const double *, double *, int, int,
+                                                        hipStream_t);
+template hipError_t launch_scatter_rows<float, double>(const int32_t *, const float *, double *, int, int,
+                                                       hipStream_t);
 
 hipError_t launch_check_finite(const double *v, int64_t n, int *flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;

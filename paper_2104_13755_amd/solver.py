@@ -26,11 +26,21 @@ def _stream():
     return _c(torch.cuda.current_stream().cuda_stream)
 
 
-def _dev_f64(t, shape=None):
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float64 CUDA tensor")
+def _dev_f64(t, shape=None, device=None, dtype=torch.float64, name="tensor"):
+    """Check a tensor before its pointer crosses the ABI: a contiguous CUDA
+    tensor of `dtype` (on `device` if given) with exactly `shape`."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name}: on cuda:{t.device.index}, the solver is on cuda:{device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
     if shape is not None and tuple(t.shape) != tuple(shape):
-        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
     return t
 
 
@@ -230,6 +240,28 @@ class Solver:
             self._lib.smg_solver_destroy(self._s)
             self._s = None
 
+    # ---- argument checks (every pointer is checked before the C call) ---
+    def _level(self, l, smoothed=False, transfer=False):
+        nl = self.num_levels
+        if not (0 <= int(l) < nl):
+            raise ValueError(f"level {l} out of range 0..{nl - 1}")
+        if (smoothed or transfer) and int(l) == nl - 1:
+            raise ValueError(f"level {l} is the coarsest level")
+        return int(l)
+
+    def _vecs(self, n, *named):
+        """Each (name, tensor) must be an n x k float64 CUDA tensor on the
+        solver's device, contiguous, with one k (1..4) for all; returns k."""
+        k = None
+        for name, t in named:
+            if not isinstance(t, torch.Tensor) or t.dim() != 2:
+                raise ValueError(f"{name}: expected an n x k tensor")
+            k = t.shape[1] if k is None else k
+            _dev_f64(t, (n, k), self.device, name=name)
+        if not 1 <= k <= 4:
+            raise ValueError(f"k = {k} right-hand sides; 1..4 supported")
+        return k
+
     # ---- structure ------------------------------------------------------
     @property
     def num_levels(self):
@@ -268,13 +300,16 @@ class Solver:
         cotangent Laplacian and lumped mass (optional per-vertex mass scales
         and per-edge float32 weights).  Returns (a, l, m): values of A on the
         solver's pattern, of L if want_l, the lumped mass if want_mass."""
+        _dev_f64(V, (self.n, 3), self.device, name="V")
+        if mass_scale is not None:
+            _dev_f64(mass_scale, (self.n,), self.device, name="mass_scale")
+        if edge_w is not None:
+            _dev_f64(edge_w, ((self.nnz - self.n) // 2,), self.device, torch.float32, name="edge_w")
         dev = V.device
         a = torch.empty(self.nnz, dtype=torch.float64, device=dev)
         lv = torch.empty(self.nnz, dtype=torch.float64, device=dev) if want_l else None
         m = torch.empty(self.n, dtype=torch.float64, device=dev) if want_mass else None
-        if edge_w is not None and edge_w.dtype != torch.float32:
-            raise TypeError("edge weights must be float32")
-        L.check(self._lib.smg_assemble(self._s, _t_ptr(_dev_f64(V, (self.n, 3))), float(t),
+        L.check(self._lib.smg_assemble(self._s, _t_ptr(V), float(t),
                                        _t_ptr(mass_scale), _t_ptr(edge_w), _t_ptr(a), _t_ptr(lv),
                                        _t_ptr(m), _stream()), "assemble")
         return a, lv, m
@@ -283,7 +318,8 @@ class Solver:
         """New values of A_0 on the pattern: every Galerkin level
         A_{l+1} = P_l^T A_l P_l and the coarsest factor are recomputed on the
         device (Alg. "Galerkin Surface Multigrid Solver")."""
-        L.check(self._lib.smg_set_values(self._s, _t_ptr(_dev_f64(a_vals, (self.nnz,))), _stream()), "set_values")
+        L.check(self._lib.smg_set_values(self._s, _t_ptr(_dev_f64(a_vals, (self.nnz,), self.device, name="a_vals")),
+                                         _stream()), "set_values")
 
     # ---- solve ----------------------------------------------------------
     def solve(self, b, rtol=1e-8, max_cycles=100, precision="fp64", fixed_cycles=0,
@@ -293,8 +329,8 @@ class Solver:
         device.  precision "fp32ir" runs FP32 cycles inside FP64 iterative
         refinement.  Returns (x, info) with info cycles, rel_res, ms."""
         b2 = b if b.dim() == 2 else b.unsqueeze(1)
-        b2 = _dev_f64(b2.contiguous())
-        k = b2.shape[1]
+        b2 = b2.contiguous()
+        k = self._vecs(self.n, ("b", b2))
         x = torch.empty_like(b2)
         p = L.SolveParams(float(rtol), int(max_cycles), PRECISION[precision], int(fixed_cycles), int(bool(use_graph)))
         info = L.SolveInfo()
@@ -307,8 +343,9 @@ class Solver:
     def split_prepare(self, q_vals, m_vals):
         """Keep the Galerkin levels of two level-0 matrices (values on the
         solver's pattern) for split_combine (App. E linearity)."""
-        L.check(self._lib.smg_split_prepare(self._s, _t_ptr(_dev_f64(q_vals)), _t_ptr(_dev_f64(m_vals)), _stream()),
-                "split_prepare")
+        q = _dev_f64(q_vals, (self.nnz,), self.device, name="q_vals")
+        m = _dev_f64(m_vals, (self.nnz,), self.device, name="m_vals")
+        L.check(self._lib.smg_split_prepare(self._s, _t_ptr(q), _t_ptr(m), _stream()), "split_prepare")
 
     def split_combine(self, a, b):
         """Values a Q + b M on every level without assembly or Galerkin products."""
@@ -329,8 +366,8 @@ class Solver:
         """Conjugate gradients preconditioned by one symmetric V-cycle
         (smg_pcg_solve); returns (x, info) with info["iterations"]."""
         b2 = b if b.dim() == 2 else b.unsqueeze(1)
-        b2 = _dev_f64(b2.contiguous())
-        k = b2.shape[1]
+        b2 = b2.contiguous()
+        k = self._vecs(self.n, ("b", b2))
         x = torch.empty_like(b2)
         p = L.SolveParams(float(rtol), int(max_iters), PRECISION[precision], int(fixed_iters), 0)
         info = L.SolveInfo()
@@ -340,40 +377,100 @@ class Solver:
         out = dict(status=st, iterations=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
         return (x if b.dim() == 2 else x[:, 0]), out
 
-    def vcycle(self, b, x):
-        """One V-cycle (Alg. "V-cycle") updating x in place."""
-        k = b.shape[1]
-        L.check(self._lib.smg_vcycle(self._s, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), k, _stream()), "vcycle")
+    def vcycle(self, b, x, precision="fp64"):
+        """One cycle updating x in place: a V-cycle (Alg. "V-cycle"), or with
+        "fp32ir" one refinement step (FP64 residual, FP32 V-cycle on it
+        scaled by its column max, FP64 update)."""
+        k = self._vecs(self.n, ("b", b), ("x", x))
+        L.check(self._lib.smg_vcycle(self._s, PRECISION[precision], _t_ptr(b), _t_ptr(x), k, _stream()), "vcycle")
         return x
 
     # ---- single steps (level-natural numbering) ------------------------
-    def residual(self, l, b, x):
+    # precision "fp32ir" runs the FP32 kernels of the inner cycles on the
+    # inputs rounded to FP32 (results returned in float64).
+    def residual(self, l, b, x, precision="fp64"):
         """r = b - A_l x on level l."""
+        l = self._level(l, smoothed=True)
+        k = self._vecs(self.level_size(l), ("b", b), ("x", x))
         r = torch.empty_like(b)
-        L.check(self._lib.smg_residual(self._s, l, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), _t_ptr(r), b.shape[1], _stream()), "residual")
+        L.check(self._lib.smg_residual(self._s, l, PRECISION[precision], _t_ptr(b), _t_ptr(x), _t_ptr(r), k,
+                                       _stream()), "residual")
         return r
 
-    def smooth(self, l, b, x, sweeps):
+    def smooth(self, l, b, x, sweeps, precision="fp64"):
         """`sweeps` relaxation sweeps of the current smoother on level l, in place."""
-        L.check(self._lib.smg_smooth(self._s, l, _t_ptr(_dev_f64(b)), _t_ptr(_dev_f64(x)), b.shape[1], sweeps, _stream()), "smooth")
+        l = self._level(l, smoothed=True)
+        k = self._vecs(self.level_size(l), ("b", b), ("x", x))
+        L.check(self._lib.smg_smooth(self._s, l, PRECISION[precision], _t_ptr(b), _t_ptr(x), k, int(sweeps),
+                                     _stream()), "smooth")
         return x
 
-    def restrict(self, l, r):
+    def restrict(self, l, r, precision="fp64"):
         """P_l^T r: level l to level l + 1."""
-        rc = torch.empty((self.level_size(l + 1), r.shape[1]), dtype=torch.float64, device=r.device)
-        L.check(self._lib.smg_restrict(self._s, l, _t_ptr(_dev_f64(r)), _t_ptr(rc), r.shape[1], _stream()), "restrict")
+        l = self._level(l, transfer=True)
+        k = self._vecs(self.level_size(l), ("r", r))
+        rc = torch.empty((self.level_size(l + 1), k), dtype=torch.float64, device=r.device)
+        L.check(self._lib.smg_restrict(self._s, l, PRECISION[precision], _t_ptr(r), _t_ptr(rc), k, _stream()),
+                "restrict")
         return rc
 
-    def prolong_add(self, l, e, x):
+    def prolong_add(self, l, e, x, precision="fp64"):
         """x += P_l e: level l + 1 to level l, in place."""
-        L.check(self._lib.smg_prolong_add(self._s, l, _t_ptr(_dev_f64(e)), _t_ptr(_dev_f64(x)), x.shape[1], _stream()), "prolong_add")
+        l = self._level(l, transfer=True)
+        k = self._vecs(self.level_size(l), ("x", x))
+        if self._vecs(self.level_size(l + 1), ("e", e)) != k:
+            raise ValueError("e and x need the same number of columns")
+        L.check(self._lib.smg_prolong_add(self._s, l, PRECISION[precision], _t_ptr(e), _t_ptr(x), k, _stream()),
+                "prolong_add")
         return x
 
-    def coarse_solve(self, b):
+    def coarse_solve(self, b, precision="fp64"):
         """x = A_H^{-1} b on the coarsest level (dense Cholesky factor)."""
+        k = self._vecs(self.level_size(self.num_levels - 1), ("b", b))
         x = torch.empty_like(b)
-        L.check(self._lib.smg_coarse_solve(self._s, _t_ptr(_dev_f64(b)), _t_ptr(x), b.shape[1], _stream()), "coarse_solve")
+        L.check(self._lib.smg_coarse_solve(self._s, PRECISION[precision], _t_ptr(b), _t_ptr(x), k, _stream()),
+                "coarse_solve")
         return x
+
+    # ---- steps of the one-workgroup tail (smg_tail_step) ---------------
+    def tail_first(self, k, precision="fp64"):
+        """Finest level the one-workgroup tail covers (num_levels - 1: none)."""
+        return self._lib.smg_tail_first_level(self._s, PRECISION[precision], int(k))
+
+    def _tail(self, l, step, a, a2, out, k, sweeps, precision):
+        L.check(self._lib.smg_tail_step(self._s, l, step, PRECISION[precision], _t_ptr(a), _t_ptr(a2), _t_ptr(out),
+                                        k, int(sweeps), _stream()), "tail_step")
+        return out
+
+    def tail_relax(self, l, b, x, sweeps, precision="fp64"):
+        """|sweeps| Gauss-Seidel sweeps in the tail's code, in place on x
+        (colors descending if sweeps < 0)."""
+        l = self._level(l, smoothed=True)
+        k = self._vecs(self.level_size(l), ("b", b), ("x", x))
+        return self._tail(l, L.SMG_TAIL_RELAX, b, None, x, k, sweeps, precision)
+
+    def tail_residual(self, l, b, x, precision="fp64"):
+        l = self._level(l, smoothed=True)
+        k = self._vecs(self.level_size(l), ("b", b), ("x", x))
+        return self._tail(l, L.SMG_TAIL_RESIDUAL, b, x, torch.empty_like(b), k, 0, precision)
+
+    def tail_restrict(self, l, r, precision="fp64"):
+        l = self._level(l, transfer=True)
+        k = self._vecs(self.level_size(l), ("r", r))
+        out = torch.empty((self.level_size(l + 1), k), dtype=torch.float64, device=r.device)
+        return self._tail(l, L.SMG_TAIL_RESTRICT, r, None, out, k, 0, precision)
+
+    def tail_prolong(self, l, e, x, precision="fp64"):
+        l = self._level(l, transfer=True)
+        k = self._vecs(self.level_size(l), ("x", x))
+        if self._vecs(self.level_size(l + 1), ("e", e)) != k:
+            raise ValueError("e and x need the same number of columns")
+        return self._tail(l, L.SMG_TAIL_PROLONG, e, None, x, k, 0, precision)
+
+    def tail_coarse(self, b, precision="fp64"):
+        l = self.num_levels - 1
+        k = self._vecs(self.level_size(l), ("b", b))
+        return self._tail(l, L.SMG_TAIL_COARSE, b, None, torch.empty_like(b), k, 0, precision)
 
     # ---- per-launch timing --------------------------------------------
     PROF = {"gs": 0, "residual": 1, "restrict": 2, "prolong": 3, "coarse": 4, "galerkin": 5}
@@ -390,11 +487,22 @@ class Solver:
 
     # ---- adjoint helpers ----------------------------------------------
     def spmv_dot(self, l_vals, lam, u):
+        """lam^T L u over the level-0 pattern (one column)."""
+        _dev_f64(l_vals, (self.nnz,), self.device, name="l_vals")
+        lam = lam.reshape(self.n) if lam.numel() == self.n else lam
+        u = u.reshape(self.n) if u.numel() == self.n else u
+        _dev_f64(lam, (self.n,), self.device, name="lam")
+        _dev_f64(u, (self.n,), self.device, name="u")
         out = ctypes.c_double(0.0)
-        L.check(self._lib.smg_spmv_dot(self._s, _t_ptr(_dev_f64(l_vals)), _t_ptr(_dev_f64(lam)), _t_ptr(_dev_f64(u)), ctypes.byref(out), _stream()), "spmv_dot")
+        L.check(self._lib.smg_spmv_dot(self._s, _t_ptr(l_vals), _t_ptr(lam), _t_ptr(u), ctypes.byref(out), _stream()),
+                "spmv_dot")
         return out.value
 
     def mass_grad(self, lam, m, u):
+        """-lam_i m_i u_i per vertex."""
+        for name, t in (("lam", lam), ("m", m), ("u", u)):
+            _dev_f64(t, (self.n,), self.device, name=name)
         out = torch.empty_like(lam)
-        L.check(self._lib.smg_mass_grad(self._s, _t_ptr(_dev_f64(lam)), _t_ptr(_dev_f64(m)), _t_ptr(_dev_f64(u)), _t_ptr(out), _stream()), "mass_grad")
+        L.check(self._lib.smg_mass_grad(self._s, _t_ptr(lam), _t_ptr(m), _t_ptr(u), _t_ptr(out), _stream()),
+                "mass_grad")
         return out

@@ -94,10 +94,22 @@ def test_nonfinite_matrix():
 
 
 def test_bad_arguments(prob):
-    from paper_2104_13755_amd._lib import SmgError
+    """k = 5 and a residual on the coarsest level: the binding refuses them
+    before the library, and the library itself returns INVALID_ARG."""
+    import ctypes
+    import torch
+    from paper_2104_13755_amd import _lib as L
+    S = prob.gpu
     b = _t(np.ones((prob.sizes[0], 5)))
-    with pytest.raises(SmgError):
-        prob.gpu.solve(b, rtol=1e-8)
-    with pytest.raises(SmgError):
-        prob.gpu.residual(prob.gpu.num_levels - 1, _t(np.ones((prob.sizes[-1], 1))),
-                          _t(np.ones((prob.sizes[-1], 1))))
+    with pytest.raises(ValueError):
+        S.solve(b, rtol=1e-8)
+    x = torch.empty_like(b)
+    p = L.SolveParams(1e-8, 100, L.SMG_FP64, 0, 0)
+    st = S._lib.smg_solve(S._s, b.data_ptr(), x.data_ptr(), 5, ctypes.byref(p), None, None)
+    assert st == -1
+    last = S.num_levels - 1
+    bc = _t(np.ones((prob.sizes[-1], 1)))
+    with pytest.raises(ValueError):
+        S.residual(last, bc, bc)
+    rc = torch.empty_like(bc)
+    assert S._lib.smg_residual(S._s, last, L.SMG_FP64, bc.data_ptr(), bc.data_ptr(), rc.data_ptr(), 1, None) == -1

@@ -2,8 +2,9 @@
 vertex torus (3 RHS, 7 levels).  The oracle builds everything itself (its
 own assembly, successive self-parameterization, Galerkin levels, coloring)
 and every output is compared whole: A_0, P_l, A_l, colors, coarsest factor,
-three fixed FP64 V-cycles, and the converged FP64 / mixed solutions checked
-with the oracle's own residual."""
+three fixed FP64 V-cycles, the converged FP64 / mixed solutions against the
+oracle's converged solve (same cycle count, FP64 iterate within 1e-8,
+mixed within 1e-6 of x* solved to 1e-13) and the oracle's own residual."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -70,6 +71,23 @@ def test_torus_1m_bench_configuration():
     xg, _ = S.solve(bd, fixed_cycles=3, precision="fp64")
     xo, _, _ = O.solve(b, 0.0, fixed_cycles=3)
     assert np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-12
+    print("[full] oracle converged solve (and x* to 1e-13)", flush=True)
+    xo, co, _ = O.solve(b, 1e-8)
+    xstar, _, _ = O.solve(b, 1e-13, x0=xo)
+    print(f"[full] oracle: {co} cycles", flush=True)
+    for prec in ("fp64", "fp32ir"):
+        x, info = S.solve(bd, rtol=1e-8, precision=prec)
+        x = x.cpu().numpy()
+        res = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+        err = np.linalg.norm(x - xstar) / np.linalg.norm(xstar)
+        print(f"[full] {prec} on the oracle's A: cycles={info['cycles']} residual={res.max():.3e} "
+              f"error vs x*={err:.3e}", flush=True)
+        assert info["cycles"] == co
+        assert res.max() <= 1e-8 * 1.0001
+        if prec == "fp64":
+            # the same iterate as the oracle's (cycle for cycle)
+            assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-8
+        assert err <= 1e-6
     print("[full] converged solves (the library's own assembly, as bench.py)", flush=True)
     S.set_values(a)
     for prec in ("fp64", "fp32ir"):
@@ -78,7 +96,7 @@ def test_torus_1m_bench_configuration():
         res = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
         print(f"[full] {prec}: cycles={info['cycles']} oracle residual={res.max():.3e}", flush=True)
         assert res.max() <= 1e-8 * 1.0001
-        assert info["cycles"] == 44
+        assert info["cycles"] == co
     # V-cycle-preconditioned CG on the same system (FP64 vectors; the stop
     # test is on the recurrence residual, checked here with the oracle's A)
     for prec in ("fp64", "fp32ir"):

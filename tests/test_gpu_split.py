@@ -1,7 +1,8 @@
 """Split Galerkin (App. E): after smg_split_prepare(L, M), smg_split_combine
-(a, b) gives the same levels as setting the values a L + b M directly (every
-Galerkin level 1e-13 relative, coarsest factor 1e-12, identical cycle
-counts), for several coefficient pairs, and the errors of the entry points."""
+(a, b) gives the oracle's a P^T L P + b P^T M P on every level (1e-13
+relative), the same levels as setting the values a L + b M directly, the same
+coarsest factor (1e-12) and identical cycle counts, for several coefficient
+pairs, and the errors of the entry points."""
 import numpy as np
 import scipy.sparse as sp
 import pytest
@@ -42,6 +43,15 @@ def test_combine_equals_direct_values(prob):
         S.split_combine(1.0, 1.0)              # nothing prepared
     S.split_prepare(_t(prob.Lv), _t(prob.Mv))
     D = prob.gpu_solver()
+    # the oracle's App. E combination: a G_l(L) + c G_l(M), each Galerkin
+    # chain formed once on the oracle's side from the same prolongations
+    from oracle import hierarchy as OH
+    A = prob.A.tocsr()
+    GL = [sp.csr_matrix((prob.Lv, A.indices, A.indptr), shape=A.shape)]
+    GM = [sp.csr_matrix((prob.Mv, A.indices, A.indptr), shape=A.shape)]
+    for P in prob.Ps:
+        GL.append(OH.galerkin(GL[-1], P))
+        GM.append(OH.galerkin(GM[-1], P))
     rng = np.random.default_rng(61)
     b = prob.m[:, None] * rng.uniform(-1, 1, (prob.sizes[0], 2))
     for a, c in ((prob.t, 1.0), (3 * prob.t, 1.0), (0.1, 2.0)):
@@ -51,6 +61,8 @@ def test_combine_equals_direct_values(prob):
             As, Ad = S.level_matrix(l), D.level_matrix(l)
             assert np.array_equal(As.indices, Ad.indices)
             assert rel(As.data, Ad.data) < 1e-13, (a, c, l)
+            assert np.array_equal(As.indptr, GL[l].indptr) and np.array_equal(As.indices, GL[l].indices)
+            assert rel(As.data, a * GL[l].data + c * GM[l].data) < 1e-13, (a, c, l)
         assert rel(S.coarse_factor(), D.coarse_factor()) < 1e-12
         xs, i_s = S.solve(_t(b), rtol=1e-9, precision="fp32ir")
         xd, i_d = D.solve(_t(b), rtol=1e-9, precision="fp32ir")

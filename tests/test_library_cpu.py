@@ -217,6 +217,23 @@ def test_solver_create_rejects_bad_pattern_before_any_device_call():
         assert msg in lib.smg_last_error().decode()
 
 
+def test_solver_create_rejects_an_oversized_coarsest_level():
+    """A coarsest level above the dense factorization's limit (16384 rows)
+    is refused on the host, before any allocation or device call."""
+    import ctypes
+    from paper_2104_13755_amd import _lib as L
+    from paper_2104_13755_amd.solver import Hierarchy
+    n = 16385
+    h = Hierarchy.from_prolongations([n], [], [])
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    lib = L.load()
+    out = ctypes.c_void_p()
+    st = lib.smg_solver_create(0, h._h, rp.ctypes.data, ci.ctypes.data, None, ctypes.byref(out))
+    assert st == -1 and not out.value
+    assert "16384" in lib.smg_last_error().decode()
+
+
 def test_external_prolongations_are_validated():
     from paper_2104_13755_amd.solver import Hierarchy
     from paper_2104_13755_amd._lib import SmgError
