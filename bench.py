@@ -600,6 +600,15 @@ def main():
     log(f"fp64: {t_fp64 / args.steps * 1e3:.2f} ms/step cycles={infos_d[-1]['cycles']} res={max(infos_d[-1]['rel_res']):.2e}")
     so_m, _ = time_solve_only(S, b, rtol, "fp32ir", args.steps, use_graph)
     so_d, _ = time_solve_only(S, b, rtol, "fp64", args.steps, use_graph)
+    # one more step per precision with an event at every change of phase
+    # (the paper's Tab. "profile" buckets), outside the timed region
+    phases = {}
+    for prec in ("fp32ir", "fp64"):
+        a, _, _ = S.assemble(Vd, w["t"])
+        S.set_values(a)
+        _, inf = S.solve(b, rtol=rtol, precision=prec, timed=True)
+        phases[prec] = {k: round(v, 3) for k, v in inf["ms_phase"].items()}
+        log(f"phases {prec}: {phases[prec]}")
     diff = float(torch.linalg.norm(x_m - x_d) / torch.linalg.norm(x_d))
 
     def summary(p):
@@ -638,6 +647,11 @@ def main():
         "mixed": {"cycles": infos_m[-1]["cycles"], "rel_res": infos_m[-1]["rel_res"],
                   "solve_only_per_s": 1.0 / so_m, "rel_diff_vs_fp64": diff},
         "setup": setup,
+        "phases_ms": dict(phases, buckets="prepare = Galerkin levels + coarsest factor (the value refresh); "
+                                           "relax = Gauss-Seidel launches + one-workgroup tail; transfer = "
+                                           "residuals feeding restriction, restriction, prolongation; norm = "
+                                           "level-0 FP64 residual + column norms; other = refinement glue, "
+                                           "set-up of the solve"),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -19,9 +19,13 @@
  *  - Pointers named d_* are device pointers on the solver's device; h_* and
  *    unprefixed arrays are host pointers.  The caller owns every pointer it
  *    passes; the library never frees them and keeps none after returning,
- *    except where stated.  The library owns its internal device buffers
- *    (allocated with hipMalloc in smg_solver_create / smg_batch_create and
- *    released by the matching destroy call).
+ *    except where stated.  The library owns its internal device buffers: it
+ *    takes them in smg_solver_create / smg_batch_create from the allocator of
+ *    the solver's context (hipMalloc by default, or the caller's functions,
+ *    see smg_ctx_create) and returns them in the matching destroy call.  Of
+ *    the other entry points only smg_solver_attach_mesh (the mesh arrays)
+ *    and the first smg_split_prepare (two copies of the level values) take
+ *    more; solves, cycles, steps and value refreshes take none.
  *  - stream is a hipStream_t (NULL = default stream).  Work is enqueued on it;
  *    calls that return values to the host synchronize that stream.
  *  - Vectors of level l are in that level's natural vertex numbering (level 0:
@@ -55,6 +59,7 @@ enum {
 enum { SMG_FP64 = 0, SMG_FP32_IR = 1 };   /* precision of smg_solve / smg_vcycle */
 enum { SMG_SMOOTH_GS = 0, SMG_SMOOTH_JACOBI = 1 };   /* relaxation, smg_set_smoother */
 
+typedef struct smg_ctx_s *smg_ctx;         /* device + allocator of solvers */
 typedef struct smg_hier_s *smg_hier;       /* host-side hierarchy (prolongations) */
 typedef struct smg_solver_s *smg_solver;   /* device-resident solver of one mesh */
 typedef struct smg_batch_s *smg_batch;     /* many solvers in one launch schedule */
@@ -98,6 +103,16 @@ smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_t *sizes,
                                        const int32_t *const *p_cols,
                                        const double *const *p_w, smg_hier *out);
 
+/* Write / read a hierarchy (sizes, vertex positions when known, P_l, the
+ * decimation statistics) as a versioned binary file with a checksum, so the
+ * geometry-only precompute is done once per mesh (Sec. 5) and reused.  A
+ * loaded hierarchy is checked like smg_hier_from_prolongations and gives the
+ * same solver layout as the one saved.  *out is released with
+ * smg_hier_free.  Errors: INVALID_ARG (null, I/O error, wrong magic or
+ * version, truncated file, checksum mismatch, invalid prolongation). */
+smg_status smg_hier_save(smg_hier h, const char *path);
+smg_status smg_hier_load(const char *path, smg_hier *out);
+
 int32_t smg_hier_num_levels(smg_hier h);
 int32_t smg_hier_level_size(smg_hier h, int32_t level);
 /* Copy P_level (n_level x 3 ELL, unused slots: col -1, weight 0). */
@@ -119,6 +134,32 @@ int32_t smg_color_pattern(int32_t n, const int32_t *rowptr, const int32_t *cols,
 smg_status smg_mesh_pattern(int32_t n, const int32_t *F, int32_t m, int32_t *rowptr,
                             int32_t *cols, int32_t *nnz);
 
+/* Host assembly (Sec. 6 systems A = M + t L, assembled once): the cotangent
+ * Laplacian L (L_ij = -1/2 (cot alpha + cot beta) over the faces at edge ij,
+ * one term on a boundary edge; L_ii = -sum_j L_ij) in the CSR order of
+ * (rowptr, cols) = smg_mesh_pattern(F), and the lumped mass M_ii = (area of
+ * the faces at i) / 3.  L_vals: rowptr[n] doubles, M_diag: n doubles, both
+ * caller-sized host arrays.  Errors: INVALID_ARG (null, bad index, a
+ * degenerate face, a pattern missing a diagonal or a face edge). */
+smg_status smg_pre_assemble(const double *V, int32_t n, const int32_t *F, int32_t m, const int32_t *rowptr,
+                            const int32_t *cols, double *L_vals, double *M_diag);
+
+/* ------------------------------------------------------------------------ */
+/* Context: the device and the allocator of every internal device buffer.  */
+
+/* alloc returns `bytes` of device memory on the context's device (NULL on
+ * failure), aligned to at least 256 bytes; free returns a block with the
+ * size it was taken with.  They are called only inside smg_solver_create,
+ * smg_batch_create and the destroy calls, on the calling thread (e.g. torch's
+ * caching allocator from Python). */
+typedef void *(*smg_alloc_fn)(size_t bytes, void *user);
+typedef void (*smg_free_fn)(void *p, size_t bytes, void *user);
+/* alloc and free both NULL: hipMalloc / hipFree.  The context must outlive
+ * every solver created in it.  Errors: INVALID_ARG (bad device, only one
+ * function given). */
+smg_status smg_ctx_create(int32_t device, smg_alloc_fn alloc, smg_free_fn free_fn, void *user, smg_ctx *out);
+void smg_ctx_destroy(smg_ctx ctx);
+
 /* ------------------------------------------------------------------------ */
 /* Device solver.                                                           */
 
@@ -139,6 +180,12 @@ typedef struct {
                               4 that fits a whole color in one pass); launch shape
                               only: results do not depend on it beyond
                               summation order                              */
+    int32_t team_level;    /* > 0: this level and all coarser ones run in one
+                              kernel by a team of workgroups on one XCD that
+                              meet at L2-local barriers (between colors and
+                              phases) instead of kernel boundaries; 0 = off
+                              (per-color launches, then the LDS tail)     */
+    int32_t team_size;     /* workgroups of that team, 1..16 (0 = 16)       */
 } smg_opts;
 
 /* Upload a hierarchy for the level-0 pattern (a0_rowptr, a0_cols: host CSR,
@@ -147,10 +194,14 @@ typedef struct {
  * numeric plans, the coloring of every smoothed level (App. A) and the
  * color-major layout; then copies everything to device `device`.
  * opts may be NULL (2/2).  The coarsest level is factored densely and may
- * have at most 16384 rows (INVALID_ARG beyond).  Errors: INVALID_ARG, OOM,
- * HIP. */
+ * have at most 16384 rows (INVALID_ARG beyond).  Every device buffer any
+ * later call needs (work vectors of CG and of damped Jacobi included) is
+ * taken here.  Errors: INVALID_ARG, OOM, HIP. */
 smg_status smg_solver_create(int32_t device, smg_hier h, const int32_t *a0_rowptr,
                              const int32_t *a0_cols, const smg_opts *opts, smg_solver *out);
+/* The same on the device of ctx, with its allocator. */
+smg_status smg_solver_create_ctx(smg_ctx ctx, smg_hier h, const int32_t *a0_rowptr,
+                                 const int32_t *a0_cols, const smg_opts *opts, smg_solver *out);
 void smg_solver_destroy(smg_solver s);
 
 /* Enable on-device assembly for the mesh faces F (m x 3, host). The level-0
@@ -252,13 +303,29 @@ typedef struct {
     int32_t precision;     /* SMG_FP64 or SMG_FP32_IR                            */
     int32_t fixed_cycles;  /* > 0: run exactly this many cycles, no stop test   */
     int32_t use_graph;     /* 1: replay each cycle from a captured hipGraph     */
+    int32_t timed;         /* 1: fill info->ms_phase (an event at every change
+                              of phase on the stream; cycles run eagerly)     */
 } smg_solve_params;
+
+/* Phases of a solve, as Tab. "profile" of the paper splits the time */
+enum { SMG_PHASE_PREPARE = 0,   /* A_{l+1} = P^T A P and coarsest factor (the last
+                                   smg_set_values / smg_split_combine)          */
+       SMG_PHASE_RELAX = 1,     /* Gauss-Seidel / Jacobi sweeps; the one-workgroup
+                                   tail (mostly relaxation passes) counts here  */
+       SMG_PHASE_TRANSFER = 2,  /* residuals feeding the restriction,
+                                   restriction, prolongation                    */
+       SMG_PHASE_NORM = 3,      /* level-0 FP64 residual and its column norms
+                                   (the stop test and the refinement residual)  */
+       SMG_PHASE_OTHER = 4 };   /* coarsest solves outside the tail, refinement
+                                   scaling and update, set-up of the solve      */
 
 typedef struct {
     int32_t cycles;        /* V-cycles run (outer refinement steps for FP32_IR) */
     int32_t k;
     double rel_res[4];     /* final FP64 relative residual per column           */
     double ms;             /* wall time of the solve on the stream              */
+    double ms_phase[5];    /* device time by SMG_PHASE_* (index); [0] always,
+                              [1..4] when params->timed, else 0               */
 } smg_solve_info;
 
 /* x = A^{-1} b from x0 = 0.  SMG_FP32_IR runs relaxation, residual and
@@ -323,8 +390,8 @@ smg_status smg_split_combine(smg_solver s, double a, double b, smg_stream stream
  * v <- D_l^{-1} A_l v from v_i = frac(0.6180339887498949 (i + 1)) - 1/2
  * (i the natural row index), recomputed whenever the values change.
  * Applies to every later smooth, V-cycle, solve and PCG call of s (the
- * Jacobi V-cycle is symmetric as it is); the first Jacobi selection
- * allocates a second n x 4 iterate per level (FP64 and FP32).  Waits for the
+ * Jacobi V-cycle is symmetric as it is); its second iterate per level is
+ * taken at smg_solver_create.  Waits for the
  * device and drops captured cycle graphs.  Batches take GS solvers only.
  * Errors: INVALID_ARG (omega >= 2 or NaN, unknown kind), OOM. */
 smg_status smg_set_smoother(smg_solver s, int32_t kind, double omega);
@@ -343,8 +410,8 @@ smg_status smg_get_jacobi_omega(smg_solver s, int32_t level, double *omega);
  * > 0 runs exactly that many.  p->precision: SMG_FP64, or SMG_FP32_IR for
  * an FP32 V-cycle on r scaled by max |r| per column (vectors, dot products
  * and updates stay FP64).  p->use_graph must be 0.  info->cycles =
- * iterations, info->rel_res = final recurrence residuals.  The first call
- * allocates three n x 4 FP64 work vectors.  Errors: INVALID_ARG, STATE,
+ * iterations, info->rel_res = final recurrence residuals.  Its three n x 4
+ * FP64 work vectors are taken at smg_solver_create.  Errors: INVALID_ARG, STATE,
  * NONFINITE, NO_CONVERGENCE, OOM. */
 smg_status smg_pcg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k,
                          const smg_solve_params *p, smg_solve_info *info, smg_stream stream);

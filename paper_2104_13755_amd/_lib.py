@@ -23,16 +23,17 @@ class PreOpts(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("mu_pre", c_int32), ("mu_post", c_int32), ("tail_rows", c_int32),
-                ("lanes_per_row", c_int32 * 16)]
+                ("lanes_per_row", c_int32 * 16), ("team_level", c_int32), ("team_size", c_int32)]
 
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("rtol", c_double), ("max_cycles", c_int32), ("precision", c_int32),
-                ("fixed_cycles", c_int32), ("use_graph", c_int32)]
+                ("fixed_cycles", c_int32), ("use_graph", c_int32), ("timed", c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
-    _fields_ = [("cycles", c_int32), ("k", c_int32), ("rel_res", c_double * 4), ("ms", c_double)]
+    _fields_ = [("cycles", c_int32), ("k", c_int32), ("rel_res", c_double * 4), ("ms", c_double),
+                ("ms_phase", c_double * 5)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -50,12 +51,23 @@ SMG_SMOOTH_JACOBI = 1
 SMG_COLLAPSE_ALL = 0
 SMG_COLLAPSE_INTERIOR = 1
 SMG_COLLAPSE_STRAIGHT = 2
+PHASES = ("prepare", "relax", "transfer", "norm", "other")   # SMG_PHASE_* order
 SMG_TAIL_RELAX, SMG_TAIL_RESIDUAL, SMG_TAIL_RESTRICT, SMG_TAIL_PROLONG, SMG_TAIL_COARSE = range(5)
+
+# caller allocator of a context: void *alloc(size_t, void *user), void free(void *, size_t, void *user)
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, ctypes.c_size_t, c_void_p)
 
 # name -> (restype, argtypes)
 SIGNATURES = {
+    "smg_ctx_create": (c_int32, [c_int32, ALLOC_FN, FREE_FN, c_void_p, ctypes.POINTER(c_void_p)]),
+    "smg_ctx_destroy": (None, [c_void_p]),
+    "smg_solver_create_ctx": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(Opts), ctypes.POINTER(c_void_p)]),
     "smg_pre_build": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(PreOpts), ctypes.POINTER(c_void_p)]),
     "smg_hier_from_prolongations": (c_int32, [c_int32, c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "smg_pre_assemble": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "smg_hier_save": (c_int32, [c_void_p, ctypes.c_char_p]),
+    "smg_hier_load": (c_int32, [ctypes.c_char_p, ctypes.POINTER(c_void_p)]),
     "smg_hier_num_levels": (c_int32, [c_void_p]),
     "smg_hier_level_size": (c_int32, [c_void_p, c_int32]),
     "smg_hier_get_prolongation": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),

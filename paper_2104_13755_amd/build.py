@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsmg.so")
 
-HOST_SRC = ["ssp.cpp", "hier.cpp"]
+HOST_SRC = ["ssp.cpp", "hier.cpp", "hier_io.cpp", "assemble_host.cpp"]
 HIP_SRC = ["kernels.hip", "api.hip", "batch.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -177,6 +177,41 @@ extern "C" smg_status smg_hier_from_prolongations(int32_t n_levels, const int32_
     return SMG_OK;
 }
 
+extern "C" smg_status smg_pre_assemble(const double *V, int32_t n, const int32_t *F, int32_t m,
+                                       const int32_t *rowptr, const int32_t *cols, double *L_vals,
+                                       double *M_diag) {
+    if (!V || !F || !rowptr || !cols || !L_vals || !M_diag || n < 1 || m < 1)
+        return fail(SMG_ERR_INVALID_ARG, "smg_pre_assemble: null or empty argument");
+    for (int64_t i = 0; i < 3 * (int64_t)m; ++i)
+        if (F[i] < 0 || F[i] >= n) return fail(SMG_ERR_INVALID_ARG, "smg_pre_assemble: face index out of range");
+    if (rowptr[0] != 0) return fail(SMG_ERR_INVALID_ARG, "smg_pre_assemble: rowptr[0] != 0");
+    for (int i = 0; i < n; ++i)
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            if (cols[p] < 0 || cols[p] >= n || (p > rowptr[i] && cols[p] <= cols[p - 1]))
+                return fail(SMG_ERR_INVALID_ARG, "smg_pre_assemble: columns out of range or not ascending");
+    std::string err;
+    if (!host_assemble(V, n, F, m, rowptr, cols, L_vals, M_diag, err))
+        return fail(SMG_ERR_INVALID_ARG, "smg_pre_assemble: " + err);
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_hier_save(smg_hier h, const char *path) {
+    if (!h || !path) return fail(SMG_ERR_INVALID_ARG, "smg_hier_save: null argument");
+    std::string err;
+    if (!hier_write(h->H, path, err)) return fail(SMG_ERR_INVALID_ARG, "smg_hier_save: " + err);
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_hier_load(const char *path, smg_hier *out) {
+    if (!path || !out) return fail(SMG_ERR_INVALID_ARG, "smg_hier_load: null argument");
+    *out = nullptr;
+    auto h = std::make_unique<smg_hier_s>();
+    std::string err;
+    if (!hier_read(path, h->H, err)) return fail(SMG_ERR_INVALID_ARG, "smg_hier_load: " + err);
+    *out = h.release();
+    return SMG_OK;
+}
+
 extern "C" int32_t smg_hier_num_levels(smg_hier h) { return h ? h->H.nlev : 0; }
 extern "C" int32_t smg_hier_level_size(smg_hier h, int32_t l) {
     return (h && l >= 0 && l < h->H.nlev) ? h->H.sizes[l] : -1;
@@ -311,16 +346,14 @@ extern "C" smg_status smg_mesh_pattern(int32_t n, const int32_t *F, int32_t m, i
 namespace smg {
 
 template <typename T>
-static smg_status dalloc(T **p, size_t count, std::vector<void *> &owned) {
-    *p = nullptr;
+static smg_status dalloc(T **p, size_t count, DevMem &owned) {
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) return fail(SMG_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    owned.push_back(*p);
+    *p = (T *)owned.take(count * sizeof(T));
+    if (!*p) return fail(SMG_ERR_OOM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
     return SMG_OK;
 }
 template <typename T>
-static smg_status dupload(T **p, const std::vector<T> &h, std::vector<void *> &owned) {
+static smg_status dupload(T **p, const std::vector<T> &h, DevMem &owned) {
     smg_status st = dalloc(p, h.size(), owned);
     if (st) return st;
     if (!h.empty()) {
@@ -338,9 +371,45 @@ static smg_status dupload(T **p, const std::vector<T> &h, std::vector<void *> &o
         if (s_ != SMG_OK) return s_;        \
     } while (0)
 
+extern "C" smg_status smg_ctx_create(int32_t device, smg_alloc_fn alloc, smg_free_fn free_fn, void *user,
+                                     smg_ctx *out) {
+    if (!out) return fail(SMG_ERR_INVALID_ARG, "smg_ctx_create: null output");
+    *out = nullptr;
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(SMG_ERR_INVALID_ARG, "smg_ctx_create: give both allocator functions or neither");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SMG_ERR_INVALID_ARG, "smg_ctx_create: bad device");
+    smg_ctx c = new smg_ctx_s;
+    c->device = device;
+    c->alloc = alloc;
+    c->free = free_fn;
+    c->user = user;
+    *out = c;
+    return SMG_OK;
+}
+
+extern "C" void smg_ctx_destroy(smg_ctx ctx) { delete ctx; }
+
+static smg_status solver_create(const smg_ctx_s &ctx, smg_hier h, const int32_t *a0_rowptr,
+                                const int32_t *a0_cols, const smg_opts *opts, smg_solver *out);
+
 extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_t *a0_rowptr,
-                                        const int32_t *a0_cols, const smg_opts *opts,
-                                        smg_solver *out) {
+                                        const int32_t *a0_cols, const smg_opts *opts, smg_solver *out) {
+    smg_ctx_s ctx;
+    ctx.device = device;
+    return solver_create(ctx, h, a0_rowptr, a0_cols, opts, out);
+}
+
+extern "C" smg_status smg_solver_create_ctx(smg_ctx ctx, smg_hier h, const int32_t *a0_rowptr,
+                                            const int32_t *a0_cols, const smg_opts *opts, smg_solver *out) {
+    if (!ctx) return fail(SMG_ERR_INVALID_ARG, "smg_solver_create_ctx: null context");
+    return solver_create(*ctx, h, a0_rowptr, a0_cols, opts, out);
+}
+
+static smg_status solver_create(const smg_ctx_s &ctx, smg_hier h, const int32_t *a0_rowptr,
+                                const int32_t *a0_cols, const smg_opts *opts, smg_solver *out) {
+    const int device = ctx.device;
     if (!h || !a0_rowptr || !a0_cols || !out) return fail(SMG_ERR_INVALID_ARG, "smg_solver_create: null argument");
     const int n0 = h->H.sizes[0];
     Csr A0;
@@ -367,10 +436,16 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     HIPCHK(hipSetDevice(device));
     auto S = std::make_unique<smg_solver_s>();
     S->device = device;
+    S->owned.ctx = ctx;
     S->mu_pre = opts && opts->mu_pre >= 0 ? opts->mu_pre : 2;
     S->mu_post = opts && opts->mu_post >= 0 ? opts->mu_post : 2;
     if (!opts) S->mu_pre = S->mu_post = 2;
     const int tail_rows = (opts && opts->tail_rows != 0) ? opts->tail_rows : kTailRowsDefault;
+    if (opts && (opts->team_level < 0 || opts->team_size < 0 || opts->team_size > 16))
+        return fail(SMG_ERR_INVALID_ARG, "team_level must be >= 0 and team_size 0..16");
+    S->team_level = opts ? opts->team_level : 0;
+    if (S->team_level >= h->H.nlev - 1) S->team_level = 0;   // needs a smoothed level
+    S->team_size = (opts && opts->team_size > 0) ? opts->team_size : 16;
     std::vector<int> lpr(16, 0);
     if (opts) for (int l = 0; l < 16; ++l) lpr[l] = opts->lanes_per_row[l];
     std::vector<LevelHost> levels;
@@ -546,12 +621,52 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
     CHK(dalloc(&S->partial, (size_t)S->npartial, S->owned));
     CHK(dalloc(&S->norms, 16, S->owned));
     CHK(dalloc(&S->flag, 4, S->owned));
+    HIPCHK(hipMemset(S->flag, 0, 4 * sizeof(int)));
+    // one-XCD team: the levels as the team code reads them, and its counter
+    {
+        std::vector<TailLevel<double>> h64(S->nlev);
+        std::vector<TailLevel<float>> h32(S->nlev);
+        for (int l = 0; l < S->nlev; ++l) {
+            const DevLevel &D = S->lev[l];
+            const int grp = l == 0 ? 1 : 8;
+            h64[l] = {D.n, D.ncolors, D.lpr, grp, D.color_row, D.slice_row0, D.slice_off, D.row_slice, D.rowlen,
+                      D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw, D.rptr, D.ridx, D.rw};
+            h32[l] = {D.n, D.ncolors, D.lpr, grp, D.color_row, D.slice_row0, D.slice_off, D.row_slice, D.rowlen,
+                      D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32, D.pc, D.pw32, D.rptr, D.ridx, D.rw32};
+        }
+        CHK(dupload(&S->team64, h64, S->owned));
+        CHK(dupload(&S->team32, h32, S->owned));
+        CHK(dalloc(&S->team_ctr, 64, S->owned));
+    }
+    // work vectors of the later entry points, so that none of them allocates:
+    // damped Jacobi (a second iterate per smoothed level, power-step scratch,
+    // per-level factors) and preconditioned CG (x, p, A p, column scalars)
+    {
+        int64_t nmax = 1;
+        for (smg::DevLevel &D : S->lev)
+            if (!D.coarsest) {
+                nmax = std::max<int64_t>(nmax, D.n);
+                CHK(dalloc(&D.xj, (size_t)D.n * 4, S->owned));
+                CHK(dalloc(&D.xj32, (size_t)D.n * 4, S->owned));
+            }
+        CHK(dalloc(&S->jac_v, (size_t)nmax, S->owned));
+        CHK(dalloc(&S->jac_u, (size_t)nmax, S->owned));
+        CHK(dalloc(&S->jac_sums, 4, S->owned));
+        CHK(dalloc(&S->d_omega, (size_t)S->nlev, S->owned));
+        const size_t nv = (size_t)S->lev[0].n * 4;
+        CHK(dalloc(&S->cg_x, nv, S->owned));
+        CHK(dalloc(&S->cg_p, nv, S->owned));
+        CHK(dalloc(&S->cg_ap, nv, S->owned));
+        CHK(dalloc(&S->cg_s, 32, S->owned));
+    }
     HIPCHK(hipHostMalloc((void **)&S->h_norms, 16 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHK(hipHostGetDevicePointer((void **)&S->d_hnorms, S->h_norms, 0));
     HIPCHK(hipHostMalloc((void **)&S->h_flag, 4 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreate(&S->ev_prep0));
+    HIPCHK(hipEventCreate(&S->ev_prep1));
     *out = S.release();
     return SMG_OK;
 }
@@ -559,10 +674,13 @@ extern "C" smg_status smg_solver_create(int32_t device, smg_hier h, const int32_
 smg_solver_s::~smg_solver_s() {
     (void)hipSetDevice(device);
     for (auto &g : graphs) if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    for (void *p : owned) (void)hipFree(p);
+    owned.release_all();
     if (h_norms) (void)hipHostFree(h_norms);
     if (h_flag) (void)hipHostFree(h_flag);
     for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ph_pool) (void)hipEventDestroy(e);
+    if (ev_prep0) (void)hipEventDestroy(ev_prep0);
+    if (ev_prep1) (void)hipEventDestroy(ev_prep1);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -662,9 +780,16 @@ extern "C" smg_status smg_set_values(smg_solver s, const double *d_a0_vals, smg_
     if (!s || !d_a0_vals) return fail(SMG_ERR_INVALID_ARG, "smg_set_values: null argument");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipEventRecord(s->ev_prep0, st));
     CHK(refresh_values(s, d_a0_vals, st));
+    HIPCHK(hipEventRecord(s->ev_prep1, st));
     HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev_prep0, s->ev_prep1));
+        s->ms_prepare = ms;
+    }
     if (s->h_flag[0]) { s->values_set = false; return fail(SMG_ERR_NONFINITE, "non-finite matrix value"); }
     if (s->h_flag[1]) { s->values_set = false; return fail(SMG_ERR_NOT_SPD, "coarsest Cholesky: non-positive pivot"); }
     s->values_set = true;
@@ -726,6 +851,7 @@ extern "C" smg_status smg_split_combine(smg_solver s, double a, double b, smg_st
     if (!std::isfinite(a) || !std::isfinite(b)) return fail(SMG_ERR_INVALID_ARG, "non-finite coefficient");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipEventRecord(s->ev_prep0, st));
     HIPCHK(launch_fill<int>(s->flag, 0, 2, st));
     for (DevLevel &D : s->lev) {
         if (D.coarsest) {
@@ -736,8 +862,14 @@ extern "C" smg_status smg_split_combine(smg_solver s, double a, double b, smg_st
         }
     }
     CHK(finish_values(s, st));
+    HIPCHK(hipEventRecord(s->ev_prep1, st));
     HIPCHK(hipMemcpyAsync(s->h_flag, s->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev_prep0, s->ev_prep1));
+        s->ms_prepare = ms;
+    }
     if (s->h_flag[1]) { s->values_set = false; return fail(SMG_ERR_NOT_SPD, "coarsest Cholesky: non-positive pivot"); }
     s->values_set = true;
     return SMG_OK;
@@ -860,6 +992,9 @@ template <>
 SellView<float> sell_view<float>(const DevLevel &D) {
     return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32};
 }
+template <typename T> static const TailLevel<T> *team_desc(const smg_solver_s *s);
+template <> const TailLevel<double> *team_desc<double>(const smg_solver_s *s) { return s->team64; }
+template <> const TailLevel<float> *team_desc<float>(const smg_solver_s *s) { return s->team32; }
 template <typename T> static const LdsLevel<T> *tail_desc(const smg_solver_s *s);
 template <> const LdsLevel<double> *tail_desc<double>(const smg_solver_s *s) { return s->lds64; }
 template <> const LdsLevel<float> *tail_desc<float>(const smg_solver_s *s) { return s->lds32; }
@@ -901,6 +1036,7 @@ static double sweep_bytes(int64_t z, int64_t n, int k, double sb, bool first) {
 
 template <typename T>
 smg_status jacobi_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool x_zero) {
+    phase_mark(s, st, SMG_PHASE_RELAX);
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
@@ -922,6 +1058,7 @@ template <typename T>
 smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t st, bool descending = false,
                         bool x_zero = false) {
     if (s->smoother == SMG_SMOOTH_JACOBI) return jacobi_level<T>(s, l, k, sweeps, st, x_zero);
+    phase_mark(s, st, SMG_PHASE_RELAX);
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
@@ -941,6 +1078,7 @@ smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
 
 template <typename T>
 smg_status residual_level(smg_solver_s *s, int l, int k, bool norms, hipStream_t st) {
+    phase_mark(s, st, norms ? SMG_PHASE_NORM : SMG_PHASE_TRANSFER);
     DevLevel &D = s->lev[l];
     int nblk = 0;
     const double sb = sizeof(T);
@@ -959,12 +1097,22 @@ template <typename T>
 smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part, bool sym) {
     DevLevel &D = s->lev[l];
     if (D.coarsest) {
+        phase_mark(s, st, SMG_PHASE_OTHER);
         if (part != kCyclePre)
             HIPCHK((launch_coarse_solve<T, T>(D.dense_inv, D.n, bbuf<T>(D), xbuf<T>(D), k, st)));
         return SMG_OK;
     }
     const int pr = sizeof(T) == 8 ? 0 : 1;
+    if (s->smoother == SMG_SMOOTH_GS && s->team_level > 0 && l == s->team_level && !sym) {
+        phase_mark(s, st, SMG_PHASE_RELAX);
+        if (part != kCyclePre)
+            HIPCHK(launch_team_vcycle<T>(team_desc<T>(s), l, s->nlev, s->mu_pre, s->mu_post,
+                                         s->lev[s->nlev - 1].dense_inv, s->team_ctr, s->flag + 2, s->team_size, k,
+                                         st));
+        return SMG_OK;
+    }
     if (s->smoother == SMG_SMOOTH_GS && l >= s->tail_first[pr][k]) {   // this level and all coarser ones in one launch
+        phase_mark(s, st, SMG_PHASE_RELAX);
         if (part != kCyclePre)
             HIPCHK(launch_tail_lds<T>(tail_desc<T>(s), s->tpass, s->twave, l, s->nlev, s->mu_pre, s->mu_post,
                                       s->lev[s->nlev - 1].dense_inv, k, s->tail_lds[pr][k][l], st, sym,
@@ -978,8 +1126,10 @@ smg_status vcycle_from(smg_solver_s *s, int l, int k, hipStream_t st, int part, 
     if (part == kCyclePre) return SMG_OK;
     CHK(residual_level<T>(s, l, k, false, st));                    // r = b - A x'
     // P^T r; the coarse iterate starts from zero
+    phase_mark(s, st, SMG_PHASE_TRANSFER);
     HIPCHK(launch_restrict<T>(P, rwbuf<T>(D), rbuf<T>(D), bbuf<T>(C), k, st, C.coarsest ? nullptr : xbuf<T>(C)));
     CHK(vcycle_from<T>(s, l + 1, k, st, kCycleWhole, sym));        // coarse correction
+    phase_mark(s, st, SMG_PHASE_TRANSFER);
     HIPCHK(launch_prolong_add<T>(P, pwbuf<T>(D), xbuf<T>(C), xbuf<T>(D), k, st));  // x' + P c
     CHK(smooth_level<T>(s, l, k, s->mu_post, st, sym));            // post-relaxation
     return SMG_OK;
@@ -1224,6 +1374,20 @@ extern "C" smg_status smg_vcycle(smg_solver s, int32_t precision, const double *
 // ------------------------------------------------------------------ solve
 namespace smg {
 
+// The one-XCD team raises flag[2] when a workgroup ran on another XCD or a
+// barrier wait timed out; the result of that solve is then not to be used.
+static smg_status check_team(smg_solver_s *s, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(s->h_flag + 2, s->flag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (s->h_flag[2]) {
+        const int code = s->h_flag[2];
+        HIPCHK(launch_fill<int>(s->flag + 2, 0, 1, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return fail(SMG_ERR_HIP, "team V-cycle: a barrier wait timed out (code " + std::to_string(code) + ")");
+    }
+    return SMG_OK;
+}
+
 // Wait for the column norms (sum of squares, max) of the last reduction: the
 // reduction kernel writes them to h_norms itself (no copy back), so this only
 // waits, polling, for the stream to drain.
@@ -1271,9 +1435,13 @@ smg_status cycle_enqueue(smg_solver_s *s, int k, int precision, hipStream_t st, 
         CHK(vcycle_from<double>(s, 0, k, st));
     } else {
         // x32 is zero here: cleared at the start of the solve and by every ir_up
-        if (part != kCycleAfterPre) HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
+        if (part != kCycleAfterPre) {
+            phase_mark(s, st, SMG_PHASE_OTHER);
+            HIPCHK(launch_ir_down(D.r, s->norms, D.b32, D.n, k, st));
+        }
         CHK(vcycle_from<float>(s, 0, k, st, part));
         if (part == kCyclePre) return SMG_OK;
+        phase_mark(s, st, SMG_PHASE_OTHER);
         HIPCHK(launch_ir_up(D.x32, s->norms, D.x, D.n, k, st));
     }
     if (D.coarsest) {
@@ -1300,12 +1468,21 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
     // graph capture needs a capturable stream: the cycles then run on the
     // solver's own stream, ordered after and before the caller's work
     hipStream_t st = caller;
-    const bool graphs = p->use_graph && s->prof_kind < 0;
+    const bool graphs = p->use_graph && s->prof_kind < 0 && !p->timed;
     if (graphs) {
         st = s->gstream;
         HIPCHK(hipEventRecord(s->ev_in, caller));
         HIPCHK(hipStreamWaitEvent(st, s->ev_in, 0));
     }
+    s->ph_on = p->timed != 0;
+    s->ph_cur = -1;
+    s->ph_tag.clear();
+    // an early return leaves no phase timing switched on
+    struct PhaseOff {
+        smg_solver_s *s;
+        ~PhaseOff() { s->ph_on = false; s->ph_cur = -1; s->ph_tag.clear(); }
+    } phase_off{s};
+    phase_mark(s, st, SMG_PHASE_OTHER);
     HIPCHK(launch_fill<int>(s->flag, 0, 1, st));
     HIPCHK(launch_check_finite(d_b, (int64_t)D.n * k, s->flag, st));
     HIPCHK(launch_gather_rows(D.perm, d_b, D.b, D.n, k, st));
@@ -1376,12 +1553,17 @@ extern "C" smg_status smg_solve(smg_solver s, const double *d_b, double *d_x, in
         HIPCHK(hipEventRecord(s->ev_out, st));
         HIPCHK(hipStreamWaitEvent(caller, s->ev_out, 0));
     }
+    double ph[5] = {0, 0, 0, 0, 0};
+    CHK(phase_sum(s, st, ph));
     HIPCHK(hipStreamSynchronize(st));
+    if (s->team_level > 0) CHK(check_team(s, st));
     if (info) {
         info->cycles = cycles;
         info->k = k;
         for (int q = 0; q < 4; ++q) info->rel_res[q] = q < k ? rho[q] : 0.0;
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ph[SMG_PHASE_PREPARE] = s->ms_prepare;
+        for (int q = 0; q < 5; ++q) info->ms_phase[q] = ph[q];
     }
     if (s->prof_kind >= 0) CHK(prof_collect(s));
     if (status == SMG_ERR_NO_CONVERGENCE) return fail(status, "cycle cap reached");
@@ -1403,6 +1585,7 @@ smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_
         info->k = k;
         for (int q = 0; q < 4; ++q) info->rel_res[q] = 0.0;
         info->ms = 0.0;
+        for (int q = 0; q < 5; ++q) info->ms_phase[q] = q == SMG_PHASE_PREPARE ? s->ms_prepare : 0.0;
     }
     return SMG_OK;
 }
@@ -1435,19 +1618,6 @@ extern "C" smg_status smg_set_smoother(smg_solver s, int32_t kind, double omega)
     if (kind != SMG_SMOOTH_GS && kind != SMG_SMOOTH_JACOBI) return fail(SMG_ERR_INVALID_ARG, "unknown smoother");
     if (kind == SMG_SMOOTH_JACOBI && !(omega < 2.0)) return fail(SMG_ERR_INVALID_ARG, "Jacobi damping must be below 2");
     HIPCHK(hipSetDevice(s->device));
-    if (kind == SMG_SMOOTH_JACOBI && !s->d_omega) {
-        int64_t nmax = 1;
-        for (smg::DevLevel &D : s->lev)
-            if (!D.coarsest) {
-                nmax = std::max<int64_t>(nmax, D.n);
-                CHK(smg::dalloc(&D.xj, (size_t)D.n * 4, s->owned));
-                CHK(smg::dalloc(&D.xj32, (size_t)D.n * 4, s->owned));
-            }
-        CHK(smg::dalloc(&s->jac_v, (size_t)nmax, s->owned));
-        CHK(smg::dalloc(&s->jac_u, (size_t)nmax, s->owned));
-        CHK(smg::dalloc(&s->jac_sums, 4, s->owned));
-        CHK(smg::dalloc(&s->d_omega, (size_t)s->nlev, s->owned));
-    }
     // captured cycles hold the previous smoother's launches
     HIPCHK(hipDeviceSynchronize());
     for (auto &g : s->graphs) if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -1513,13 +1683,6 @@ extern "C" smg_status smg_pcg_solve(smg_solver s, const double *d_b, double *d_x
     hipStream_t st = (hipStream_t)stream;
     DevLevel &D = s->lev[0];
     if (D.coarsest) return smg_solve_single_level(s, d_b, d_x, k, p, info, st);
-    if (!s->cg_x) {
-        const size_t nv = (size_t)D.n * 4;
-        CHK(dalloc(&s->cg_x, nv, s->owned));
-        CHK(dalloc(&s->cg_p, nv, s->owned));
-        CHK(dalloc(&s->cg_ap, nv, s->owned));
-        CHK(dalloc(&s->cg_s, 32, s->owned));
-    }
     const auto t0 = std::chrono::steady_clock::now();
     const int prec = p->precision;
     const bool f32 = prec != SMG_FP64;
@@ -1594,6 +1757,7 @@ extern "C" smg_status smg_pcg_solve(smg_solver s, const double *d_b, double *d_x
         info->k = k;
         for (int q = 0; q < 4; ++q) info->rel_res[q] = q < k ? rho[q] : 0.0;
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int q = 0; q < 5; ++q) info->ms_phase[q] = q == SMG_PHASE_PREPARE ? s->ms_prepare : 0.0;
     }
     if (status == SMG_ERR_NO_CONVERGENCE) return fail(status, "iteration cap reached");
     if (status == SMG_ERR_NONFINITE) return fail(status, "non-finite residual");
@@ -1639,6 +1803,36 @@ int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t s
     const int idx = (int)s->prof_used++;
     s->prof_bytes_pending.push_back(bytes);
     return idx;
+}
+
+void phase_mark(smg_solver_s *s, hipStream_t st, int phase) {
+    if (!s->ph_on || phase == s->ph_cur) return;
+    const size_t i = s->ph_tag.size();
+    if (s->ph_pool.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { s->ph_on = false; return; }
+        s->ph_pool.push_back(e);
+    }
+    if (hipEventRecord(s->ph_pool[i], st) != hipSuccess) { s->ph_on = false; return; }
+    s->ph_tag.push_back(phase);
+    s->ph_cur = phase;
+}
+
+smg_status phase_sum(smg_solver_s *s, hipStream_t st, double *ms) {
+    const bool was_on = s->ph_on;
+    phase_mark(s, st, -1);   // closes the last interval
+    s->ph_on = false;
+    s->ph_cur = -1;
+    if (was_on) {
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i + 1 < s->ph_tag.size(); ++i) {
+            float dt = 0.0f;
+            HIPCHK(hipEventElapsedTime(&dt, s->ph_pool[i], s->ph_pool[i + 1]));
+            if (ms && s->ph_tag[i] >= 0 && s->ph_tag[i] < 5) ms[s->ph_tag[i]] += dt;
+        }
+    }
+    s->ph_tag.clear();
+    return SMG_OK;
 }
 
 hipEvent_t prof_ev(smg_solver_s *s, int idx, int which) {

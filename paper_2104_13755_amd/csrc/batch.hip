@@ -12,6 +12,7 @@
 #include <memory>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -57,18 +58,12 @@ struct smg_batch_s {
     std::vector<int32_t> last_k;
     smg_solve_params last_p{};
     bool have_last = false;
+    int team_capacity = 0;                                 // entries of d_team_mesh / d_team_rank
+    DevMem mem;                                            // device buffers (the first solver's allocator)
     ~smg_batch_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
-        if (d64) (void)hipFree(d64);
-        if (d32) (void)hipFree(d32);
-        if (d_mesh) (void)hipFree(d_mesh);
-        if (d_team_mesh) (void)hipFree(d_team_mesh);
-        if (d_team_rank) (void)hipFree(d_team_rank);
-        if (d_ctr) (void)hipFree(d_ctr);
-        if (d_abort) (void)hipFree(d_abort);
-        if (d_partial) (void)hipFree(d_partial);
+        mem.release_all();
         if (h_abort) (void)hipHostFree(h_abort);
-        if (d_out) (void)hipFree(d_out);
         if (h_out) (void)hipHostFree(h_out);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
@@ -110,6 +105,7 @@ static smg_status layout_teams(smg_batch_s *b) {
         --tmax;
     }
     if (b->total_blocks > capacity) return fail(SMG_ERR_INVALID_ARG, "batch too large to be resident at once");
+    if (b->total_blocks > b->team_capacity) return fail(SMG_ERR_INVALID_ARG, "batch team table too small");
     std::vector<int32_t> order(b->count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -118,9 +114,6 @@ static smg_status layout_teams(smg_batch_s *b) {
     std::vector<int32_t> tm, tr;
     for (int i : order)
         for (int r = 0; r < b->team[i]; ++r) { tm.push_back(i); tr.push_back(r); }
-    if (b->d_team_mesh) { (void)hipFree(b->d_team_mesh); (void)hipFree(b->d_team_rank); }
-    HIPCHK(hipMalloc((void **)&b->d_team_mesh, tm.size() * sizeof(int32_t)));
-    HIPCHK(hipMalloc((void **)&b->d_team_rank, tr.size() * sizeof(int32_t)));
     HIPCHK(hipMemcpy(b->d_team_mesh, tm.data(), tm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->d_team_rank, tr.data(), tr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     return SMG_OK;
@@ -198,19 +191,28 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
     if (b->lanes0 != 1 && b->lanes0 != 2) return fail(SMG_ERR_INVALID_ARG, "lanes_level0 must be 1 or 2");
     if (b->lanes_c != 1 && b->lanes_c != 2 && b->lanes_c != 4 && b->lanes_c != 8) return fail(SMG_ERR_INVALID_ARG, "lanes_coarse must be 1, 2, 4 or 8");
     HIPCHK(hipSetDevice(b->device));
-    HIPCHK(hipMalloc((void **)&b->d64, b->h64.size() * sizeof(TailLevel<double>)));
-    HIPCHK(hipMalloc((void **)&b->d32, b->h32.size() * sizeof(TailLevel<float>)));
-    HIPCHK(hipMalloc((void **)&b->d_mesh, count * sizeof(BatchMesh)));
-    HIPCHK(hipMalloc((void **)&b->d_out, count * 8 * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&b->d_ctr, count * sizeof(unsigned)));
-    HIPCHK(hipMalloc((void **)&b->d_abort, count * sizeof(int)));
-    HIPCHK(hipMalloc((void **)&b->d_partial, (size_t)count * 8 * 64 * sizeof(double)));
-    HIPCHK(hipHostMalloc((void **)&b->h_abort, count * sizeof(int), hipHostMallocDefault));
     {
         hipDeviceProp_t prop;
         HIPCHK(hipGetDeviceProperties(&prop, b->device));
         b->cus = prop.multiProcessorCount;
     }
+    // every device buffer now, from the first solver's allocator; the team
+    // tables hold the most workgroups any launch shape can keep resident
+    b->mem.ctx = solvers[0]->owned.ctx;
+    for (int t : {256, 512, 1024}) b->team_capacity = std::max(b->team_capacity, batch_blocks_per_cu(t) * b->cus);
+    b->team_capacity = std::max(b->team_capacity, 1);
+    auto take = [&](auto **p, size_t bytes) {
+        *p = (std::remove_reference_t<decltype(**p)> *)b->mem.take(std::max<size_t>(bytes, 1));
+        return *p != nullptr;
+    };
+    if (!take(&b->d64, b->h64.size() * sizeof(TailLevel<double>)) ||
+        !take(&b->d32, b->h32.size() * sizeof(TailLevel<float>)) || !take(&b->d_mesh, count * sizeof(BatchMesh)) ||
+        !take(&b->d_out, count * 8 * sizeof(double)) || !take(&b->d_ctr, count * sizeof(unsigned)) ||
+        !take(&b->d_abort, count * sizeof(int)) || !take(&b->d_partial, (size_t)count * 8 * 64 * sizeof(double)) ||
+        !take(&b->d_team_mesh, (size_t)b->team_capacity * sizeof(int32_t)) ||
+        !take(&b->d_team_rank, (size_t)b->team_capacity * sizeof(int32_t)))
+        return fail(SMG_ERR_OOM, "smg_batch_create: device allocation failed");
+    HIPCHK(hipHostMalloc((void **)&b->h_abort, count * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&b->h_out, count * 8 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
@@ -318,6 +320,7 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
             infos[i].k = k[i];
             for (int q = 0; q < 4; ++q) infos[i].rel_res[q] = q < k[i] ? o[1 + q] : 0.0;
             infos[i].ms = ms;
+            for (int q = 0; q < 5; ++q) infos[i].ms_phase[q] = q == SMG_PHASE_PREPARE ? b->solvers[i]->ms_prepare : 0.0;
         }
     }
     if (worst == SMG_ERR_NONFINITE) return fail(worst, "non-finite residual in a batch member");

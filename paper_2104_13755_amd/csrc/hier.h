@@ -137,6 +137,17 @@ struct HierHost {
     std::vector<std::array<double, 8>> stats;
 };
 
+// Cotangent Laplacian values and lumped mass on a CSR pattern that holds the
+// diagonal and every mesh edge (assemble_host.cpp); false + message on a
+// degenerate face or a pattern without an edge of a face.
+bool host_assemble(const double *V, int n, const int32_t *F, int m, const int32_t *rowptr, const int32_t *cols,
+                   double *L, double *M, std::string &err);
+
+// Versioned binary file of a hierarchy (hier_io.cpp); false + message on an
+// I/O error or a malformed file.
+bool hier_write(const HierHost &H, const char *path, std::string &err);
+bool hier_read(const char *path, HierHost &H, std::string &err);
+
 // Lanes per row for a level whose rows average `avg` off-diagonal entries.
 int default_lanes_per_row(double avg);
 

@@ -204,6 +204,14 @@ struct BatchMesh {
     double *x_user;                   // n x k, caller order
     double *out;                      // [cycles, rel_res[k]]
 };
+// Alg. "V-cycle" from level `first` to the coarsest by one team of m
+// workgroups (1024 threads) on one XCD meeting at L2-local barriers; lv: the
+// levels as TailLevel descriptors (device array); cb: 64 unsigned of team
+// control, 256-byte aligned (cleared by the launch); flag[0] becomes nonzero if a barrier wait
+// timed out.  m <= 16 keeps every workgroup resident on the XCD.
+template <typename T>
+hipError_t launch_team_vcycle(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
+                              const double *Ainv, unsigned *cb, int *flag, int m, int k, hipStream_t st);
 // team_mesh / team_rank: mesh and member index of every workgroup; ctrs and
 // aborts (count entries) are cleared by the launch; partials: count * 512.
 hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,

@@ -734,6 +734,115 @@ __global__ __launch_bounds__(1024) void k_cholesky_blocked(double *__restrict__ 
     }
 }
 
+// ------------------------------------------- blocked Cholesky on many CUs
+// Right-looking A = G G^T (column-major, lower) in panels of kCholNb columns:
+// per panel, one workgroup factors the diagonal block in LDS, every row below
+// it is solved against that block (one thread per row), and the trailing
+// lower triangle is updated A22 -= L21 L21^T in 16 x 16 tiles, one
+// wavefront per tile on the FP64 matrix cores (v_mfma_f64_16x16x4f64, K = 4
+// per instruction).  A pivot <= 0 sets *flag and every later kernel returns
+// at once.
+constexpr int kCholNb = 32;
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_chol_diag(double *__restrict__ A, int n, int k0, int b,
+                                                   int *__restrict__ flag) {
+    __shared__ double T[kCholNb * kCholNb];
+    __shared__ int bad;
+    if (*flag) return;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < b * b; t += blockDim.x) {
+        const int i = t % b, j = t / b;
+        T[j * kCholNb + i] = A[(size_t)(k0 + j) * n + k0 + i];
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < b; ++j) {
+        if (tid == 0) {
+            const double d = T[j * kCholNb + j];
+            if (!(d > 0.0)) { bad = 1; *flag = 1; }
+            else T[j * kCholNb + j] = sqrt(d);
+        }
+        __syncthreads();
+        if (bad) return;
+        const double djj = T[j * kCholNb + j];
+        for (int i = j + 1 + tid; i < b; i += blockDim.x) T[j * kCholNb + i] /= djj;
+        __syncthreads();
+        for (int t = tid; t < b * b; t += blockDim.x) {
+            const int i = t % b, c = t / b;
+            if (c > j && i >= c) T[c * kCholNb + i] -= T[j * kCholNb + i] * T[j * kCholNb + c];
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < b * b; t += blockDim.x) {
+        const int i = t % b, j = t / b;
+        if (i >= j) A[(size_t)(k0 + j) * n + k0 + i] = T[j * kCholNb + i];
+    }
+}
+
+// rows k0 + b .. n-1 of the panel: x L11^T = a, one thread per row
+__global__ __launch_bounds__(256) void k_chol_panel(double *__restrict__ A, int n, int k0, int b,
+                                                    const int *__restrict__ flag) {
+    __shared__ double T[kCholNb * kCholNb];
+    if (*flag) return;
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+        const int i = t % b, j = t / b;
+        T[j * kCholNb + i] = i >= j ? A[(size_t)(k0 + j) * n + k0 + i] : 0.0;
+    }
+    __syncthreads();
+    const int i = k0 + b + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x[kCholNb];
+#pragma unroll
+    for (int j = 0; j < kCholNb; ++j) {
+        if (j < b) {
+            double s = A[(size_t)(k0 + j) * n + i];
+#pragma unroll
+            for (int p = 0; p < j; ++p) s -= x[p] * T[p * kCholNb + j];
+            x[j] = s / T[j * kCholNb + j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kCholNb; ++j)
+        if (j < b) A[(size_t)(k0 + j) * n + i] = x[j];
+}
+
+// trailing update of the lower triangle of rows / columns r0.. (r0 = k0 + b)
+__global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ A, int n, int k0, int b, int ntile,
+                                                     const int *__restrict__ flag) {
+    if (*flag) return;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int T = (n - k0 - b + 15) / 16;
+    if (w >= ntile) return;
+    int ti = (int)((sqrt(8.0 * w + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= w) ++ti;
+    while (ti * (ti + 1) / 2 > w) --ti;
+    const int tj = w - ti * (ti + 1) / 2;
+    (void)T;
+    const int r0 = k0 + b + 16 * ti, c0 = k0 + b + 16 * tj;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < b; p += 4) {
+        const int kk = p + lk;
+        const double a = (kk < b && r0 + lr < n) ? A[(size_t)(k0 + kk) * n + r0 + lr] : 0.0;
+        const double bb = (kk < b && c0 + lr < n) ? A[(size_t)(k0 + kk) * n + c0 + lr] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+    }
+    // lane holds D[4 (lane / 16) + q][lane % 16], q = 0..3
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = r0 + 4 * lk + q, c = c0 + lr;
+        if (r < n && c < n && r >= c) A[(size_t)c * n + r] -= acc[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_upper(double *__restrict__ A, int n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    const int i = (int)(t % n), c = (int)(t / n);
+    if (i < c) A[t] = 0.0;
+}
+
 // W = G^{-1} one column per wavefront: forward substitution G w = e_c in
 // column order (w_k /= G_kk, then w_i -= G_ik w_k below), w kept in LDS.
 __global__ __launch_bounds__(256) void k_tri_inverse_cols(const double *__restrict__ G, int n,
@@ -840,13 +949,48 @@ struct Team {
     int *abort;             // raised when a wait times out
     unsigned target;        // arrivals expected at the next barrier
     double *partial;        // nblk * 8 doubles for team reductions
+    int local = 0;          // 1: every workgroup of the team sits on one XCD (one L2)
 };
 
 __device__ __forceinline__ Team single_team() {
-    return Team{(int)threadIdx.x, (int)blockDim.x, 0, 1, nullptr, nullptr, 0u, nullptr};
+    return Team{(int)threadIdx.x, (int)blockDim.x, 0, 1, nullptr, nullptr, 0u, nullptr, 0};
+}
+
+// Index of the XCD (accelerator complex die) this wavefront runs on.
+__device__ __forceinline__ unsigned xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;   // HW_REG_XCC_ID, bits 3:0
+}
+
+// Barrier of a team whose workgroups share one L2 (one XCD).  Every wave
+// waits until its stores are acknowledged by the L2; thread 0 then adds its
+// arrival with an atomic that executes in that L2 and polls the counter with
+// loads that read the L2 (workgroup-scope atomics: no L2 write-back or
+// invalidation, which only the scope of the whole device needs); after the
+// wait it invalidates the compute unit's L1 so that later loads see the
+// other workgroups' stores.  The wait is bounded (abort flag).
+__device__ void team_sync_local(Team &T) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    T.target += (unsigned)T.nblk;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(T.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        unsigned spins = 0;
+        while (__hip_atomic_load(T.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < T.target) {
+            if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (++spins > (1u << 22)) {
+                __hip_atomic_store(T.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __syncthreads();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 __device__ void team_sync(Team &T) {
+    if (T.local) { team_sync_local(T); return; }
     __syncthreads();
     if (T.nblk > 1) {
         T.target += (unsigned)T.nblk;
@@ -1085,6 +1229,50 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
         team_sync(tm);
         wg_relax<K, T>(tm, L, mu_post);
     }
+}
+
+// ----------------------------------------------- one-XCD team V-cycle
+// Alg. "V-cycle" from level `first` down to the coarsest and back by m
+// workgroups that share one XCD (one L2), meeting at L2-local team barriers
+// instead of kernel boundaries.  The grid has 8 m workgroups; they are handed
+// to the 8 XCDs in turn, so every XCD receives m of them.  The first
+// workgroup to start claims its XCD for the team (cb[0] = xcc + 1), the
+// workgroups of that XCD take ranks 0..m-1 from cb[1], all others return.
+// cb[32] is the barrier counter (a cache line of its own: it lives in that
+// XCD's L2 while cb[0..1] are updated at device scope); cb[0..63] are zero
+// before the launch.  A team that
+// does not come together (a barrier wait that times out) raises flag[0].
+template <int K, typename T>
+__global__ __launch_bounds__(1024) void k_team_vcycle(const TailLevel<T> *__restrict__ lv, int first, int nlev,
+                                                      int mu_pre, int mu_post, const double *__restrict__ Ainv,
+                                                      unsigned *__restrict__ cb, int *__restrict__ flag, int m) {
+    __shared__ int s_rank;
+    if (threadIdx.x == 0) {
+        const unsigned mine = xcc_id() + 1u;
+        unsigned expect = 0u;
+        __hip_atomic_compare_exchange_strong(cb, &expect, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned owner = expect == 0u ? mine : expect;   // expect holds the winner when the exchange failed
+        int rank = -1;
+        if (owner == mine) {
+            rank = (int)__hip_atomic_fetch_add(cb + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (rank >= m) rank = -1;
+        }
+        s_rank = rank;
+    }
+    __syncthreads();
+    if (s_rank < 0) return;
+    Team tm;
+    tm.rank = s_rank;
+    tm.nblk = m;
+    tm.tid = tm.rank * (int)blockDim.x + (int)threadIdx.x;
+    tm.nthreads = m * (int)blockDim.x;
+    tm.ctr = cb + 32;
+    tm.abort = flag;
+    tm.target = 0u;
+    tm.partial = nullptr;
+    tm.local = 1;
+    wg_vcycle<K, T>(tm, lv, first, nlev, mu_pre, mu_post, Ainv);
 }
 
 // ------------------------------------------------------ LDS-resident tail
@@ -1968,6 +2156,19 @@ hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double 
 
 hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (n > 256) {   // many compute units, the trailing updates on the FP64 matrix cores
+        for (int k0 = 0; k0 < n; k0 += kCholNb) {
+            const int b = min(kCholNb, n - k0), m = n - k0 - b;
+            k_chol_diag<<<1, 256, 0, st>>>(A, n, k0, b, flag);
+            if (m > 0) {
+                k_chol_panel<<<(m + 255) / 256, 256, 0, st>>>(A, n, k0, b, flag);
+                const int T = (m + 15) / 16, ntile = T * (T + 1) / 2;
+                k_chol_update<<<(ntile + 3) / 4, 256, 0, st>>>(A, n, k0, b, ntile, flag);
+            }
+        }
+        k_zero_upper<<<(int)(((int64_t)n * n + 255) / 256), 256, 0, st>>>(A, n);
+        return hipGetLastError();
+    }
     int nb = 16;   // panel width: the panel (n x nb doubles) must fit 128 KB of LDS
     while (nb > 1 && (size_t)n * nb * sizeof(double) > 128 * 1024) nb >>= 1;
     const size_t lds = (size_t)n * nb * sizeof(double);
@@ -2114,6 +2315,19 @@ hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
     else k_batch_solve<1024><<<nblocks_total, 1024, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_team_vcycle(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
+                              const double *Ainv, unsigned *cb, int *flag, int m, int k, hipStream_t st) {
+    k_fill<unsigned><<<1, kBlock, 0, st>>>(cb, 0u, 64);   // election, ranks, barrier counter
+    SMG_K_SWITCH(k, (k_team_vcycle<KK, T><<<8 * m, 1024, 0, st>>>(lv, first, nlev, mu_pre, mu_post, Ainv, cb,
+                                                                    flag, m)));
+    return hipGetLastError();
+}
+template hipError_t launch_team_vcycle<float>(const TailLevel<float> *, int, int, int, int, const double *,
+                                              unsigned *, int *, int, int, hipStream_t);
+template hipError_t launch_team_vcycle<double>(const TailLevel<double> *, int, int, int, int, const double *,
+                                               unsigned *, int *, int, int, hipStream_t);
 
 int batch_blocks_per_cu(int threads) {
     int occ = 0;

@@ -10,7 +10,38 @@
 #include "kernels.h"
 #include "smg.h"
 
+struct smg_ctx_s {
+    int device = 0;
+    smg_alloc_fn alloc = nullptr;
+    smg_free_fn free = nullptr;
+    void *user = nullptr;
+};
+
 namespace smg {
+
+// Device buffers owned by a solver or a batch: taken from the context's
+// allocator (hipMalloc when it has none) and all returned on destruction.
+struct DevMem {
+    smg_ctx_s ctx;
+    std::vector<std::pair<void *, size_t>> blocks;
+    void *take(size_t bytes) {
+        void *p = nullptr;
+        if (ctx.alloc) {
+            p = ctx.alloc(bytes, ctx.user);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+        }
+        if (p) blocks.push_back({p, bytes});
+        return p;
+    }
+    void release_all() {
+        for (auto &b : blocks) {
+            if (ctx.free) ctx.free(b.first, b.second, ctx.user);
+            else (void)hipFree(b.first);
+        }
+        blocks.clear();
+    }
+};
 
 struct DevLevel {
     int n = 0, ncolors = 0, nslices = 0, lpr = 1;
@@ -95,6 +126,12 @@ struct smg_solver_s {
     int32_t *tpass = nullptr;                  // pass table of all tail levels
     int32_t *twave = nullptr;                  // wavefront table of all tail levels
     std::vector<size_t> tail_lds[2][5];        // LDS bytes of a tail from level l
+    // one-XCD team V-cycle from team_level (0: off), team_size workgroups,
+    // levels as TailLevel descriptors, its barrier counter
+    int team_level = 0, team_size = 16;
+    smg::TailLevel<double> *team64 = nullptr;
+    smg::TailLevel<float> *team32 = nullptr;
+    unsigned *team_ctr = nullptr;
     bool values_set = false;
     std::vector<smg::DevLevel> lev;
     smg::MeshDev mesh;
@@ -110,7 +147,7 @@ struct smg_solver_s {
     // (n x 4 each) and column scalars: r.z at [0] / [8] (alternating), p.Ap at [16]
     double *cg_x = nullptr, *cg_p = nullptr, *cg_ap = nullptr, *cg_s = nullptr;
     int *h_flag = nullptr;         // pinned
-    std::vector<void *> owned;
+    smg::DevMem owned;               // every device buffer of the solver
     std::vector<smg::CycleGraph> graphs;
     hipStream_t gstream = nullptr;  // capture/replay stream for cycle graphs
     // per-launch profiling
@@ -121,6 +158,14 @@ struct smg_solver_s {
     double prof_ms = 0.0, prof_bytes = 0.0;
     int64_t prof_launches = 0;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // phase timing of a solve (smg_solve_params.timed): an event at every
+    // change of phase, tagged with the phase it starts
+    bool ph_on = false;
+    int ph_cur = -1;
+    std::vector<hipEvent_t> ph_pool;
+    std::vector<int> ph_tag;
+    double ms_prepare = 0.0;                     // device time of the last value refresh
+    hipEvent_t ev_prep0 = nullptr, ev_prep1 = nullptr;
     ~smg_solver_s();
 };
 
@@ -145,6 +190,11 @@ smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st
 int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st);
 hipEvent_t prof_ev(smg_solver_s *s, int idx, int which);
 smg_status prof_collect(smg_solver_s *s);
+// phase timing: phase_mark records an event on st when the phase changes
+// (timed solves only); phase_sum closes the record and adds the intervals
+// between the events into ms[SMG_PHASE_*]
+void phase_mark(smg_solver_s *s, hipStream_t st, int phase);
+smg_status phase_sum(smg_solver_s *s, hipStream_t st, double *ms);
 smg_status smg_solve_single_level(smg_solver_s *s, const double *d_b, double *d_x, int k,
                                   const smg_solve_params *p, smg_solve_info *info,
                                   hipStream_t st);

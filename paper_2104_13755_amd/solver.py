@@ -56,6 +56,23 @@ def mesh_pattern(n, F):
     return rowptr, cols
 
 
+def host_assemble(V, F, rowptr=None, cols=None):
+    """Cotangent Laplacian values (CSR order of the mesh pattern) and lumped
+    mass on the host (smg_pre_assemble).  Returns (rowptr, cols, L_vals, M)."""
+    lib = L.load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    if rowptr is None:
+        rowptr, cols = mesh_pattern(len(V), F)
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    lv = np.zeros(len(cols))
+    m = np.zeros(len(V))
+    L.check(lib.smg_pre_assemble(_np_ptr(V), len(V), _np_ptr(F), len(F), _np_ptr(rowptr), _np_ptr(cols),
+                                 _np_ptr(lv), _np_ptr(m)), "pre_assemble")
+    return rowptr, cols, lv, m
+
+
 def color_pattern(rowptr, cols):
     """Greedy coloring of a CSR pattern's off-diagonal graph (host)."""
     lib = L.load()
@@ -128,22 +145,18 @@ class Hierarchy:
         return cols, w
 
     def save(self, path):
-        """Write the prolongations to an .npz file (no pickled objects): the
-        precompute depends on the geometry only, so a saved hierarchy serves
-        every later system on the same mesh."""
-        arrays = {"sizes": np.asarray(self.sizes, dtype=np.int32)}
-        for l in range(self.num_levels - 1):
-            arrays[f"pcols{l}"], arrays[f"pw{l}"] = self.prolongation(l)
-        np.savez(path, **arrays)
+        """Write the hierarchy (smg_hier_save: versioned binary file with a
+        checksum): the precompute depends on the geometry only, so a saved
+        hierarchy serves every later system on the same mesh."""
+        L.check(self._lib.smg_hier_save(self._h, str(path).encode()), "hier_save")
 
     @classmethod
     def load(cls, path):
-        """Hierarchy from a file written by save() (statistics are not kept)."""
-        with np.load(path, allow_pickle=False) as z:
-            sizes = z["sizes"]
-            nl = len(sizes)
-            return cls.from_prolongations(sizes, [z[f"pcols{l}"] for l in range(nl - 1)],
-                                          [z[f"pw{l}"] for l in range(nl - 1)])
+        """Hierarchy from a file written by save() (smg_hier_load)."""
+        lib = L.load()
+        h = _c()
+        L.check(lib.smg_hier_load(str(path).encode(), ctypes.byref(h)), "hier_load")
+        return cls(h)
 
     def stats(self, l):
         s = np.zeros(8)
@@ -205,6 +218,46 @@ class DirichletSystem:
         return uv, (rhs if b.dim() == 2 else rhs[:, 0])
 
 
+class TorchAllocator:
+    """A library context whose device buffers come from torch's caching
+    allocator (smg_ctx_create with caller functions): solver and batch
+    buffers then show in torch's memory statistics and are reused by it
+    once the solver is destroyed.  Keep it alive while its solvers live
+    (each Solver made with it holds a reference)."""
+
+    def __init__(self, device=0):
+        self._lib = L.load()
+        self.device = int(device)
+        self.live = {}                       # pointer -> bytes, for statistics
+        self._alloc = L.ALLOC_FN(self._take)
+        self._free = L.FREE_FN(self._give)
+        h = _c()
+        L.check(self._lib.smg_ctx_create(self.device, self._alloc, self._free, None, ctypes.byref(h)), "ctx_create")
+        self._ctx = h
+
+    def _take(self, nbytes, user):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                   torch.cuda.current_stream(self.device))
+        except Exception:
+            return None
+        self.live[p] = int(nbytes)
+        return p
+
+    def _give(self, p, nbytes, user):
+        self.live.pop(p, None)
+        torch.cuda.caching_allocator_delete(p)
+
+    @property
+    def bytes_in_use(self):
+        return sum(self.live.values())
+
+    def __del__(self):
+        if getattr(self, "_ctx", None):
+            self._lib.smg_ctx_destroy(self._ctx)
+            self._ctx = None
+
+
 PRECISION = {"fp64": L.SMG_FP64, "fp32ir": L.SMG_FP32_IR}
 SMOOTHER = {"gs": L.SMG_SMOOTH_GS, "jacobi": L.SMG_SMOOTH_JACOBI}
 
@@ -213,11 +266,13 @@ class Solver:
     """Device-resident multigrid solver of one mesh."""
 
     def __init__(self, hier, rowptr, cols, device=0, mu_pre=2, mu_post=2, faces=None,
-                 tail_rows=0, lanes_per_row=None):
+                 tail_rows=0, lanes_per_row=None, allocator=None, team_level=0, team_size=0):
         """Upload a hierarchy for the level-0 CSR pattern (rowptr, cols: host
         int32, diagonal present, columns ascending).  Builds colorings,
         layouts and the symbolic Galerkin plans; `faces` enables assemble().
-        tail_rows / lanes_per_row are launch shapes (0 = defaults)."""
+        tail_rows / lanes_per_row are launch shapes (0 = defaults).
+        allocator: a TorchAllocator to take the device buffers from torch's
+        caching allocator (default: the library's hipMalloc)."""
         self._lib = L.load()
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         cols = np.ascontiguousarray(cols, dtype=np.int32)
@@ -227,9 +282,17 @@ class Solver:
         self.device = device
         lpr = list(lanes_per_row or [])
         o = L.Opts(int(mu_pre), int(mu_post), int(tail_rows),
-                   (ctypes.c_int32 * 16)(*(lpr + [0] * (16 - len(lpr)))))
+                   (ctypes.c_int32 * 16)(*(lpr + [0] * (16 - len(lpr)))), int(team_level), int(team_size))
         h = _c()
-        L.check(self._lib.smg_solver_create(device, hier._h, _np_ptr(rowptr), _np_ptr(cols), ctypes.byref(o), ctypes.byref(h)), "solver_create")
+        self.allocator = allocator
+        if allocator is not None:
+            if allocator.device != device:
+                raise ValueError("the allocator's device differs from the solver's")
+            L.check(self._lib.smg_solver_create_ctx(allocator._ctx, hier._h, _np_ptr(rowptr), _np_ptr(cols),
+                                                    ctypes.byref(o), ctypes.byref(h)), "solver_create")
+        else:
+            L.check(self._lib.smg_solver_create(device, hier._h, _np_ptr(rowptr), _np_ptr(cols), ctypes.byref(o),
+                                                ctypes.byref(h)), "solver_create")
         self._s = h
         if faces is not None:
             F = np.ascontiguousarray(faces, dtype=np.int32)
@@ -323,21 +386,25 @@ class Solver:
 
     # ---- solve ----------------------------------------------------------
     def solve(self, b, rtol=1e-8, max_cycles=100, precision="fp64", fixed_cycles=0,
-              use_graph=False, raise_on_error=True):
+              use_graph=False, raise_on_error=True, timed=False):
         """V-cycles from x = 0 until every column's relative residual is at most
         rtol (or exactly fixed_cycles).  b: n or n x k (k <= 4) float64 on the
         device.  precision "fp32ir" runs FP32 cycles inside FP64 iterative
-        refinement.  Returns (x, info) with info cycles, rel_res, ms."""
+        refinement.  Returns (x, info) with info cycles, rel_res, ms and
+        ms_phase (device ms per phase of Tab. "profile": prepare = the last
+        value refresh, and with timed=True relax, transfer, norm, other)."""
         b2 = b if b.dim() == 2 else b.unsqueeze(1)
         b2 = b2.contiguous()
         k = self._vecs(self.n, ("b", b2))
         x = torch.empty_like(b2)
-        p = L.SolveParams(float(rtol), int(max_cycles), PRECISION[precision], int(fixed_cycles), int(bool(use_graph)))
+        p = L.SolveParams(float(rtol), int(max_cycles), PRECISION[precision], int(fixed_cycles), int(bool(use_graph)),
+                          int(bool(timed)))
         info = L.SolveInfo()
         st = self._lib.smg_solve(self._s, _t_ptr(b2), _t_ptr(x), k, ctypes.byref(p), ctypes.byref(info), _stream())
         if raise_on_error:
             L.check(st, "solve")
-        out = dict(status=st, cycles=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms)
+        out = dict(status=st, cycles=info.cycles, rel_res=list(info.rel_res)[:k], ms=info.ms,
+                   ms_phase=dict(zip(L.PHASES, list(info.ms_phase))))
         return (x if b.dim() == 2 else x[:, 0]), out
 
     def split_prepare(self, q_vals, m_vals):
@@ -369,7 +436,7 @@ class Solver:
         b2 = b2.contiguous()
         k = self._vecs(self.n, ("b", b2))
         x = torch.empty_like(b2)
-        p = L.SolveParams(float(rtol), int(max_iters), PRECISION[precision], int(fixed_iters), 0)
+        p = L.SolveParams(float(rtol), int(max_iters), PRECISION[precision], int(fixed_iters), 0, 0)
         info = L.SolveInfo()
         st = self._lib.smg_pcg_solve(self._s, _t_ptr(b2), _t_ptr(x), k, ctypes.byref(p), ctypes.byref(info), _stream())
         if raise_on_error:

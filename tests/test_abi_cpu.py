@@ -17,13 +17,14 @@ HEADER = os.path.join(ROOT, "include", "smg.h")
 
 STRUCTS = {
     "smg_pre_opts": ("PreOpts", ["n_levels", "min_coarse", "collapses"]),
-    "smg_opts": ("Opts", ["mu_pre", "mu_post", "tail_rows", "lanes_per_row"]),
-    "smg_solve_params": ("SolveParams", ["rtol", "max_cycles", "precision", "fixed_cycles", "use_graph"]),
-    "smg_solve_info": ("SolveInfo", ["cycles", "k", "rel_res", "ms"]),
+    "smg_opts": ("Opts", ["mu_pre", "mu_post", "tail_rows", "lanes_per_row", "team_level", "team_size"]),
+    "smg_solve_params": ("SolveParams", ["rtol", "max_cycles", "precision", "fixed_cycles", "use_graph", "timed"]),
+    "smg_solve_info": ("SolveInfo", ["cycles", "k", "rel_res", "ms", "ms_phase"]),
     "smg_batch_opts": ("BatchOpts", ["threads", "lanes_level0", "lanes_coarse", "team_max", "cache_file"]),
 }
 CONSTANTS = ["SMG_OK", "SMG_FP64", "SMG_FP32_IR", "SMG_SMOOTH_GS", "SMG_SMOOTH_JACOBI",
              "SMG_COLLAPSE_ALL", "SMG_COLLAPSE_INTERIOR", "SMG_COLLAPSE_STRAIGHT",
+             "SMG_PHASE_PREPARE", "SMG_PHASE_RELAX", "SMG_PHASE_TRANSFER", "SMG_PHASE_NORM", "SMG_PHASE_OTHER",
              "SMG_ERR_INVALID_ARG", "SMG_ERR_OOM", "SMG_ERR_HIP", "SMG_ERR_NOT_SPD",
              "SMG_ERR_NO_CONVERGENCE", "SMG_ERR_NONFINITE", "SMG_ERR_STATE", "SMG_ERR_PRECOMPUTE"]
 
@@ -73,6 +74,7 @@ def test_constants_match(c_layout):
     for k in CONSTANTS:
         if k.startswith("SMG_ERR_"):
             assert L.STATUS[c_layout[("const", k)]] == k[len("SMG_ERR_"):], k
+    assert [c_layout[("const", "SMG_PHASE_" + p.upper())] for p in L.PHASES] == [0, 1, 2, 3, 4]
     from paper_2104_13755_amd import solver
     assert solver.PRECISION == {"fp64": c_layout[("const", "SMG_FP64")],
                                 "fp32ir": c_layout[("const", "SMG_FP32_IR")]}
@@ -99,7 +101,7 @@ def _kind_c(decl):
     if "*" in d:
         return "ptr"
     base = d.replace("const ", "").split()[0]
-    if base in ("smg_hier", "smg_solver", "smg_batch", "smg_stream"):
+    if base in ("smg_hier", "smg_solver", "smg_batch", "smg_stream", "smg_ctx", "smg_alloc_fn", "smg_free_fn"):
         return "ptr"
     return {"int32_t": "i32", "smg_status": "i32", "int64_t": "i64", "double": "f64", "void": "void"}[base]
 
@@ -113,7 +115,7 @@ def _kind_py(t):
         return "i64"
     if t is ctypes.c_double:
         return "f64"
-    if t in (ctypes.c_void_p, ctypes.c_char_p) or issubclass(t, (ctypes._Pointer, ctypes.c_void_p)):
+    if t in (ctypes.c_void_p, ctypes.c_char_p) or issubclass(t, (ctypes._Pointer, ctypes.c_void_p, ctypes._CFuncPtr)):
         return "ptr"
     raise AssertionError(t)
 

@@ -206,3 +206,20 @@ def _shape_problem():
     if not _SHAPE_PROBLEM:
         _SHAPE_PROBLEM.append(Problem("heightfield-70x66", n_levels=5))
     return _SHAPE_PROBLEM[0]
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_coarsest_factor_many_workgroups(levels):
+    """Coarsest levels of 2,561 and 640 rows take the blocked factorization
+    over many workgroups (diagonal block, panel solve, trailing update on the
+    FP64 matrix cores): factor within 1e-12 of numpy's Cholesky of the
+    oracle's A_H, coarsest solve within 1e-12."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    p = Problem("icosphere-L5", n_levels=levels)
+    S = p.gpu_solver()
+    O = p.oracle
+    assert S.level_size(S.num_levels - 1) == O.A[-1].shape[0] == (2561 if levels == 2 else 640)
+    assert rel(S.coarse_factor(), O.G) < 1e-12
+    bc = np.random.default_rng(9).uniform(-1, 1, (O.A[-1].shape[0], 2))
+    assert rel(_np(S.coarse_solve(_t(bc))), O.coarse_solve(bc)) < 1e-12

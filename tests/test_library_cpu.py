@@ -97,11 +97,16 @@ def test_flat_closed_form_product(collapses):
 
 
 def test_hierarchy_save_load_round_trip(tmp_path):
+    """smg_hier_save / smg_hier_load through the C ABI: sizes, every P_l and
+    the decimation statistics come back bitwise; hierarchies without
+    positions too; a truncated, altered or foreign file is refused."""
+    import ctypes
+    from paper_2104_13755_amd import _lib as L
     from paper_2104_13755_amd.solver import Hierarchy
     rng = np.random.default_rng(4)
     V, F = synth.disc_grid(40, 37, rng, 0.1, height=lambda x, y: 0.1 * np.sin(3 * x))
     h = Hierarchy.build(V, F, n_levels=4)
-    path = tmp_path / "hier.npz"
+    path = tmp_path / "hier.smg"
     h.save(path)
     g = Hierarchy.load(path)
     assert g.sizes == h.sizes
@@ -109,6 +114,23 @@ def test_hierarchy_save_load_round_trip(tmp_path):
         c0, w0 = h.prolongation(l)
         c1, w1 = g.prolongation(l)
         assert np.array_equal(c0, c1) and np.array_equal(w0, w1)
+        assert h.stats(l) == g.stats(l)
+    # a hierarchy given as prolongations (no positions) round-trips as well
+    e = Hierarchy.from_prolongations(h.sizes, *zip(*[h.prolongation(l) for l in range(h.num_levels - 1)]))
+    e.save(tmp_path / "ext.smg")
+    e2 = Hierarchy.load(tmp_path / "ext.smg")
+    assert e2.sizes == h.sizes and np.array_equal(e2.prolongation(2)[1], h.prolongation(2)[1])
+    lib = L.load()
+    raw = path.read_bytes()
+    bad = {"truncated": raw[:-9], "altered": raw[:100] + bytes([raw[100] ^ 1]) + raw[101:],
+           "foreign": b"NOTAHIER" + raw[8:], "trailing": raw + b"x"}
+    for name, data in bad.items():
+        q = tmp_path / (name + ".smg")
+        q.write_bytes(data)
+        out = ctypes.c_void_p()
+        st = lib.smg_hier_load(str(q).encode(), ctypes.byref(out))
+        assert st == -1 and not out.value, name
+    assert lib.smg_hier_load(str(tmp_path / "missing.smg").encode(), ctypes.byref(ctypes.c_void_p())) == -1
 
 
 def test_coloring_matches_oracle():
@@ -347,3 +369,36 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     out = json.loads(r.stdout.strip().splitlines()[-1])
     assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+@pytest.mark.parametrize("mesh", ["icosphere", "disc", "heightfield"])
+def test_host_assembly_matches_oracle(mesh):
+    """smg_pre_assemble (faces scattered one by one) against the oracle's
+    cotangent Laplacian and lumped mass (vectorised numpy), on closed and
+    bounded meshes: 1e-13 of the largest entry; bad input is refused."""
+    import ctypes
+    from paper_2104_13755_amd import _lib as L
+    from paper_2104_13755_amd.solver import host_assemble
+    rng = np.random.default_rng(8)
+    if mesh == "icosphere":
+        V, F = synth.small_icosphere(4, seed=3, sigma=0.01)
+    elif mesh == "disc":
+        V, F = synth.flat_disc(40, seed=4, jitter=0.1)
+    else:
+        V, F = synth.disc_grid(40, 38, rng, 0.1, height=lambda x, y: 0.1 * np.sin(3 * x) * np.cos(2 * y))
+    rp, ci, lv, m = host_assemble(V, F)
+    _, Lo, mo = AS.system(V, F, 1.0)
+    assert np.array_equal(rp, Lo.indptr) and np.array_equal(ci, Lo.indices)
+    assert abs(lv - Lo.data).max() < 1e-13 * abs(Lo.data).max()
+    assert abs(m - mo).max() < 1e-15 * mo.max()
+    lib = L.load()
+    Fb = np.ascontiguousarray(F.copy(), dtype=np.int32)
+    Fb[3, 1] = len(V)
+    out_l, out_m = np.zeros(len(ci)), np.zeros(len(V))
+    Vc = np.ascontiguousarray(V)
+    assert lib.smg_pre_assemble(Vc.ctypes.data, len(V), Fb.ctypes.data, len(F), rp.ctypes.data, ci.ctypes.data,
+                                out_l.ctypes.data, out_m.ctypes.data) == -1
+    rp2 = rp.copy()
+    rp2[0] = 1
+    assert lib.smg_pre_assemble(Vc.ctypes.data, len(V), np.ascontiguousarray(F, dtype=np.int32).ctypes.data, len(F),
+                                rp2.ctypes.data, ci.ctypes.data, out_l.ctypes.data, out_m.ctypes.data) == -1
