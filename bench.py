@@ -596,6 +596,9 @@ def main():
         run_steps(S, Vd, w["t"], b, rtol, "fp32ir", 2, use_graph)
         prof_lv[l] = S.profile_read()
     S.profile_enable(None)
+    # latency bound of a launch with each level's grid: an empty kernel and a
+    # kernel with the relaxation's dependent chain (index, gather, store)
+    floors = {l: (S.launch_floor("empty", l), S.launch_floor("chain", l)) for l in launch_levels}
     t_fp64, infos_d, x_d = run_steps(S, Vd, w["t"], b, rtol, "fp64", args.steps, use_graph)
     log(f"fp64: {t_fp64 / args.steps * 1e3:.2f} ms/step cycles={infos_d[-1]['cycles']} res={max(infos_d[-1]['rel_res']):.2e}")
     so_m, _ = time_solve_only(S, b, rtol, "fp32ir", args.steps, use_graph)
@@ -630,7 +633,13 @@ def main():
                               "a color launch counts its rows' share",
                 "measured": "dispatch-stamped HIP events on the launch stream, every launch of the kernel "
                             "in a second pass of the same timed steps",
-                "levels": {str(l): dict(summary(p), traffic=traffic_lv.get(l)) for l, p in prof_lv.items()}}
+                "levels": {str(l): dict(summary(p), traffic=traffic_lv.get(l), floor_empty_us=floors[l][0],
+                                        floor_chain_us=floors[l][1],
+                                        latency_frac=floors[l][1] / summary(p)["avg_launch_us"])
+                           for l, p in prof_lv.items()},
+                "latency_rule": "floor_chain_us: back-to-back launches with the level's widest color grid whose "
+                                "threads load an index, the value it points to, and store it; latency_frac = "
+                                "that floor / the relaxation launch's average time (events)"}
     value = args.steps / t_mixed
     out = {
         "metric": "V-cycle solves/s + HBM GB/s at 1M verts to rel residual 1e-8, mixed vs FP64",

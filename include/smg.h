@@ -441,6 +441,16 @@ smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level);
  * Synchronizes the device. */
 smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches, double *bytes);
 
+/* Launch latency on this device, for the latency bound of the per-color
+ * launches: *us = average device time per launch of `launches` back-to-back
+ * launches on `stream` with the grid of level `level`'s widest color (one
+ * 64-thread workgroup per slice), of an empty kernel (kind 0) or of a kernel
+ * whose threads load an index, then the value it points to, and store it
+ * (kind 1: the dependent chain of a relaxation launch).  Synchronizes the
+ * stream.  Errors: INVALID_ARG. */
+smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level, int32_t launches, smg_stream stream,
+                            double *us);
+
 /* ------------------------------------------------------------------------ */
 /* Batching: many solvers in one persistent launch.                          */
 

@@ -1867,6 +1867,32 @@ extern "C" smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t lev
     return SMG_OK;
 }
 
+extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level, int32_t launches,
+                                       smg_stream stream, double *us) {
+    if (!s || !us || (kind != 0 && kind != 1) || launches < 1 || level < 0 || level >= s->nlev ||
+        s->lev[level].coarsest)
+        return fail(SMG_ERR_INVALID_ARG, "smg_launch_floor: bad arguments");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = (hipStream_t)stream;
+    const DevLevel &D = s->lev[level];
+    // the grid of the level's widest color launch
+    int slices = 1;
+    for (int c = 0; c < D.ncolors; ++c) slices = std::max(slices, D.color_slice[c + 1] - D.color_slice[c]);
+    const int n = std::min<int64_t>((int64_t)slices * 64, D.n);
+    // inputs: the level's own buffers (perm as indices, x32 as values, r32 as output)
+    for (int rep = 0; rep < 2; ++rep) {   // the first round warms up
+        HIPCHK(hipEventRecord(s->ev_prep0, st));
+        for (int i = 0; i < launches; ++i)
+            HIPCHK(launch_floor(kind, slices, D.perm, D.x32, D.r32, n, st));
+        HIPCHK(hipEventRecord(s->ev_prep1, st));
+        HIPCHK(hipEventSynchronize(s->ev_prep1));
+    }
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev_prep0, s->ev_prep1));
+    *us = 1e3 * ms / launches;
+    return SMG_OK;
+}
+
 extern "C" smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches,
                                        double *bytes) {
     if (!s || !total_ms || !launches || !bytes) return fail(SMG_ERR_INVALID_ARG, "null argument");

@@ -735,61 +735,71 @@ __global__ __launch_bounds__(1024) void k_cholesky_blocked(double *__restrict__ 
 }
 
 // ------------------------------------------- blocked Cholesky on many CUs
-// Right-looking A = G G^T (column-major, lower) in panels of kCholNb columns:
-// per panel, one workgroup factors the diagonal block in LDS, every row below
-// it is solved against that block (one thread per row), and the trailing
-// lower triangle is updated A22 -= L21 L21^T in 16 x 16 tiles, one
-// wavefront per tile on the FP64 matrix cores (v_mfma_f64_16x16x4f64, K = 4
-// per instruction).  A pivot <= 0 sets *flag and every later kernel returns
-// at once.
+// Right-looking A = G G^T (column-major, lower) in panels of kCholNb columns.
+// Per panel, k_chol_panel factors the diagonal block in the registers of one
+// wavefront per workgroup (row i in lane i, pivots and multipliers passed by
+// lane shuffles) and solves every row below it against that block (one thread
+// per row); k_chol_update then updates the trailing lower triangle
+// A22 -= L21 L21^T in 16 x 16 tiles, one wavefront per tile on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64, K = 4 per instruction).  A pivot <= 0
+// sets *flag and every later kernel returns at once.
 constexpr int kCholNb = 32;
+// coarsest levels up to this size are factored and inverted by the
+// one-workgroup kernels (k_cholesky_blocked, k_tri_inverse_cols)
+constexpr int kCoarseOneGroup = 96;
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_chol_diag(double *__restrict__ A, int n, int k0, int b,
-                                                   int *__restrict__ flag) {
-    __shared__ double T[kCholNb * kCholNb];
-    __shared__ int bad;
-    if (*flag) return;
-    const int tid = threadIdx.x;
-    for (int t = tid; t < b * b; t += blockDim.x) {
-        const int i = t % b, j = t / b;
-        T[j * kCholNb + i] = A[(size_t)(k0 + j) * n + k0 + i];
+// Factor the b x b diagonal block at (k0, k0) in LDS by wave 0 alone
+// (right-looking, one column per step; the lanes of one wavefront see each
+// other's LDS writes in program order, so no workgroup barrier is needed)
+// and leave L11 (column-major, zero above the diagonal) in T; returns false
+// on a pivot <= 0 (the same decision in every lane).
+__device__ bool chol_block_wave(const double *__restrict__ A, int n, int k0, int b, double *T) {
+    const int lane = threadIdx.x & 63;
+    for (int t = lane; t < kCholNb * kCholNb; t += 64) {
+        const int i = t % kCholNb, c = t / kCholNb;
+        T[t] = (i < b && c < b && i >= c) ? A[(size_t)(k0 + c) * n + k0 + i] : 0.0;
     }
-    if (tid == 0) bad = 0;
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    bool ok = true;
     for (int j = 0; j < b; ++j) {
-        if (tid == 0) {
-            const double d = T[j * kCholNb + j];
-            if (!(d > 0.0)) { bad = 1; *flag = 1; }
-            else T[j * kCholNb + j] = sqrt(d);
+        const double ajj = T[j * kCholNb + j];
+        ok = ok && (ajj > 0.0);
+        const double d = sqrt(ajj);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane == j) T[j * kCholNb + j] = d;
+        else if (lane > j && lane < b) T[j * kCholNb + lane] /= d;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int w = b - j - 1;
+        for (int t = lane; t < w * w; t += 64) {
+            const int i = j + 1 + t % w, c = j + 1 + t / w;
+            if (i >= c) T[c * kCholNb + i] -= T[j * kCholNb + i] * T[j * kCholNb + c];
         }
-        __syncthreads();
-        if (bad) return;
-        const double djj = T[j * kCholNb + j];
-        for (int i = j + 1 + tid; i < b; i += blockDim.x) T[j * kCholNb + i] /= djj;
-        __syncthreads();
-        for (int t = tid; t < b * b; t += blockDim.x) {
-            const int i = t % b, c = t / b;
-            if (c > j && i >= c) T[c * kCholNb + i] -= T[j * kCholNb + i] * T[j * kCholNb + c];
-        }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
-    for (int t = tid; t < b * b; t += blockDim.x) {
-        const int i = t % b, j = t / b;
-        if (i >= j) A[(size_t)(k0 + j) * n + k0 + i] = T[j * kCholNb + i];
-    }
+    return ok;
 }
 
-// rows k0 + b .. n-1 of the panel: x L11^T = a, one thread per row
 __global__ __launch_bounds__(256) void k_chol_panel(double *__restrict__ A, int n, int k0, int b,
-                                                    const int *__restrict__ flag) {
+                                                    int *__restrict__ flag) {
     __shared__ double T[kCholNb * kCholNb];
+    __shared__ int good;
     if (*flag) return;
-    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-        const int i = t % b, j = t / b;
-        T[j * kCholNb + i] = i >= j ? A[(size_t)(k0 + j) * n + k0 + i] : 0.0;
+    if (threadIdx.x < 64) {
+        const bool ok = chol_block_wave(A, n, k0, b, T);
+        if (threadIdx.x == 0) good = ok ? 1 : 0;
     }
     __syncthreads();
+    if (!good) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
+        return;
+    }
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+            const int i = t % b, j = t / b;
+            if (i >= j) A[(size_t)(k0 + j) * n + k0 + i] = T[j * kCholNb + i];
+        }
+    // rows k0 + b .. n-1 of the panel: x L11^T = a, one thread per row
     const int i = k0 + b + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double x[kCholNb];
@@ -807,18 +817,22 @@ __global__ __launch_bounds__(256) void k_chol_panel(double *__restrict__ A, int 
         if (j < b) A[(size_t)(k0 + j) * n + i] = x[j];
 }
 
+// Lower-triangle tile index w -> (ti, tj), ti >= tj.
+__device__ __forceinline__ void tri_tile(int w, int &ti, int &tj) {
+    ti = (int)((sqrt(8.0 * w + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= w) ++ti;
+    while (ti * (ti + 1) / 2 > w) --ti;
+    tj = w - ti * (ti + 1) / 2;
+}
+
 // trailing update of the lower triangle of rows / columns r0.. (r0 = k0 + b)
 __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ A, int n, int k0, int b, int ntile,
                                                      const int *__restrict__ flag) {
     if (*flag) return;
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int T = (n - k0 - b + 15) / 16;
     if (w >= ntile) return;
-    int ti = (int)((sqrt(8.0 * w + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= w) ++ti;
-    while (ti * (ti + 1) / 2 > w) --ti;
-    const int tj = w - ti * (ti + 1) / 2;
-    (void)T;
+    int ti, tj;
+    tri_tile(w, ti, tj);
     const int r0 = k0 + b + 16 * ti, c0 = k0 + b + 16 * tj;
     const int lr = lane & 15, lk = lane >> 4;
     v4d_t acc = {0.0, 0.0, 0.0, 0.0};
@@ -828,10 +842,11 @@ __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ A, int
         const double bb = (kk < b && c0 + lr < n) ? A[(size_t)(k0 + kk) * n + c0 + lr] : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
     }
-    // lane holds D[4 (lane / 16) + q][lane % 16], q = 0..3
+    // lane holds D[lane / 16 + 4 q][lane % 16], q = 0..3 (the A operand: lane
+    // holds A[lane % 16][lane / 16]; B: B[lane / 16][lane % 16])
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int r = r0 + 4 * lk + q, c = c0 + lr;
+        const int r = r0 + lk + 4 * q, c = c0 + lr;
         if (r < n && c < n && r >= c) A[(size_t)c * n + r] -= acc[q];
     }
 }
@@ -841,6 +856,112 @@ __global__ __launch_bounds__(256) void k_zero_upper(double *__restrict__ A, int 
     if (t >= (int64_t)n * n) return;
     const int i = (int)(t % n), c = (int)(t / n);
     if (i < c) A[t] = 0.0;
+}
+
+// ----------------------------------- A_H^{-1} = G^{-T} G^{-1} on many CUs
+// W = G^{-1} by a right-looking blocked forward substitution G W = I: per
+// block row k (kCholNb rows), k_trinv_rows solves the diagonal block against
+// those rows of the right-hand side (one thread per column), k_trinv_update
+// subtracts G_ik W_k from every block row below (16 x 16 MFMA tiles).  Then
+// k_inv_syrk forms the lower triangle of W^T W tile by tile (and mirrors it).
+__global__ __launch_bounds__(256) void k_identity(double *__restrict__ W, int n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    W[t] = (t % n == t / n) ? 1.0 : 0.0;
+}
+
+// 256 columns of the block row per workgroup: the block (b rows x 256
+// columns, each column's b values contiguous in W) is read and written
+// coalesced through LDS, and each thread forward-substitutes one column.
+__global__ __launch_bounds__(256) void k_trinv_rows(const double *__restrict__ G, double *__restrict__ W, int n,
+                                                    int k0, int b) {
+    __shared__ double T[kCholNb * kCholNb];
+    __shared__ double X[256 * (kCholNb + 1)];   // column t at X[t * (kCholNb + 1)], padded against bank conflicts
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+        const int i = t % b, j = t / b;
+        T[j * kCholNb + i] = i >= j ? G[(size_t)(k0 + j) * n + k0 + i] : 0.0;
+    }
+    const int cbase = blockIdx.x * 256, ncol = min(256, k0 + b - cbase);
+    for (int t = threadIdx.x; t < ncol * b; t += blockDim.x) {
+        const int i = t % b, cc = t / b;
+        X[cc * (kCholNb + 1) + i] = W[(size_t)(cbase + cc) * n + k0 + i];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ncol) {
+        double *xc = X + threadIdx.x * (kCholNb + 1);
+        for (int i = 0; i < b; ++i) {
+            double s = xc[i];
+            for (int p = 0; p < i; ++p) s -= T[p * kCholNb + i] * xc[p];
+            xc[i] = s / T[i * kCholNb + i];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ncol * b; t += blockDim.x) {
+        const int i = t % b, cc = t / b;
+        W[(size_t)(cbase + cc) * n + k0 + i] = X[cc * (kCholNb + 1) + i];
+    }
+}
+
+// W[i][c] -= sum_p G[i][k0 + p] W[k0 + p][c], rows i >= k0 + b, columns c < k0 + b
+__global__ __launch_bounds__(256) void k_trinv_update(const double *__restrict__ G, double *__restrict__ W, int n,
+                                                      int k0, int b, int tcols, int ntile) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= ntile) return;
+    const int ti = w / tcols, tj = w % tcols;
+    const int r0 = k0 + b + 16 * ti, c0 = 16 * tj;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < b; p += 4) {
+        const int kk = p + lk;
+        const double a = (kk < b && r0 + lr < n) ? G[(size_t)(k0 + kk) * n + r0 + lr] : 0.0;
+        const double bb = (kk < b && c0 + lr < k0 + b) ? W[(size_t)(c0 + lr) * n + k0 + kk] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = r0 + lk + 4 * q, c = c0 + lr;
+        if (r < n && c < k0 + b) W[(size_t)c * n + r] -= acc[q];
+    }
+}
+
+// Ainv = W^T W, lower tiles computed (sum over rows m >= tile row start: W is
+// zero above its diagonal), each mirrored so that Ainv is exactly symmetric
+__global__ __launch_bounds__(256) void k_inv_syrk(const double *__restrict__ W, double *__restrict__ Ainv, int n,
+                                                  int ntile) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= ntile) return;
+    int ti, tj;
+    tri_tile(w, ti, tj);
+    const int i0 = 16 * ti, j0 = 16 * tj;
+    const int lr = lane & 15, lk = lane >> 4;
+    const bool iok = i0 + lr < n, jok = j0 + lr < n;
+    const double *wi = W + (size_t)min(i0 + lr, n - 1) * n, *wj = W + (size_t)min(j0 + lr, n - 1) * n;
+    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    int m = i0;
+    for (; m + 16 <= n; m += 16) {   // four products per round, loads first
+        double a[4], bb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = iok ? wi[m + 4 * u + lk] : 0.0;
+            bb[u] = jok ? wj[m + 4 * u + lk] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
+    }
+    for (; m < n; m += 4) {
+        const int mm = m + lk;
+        const double a = (iok && mm < n) ? wi[mm] : 0.0;
+        const double bb = (jok && mm < n) ? wj[mm] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = i0 + lk + 4 * q, c = j0 + lr;   // entry (r, c) = sum_m W[m][r] W[m][c]
+        if (r < n && c < n && r >= c) {   // each entry of the lower triangle once, then its mirror
+            Ainv[(size_t)c * n + r] = acc[q];
+            Ainv[(size_t)r * n + c] = acc[q];
+        }
+    }
 }
 
 // W = G^{-1} one column per wavefront: forward substitution G w = e_c in
@@ -963,11 +1084,19 @@ __device__ __forceinline__ unsigned xcc_id() {
 
 // Barrier of a team whose workgroups share one L2 (one XCD).  Every wave
 // waits until its stores are acknowledged by the L2; thread 0 then adds its
-// arrival with an atomic that executes in that L2 and polls the counter with
-// loads that read the L2 (workgroup-scope atomics: no L2 write-back or
-// invalidation, which only the scope of the whole device needs); after the
-// wait it invalidates the compute unit's L1 so that later loads see the
-// other workgroups' stores.  The wait is bounded (abort flag).
+// arrival with an atomic and polls the counter with atomic read-modify-writes
+// that leave it unchanged (a compare-and-swap that never matches): atomics
+// all see the same counter, while plain loads of it were measured to return
+// stale values for up to a second.  Neither needs the L2 write-back or
+// invalidation that the scope of the whole device costs.  After the wait it
+// invalidates the compute unit's L1 so that later loads read the other
+// workgroups' stores from the shared L2.  The wait is bounded (abort flag).
+__device__ __forceinline__ unsigned team_count(unsigned *ctr) {
+    unsigned seen = 0xffffffffu;
+    __hip_atomic_compare_exchange_strong(ctr, &seen, 0xffffffffu, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return seen;
+}
 __device__ void team_sync_local(Team &T) {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_s_waitcnt(0);
@@ -976,7 +1105,7 @@ __device__ void team_sync_local(Team &T) {
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(T.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         unsigned spins = 0;
-        while (__hip_atomic_load(T.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < T.target) {
+        while (team_count(T.ctr) < T.target) {
             if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             if (++spins > (1u << 22)) {
                 __hip_atomic_store(T.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2156,12 +2285,11 @@ hipError_t launch_reduce_partial(const double *partial, int nblk, int k, double 
 
 hipError_t launch_cholesky(double *A, int n, int *flag, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    if (n > 256) {   // many compute units, the trailing updates on the FP64 matrix cores
+    if (n > kCoarseOneGroup) {   // many compute units, the trailing updates on the FP64 matrix cores
         for (int k0 = 0; k0 < n; k0 += kCholNb) {
             const int b = min(kCholNb, n - k0), m = n - k0 - b;
-            k_chol_diag<<<1, 256, 0, st>>>(A, n, k0, b, flag);
+            k_chol_panel<<<max(1, (m + 255) / 256), 256, 0, st>>>(A, n, k0, b, flag);
             if (m > 0) {
-                k_chol_panel<<<(m + 255) / 256, 256, 0, st>>>(A, n, k0, b, flag);
                 const int T = (m + 15) / 16, ntile = T * (T + 1) / 2;
                 k_chol_update<<<(ntile + 3) / 4, 256, 0, st>>>(A, n, k0, b, ntile, flag);
             }
@@ -2192,6 +2320,20 @@ hipError_t launch_coarse_solve(const double *Ainv, int n, const Tin *b, Tout *x,
 
 hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (n > kCoarseOneGroup) {   // blocked, the updates and W^T W on the FP64 matrix cores
+        k_identity<<<(int)(((int64_t)n * n + 255) / 256), 256, 0, st>>>(W, n);
+        for (int k0 = 0; k0 < n; k0 += kCholNb) {
+            const int b = min(kCholNb, n - k0), m = n - k0 - b;
+            k_trinv_rows<<<(k0 + b + 255) / 256, 256, 0, st>>>(G, W, n, k0, b);
+            if (m > 0) {
+                const int tr = (m + 15) / 16, tc = (k0 + b + 15) / 16, ntile = tr * tc;
+                k_trinv_update<<<(ntile + 3) / 4, 256, 0, st>>>(G, W, n, k0, b, tc, ntile);
+            }
+        }
+        const int T = (n + 15) / 16, ntile = T * (T + 1) / 2;
+        k_inv_syrk<<<(ntile + 3) / 4, 256, 0, st>>>(W, Ainv, n, ntile);
+        return hipGetLastError();
+    }
     const size_t lds = (size_t)4 * n * sizeof(double);
     if (lds <= 128 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_tri_inverse_cols, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -2313,6 +2455,24 @@ hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
     if (threads == 256) k_batch_solve<256><<<nblocks_total, 256, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
     else if (threads == 512) k_batch_solve<512><<<nblocks_total, 512, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
     else k_batch_solve<1024><<<nblocks_total, 1024, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
+    return hipGetLastError();
+}
+
+// Launch-latency probes with the grid of a relaxation launch (64-thread
+// workgroups, xcd_block order): an empty kernel, and one whose every thread
+// loads an index, then the value it points to, and stores it (the dependent
+// chain of a relaxation: matrix entry, then neighbour gather, then store).
+__global__ __launch_bounds__(kGsBlock) void k_floor_empty() {}
+__global__ __launch_bounds__(kGsBlock) void k_floor_chain(const int32_t *__restrict__ idx,
+                                                          const float *__restrict__ v, float *__restrict__ out,
+                                                          int n) {
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kGsBlock + threadIdx.x;
+    if (t >= n) return;
+    out[t] = v[idx[t]];
+}
+hipError_t launch_floor(int kind, int nblk, const int32_t *idx, const float *v, float *out, int n, hipStream_t st) {
+    if (kind == 0) k_floor_empty<<<nblk, kGsBlock, 0, st>>>();
+    else k_floor_chain<<<nblk, kGsBlock, 0, st>>>(idx, v, out, n);
     return hipGetLastError();
 }
 

@@ -545,6 +545,14 @@ class Solver:
     def profile_enable(self, kind, level=0):
         L.check(self._lib.smg_profile_enable(self._s, self.PROF[kind] if kind else -1, level), "profile_enable")
 
+    def launch_floor(self, kind, level, launches=2000):
+        """Average µs per back-to-back launch with level `level`'s widest color
+        grid: kind "empty" or "chain" (index load, dependent load, store)."""
+        us = ctypes.c_double(0.0)
+        L.check(self._lib.smg_launch_floor(self._s, {"empty": 0, "chain": 1}[kind], int(level), int(launches),
+                                           _stream(), ctypes.byref(us)), "launch_floor")
+        return us.value
+
     def profile_read(self):
         ms = ctypes.c_double(0.0)
         n = ctypes.c_int64(0)
