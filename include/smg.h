@@ -420,6 +420,21 @@ smg_status smg_pcg_solve(smg_solver s, const double *d_b, double *d_x, int32_t k
 /* *h_out = lambda^T L u over the level-0 pattern (d_l_vals in CSR order), k = 1 */
 smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const double *d_lambda,
                         const double *d_u, double *h_out, smg_stream stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the value of
+ * smg_spmv_dot, lambda^T L u, with no solver and no allocation.  d_rowptr
+ * (n + 1), d_cols and d_vals (rowptr[n] entries) are the CSR matrix, d_lambda
+ * and d_u length n, all device memory owned by the caller; the sum is written
+ * to d_out[0] (device) on `stream`, with the kernels and summation order of
+ * smg_spmv_dot (the same value bit for bit).  Its per-block partial sums live
+ * in a static 1 MiB device array (one per GPU, kept until the process ends):
+ * n may be at most 16,776,960 rows (INVALID_ARG above that, before any
+ * launch).  Every call on one GPU shares that array, so calls that overlap on
+ * one GPU (different streams or host threads) race; calls in one stream order
+ * are safe.  Errors: INVALID_ARG, HIP. */
+smg_status smg_spmv_dot_noalloc(int32_t n, const int32_t *d_rowptr, const int32_t *d_cols,
+                                const double *d_vals, const double *d_lambda, const double *d_u,
+                                double *d_out, smg_stream stream);
 /* d_out[i] = -lambda_i * m_i * u_i */
 smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const double *d_m,
                          const double *d_u, double *d_out, smg_stream stream);

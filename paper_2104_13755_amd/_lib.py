@@ -105,6 +105,8 @@ SIGNATURES = {
     "smg_get_jacobi_omega": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_double)]),
     "smg_pcg_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveInfo), c_void_p]),
     "smg_spmv_dot": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, P_f64, c_void_p]),
+    "smg_spmv_dot_noalloc": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p]),
     "smg_mass_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "smg_profile_enable": (c_int32, [c_void_p, c_int32, c_int32]),
     "smg_launch_floor": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P_f64]),

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1777,6 +1778,52 @@ extern "C" smg_status smg_spmv_dot(smg_solver s, const double *d_l_vals, const d
     HIPCHK(launch_reduce_partial(s->partial, nblk, 1, s->norms, st, s->d_hnorms));
     CHK(fetch_norms(s, 1, st));
     *h_out = s->h_norms[0];
+    return SMG_OK;
+}
+
+// ------------------------------- lambda^T L u with no allocation at all
+// Scratch of smg_spmv_dot_noalloc: per-block partial sums of k_spmv_dot (two
+// doubles per block) and the reduced pair, in a file-scope device array.
+// Each device holds its own copy until the process ends; the host reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kNoallocScratch = size_t(1) << 17;             // doubles (1 MiB)
+static __device__ __align__(256) double scratch[kNoallocScratch];
+constexpr int kNoallocMaxBlocks = (int)((kNoallocScratch - 2) / 2);
+static std::mutex g_scratch_mu;
+static double *g_scratch[64] = {};                               // per device, set once
+
+static smg_status noalloc_scratch(int device, double **out) {
+    if (device < 0 || device >= 64) return fail(SMG_ERR_INVALID_ARG, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SMG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[device] = (double *)p;
+    }
+    *out = g_scratch[device];
+    return SMG_OK;
+}
+
+extern "C" smg_status smg_spmv_dot_noalloc(int32_t n, const int32_t *d_rowptr, const int32_t *d_cols,
+                                           const double *d_vals, const double *d_lambda, const double *d_u,
+                                           double *d_out, smg_stream stream) {
+    if (!d_rowptr || !d_cols || !d_vals || !d_lambda || !d_u || !d_out || n < 1)
+        return fail(SMG_ERR_INVALID_ARG, "smg_spmv_dot_noalloc: null argument or empty matrix");
+    if ((n + 255) / 256 > kNoallocMaxBlocks)
+        return fail(SMG_ERR_INVALID_ARG, "smg_spmv_dot_noalloc: " + std::to_string(n) + " rows; at most " +
+                                             std::to_string((int64_t)kNoallocMaxBlocks * 256));
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
+    double *scr = nullptr;
+    CHK(noalloc_scratch(device, &scr));
+    hipStream_t st = (hipStream_t)stream;
+    int nblk = 0;
+    double *partial = scr, *red = scr + kNoallocScratch - 2;
+    HIPCHK(launch_spmv_dot(d_rowptr, d_cols, d_vals, d_lambda, d_u, n, partial, &nblk, st));
+    HIPCHK(launch_reduce_partial(partial, nblk, 1, red, st));
+    HIPCHK(launch_axpby(1, 1.0, red, 0.0, red, d_out, st));   // d_out = the sum
     return SMG_OK;
 }
 
