@@ -16,6 +16,7 @@ paper).  Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -51,6 +52,185 @@ def measured_traffic():
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------
+# Summaries of rocprofv3 output (run on the machine that profiled, the
+# markdown goes to profiles/).  The dominant kernel's launches are told apart
+# by their position: every FP32 cycle launches, per relaxed level l in order,
+# mu_pre * colors_l pre-relaxation launches, then the post-relaxation ones in
+# reverse level order; a step may end with the run-ahead prefix of one more
+# cycle (level-0 pre-relaxation launches only).
+DOMINANT = r"k_gs_color(_w)?<3, float>"
+
+
+def _cycle_levels(colors, mu_pre=2, mu_post=2):
+    """Level of each dominant launch of one cycle, in launch order."""
+    seq = []
+    for l, c in enumerate(colors):
+        seq += [l] * (mu_pre * c)
+    for l in reversed(range(len(colors))):
+        seq += [l] * (mu_post * colors[l])
+    return seq
+
+
+def _step_levels(n, colors):
+    """Levels of the n dominant launches of one step (whole cycles, then a
+    pre-relaxation prefix)."""
+    cyc = _cycle_levels(colors)
+    full, rest = divmod(n, len(cyc))
+    return cyc * full + cyc[:rest]
+
+
+def _step_groups(n, colors):
+    """Relaxation call (one level's pre- or post-relaxation of one cycle) of
+    each of the n dominant launches of one step, numbered in launch order."""
+    cyc, g = [], 0
+    for l, c in enumerate(colors):
+        cyc += [g] * (2 * c)
+        g += 1
+    for l in reversed(range(len(colors))):
+        cyc += [g] * (2 * colors[l])
+        g += 1
+    full, rest = divmod(n, len(cyc))
+    return [x + 2 * len(colors) * (i // len(cyc)) for i, x in enumerate(cyc * full + cyc[:rest])]
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def kernel_table(d, top=24):
+    """Markdown table of the kernels of a rocprofv3 --stats run (directory d)."""
+    import re
+    stats = _read_csv(os.path.join(d, "run_kernel_stats.csv"))
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    out = [f"Total kernel time: {tot / 1e6:.1f} ms over {sum(int(r['Calls']) for r in stats)} dispatches.", "",
+           "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        name = re.sub(r"^(void )?smg::\(anonymous namespace\)::", "", r["Name"]).split("(")[0]
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / tot * 100:.1f} |")
+    return "\n".join(out)
+
+
+def trace_summary(d, bench_json):
+    """Markdown summary of `rocprofv3 --kernel-trace --stats` of a bench run
+    (directory d, files run_*) next to the JSON line of a plain run with the
+    same --steps / --warmup: per-kernel table, the dominant kernel's average
+    per pass of the bench, and per level its kernel time and its time per
+    launch inside each relaxation call (first start to last end of the call's
+    back-to-back launches / launches: what the bench's events measure)."""
+    import re
+    b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    roof = b["roofline"]
+    steps, warm = b["steps"], b["warmup"]
+    colors = [roof["levels"][str(l)]["colors"] for l in range(len(roof["levels"]))]
+    tr = _read_csv(os.path.join(d, "run_kernel_trace.csv"))
+    tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+    dom = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in tr if re.search(DOMINANT, r["Kernel_Name"])]
+    per_step = roof["launches"] // steps
+    passes = [("warmup (FP32 cycles)", warm), ("timed steps (no instrumentation)", steps),
+              ("event-timed pass (the bench line's figure)", steps)]
+    passes += [(f"level-{l} event pass", 2) for l in range(len(colors))]
+    passes += [("solve-only timing", steps), ("phase-timed step", 1)]
+
+    def per_level(seg, k):
+        acc = {}
+        for st in range(k):
+            part = seg[st * per_step:(st + 1) * per_step]
+            lv, gr = _step_levels(len(part), colors), _step_groups(len(part), colors)
+            calls = {}
+            for (t0, t1), l, g in zip(part, lv, gr):
+                a = acc.setdefault(l, [0.0, 0, 0.0, 0])
+                a[0] += (t1 - t0) * 1e-3
+                a[1] += 1
+                c = calls.setdefault(g, [l, t0, t1, 0])
+                c[2] = t1
+                c[3] += 1
+            for l, t0, t1, n in calls.values():
+                acc[l][2] += (t1 - t0) * 1e-3
+                acc[l][3] += n
+        return acc
+
+    rows, i, lev = [], 0, {}
+    for name, k in passes:
+        seg = dom[i:i + k * per_step]
+        if not seg:
+            break
+        avg = sum(t1 - t0 for t0, t1 in seg) * 1e-3 / len(seg)
+        rows.append(f"| {name} | {k} | {len(seg)} | {avg:.3f} |")
+        if name.startswith("timed") or name.startswith("event-timed"):
+            lev[name.split(" ")[0]] = (per_level(seg, k), avg)
+        i += k * per_step
+    lines = [kernel_table(d)]
+    lines += ["", f"Dominant kernel (`{DOMINANT}`, {per_step} launches per step) by pass of the bench, "
+              "in trace order:", "", "| pass | steps | launches | avg kernel us |", "|---|---|---|---|"]
+    lines += rows
+    lines += ["", "Per level: kernel time per launch, and time per launch inside each relaxation call (first "
+              "start to last end / launches), from the trace; the plain run's event figure beside them:", "",
+              "| level | colors | pass | launches | kernel us | per launch in calls us | plain run's events us | "
+              "algorithmic MB/launch | GB/s (per launch in calls) | frac |", "|---|---|---|---|---|---|---|---|---|---|"]
+    for key, (acc, _) in lev.items():
+        for l in sorted(acc):
+            s_us, n, c_us, cn = acc[l]
+            lv = roof["levels"][str(l)]
+            by = lv["algorithmic_bytes_per_launch"]
+            gbs = by / (c_us / cn * 1e-6) / 1e9
+            lines.append(f"| {l} | {colors[l]} | {key} | {n} | {s_us / n:.3f} | {c_us / cn:.3f} | "
+                         f"{lv['avg_launch_us']:.3f} | {by / 1e6:.3f} | {gbs:.0f} | {gbs / HBM_PEAK_GBS:.4f} |")
+    ab = roof["algorithmic_bytes_per_launch"]
+    for key, (acc, avg) in lev.items():
+        c_us = sum(a[2] for a in acc.values()) / sum(a[3] for a in acc.values())
+        lines.append("")
+        lines.append(f"Every level, {key} pass: kernel {avg:.3f} us per launch, {c_us:.3f} us per launch inside "
+                     f"relaxation calls -> {ab / (c_us * 1e-6) / 1e9:.0f} GB/s = "
+                     f"{ab / (c_us * 1e-6) / 1e9 / HBM_PEAK_GBS:.4f} of 8 TB/s.")
+    lines += ["", f"Plain run's bench line: {roof['avg_launch_us']:.3f} us per launch, {roof['achieved']:.0f} GB/s, "
+              f"frac {roof['frac']:.4f}."]
+    return "\n".join(lines)
+
+
+def pmc_summary(fetch_dir, write_dir, colors):
+    """HBM traffic per dominant launch from two `rocprofv3 --pmc` runs of
+    `bench.py --pmc-probe` (FETCH_SIZE, then WRITE_SIZE), each scaled by what
+    the counter reads for the probe's three 256 MiB streaming multiplies."""
+    import re
+
+    def per_dispatch(d, counter):
+        rows = _read_csv(os.path.join(d, "run_counter_collection.csv"))
+        acc = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            k = int(r["Dispatch_Id"])
+            acc.setdefault(k, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return [acc[k] for k in sorted(acc)]
+
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = per_dispatch(d, counter)
+        copies = [v for n, v in disp if "elementwise" in n][-3:]
+        scale = 262144.0 / (sum(copies) / len(copies))          # KiB moved per copy / KiB counted
+        dom = [v for n, v in disp if re.search(DOMINANT, n)]
+        res[counter] = (scale, sum(copies) / len(copies), dom)
+    nd = len(res["FETCH_SIZE"][2])
+    levels = _step_levels(nd, colors)
+    tot = [res["FETCH_SIZE"][0] * f + res["WRITE_SIZE"][0] * w
+           for f, w in zip(res["FETCH_SIZE"][2], res["WRITE_SIZE"][2])]
+    out = {"scale_fetch": res["FETCH_SIZE"][0], "scale_write": res["WRITE_SIZE"][0],
+           "copy_fetch_kib": res["FETCH_SIZE"][1], "copy_write_kib": res["WRITE_SIZE"][1], "launches": nd,
+           "all": {"fetch_kib": sum(res["FETCH_SIZE"][2]) / nd, "write_kib": sum(res["WRITE_SIZE"][2]) / nd,
+                   "bytes": sum(tot) / nd * 1024}}
+    for l in sorted(set(levels)):
+        idx = [i for i, x in enumerate(levels) if x == l]
+        out[l] = {"launches": len(idx), "fetch_kib": sum(res["FETCH_SIZE"][2][i] for i in idx) / len(idx),
+                  "write_kib": sum(res["WRITE_SIZE"][2][i] for i in idx) / len(idx),
+                  "bytes": sum(tot[i] for i in idx) / len(idx) * 1024}
+    return out
 
 
 def gpu_setup(w, n_levels):
@@ -171,6 +351,81 @@ def build_solvers(meshes, threads=16):
     return out, t_pre
 
 
+def cycle_bytes(S, k, sweeps=4, s=4):
+    """Algorithmic bytes of one V-cycle with FP32 values (s = 4) for k
+    right-hand sides: every relaxation sweep and residual by the CSR rule
+    z(s+4) + 4(n+1) + 3kns, a transfer as P's three columns and weights per
+    row plus the vectors it reads and writes, the coarsest dense apply, and
+    the refinement's level-0 FP64 residual."""
+    L = S.num_levels
+    relax = resid = transfer = 0.0
+    for l in range(L - 1):
+        n, z, nc = S.level_size(l), S.level_nnz(l), S.level_size(l + 1)
+        csr = z * (s + 4) + 4 * (n + 1) + 3 * k * n * s
+        relax += sweeps * csr
+        resid += csr
+        transfer += 2 * 3 * n * (4 + s) + (k * n * s + k * nc * s) + (k * nc * s + 2 * k * n * s)
+    nH = S.level_size(L - 1)
+    z0, n0 = S.level_nnz(0), S.level_size(0)
+    return dict(relax=relax, residual=resid, transfer=transfer, coarse=nH * nH * 8.0 + 2 * k * nH * s,
+                ir=z0 * (8 + 4) + 4 * (n0 + 1) + 3 * k * n0 * 8.0)
+
+
+def bench_coarse(args):
+    """Coarsest-level value refresh at a chosen coarsest size n_H (Galerkin
+    product into it, dense Cholesky, A_H^{-1}): a two-level hierarchy of a
+    jittered torus grid with about 4 n_H vertices.  Run it under rocprofv3
+    --kernel-trace --stats and divide the factor and inverse kernels' time by
+    the refreshes this prints."""
+    import torch
+    from paper_2104_13755_amd.solver import Hierarchy, Solver, mesh_pattern
+    from synth.meshes import torus_grid
+    a = max(8, int(round(math.sqrt(4 * args.coarse_n))))
+    V, F = torus_grid(a, a, 1.0, 0.3, np.random.default_rng(3), jitter=0.2)
+    h = Hierarchy.build(V, F, n_levels=2)
+    rp, ci = mesh_pattern(len(V), F)
+    S = Solver(h, rp, ci, faces=F)
+    Vd = torch.tensor(V, dtype=torch.float64, device="cuda")
+    vals, _, _ = S.assemble(Vd, 1e-2)
+    refreshes = 0
+    for _ in range(args.warmup):
+        S.set_values(vals)
+        refreshes += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.set_values(vals)
+        refreshes += 1
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    nH = h.sizes[-1]
+    print(json.dumps({"workload": f"torus-{a}x{a}, 2 levels", "sizes": h.sizes, "n_H": nH,
+                      "refreshes": refreshes, "refresh_ms": dt * 1e3,
+                      "factor_flop": nH ** 3 / 3.0, "inverse_flop": 2 * nH ** 3 / 3.0}), flush=True)
+
+
+def coarse_summary(runs):
+    """Markdown table from rocprofv3 --stats runs of --workload coarse: list
+    of (rocprof dir, JSON file) pairs."""
+    factor = ("k_chol_panel", "k_chol_update", "k_zero_upper", "k_cholesky_blocked", "k_cholesky(")
+    inverse = ("k_identity", "k_trinv_rows", "k_trinv_update", "k_inv_syrk", "k_tri_inverse_cols",
+               "k_tri_inverse(", "k_inverse_product")
+    out = ["| n_H | refreshes | factor us | factor TFLOP/s (n^3/3) | frac of 78.6 | inverse us | "
+           "inverse TFLOP/s (2n^3/3) | refresh ms (wall) | factor kernels |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for d, js in runs:
+        j = json.loads(open(js).read().strip().splitlines()[-1])
+        stats = _read_csv(os.path.join(d, "run_kernel_stats.csv"))
+        tf = sum(float(r["TotalDurationNs"]) for r in stats if any(k in r["Name"] for k in factor))
+        ti = sum(float(r["TotalDurationNs"]) for r in stats if any(k in r["Name"] for k in inverse))
+        names = sorted({r["Name"].split("::")[-1].split("(")[0] for r in stats if any(k in r["Name"] for k in factor)})
+        f_us, i_us = tf / j["refreshes"] / 1e3, ti / j["refreshes"] / 1e3
+        out.append(f"| {j['n_H']} | {j['refreshes']} | {f_us:.1f} | {j['factor_flop'] / f_us / 1e6:.2f} | "
+                   f"{j['factor_flop'] / f_us / 1e6 / 78.6:.4f} | {i_us:.1f} | "
+                   f"{j['inverse_flop'] / i_us / 1e6:.2f} | {j['refresh_ms']:.3f} | {', '.join(names)} |")
+    return "\n".join(out)
+
+
 def bench_batch(args):
     """64 meshes (20k-300k vertices, 1-3 RHS) in one persistent launch."""
     import torch
@@ -203,6 +458,24 @@ def bench_batch(args):
     dt = (time.perf_counter() - t0) / args.steps
     worst = max(max(i["rel_res"]) for i in infos)
     n_tot = sum(len(w["V"]) for w in meshes)
+    # roofline of the one dispatch: smoother + SpMV bytes of every cycle of
+    # every mesh over the whole dispatch's time (a lower bound for those
+    # kernels' own rate: the dispatch also holds transfers, coarsest solves
+    # and team barriers)
+    sm = tot_all = 0.0
+    for (S, _, _, _), b, inf in zip(built, bs, infos):
+        cb = cycle_bytes(S, b.shape[1] if b.dim() > 1 else 1)
+        sm += inf["cycles"] * (cb["relax"] + cb["residual"] + cb["ir"])
+        tot_all += inf["cycles"] * sum(cb.values())
+    roof = {"bound": "hbm", "achieved": sm / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": sm / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_batch_solve (one persistent dispatch: every cycle of every mesh)",
+            "bytes_per_batch": sm, "bytes_per_batch_all_steps": tot_all,
+            "all_steps_frac": tot_all / dt / 1e9 / HBM_PEAK_GBS,
+            "bytes_rule": "per cycle: 4 relaxation sweeps + 1 residual per level above the coarsest, each "
+                          "z(s+4) + 4(n+1) + 3kns with s = 4, plus the level-0 FP64 residual z 12 + 4(n+1) + 24kn "
+                          "of the refinement; all_steps adds transfers (P: 3 columns + weights per row, vectors) "
+                          "and the coarsest dense apply n_H^2 8"}
     print(json.dumps({
         "metric": "batched V-cycle solves/s (64 meshes, 20k-300k vertices, 1-3 RHS, rel residual 1e-8, FP32+FP64 IR, one persistent launch)",
         "value": len(meshes) / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -212,7 +485,7 @@ def bench_batch(args):
                    "vertices": n_tot, "shape": shape},
         "unbatched_solves_per_s": len(meshes) / t_unbatched, "max_rel_res": worst,
         "cycles": [i["cycles"] for i in infos], "cycles_unbatched": cyc_u,
-        "precompute_s": t_pre}), flush=True)
+        "precompute_s": t_pre, "roofline": roof}), flush=True)
 
 
 def bench_grad(args):
@@ -339,6 +612,9 @@ def bench_jacobi(args):
                                "7 levels, damped Jacobi omega_l = 2/(1+lambda_l), mu 2/2, rtol 1e-8",
                    "vertices": len(w["V"]), "levels": h.sizes, "rhs": 3},
         "omega_per_level": [S.jacobi_omega(l) for l in range(len(h.sizes) - 1)],
+        "omega_rule": "the paper names damped Jacobi without a factor: omega_l = 2/(1 + lambda_l), lambda_l the "
+                      "Rayleigh quotient of D^-1 A after 20 power steps from a fixed golden-ratio start vector "
+                      "(a fixed 2/3 diverged on this torus, whose levels have lambda 1.9 to 2.8)",
         "cycles": res["cycles"], "pcg": res["pcg"]}), flush=True)
 
 
@@ -528,14 +804,56 @@ def main():
     ap.add_argument("--size", type=int, nargs=2, default=(1000, 1000))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=0)
-    ap.add_argument("--profile-kind", default="gs")
-    ap.add_argument("--workload", default="torus", choices=["torus", "batch", "grad", "frames", "pcg", "jacobi", "split", "smooth"])
+    ap.add_argument("--profile-kind", default="gs_group")
+    ap.add_argument("--workload", default="torus",
+                    choices=["torus", "batch", "grad", "frames", "pcg", "jacobi", "split", "smooth", "coarse"])
+    ap.add_argument("--coarse-n", type=int, default=1960, help="coarsest size of --workload coarse")
+    ap.add_argument("--coarse-summary", nargs="+", metavar="DIR=JSON",
+                    help="print the table of rocprofv3 --stats runs of --workload coarse")
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--stats-table", metavar="ROCPROF_DIR",
+                    help="print the kernel table of a rocprofv3 --stats run")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("ROCPROF_DIR", "BENCH_JSON"),
+                    help="print the markdown summary of a rocprofv3 --kernel-trace --stats run of this bench")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_JSON"),
+                    help="print the traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware counters: a 256 MiB copy (calibration), then 3 mixed cycles")
     args = ap.parse_args()
+    if args.stats_table:
+        print(kernel_table(args.stats_table))
+        return
+    if args.coarse_summary:
+        print(coarse_summary([tuple(x.split("=", 1)) for x in args.coarse_summary]))
+        return
+    if args.trace_summary:
+        print(trace_summary(*args.trace_summary))
+        return
+    if args.pmc_summary:
+        import hashlib
+        probe = json.loads(open(args.pmc_summary[2]).read().strip().splitlines()[-1])
+        r = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], probe["colors"])
+        src = os.path.join(ROOT, "paper_2104_13755_amd", "csrc", "kernels.hip")
+        lines = [f"Calibration on the multiply: FETCH_SIZE reads {r['copy_fetch_kib']:.0f} KiB for 262144 KiB read "
+                 f"(scale {r['scale_fetch']:.4f}); WRITE_SIZE reads {r['copy_write_kib']:.0f} KiB for 262144 KiB "
+                 f"written (scale {r['scale_write']:.4f}).  Traffic = scale_fetch * FETCH_SIZE + scale_write * "
+                 "WRITE_SIZE.", "",
+                 f"Colors per relaxed level: {probe['colors']}; {r['launches']} dominant launches in "
+                 f"{probe['cycles']} cycles.", "",
+                 "| launches | count | FETCH_SIZE KiB/launch | WRITE_SIZE KiB/launch | traffic MB/launch |",
+                 "|---|---|---|---|---|",
+                 f"| every level | {r['launches']} | {r['all']['fetch_kib']:.1f} | {r['all']['write_kib']:.1f} | "
+                 f"{r['all']['bytes'] / 1e6:.3f} |"]
+        for l in range(len(probe["colors"])):
+            lines.append(f"| level {l} | {r[l]['launches']} | {r[l]['fetch_kib']:.1f} | {r[l]['write_kib']:.1f} | "
+                         f"{r[l]['bytes'] / 1e6:.3f} |")
+        lines += ["", f"traffic_bytes_per_launch_every_level: {r['all']['bytes']:.0f}"]
+        lines += [f"traffic_bytes_per_launch_level{l}: {r[l]['bytes']:.0f}" for l in range(len(probe["colors"]))]
+        lines.append("kernels_hip_sha256: " + hashlib.sha256(open(src, "rb").read()).hexdigest())
+        print("\n".join(lines))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
@@ -547,6 +865,8 @@ def main():
         sys.exit(1)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "coarse":
+        return bench_coarse(args)
     if args.workload == "grad":
         return bench_grad(args)
     if args.workload == "frames":
@@ -574,7 +894,8 @@ def main():
         S.solve(b, fixed_cycles=3, precision="fp32ir")
         torch.cuda.synchronize()
         print(json.dumps({"pmc_probe": True, "copy_bytes_read": src.numel() * 8,
-                          "copy_bytes_written": dst.numel() * 8, "cycles": 3}), flush=True)
+                          "copy_bytes_written": dst.numel() * 8, "cycles": 3,
+                          "colors": [S.colors(l)[1] for l in range(S.tail_first(3, "fp32ir"))]}), flush=True)
         return
 
     # warmup both precisions
@@ -583,8 +904,9 @@ def main():
     # timed region: mixed precision, no instrumentation
     t_mixed, infos_m, x_m = run_steps(S, Vd, w["t"], b, rtol, "fp32ir", args.steps, use_graph)
     log(f"mixed: {t_mixed / args.steps * 1e3:.2f} ms/step cycles={infos_m[-1]['cycles']} res={max(infos_m[-1]['rel_res']):.2e}")
-    # the same steps again with every launch of the dominant kernel timed by
-    # start/stop events stamped by its own dispatch (per-level split too)
+    # the same steps again with the dominant kernel's launches timed by HIP
+    # events on their stream around each relaxation call (its sweeps x colors
+    # launches, back to back), per level too
     S.profile_enable(args.profile_kind, -1)
     t_prof, _, _ = run_steps(S, Vd, w["t"], b, rtol, "fp32ir", args.steps, use_graph)
     prof = S.profile_read()
@@ -619,27 +941,34 @@ def main():
         return {"achieved": ach, "frac": ach / HBM_PEAK_GBS if ach else None, "launches": p["launches"],
                 "avg_launch_us": p["ms"] * 1e3 / max(1, p["launches"]),
                 "algorithmic_bytes_per_launch": p["bytes"] / max(1, p["launches"])}
-    traffic_all, traffic_lv = measured_traffic() if args.profile_kind == "gs" else (None, {})
+    traffic_all, traffic_lv = measured_traffic() if args.profile_kind.startswith("gs") else (None, {})
     top = summary(prof)
     roofline = {"bound": "hbm", "achieved": top["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": top["frac"], "traffic": traffic_all,
                 "kernel": "k_gs_color_w<3, float> / k_gs_color<3, float> (multicolor Gauss-Seidel, FP32 cycles, "
                           "every level relaxed by per-color launches)"
-                          if args.profile_kind == "gs" else f"{args.profile_kind} (every level)",
+                          if args.profile_kind.startswith("gs") else f"{args.profile_kind} (every level)",
                 "launches": top["launches"], "avg_launch_us": top["avg_launch_us"],
                 "algorithmic_bytes_per_launch": top["algorithmic_bytes_per_launch"],
                 "bytes_rule": "per sweep z(s+4) + 4(n+1) + 3kns: z matrix entries incl. diagonal, n rows, "
                               "s = 4 B values, k = 3 right-hand sides, x gathers counted once; "
                               "a color launch counts its rows' share",
-                "measured": "dispatch-stamped HIP events on the launch stream, every launch of the kernel "
-                            "in a second pass of the same timed steps",
-                "levels": {str(l): dict(summary(p), traffic=traffic_lv.get(l), floor_empty_us=floors[l][0],
-                                        floor_chain_us=floors[l][1],
-                                        latency_frac=floors[l][1] / summary(p)["avg_launch_us"])
+                "measured": "HIP events on the launch stream around each relaxation call (every sweep and color "
+                            "of one level's pre- or post-relaxation, launched back to back) in a second pass of "
+                            "the same timed steps; per launch = that time / its launches (kernel time plus the "
+                            "gaps between those dependent launches)" if args.profile_kind == "gs_group" else
+                            "dispatch-stamped HIP events on the launch stream, every launch of the kernel in a "
+                            "second pass of the same timed steps",
+                "levels": {str(l): dict(summary(p), colors=S.colors(l)[1], traffic=traffic_lv.get(l),
+                                        floor_empty_us=floors[l][0][0], floor_chain_us=floors[l][1][0],
+                                        host_enqueue_us=floors[l][1][1],
+                                        latency_frac=floors[l][1][0] / summary(p)["avg_launch_us"])
                            for l, p in prof_lv.items()},
-                "latency_rule": "floor_chain_us: back-to-back launches with the level's widest color grid whose "
-                                "threads load an index, the value it points to, and store it; latency_frac = "
-                                "that floor / the relaxation launch's average time (events)"}
+                "latency_rule": "floor_chain_us: device launch-to-launch time of 2000 back-to-back launches, queued "
+                                "ahead of the device, with the level's widest color grid whose threads load an index "
+                                "(the level's column array), the value it points to, and store it (floor_empty_us: "
+                                "an empty kernel; host_enqueue_us: host time to enqueue one such launch); "
+                                "latency_frac = floor_chain_us / the level's relaxation time per launch"}
     value = args.steps / t_mixed
     out = {
         "metric": "V-cycle solves/s + HBM GB/s at 1M verts to rel residual 1e-8, mixed vs FP64",

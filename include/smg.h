@@ -441,10 +441,14 @@ smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const double *d_m
 
 /* --- per-launch kernel timing (HIP events on the launch stream) --- */
 enum { SMG_PROF_GS = 0, SMG_PROF_RESIDUAL = 1, SMG_PROF_RESTRICT = 2, SMG_PROF_PROLONG = 3,
-       SMG_PROF_COARSE = 4, SMG_PROF_GALERKIN = 5 };
+       SMG_PROF_COARSE = 4, SMG_PROF_GALERKIN = 5, SMG_PROF_GROUP = 0x100 };
 /* Time every launch of kernel `kind` on level `level` (-1: every level; any
  * precision) with start/stop events stamped by the dispatch itself, until
- * disabled (kind < 0).  Solves with use_graph run their cycles eagerly while
+ * disabled (kind < 0).  kind | SMG_PROF_GROUP (Gauss-Seidel only) instead
+ * puts one event pair around each relaxation call's launches (every sweep
+ * and color of one level's pre- or post-relaxation): the time then includes
+ * the gaps between those back-to-back launches, and the launch count is
+ * every launch inside.  Solves with use_graph run their cycles eagerly while
  * profiling is on. */
 smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level);
 /* Totals since enable: summed launch durations (ms), launch count, and the
@@ -457,14 +461,17 @@ smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t level);
 smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches, double *bytes);
 
 /* Launch latency on this device, for the latency bound of the per-color
- * launches: *us = average device time per launch of `launches` back-to-back
- * launches on `stream` with the grid of level `level`'s widest color (one
- * 64-thread workgroup per slice), of an empty kernel (kind 0) or of a kernel
- * whose threads load an index, then the value it points to, and store it
- * (kind 1: the dependent chain of a relaxation launch).  Synchronizes the
- * stream.  Errors: INVALID_ARG. */
+ * launches: `launches` (1..4000) back-to-back launches on `stream` with the
+ * grid of level `level`'s widest color (one 64-thread workgroup per slice),
+ * of an empty kernel (kind 0) or of a kernel whose threads load an index
+ * (the level's own column array), then the value it points to, and store it
+ * (kind 1: the dependent chain of a relaxation launch).  The launches are
+ * queued behind a bounded sleep kernel that outlasts their enqueueing, so
+ * *us = the device's launch-to-launch time (one event pair around them all);
+ * *us_host (may be NULL) = host time to enqueue one launch.  Synchronizes the
+ * stream.  Errors: INVALID_ARG, HIP. */
 smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level, int32_t launches, smg_stream stream,
-                            double *us);
+                            double *us, double *us_host);
 
 /* ------------------------------------------------------------------------ */
 /* Batching: many solvers in one persistent launch.                          */

@@ -109,7 +109,7 @@ SIGNATURES = {
                                        c_void_p]),
     "smg_mass_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "smg_profile_enable": (c_int32, [c_void_p, c_int32, c_int32]),
-    "smg_launch_floor": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P_f64]),
+    "smg_launch_floor": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, P_f64, P_f64]),
     "smg_profile_read": (c_int32, [c_void_p, P_f64, ctypes.POINTER(c_int64), P_f64]),
     "smg_batch_create": (c_int32, [ctypes.POINTER(c_void_p), c_int32, ctypes.POINTER(BatchOpts), ctypes.POINTER(c_void_p)]),
     "smg_batch_destroy": (None, [c_void_p]),

@@ -1063,17 +1063,25 @@ smg_status smooth_level(smg_solver_s *s, int l, int k, int sweeps, hipStream_t s
     DevLevel &D = s->lev[l];
     const SellView<T> A = sell_view<T>(D);
     const double sb = sizeof(T);
+    // group timing: one event pair around all of this call's launches
+    const int pg = s->prof_group ? prof_begin(s, SMG_PROF_GS, l, sweeps * sweep_bytes(D.offdiag_nnz + D.n, D.n, k, sb, true),
+                                              st, (int64_t)sweeps * D.ncolors)
+                                 : -1;
+    if (pg >= 0) HIPCHK(hipEventRecord(prof_ev(s, pg, 0), st));
     for (int sw = 0; sw < sweeps; ++sw)
         for (int cc = 0; cc < D.ncolors; ++cc) {
             const int c = descending ? D.ncolors - 1 - cc : cc;
-            const int pi = prof_begin(s, SMG_PROF_GS, l,
-                                      sweep_bytes(D.color_nnz[c] + D.color_rows[c], D.color_rows[c], k, sb, cc == 0),
-                                      st);
+            const int pi = s->prof_group ? -1
+                                         : prof_begin(s, SMG_PROF_GS, l,
+                                                      sweep_bytes(D.color_nnz[c] + D.color_rows[c], D.color_rows[c],
+                                                                  k, sb, cc == 0),
+                                                      st);
             const ColorSpan span{D.color_slice[c], D.color_slice[c + 1], D.color_row_h[c], D.color_row_h[c + 1],
                                  D.color_off[c], D.color_w[c]};
             HIPCHK(launch_gs_color<T>(A, span, bbuf<T>(D), xbuf<T>(D), k, st,
                                       prof_ev(s, pi, 0), prof_ev(s, pi, 1)));
         }
+    if (pg >= 0) HIPCHK(hipEventRecord(prof_ev(s, pg, 1), st));
     return SMG_OK;
 }
 
@@ -1838,7 +1846,7 @@ extern "C" smg_status smg_mass_grad(smg_solver s, const double *d_lambda, const 
 // --------------------------------------------------------------- profiling
 namespace smg {
 
-int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st) {
+int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st, int64_t launches) {
     if (s->prof_kind != kind || (s->prof_level >= 0 && s->prof_level != level)) return -1;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
@@ -1849,6 +1857,7 @@ int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t s
     }
     const int idx = (int)s->prof_used++;
     s->prof_bytes_pending.push_back(bytes);
+    s->prof_launches_pending.push_back(launches);
     return idx;
 }
 
@@ -1893,10 +1902,11 @@ smg_status prof_collect(smg_solver_s *s) {
         HIPCHK(hipEventElapsedTime(&ms, s->prof_pool[2 * i], s->prof_pool[2 * i + 1]));
         s->prof_ms += ms;
         s->prof_bytes += s->prof_bytes_pending[i];
-        s->prof_launches++;
+        s->prof_launches += s->prof_launches_pending[i];
     }
     s->prof_used = 0;
     s->prof_bytes_pending.clear();
+    s->prof_launches_pending.clear();
     return SMG_OK;
 }
 
@@ -1906,7 +1916,8 @@ extern "C" smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t lev
     if (!s) return fail(SMG_ERR_INVALID_ARG, "null solver");
     HIPCHK(hipSetDevice(s->device));
     CHK(prof_collect(s));
-    s->prof_kind = kind;
+    s->prof_group = kind >= 0 && (kind & SMG_PROF_GROUP);
+    s->prof_kind = kind >= 0 ? (kind & ~SMG_PROF_GROUP) : -1;
     s->prof_level = level;
     s->prof_ms = 0.0;
     s->prof_bytes = 0.0;
@@ -1915,9 +1926,9 @@ extern "C" smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t lev
 }
 
 extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level, int32_t launches,
-                                       smg_stream stream, double *us) {
-    if (!s || !us || (kind != 0 && kind != 1) || launches < 1 || level < 0 || level >= s->nlev ||
-        s->lev[level].coarsest)
+                                       smg_stream stream, double *us, double *us_host) {
+    if (!s || !us || (kind != 0 && kind != 1) || launches < 1 || launches > 4000 || level < 0 ||
+        level >= s->nlev || s->lev[level].coarsest)
         return fail(SMG_ERR_INVALID_ARG, "smg_launch_floor: bad arguments");
     HIPCHK(hipSetDevice(s->device));
     hipStream_t st = (hipStream_t)stream;
@@ -1925,18 +1936,42 @@ extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level
     // the grid of the level's widest color launch
     int slices = 1;
     for (int c = 0; c < D.ncolors; ++c) slices = std::max(slices, D.color_slice[c + 1] - D.color_slice[c]);
-    const int n = std::min<int64_t>((int64_t)slices * 64, D.n);
-    // inputs: the level's own buffers (perm as indices, x32 as values, r32 as output)
-    for (int rep = 0; rep < 2; ++rep) {   // the first round warms up
-        HIPCHK(hipEventRecord(s->ev_prep0, st));
-        for (int i = 0; i < launches; ++i)
-            HIPCHK(launch_floor(kind, slices, D.perm, D.x32, D.r32, n, st));
-        HIPCHK(hipEventRecord(s->ev_prep1, st));
-        HIPCHK(hipEventSynchronize(s->ev_prep1));
+    const int n = (int)std::min<int64_t>(std::min<int64_t>((int64_t)slices * 64, D.n), D.slots);
+    if (n < 1) return fail(SMG_ERR_INVALID_ARG, "smg_launch_floor: level has no slots");
+    // inputs: the level's own buffers: the first slots of its sliced column
+    // array as indices (neighbours of nearby rows, the gather's own locality;
+    // padding slots hold valid rows), x32 as values, r32 as output
+    static_assert(sizeof(*D.cols) == sizeof(int32_t), "int32 columns");
+    // The launches are queued behind a bounded sleep kernel that outlasts
+    // their enqueueing, so the device runs them back to back at its own pace
+    // (enqueueing one takes the host about as long as the device runs one).
+    hipEvent_t ed = nullptr;
+    HIPCHK(hipEventCreate(&ed));
+    smg_status rc = SMG_OK;
+    double dev_ms = 0.0, host_ms = 0.0;
+    int iters = 2 * launches + 64;   // ~3.4 us per iteration
+    for (int rep = 0; rep < 4 && rc == SMG_OK; ++rep) {   // round 0 warms up
+        if (hipEventRecord(ed, st) != hipSuccess || launch_delay(iters, st) != hipSuccess ||
+            hipEventRecord(s->ev_prep0, st) != hipSuccess) { rc = SMG_ERR_HIP; break; }
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int i = 0; i < launches && rc == SMG_OK; ++i)
+            if (launch_floor(kind, slices, D.cols, D.x32, D.r32, n, st) != hipSuccess) rc = SMG_ERR_HIP;
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rc != SMG_OK || hipEventRecord(s->ev_prep1, st) != hipSuccess ||
+            hipEventSynchronize(s->ev_prep1) != hipSuccess) { rc = SMG_ERR_HIP; break; }
+        float dm = 0.0f, delay = 0.0f;
+        if (hipEventElapsedTime(&dm, s->ev_prep0, s->ev_prep1) != hipSuccess ||
+            hipEventElapsedTime(&delay, ed, s->ev_prep0) != hipSuccess) { rc = SMG_ERR_HIP; break; }
+        dev_ms = dm;
+        host_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        if (rep == 0) continue;
+        if (host_ms < 0.9 * delay) break;   // every launch was queued before the device reached it
+        iters *= 2;                         // the host was not ahead: a longer hold
     }
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, s->ev_prep0, s->ev_prep1));
-    *us = 1e3 * ms / launches;
+    (void)hipEventDestroy(ed);
+    if (rc != SMG_OK) return fail(rc, "smg_launch_floor: timing failed");
+    *us = 1e3 * dev_ms / launches;
+    if (us_host) *us_host = 1e3 * host_ms / launches;
     return SMG_OK;
 }
 

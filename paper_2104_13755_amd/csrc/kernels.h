@@ -207,6 +207,7 @@ struct BatchMesh {
 // launch-latency probes: kind 0 an empty kernel, 1 out[t] = v[idx[t]] for
 // t < n (two dependent loads and a store), grid nblk x 64 threads
 hipError_t launch_floor(int kind, int nblk, const int32_t *idx, const float *v, float *out, int n, hipStream_t st);
+hipError_t launch_delay(int iters, hipStream_t st);
 // Alg. "V-cycle" from level `first` to the coarsest by one team of m
 // workgroups (1024 threads) on one XCD meeting at L2-local barriers; lv: the
 // levels as TailLevel descriptors (device array); cb: 64 unsigned of team

@@ -737,47 +737,75 @@ __global__ __launch_bounds__(1024) void k_cholesky_blocked(double *__restrict__ 
 // ------------------------------------------- blocked Cholesky on many CUs
 // Right-looking A = G G^T (column-major, lower) in panels of kCholNb columns.
 // Per panel, k_chol_panel factors the diagonal block in the registers of one
-// wavefront per workgroup (row i in lane i, pivots and multipliers passed by
-// lane shuffles) and solves every row below it against that block (one thread
-// per row); k_chol_update then updates the trailing lower triangle
-// A22 -= L21 L21^T in 16 x 16 tiles, one wavefront per tile on the FP64
-// matrix cores (v_mfma_f64_16x16x4f64, K = 4 per instruction).  A pivot <= 0
-// sets *flag and every later kernel returns at once.
+// wavefront per workgroup (row i in lane i, pivots and multipliers read from
+// other lanes by v_readlane) and solves every row below it against that
+// block (one thread per row); k_chol_update then updates the trailing lower
+// triangle A22 -= L21 L21^T in 16 x 16 tiles, one wavefront per tile on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64, K = 4 per instruction).  A pivot
+// <= 0 sets *flag and every later kernel returns at once.
 constexpr int kCholNb = 32;
 // coarsest levels up to this size are factored and inverted by the
 // one-workgroup kernels (k_cholesky_blocked, k_tri_inverse_cols)
 constexpr int kCoarseOneGroup = 96;
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
-// Factor the b x b diagonal block at (k0, k0) in LDS by wave 0 alone
-// (right-looking, one column per step; the lanes of one wavefront see each
-// other's LDS writes in program order, so no workgroup barrier is needed)
-// and leave L11 (column-major, zero above the diagonal) in T; returns false
-// on a pivot <= 0 (the same decision in every lane).
-__device__ bool chol_block_wave(const double *__restrict__ A, int n, int k0, int b, double *T) {
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, lane), hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Factor the b x b diagonal block at (k0, k0) in the registers of one
+// wavefront: lane i holds row i (a[c] = A(k0 + i, k0 + c), c <= i; rows b..31
+// are identity rows, so a ragged last block runs the same 32 steps).  Step j
+// takes the pivot from lane j, scales column j and updates the columns right
+// of it with L(c, j) read from lane c; nothing leaves the registers.  Leaves
+// L11 row-major in T (zero above the diagonal, identity rows below b) and
+// returns false on a pivot <= 0 (the same decision in every lane).
+__device__ bool chol_block_regs(double *__restrict__ A, int n, int k0, int b, double *T) {
     const int lane = threadIdx.x & 63;
-    for (int t = lane; t < kCholNb * kCholNb; t += 64) {
-        const int i = t % kCholNb, c = t / kCholNb;
-        T[t] = (i < b && c < b && i >= c) ? A[(size_t)(k0 + c) * n + k0 + i] : 0.0;
+    double a[kCholNb];
+#pragma unroll
+    for (int c = 0; c < kCholNb; ++c)
+    {   // in-bounds address for every lane, then a select (no branch)
+        const double v = A[(size_t)(k0 + min(c, b - 1)) * n + k0 + min(lane, b - 1)];
+        a[c] = (lane < b && c <= lane) ? v : (c == lane ? 1.0 : 0.0);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     bool ok = true;
-    for (int j = 0; j < b; ++j) {
-        const double ajj = T[j * kCholNb + j];
-        ok = ok && (ajj > 0.0);
-        const double d = sqrt(ajj);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane == j) T[j * kCholNb + j] = d;
-        else if (lane > j && lane < b) T[j * kCholNb + lane] /= d;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int w = b - j - 1;
-        for (int t = lane; t < w * w; t += 64) {
-            const int i = j + 1 + t % w, c = j + 1 + t / w;
-            if (i >= c) T[c * kCholNb + i] -= T[j * kCholNb + i] * T[j * kCholNb + c];
+#pragma unroll
+    for (int j = 0; j < kCholNb; ++j) {
+        const double piv = readlane_f64(a[j], j);
+        ok = ok && (piv > 0.0);
+        const double d = sqrt(piv);
+        a[j] = lane > j ? a[j] / d : (lane == j ? d : 0.0);
+#pragma unroll
+        for (int c = j + 1; c < kCholNb; ++c) a[c] -= a[j] * readlane_f64(a[j], c);
+    }
+    if (lane < kCholNb) {
+#pragma unroll
+        for (int c = 0; c < kCholNb; ++c) T[lane * kCholNb + c] = c <= lane ? a[c] : 0.0;
+        if (blockIdx.x == 0 && lane < b) {   // the factored block back to A (lower part)
+#pragma unroll
+            for (int c = 0; c < kCholNb; ++c)
+                if (c <= lane) A[(size_t)(k0 + c) * n + k0 + lane] = a[c];
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
     return ok;
+}
+
+// x L^T = a for one row held in registers (forward substitution against the
+// row-major lower triangle T; rows of T past the block are identity rows, so
+// x stays zero there): x_j = (a_j - sum_{p<j} L_jp x_p) / L_jj.  The same
+// recurrence solves L x = w for one column of a right-hand side.
+__device__ __forceinline__ void tri_solve_regs(double (&x)[kCholNb], const double *__restrict__ T) {
+#pragma unroll
+    for (int j = 0; j < kCholNb; ++j) {
+        double s = x[j];
+#pragma unroll
+        for (int p = 0; p < j; ++p) s -= T[j * kCholNb + p] * x[p];
+        x[j] = s / T[j * kCholNb + j];
+        __builtin_amdgcn_sched_barrier(0);   // keep row j's loads of T from being hoisted: they would spill
+    }
 }
 
 __global__ __launch_bounds__(256) void k_chol_panel(double *__restrict__ A, int n, int k0, int b,
@@ -785,8 +813,20 @@ __global__ __launch_bounds__(256) void k_chol_panel(double *__restrict__ A, int 
     __shared__ double T[kCholNb * kCholNb];
     __shared__ int good;
     if (*flag) return;
+    // rows k0 + b .. n-1 of the panel: x L11^T = a, one thread per row.  Only
+    // the last panel can be narrower than kCholNb, and it has no rows below.
+    // Each thread's row is loaded before the diagonal block is factored (the
+    // loads overlap the factorization; a thread past n loads row n-1 and
+    // stores nothing).
+    const int i = k0 + b + blockIdx.x * blockDim.x + threadIdx.x;
+    const int ii = min(i, n - 1);
+    double x[kCholNb];
+    if (k0 + b < n) {
+#pragma unroll
+        for (int j = 0; j < kCholNb; ++j) x[j] = A[(size_t)(k0 + j) * n + ii];
+    }
     if (threadIdx.x < 64) {
-        const bool ok = chol_block_wave(A, n, k0, b, T);
+        const bool ok = chol_block_regs(A, n, k0, b, T);
         if (threadIdx.x == 0) good = ok ? 1 : 0;
     }
     __syncthreads();
@@ -794,27 +834,10 @@ __global__ __launch_bounds__(256) void k_chol_panel(double *__restrict__ A, int 
         if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
         return;
     }
-    if (blockIdx.x == 0)
-        for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-            const int i = t % b, j = t / b;
-            if (i >= j) A[(size_t)(k0 + j) * n + k0 + i] = T[j * kCholNb + i];
-        }
-    // rows k0 + b .. n-1 of the panel: x L11^T = a, one thread per row
-    const int i = k0 + b + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double x[kCholNb];
+    tri_solve_regs(x, T);
 #pragma unroll
-    for (int j = 0; j < kCholNb; ++j) {
-        if (j < b) {
-            double s = A[(size_t)(k0 + j) * n + i];
-#pragma unroll
-            for (int p = 0; p < j; ++p) s -= x[p] * T[p * kCholNb + j];
-            x[j] = s / T[j * kCholNb + j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kCholNb; ++j)
-        if (j < b) A[(size_t)(k0 + j) * n + i] = x[j];
+    for (int j = 0; j < kCholNb; ++j) A[(size_t)(k0 + j) * n + i] = x[j];
 }
 
 // Lower-triangle tile index w -> (ti, tj), ti >= tj.
@@ -825,7 +848,9 @@ __device__ __forceinline__ void tri_tile(int w, int &ti, int &tj) {
     tj = w - ti * (ti + 1) / 2;
 }
 
-// trailing update of the lower triangle of rows / columns r0.. (r0 = k0 + b)
+// Trailing update of the lower triangle of rows / columns k0 + b..: one
+// wavefront per 16 x 16 tile (more wavefronts in flight hide the operand
+// loads better than 32 x 32 blocks per wavefront, measured).
 __global__ __launch_bounds__(256) void k_chol_update(double *__restrict__ A, int n, int k0, int b, int ntile,
                                                      const int *__restrict__ flag) {
     if (*flag) return;
@@ -863,7 +888,8 @@ __global__ __launch_bounds__(256) void k_zero_upper(double *__restrict__ A, int 
 // block row k (kCholNb rows), k_trinv_rows solves the diagonal block against
 // those rows of the right-hand side (one thread per column), k_trinv_update
 // subtracts G_ik W_k from every block row below (16 x 16 MFMA tiles).  Then
-// k_inv_syrk forms the lower triangle of W^T W tile by tile (and mirrors it).
+// k_inv_syrk forms the lower triangle of W^T W in 32 x 32 blocks (and mirrors
+// it).
 __global__ __launch_bounds__(256) void k_identity(double *__restrict__ W, int n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * n) return;
@@ -872,28 +898,30 @@ __global__ __launch_bounds__(256) void k_identity(double *__restrict__ W, int n)
 
 // 256 columns of the block row per workgroup: the block (b rows x 256
 // columns, each column's b values contiguous in W) is read and written
-// coalesced through LDS, and each thread forward-substitutes one column.
+// coalesced through LDS, and each thread forward-substitutes one column in
+// its registers against L_kk (row-major in LDS, identity rows past b).
 __global__ __launch_bounds__(256) void k_trinv_rows(const double *__restrict__ G, double *__restrict__ W, int n,
                                                     int k0, int b) {
     __shared__ double T[kCholNb * kCholNb];
     __shared__ double X[256 * (kCholNb + 1)];   // column t at X[t * (kCholNb + 1)], padded against bank conflicts
-    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
-        const int i = t % b, j = t / b;
-        T[j * kCholNb + i] = i >= j ? G[(size_t)(k0 + j) * n + k0 + i] : 0.0;
+    for (int t = threadIdx.x; t < kCholNb * kCholNb; t += blockDim.x) {
+        const int i = t / kCholNb, j = t % kCholNb;
+        T[t] = (i < b && j <= i) ? G[(size_t)(k0 + j) * n + k0 + i] : (i == j ? 1.0 : 0.0);
     }
     const int cbase = blockIdx.x * 256, ncol = min(256, k0 + b - cbase);
-    for (int t = threadIdx.x; t < ncol * b; t += blockDim.x) {
-        const int i = t % b, cc = t / b;
-        X[cc * (kCholNb + 1) + i] = W[(size_t)(cbase + cc) * n + k0 + i];
+    for (int t = threadIdx.x; t < ncol * kCholNb; t += blockDim.x) {   // zero rows past b
+        const int i = t % kCholNb, cc = t / kCholNb;
+        X[cc * (kCholNb + 1) + i] = i < b ? W[(size_t)(cbase + cc) * n + k0 + i] : 0.0;
     }
     __syncthreads();
     if ((int)threadIdx.x < ncol) {
         double *xc = X + threadIdx.x * (kCholNb + 1);
-        for (int i = 0; i < b; ++i) {
-            double s = xc[i];
-            for (int p = 0; p < i; ++p) s -= T[p * kCholNb + i] * xc[p];
-            xc[i] = s / T[i * kCholNb + i];
-        }
+        double x[kCholNb];
+#pragma unroll
+        for (int i = 0; i < kCholNb; ++i) x[i] = xc[i];
+        tri_solve_regs(x, T);
+#pragma unroll
+        for (int i = 0; i < kCholNb; ++i) xc[i] = x[i];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ncol * b; t += blockDim.x) {
@@ -902,7 +930,8 @@ __global__ __launch_bounds__(256) void k_trinv_rows(const double *__restrict__ G
     }
 }
 
-// W[i][c] -= sum_p G[i][k0 + p] W[k0 + p][c], rows i >= k0 + b, columns c < k0 + b
+// W[i][c] -= sum_p G[i][k0 + p] W[k0 + p][c], rows i >= k0 + b, columns
+// c < k0 + b: one wavefront per 16 x 16 tile
 __global__ __launch_bounds__(256) void k_trinv_update(const double *__restrict__ G, double *__restrict__ W, int n,
                                                       int k0, int b, int tcols, int ntile) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -924,44 +953,76 @@ __global__ __launch_bounds__(256) void k_trinv_update(const double *__restrict__
     }
 }
 
-// Ainv = W^T W, lower tiles computed (sum over rows m >= tile row start: W is
-// zero above its diagonal), each mirrored so that Ainv is exactly symmetric
+// Ainv = W^T W: one wavefront per 32 x 32 block of the lower triangle (2 x 2
+// MFMA tiles; the sum runs over rows m >= the block's first row, W being
+// zero above its diagonal), each entry r >= c written with its mirror so
+// that Ainv is exactly symmetric
 __global__ __launch_bounds__(256) void k_inv_syrk(const double *__restrict__ W, double *__restrict__ Ainv, int n,
                                                   int ntile) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (w >= ntile) return;
     int ti, tj;
     tri_tile(w, ti, tj);
-    const int i0 = 16 * ti, j0 = 16 * tj;
+    const int i0 = 32 * ti, j0 = 32 * tj;
     const int lr = lane & 15, lk = lane >> 4;
-    const bool iok = i0 + lr < n, jok = j0 + lr < n;
-    const double *wi = W + (size_t)min(i0 + lr, n - 1) * n, *wj = W + (size_t)min(j0 + lr, n - 1) * n;
-    v4d_t acc = {0.0, 0.0, 0.0, 0.0};
+    bool iok[2], jok[2];
+    const double *wi[2], *wj[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int r = i0 + 16 * h + lr, c = j0 + 16 * h + lr;
+        iok[h] = r < n;
+        jok[h] = c < n;
+        wi[h] = W + (size_t)min(r, n - 1) * n;
+        wj[h] = W + (size_t)min(c, n - 1) * n;
+    }
+    v4d_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d_t{0.0, 0.0, 0.0, 0.0};
     int m = i0;
-    for (; m + 16 <= n; m += 16) {   // four products per round, loads first
-        double a[4], bb[4];
+    for (; m + 8 <= n; m += 8) {   // two K-steps per round, loads first
+        double a[2][2], bb[2][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = iok ? wi[m + 4 * u + lk] : 0.0;
-            bb[u] = jok ? wj[m + 4 * u + lk] : 0.0;
-        }
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[u], acc, 0, 0, 0);
+            for (int h = 0; h < 2; ++h) {
+                a[u][h] = iok[h] ? wi[h][m + 4 * u + lk] : 0.0;
+                bb[u][h] = jok[h] ? wj[h][m + 4 * u + lk] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][i], bb[u][j], acc[i][j], 0, 0, 0);
     }
     for (; m < n; m += 4) {
         const int mm = m + lk;
-        const double a = (iok && mm < n) ? wi[mm] : 0.0;
-        const double bb = (jok && mm < n) ? wj[mm] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+        double a[2], bb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            a[h] = (iok[h] && mm < n) ? wi[h][mm] : 0.0;
+            bb[h] = (jok[h] && mm < n) ? wj[h][mm] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = i0 + lk + 4 * q, c = j0 + lr;   // entry (r, c) = sum_m W[m][r] W[m][c]
-        if (r < n && c < n && r >= c) {   // each entry of the lower triangle once, then its mirror
-            Ainv[(size_t)c * n + r] = acc[q];
-            Ainv[(size_t)r * n + c] = acc[q];
-        }
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = i0 + 16 * i + lk + 4 * q, c = j0 + 16 * j + lr;   // sum_m W[m][r] W[m][c]
+                if (r < n && c < n && r >= c) {
+                    Ainv[(size_t)c * n + r] = acc[i][j][q];
+                    Ainv[(size_t)r * n + c] = acc[i][j][q];
+                }
+            }
 }
 
 // W = G^{-1} one column per wavefront: forward substitution G w = e_c in
@@ -2330,7 +2391,7 @@ hipError_t launch_coarse_inverse(const double *G, int n, double *W, double *Ainv
                 k_trinv_update<<<(ntile + 3) / 4, 256, 0, st>>>(G, W, n, k0, b, tc, ntile);
             }
         }
-        const int T = (n + 15) / 16, ntile = T * (T + 1) / 2;
+        const int T = (n + 31) / 32, ntile = T * (T + 1) / 2;
         k_inv_syrk<<<(ntile + 3) / 4, 256, 0, st>>>(W, Ainv, n, ntile);
         return hipGetLastError();
     }
@@ -2473,6 +2534,16 @@ __global__ __launch_bounds__(kGsBlock) void k_floor_chain(const int32_t *__restr
 hipError_t launch_floor(int kind, int nblk, const int32_t *idx, const float *v, float *out, int n, hipStream_t st) {
     if (kind == 0) k_floor_empty<<<nblk, kGsBlock, 0, st>>>();
     else k_floor_chain<<<nblk, kGsBlock, 0, st>>>(idx, v, out, n);
+    return hipGetLastError();
+}
+
+// one wavefront sleeping for a fixed count (~3.4 us per iteration): holds a
+// stream while the host queues work behind it
+__global__ __launch_bounds__(64) void k_delay(int iters) {
+    for (int i = 0; i < iters; ++i) __builtin_amdgcn_s_sleep(127);
+}
+hipError_t launch_delay(int iters, hipStream_t st) {
+    k_delay<<<1, 64, 0, st>>>(iters);
     return hipGetLastError();
 }
 

@@ -154,6 +154,8 @@ struct smg_solver_s {
     int prof_kind = -1, prof_level = -1;
     std::vector<hipEvent_t> prof_pool;
     std::vector<double> prof_bytes_pending;      // bytes of each recorded pair
+    std::vector<int64_t> prof_launches_pending;  // launches each recorded pair spans
+    bool prof_group = false;                     // one pair per relaxation call, not per launch
     size_t prof_used = 0;
     double prof_ms = 0.0, prof_bytes = 0.0;
     int64_t prof_launches = 0;
@@ -187,7 +189,7 @@ smg_status get_cycle_graph(smg_solver_s *s, int k, int precision, hipStream_t st
                            hipGraphExec_t *out);
 // profiling helpers: begin returns the event pair index or -1; prof_ev gives
 // the start (0) / stop (1) event to hand to the launch (null when not profiled)
-int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st);
+int prof_begin(smg_solver_s *s, int kind, int level, double bytes, hipStream_t st, int64_t launches = 1);
 hipEvent_t prof_ev(smg_solver_s *s, int idx, int which);
 smg_status prof_collect(smg_solver_s *s);
 // phase timing: phase_mark records an event on st when the phase changes

@@ -540,18 +540,21 @@ class Solver:
         return self._tail(l, L.SMG_TAIL_COARSE, b, None, torch.empty_like(b), k, 0, precision)
 
     # ---- per-launch timing --------------------------------------------
-    PROF = {"gs": 0, "residual": 1, "restrict": 2, "prolong": 3, "coarse": 4, "galerkin": 5}
+    # "gs_group": one event pair around each relaxation call's launches
+    PROF = {"gs": 0, "residual": 1, "restrict": 2, "prolong": 3, "coarse": 4, "galerkin": 5, "gs_group": 0x100}
 
     def profile_enable(self, kind, level=0):
         L.check(self._lib.smg_profile_enable(self._s, self.PROF[kind] if kind else -1, level), "profile_enable")
 
     def launch_floor(self, kind, level, launches=2000):
-        """Average µs per back-to-back launch with level `level`'s widest color
-        grid: kind "empty" or "chain" (index load, dependent load, store)."""
-        us = ctypes.c_double(0.0)
+        """Launches of kind "empty" or "chain" (index load, dependent load,
+        store) with level `level`'s widest color grid, queued ahead of the
+        device: (device µs from one launch to the next, host µs to enqueue
+        one)."""
+        us, host = ctypes.c_double(0.0), ctypes.c_double(0.0)
         L.check(self._lib.smg_launch_floor(self._s, {"empty": 0, "chain": 1}[kind], int(level), int(launches),
-                                           _stream(), ctypes.byref(us)), "launch_floor")
-        return us.value
+                                           _stream(), ctypes.byref(us), ctypes.byref(host)), "launch_floor")
+        return us.value, host.value
 
     def profile_read(self):
         ms = ctypes.c_double(0.0)

@@ -99,3 +99,44 @@ def test_timed_solve_reports_phases(prob):
     total = sum(v for k, v in ph.items() if k != "prepare")
     assert total <= i1["ms"] * 1.05                      # device time inside the wall time of the solve
     assert i0["ms_phase"]["relax"] == 0.0 and i0["ms_phase"]["prepare"] == ph["prepare"]
+
+
+def test_profile_counts_every_relaxation_launch(prob):
+    """smg_profile_enable / smg_profile_read: one event pair per relaxation
+    launch (or per relaxation call with "gs_group"), every launch counted, and
+    the byte rule z (s + 4) + 4 (n + 1) + 3 k n s per sweep (z = entries incl.
+    the diagonal), summed over the colors of the sweep."""
+    S = prob.gpu_solver(tail_rows=-1)
+    k, cycles = 3, 2
+    b = _t(prob.m[:, None] * np.random.default_rng(6).uniform(-1, 1, (prob.sizes[0], k)))
+    for prec, sb in (("fp64", 8), ("fp32ir", 4)):
+        for level, kind in ((-1, "gs"), (1, "gs"), (-1, "gs_group"), (1, "gs_group")):
+            S.profile_enable(kind, level)
+            x, info = S.solve(b, fixed_cycles=cycles, precision=prec)
+            p = S.profile_read()
+            S.profile_enable(None)
+            levels = range(S.num_levels - 1) if level < 0 else [level]
+            launches = cycles * sum(4 * S.colors(l)[1] for l in levels)
+            want = cycles * sum(4 * (S.level_nnz(l) * (sb + 4) + 4 * (S.level_size(l) + 1)
+                                     + 3 * k * S.level_size(l) * sb) for l in levels)
+            assert p["launches"] == launches, (prec, level, kind)
+            assert abs(p["bytes"] - want) <= 1e-12 * want, (prec, level, kind)
+            assert 0 < p["ms"] < info["ms"] * 1.05
+    x1, _ = S.solve(b, fixed_cycles=cycles, precision="fp32ir")
+    S.profile_enable("gs", -1)
+    x2, _ = S.solve(b, fixed_cycles=cycles, precision="fp32ir")
+    S.profile_enable(None)
+    assert bool((x1 == x2).all())                     # profiling changes no result
+
+
+def test_launch_floor(prob):
+    from paper_2104_13755_amd._lib import SmgError
+    S = prob.gpu_solver(tail_rows=-1)
+    for kind in ("empty", "chain"):
+        for level in range(S.num_levels - 1):
+            us, per = S.launch_floor(kind, level, launches=200)
+            assert 0.0 < us < 1e3 and 0.0 < per < 1e3, (kind, level, us, per)
+    with pytest.raises(SmgError):
+        S.launch_floor("chain", S.num_levels - 1)          # the coarsest level has no color launches
+    with pytest.raises(SmgError):
+        S.launch_floor("chain", 0, launches=0)
