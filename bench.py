@@ -266,6 +266,25 @@ def run_steps(S, Vd, t, b, rtol, precision, steps, use_graph):
     return time.perf_counter() - t0, infos, x
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """GB/s of a plain device-to-device copy (bytes read + bytes written per
+    second), timed with events on torch's stream: the measured ceiling the
+    roofline fractions are also quoted against."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def time_solve_only(S, b, rtol, precision, steps, use_graph):
     import torch
     torch.cuda.synchronize()
@@ -467,8 +486,10 @@ def bench_batch(args):
         cb = cycle_bytes(S, b.shape[1] if b.dim() > 1 else 1)
         sm += inf["cycles"] * (cb["relax"] + cb["residual"] + cb["ir"])
         tot_all += inf["cycles"] * sum(cb.values())
+    copy_gbs = copy_bandwidth()
     roof = {"bound": "hbm", "achieved": sm / dt / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": sm / dt / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "frac": sm / dt / 1e9 / HBM_PEAK_GBS, "traffic": None, "copy_gbs": copy_gbs,
+            "frac_of_copy": sm / dt / 1e9 / copy_gbs,
             "kernel": "k_batch_solve (one persistent dispatch: every cycle of every mesh)",
             "bytes_per_batch": sm, "bytes_per_batch_all_steps": tot_all,
             "all_steps_frac": tot_all / dt / 1e9 / HBM_PEAK_GBS,
@@ -936,9 +957,13 @@ def main():
         log(f"phases {prec}: {phases[prec]}")
     diff = float(torch.linalg.norm(x_m - x_d) / torch.linalg.norm(x_d))
 
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s")
+
     def summary(p):
         ach = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else None
-        return {"achieved": ach, "frac": ach / HBM_PEAK_GBS if ach else None, "launches": p["launches"],
+        return {"achieved": ach, "frac": ach / HBM_PEAK_GBS if ach else None,
+                "frac_of_copy": ach / copy_gbs if ach else None, "launches": p["launches"],
                 "avg_launch_us": p["ms"] * 1e3 / max(1, p["launches"]),
                 "algorithmic_bytes_per_launch": p["bytes"] / max(1, p["launches"])}
     traffic_all, traffic_lv = measured_traffic() if args.profile_kind.startswith("gs") else (None, {})
@@ -964,6 +989,8 @@ def main():
                                         host_enqueue_us=floors[l][1][1],
                                         latency_frac=floors[l][1][0] / summary(p)["avg_launch_us"])
                            for l, p in prof_lv.items()},
+                "copy_gbs": copy_gbs, "frac_of_copy": top["frac_of_copy"],
+                "copy_rule": "1 GiB device-to-device copy (torch copy_), bytes read + written per second",
                 "latency_rule": "floor_chain_us: device launch-to-launch time of 2000 back-to-back launches, queued "
                                 "ahead of the device, with the level's widest color grid whose threads load an index "
                                 "(the level's column array), the value it points to, and store it (floor_empty_us: "
