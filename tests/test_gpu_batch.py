@@ -56,7 +56,7 @@ def test_batch_matches_oracle_and_unbatched(batch_case):
         _check(batch_case, xs, infos, 1e-8)
         for c, x, info in zip(batch_case, xs, infos):
             xu, iu = c["S"].solve(c["b"], rtol=1e-8, precision=prec)
-            assert abs(iu["cycles"] - info["cycles"]) <= 1
+            assert iu["cycles"] == info["cycles"], (c["w"]["name"], prec, iu["cycles"], info["cycles"])
             rel = float((x - xu).norm() / xu.norm())
             assert rel < (1e-12 if prec == "fp64" else 1e-6), (c["w"]["name"], prec, rel)
         # replay of the captured graph: bitwise identical
