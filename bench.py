@@ -941,7 +941,8 @@ def main():
     S.profile_enable(None)
     # latency bound of a launch with each level's grid: an empty kernel and a
     # kernel with the relaxation's dependent chain (index, gather, store)
-    floors = {l: (S.launch_floor("empty", l), S.launch_floor("chain", l)) for l in launch_levels}
+    floors = {l: (S.launch_floor("empty", l), S.launch_floor("chain", l), S.launch_floor("chain_rw", l))
+              for l in launch_levels}
     t_fp64, infos_d, x_d = run_steps(S, Vd, w["t"], b, rtol, "fp64", args.steps, use_graph)
     log(f"fp64: {t_fp64 / args.steps * 1e3:.2f} ms/step cycles={infos_d[-1]['cycles']} res={max(infos_d[-1]['rel_res']):.2e}")
     so_m, _ = time_solve_only(S, b, rtol, "fp32ir", args.steps, use_graph)
@@ -986,6 +987,7 @@ def main():
                             "second pass of the same timed steps",
                 "levels": {str(l): dict(summary(p), colors=S.colors(l)[1], traffic=traffic_lv.get(l),
                                         floor_empty_us=floors[l][0][0], floor_chain_us=floors[l][1][0],
+                                        floor_chain_rw_us=floors[l][2][0],
                                         host_enqueue_us=floors[l][1][1],
                                         latency_frac=floors[l][1][0] / summary(p)["avg_launch_us"])
                            for l, p in prof_lv.items()},
@@ -994,7 +996,8 @@ def main():
                 "latency_rule": "floor_chain_us: device launch-to-launch time of 2000 back-to-back launches, queued "
                                 "ahead of the device, with the level's widest color grid whose threads load an index "
                                 "(the level's column array), the value it points to, and store it (floor_empty_us: "
-                                "an empty kernel; host_enqueue_us: host time to enqueue one such launch); "
+                                "an empty kernel; floor_chain_rw_us: the chain gathering what the previous launch "
+                                "wrote, as color launches do; host_enqueue_us: host time to enqueue one such launch); "
                                 "latency_frac = floor_chain_us / the level's relaxation time per launch"}
     value = args.steps / t_mixed
     out = {

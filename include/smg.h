@@ -465,8 +465,12 @@ smg_status smg_profile_read(smg_solver s, double *total_ms, int64_t *launches, d
  * grid of level `level`'s widest color (one 64-thread workgroup per slice),
  * of an empty kernel (kind 0) or of a kernel whose threads load an index
  * (the level's own column array), then the value it points to, and store it
- * (kind 1: the dependent chain of a relaxation launch).  The launches are
- * queued behind a bounded sleep kernel that outlasts their enqueueing, so
+ * (kind 1: the dependent chain of a relaxation launch), or that chain with
+ * the level's two FP32 work vectors alternating as source and destination,
+ * so each launch gathers values the previous one wrote (kind 2, as
+ * successive color launches do; both vectors are zero again on return).
+ * The launches are queued behind a bounded sleep kernel that outlasts their
+ * enqueueing, so
  * *us = the device's launch-to-launch time (one event pair around them all);
  * *us_host (may be NULL) = host time to enqueue one launch.  Synchronizes the
  * stream.  Errors: INVALID_ARG, HIP. */

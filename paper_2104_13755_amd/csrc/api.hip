@@ -1927,7 +1927,7 @@ extern "C" smg_status smg_profile_enable(smg_solver s, int32_t kind, int32_t lev
 
 extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level, int32_t launches,
                                        smg_stream stream, double *us, double *us_host) {
-    if (!s || !us || (kind != 0 && kind != 1) || launches < 1 || launches > 4000 || level < 0 ||
+    if (!s || !us || kind < 0 || kind > 2 || launches < 1 || launches > 4000 || level < 0 ||
         level >= s->nlev || s->lev[level].coarsest)
         return fail(SMG_ERR_INVALID_ARG, "smg_launch_floor: bad arguments");
     HIPCHK(hipSetDevice(s->device));
@@ -1954,8 +1954,14 @@ extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level
         if (hipEventRecord(ed, st) != hipSuccess || launch_delay(iters, st) != hipSuccess ||
             hipEventRecord(s->ev_prep0, st) != hipSuccess) { rc = SMG_ERR_HIP; break; }
         const auto t0 = std::chrono::steady_clock::now();
-        for (int i = 0; i < launches && rc == SMG_OK; ++i)
-            if (launch_floor(kind, slices, D.cols, D.x32, D.r32, n, st) != hipSuccess) rc = SMG_ERR_HIP;
+        for (int i = 0; i < launches && rc == SMG_OK; ++i) {
+            // kind 2: the two FP32 work vectors alternate, so each launch gathers
+            // what the previous one wrote
+            const bool swap = kind == 2 && (i & 1);
+            if (launch_floor(kind == 0 ? 0 : 1, slices, D.cols, swap ? D.r32 : D.x32, swap ? D.x32 : D.r32, n, st) !=
+                hipSuccess)
+                rc = SMG_ERR_HIP;
+        }
         const auto t1 = std::chrono::steady_clock::now();
         if (rc != SMG_OK || hipEventRecord(s->ev_prep1, st) != hipSuccess ||
             hipEventSynchronize(s->ev_prep1) != hipSuccess) { rc = SMG_ERR_HIP; break; }
@@ -1970,6 +1976,10 @@ extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level
     }
     (void)hipEventDestroy(ed);
     if (rc != SMG_OK) return fail(rc, "smg_launch_floor: timing failed");
+    // leave the work vectors as a solve leaves them (zero)
+    HIPCHK(launch_fill<float>(D.x32, 0.0f, (int64_t)D.n * 4, st));
+    HIPCHK(launch_fill<float>(D.r32, 0.0f, (int64_t)D.n * 4, st));
+    HIPCHK(hipStreamSynchronize(st));
     *us = 1e3 * dev_ms / launches;
     if (us_host) *us_host = 1e3 * host_ms / launches;
     return SMG_OK;

@@ -547,12 +547,14 @@ class Solver:
         L.check(self._lib.smg_profile_enable(self._s, self.PROF[kind] if kind else -1, level), "profile_enable")
 
     def launch_floor(self, kind, level, launches=2000):
-        """Launches of kind "empty" or "chain" (index load, dependent load,
-        store) with level `level`'s widest color grid, queued ahead of the
+        """Launches of kind "empty", "chain" (index load, dependent load,
+        store) or "chain_rw" (the chain gathering what the previous launch
+        wrote) with level `level`'s widest color grid, queued ahead of the
         device: (device µs from one launch to the next, host µs to enqueue
         one)."""
         us, host = ctypes.c_double(0.0), ctypes.c_double(0.0)
-        L.check(self._lib.smg_launch_floor(self._s, {"empty": 0, "chain": 1}[kind], int(level), int(launches),
+        L.check(self._lib.smg_launch_floor(self._s, {"empty": 0, "chain": 1, "chain_rw": 2}[kind], int(level),
+                                           int(launches),
                                            _stream(), ctypes.byref(us), ctypes.byref(host)), "launch_floor")
         return us.value, host.value
 

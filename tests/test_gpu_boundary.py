@@ -132,7 +132,7 @@ def test_profile_counts_every_relaxation_launch(prob):
 def test_launch_floor(prob):
     from paper_2104_13755_amd._lib import SmgError
     S = prob.gpu_solver(tail_rows=-1)
-    for kind in ("empty", "chain"):
+    for kind in ("empty", "chain", "chain_rw"):
         for level in range(S.num_levels - 1):
             us, per = S.launch_floor(kind, level, launches=200)
             assert 0.0 < us < 1e3 and 0.0 < per < 1e3, (kind, level, us, per)

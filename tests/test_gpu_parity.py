@@ -223,3 +223,41 @@ def test_coarsest_factor_many_workgroups(levels):
     assert rel(S.coarse_factor(), O.G) < 1e-12
     bc = np.random.default_rng(9).uniform(-1, 1, (O.A[-1].shape[0], 2))
     assert rel(_np(S.coarse_solve(_t(bc))), O.coarse_solve(bc)) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def ico_matrix():
+    from synth import meshes
+    from oracle import assemble as AS
+    if not gpu_available():
+        pytest.skip("no GPU")
+    V, F = meshes.icosphere_subdiv(5)
+    A, _, _ = AS.system(V, F, 1e-3)
+    return A.tocsr()
+
+
+@pytest.mark.parametrize("n_h", [97, 100, 127, 128, 129, 161, 300])
+def test_coarsest_factor_panel_edges(n_h, ico_matrix):
+    """Coarsest sizes around the panel width (32) just above the one-workgroup
+    limit (96): full panels, a last panel of 1 or 4 columns, several panels.
+    Two levels over the icosphere L5 system with P_ic = 1 for c = i mod n_H
+    (full column rank, so A_H = PᵀAP is SPD and dense); the factor and A_H⁻¹ b
+    are compared with numpy's Cholesky and solve of the same A_H within
+    1e-12."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import scipy.sparse as sp
+    from helpers import ell3
+    from paper_2104_13755_amd.solver import Hierarchy, Solver
+    A = ico_matrix
+    n0 = A.shape[0]
+    P = sp.csr_matrix((np.ones(n0), (np.arange(n0), np.arange(n0) % n_h)), shape=(n0, n_h))
+    c, w = ell3(P)
+    h = Hierarchy.from_prolongations([n0, n_h], [c], [w])
+    S = Solver(h, A.indptr, A.indices)
+    S.set_values(_t(A.data))
+    AH = (P.T @ A @ P).toarray()
+    G = np.linalg.cholesky(AH)
+    assert rel(S.coarse_factor(), G) < 1e-12
+    bc = np.random.default_rng(n_h).uniform(-1, 1, (n_h, 3))
+    assert rel(_np(S.coarse_solve(_t(bc))), np.linalg.solve(AH, bc)) < 1e-12
