@@ -261,3 +261,27 @@ def test_coarsest_factor_panel_edges(n_h, ico_matrix):
     assert rel(S.coarse_factor(), G) < 1e-12
     bc = np.random.default_rng(n_h).uniform(-1, 1, (n_h, 3))
     assert rel(_np(S.coarse_solve(_t(bc))), np.linalg.solve(AH, bc)) < 1e-12
+
+
+def test_team_vcycle_matches_launches():
+    """The opt-in one-XCD team (smg_opts.team_level: levels >= 1 in one kernel
+    whose workgroups meet at L2-local barriers) computes the same cycle as
+    the per-color launches: FP64 within 1e-12 of them and of the oracle's
+    cycles, FP32 cycles within 1e-7, equal cycle counts to 1e-8."""
+    if not gpu_available():
+        pytest.skip("no GPU")
+    p = Problem("torus-96x40")
+    base = p.gpu_solver(tail_rows=-1)
+    team = p.gpu_solver(tail_rows=-1, team_level=1, team_size=8)
+    rng = np.random.default_rng(12)
+    b = p.m[:, None] * rng.uniform(-1, 1, (p.sizes[0], 3))
+    xo, _, _ = p.oracle.solve(b, 0.0, fixed_cycles=3)
+    for prec, tol in (("fp64", 1e-12), ("fp32ir", 1e-7)):
+        x0, _ = base.solve(_t(b), fixed_cycles=3, precision=prec)
+        x1, _ = team.solve(_t(b), fixed_cycles=3, precision=prec)
+        assert np.linalg.norm(_np(x1) - _np(x0)) / np.linalg.norm(_np(x0)) < tol, prec
+        if prec == "fp64":
+            assert np.linalg.norm(_np(x1) - xo) / np.linalg.norm(xo) < 1e-12
+        _, i0 = base.solve(_t(b), rtol=1e-8, precision=prec)
+        _, i1 = team.solve(_t(b), rtol=1e-8, precision=prec)
+        assert i0["cycles"] == i1["cycles"] and max(i1["rel_res"]) <= 1e-8, prec
