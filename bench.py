@@ -126,6 +126,8 @@ def trace_summary(d, bench_json):
     back-to-back launches / launches: what the bench's events measure)."""
     import re
     b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    if b.get("config", {}).get("launch_mode_ms_per_step"):
+        raise ValueError("the launch mode was chosen by timing (extra steps): profile with --graph 0")
     roof = b["roofline"]
     steps, warm = b["steps"], b["warmup"]
     colors = [roof["levels"][str(l)]["colors"] for l in range(len(roof["levels"]))]
@@ -824,7 +826,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, nargs=2, default=(1000, 1000))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="1: replay each cycle from a captured hipGraph, 0: eager launches, -1: the faster of the two")
     ap.add_argument("--profile-kind", default="gs_group")
     ap.add_argument("--workload", default="torus",
                     choices=["torus", "batch", "grad", "frames", "pcg", "jacobi", "split", "smooth", "coarse"])
@@ -922,6 +925,24 @@ def main():
     # warmup both precisions
     for prec in ("fp32ir", "fp64"):
         run_steps(S, Vd, w["t"], b, rtol, prec, args.warmup, use_graph)
+    # Launch mode per precision: eager launches, or every cycle replayed from
+    # a captured hipGraph (the same iterates bit for bit).  --graph -1 times
+    # both after the warmup and keeps the faster: the host's cost to enqueue
+    # one launch (2.3-3.3 us) differs between machines, a replay's does not.
+    graph, mode_ms = {}, {}
+    for prec in ("fp32ir", "fp64"):
+        if args.graph >= 0:
+            graph[prec] = bool(args.graph)
+            continue
+        run_steps(S, Vd, w["t"], b, rtol, prec, 1, True)
+        te = tg = 0.0
+        for _ in range(2):
+            te += run_steps(S, Vd, w["t"], b, rtol, prec, 2, False)[0]
+            tg += run_steps(S, Vd, w["t"], b, rtol, prec, 2, True)[0]
+        graph[prec] = tg < te
+        mode_ms[prec] = {"eager": te / 4 * 1e3, "graph": tg / 4 * 1e3}
+        log(f"launch mode {prec}: eager {te / 4 * 1e3:.2f} ms/step, graph {tg / 4 * 1e3:.2f} ms/step")
+    use_graph = graph["fp32ir"]
     # timed region: mixed precision, no instrumentation
     t_mixed, infos_m, x_m = run_steps(S, Vd, w["t"], b, rtol, "fp32ir", args.steps, use_graph)
     log(f"mixed: {t_mixed / args.steps * 1e3:.2f} ms/step cycles={infos_m[-1]['cycles']} res={max(infos_m[-1]['rel_res']):.2e}")
@@ -943,10 +964,10 @@ def main():
     # kernel with the relaxation's dependent chain (index, gather, store)
     floors = {l: (S.launch_floor("empty", l), S.launch_floor("chain", l), S.launch_floor("chain_rw", l))
               for l in launch_levels}
-    t_fp64, infos_d, x_d = run_steps(S, Vd, w["t"], b, rtol, "fp64", args.steps, use_graph)
+    t_fp64, infos_d, x_d = run_steps(S, Vd, w["t"], b, rtol, "fp64", args.steps, graph["fp64"])
     log(f"fp64: {t_fp64 / args.steps * 1e3:.2f} ms/step cycles={infos_d[-1]['cycles']} res={max(infos_d[-1]['rel_res']):.2e}")
     so_m, _ = time_solve_only(S, b, rtol, "fp32ir", args.steps, use_graph)
-    so_d, _ = time_solve_only(S, b, rtol, "fp64", args.steps, use_graph)
+    so_d, _ = time_solve_only(S, b, rtol, "fp64", args.steps, graph["fp64"])
     # one more step per precision with an event at every change of phase
     # (the paper's Tab. "profile" buckets), outside the timed region
     phases = {}
@@ -1008,7 +1029,9 @@ def main():
         "dtype": "f32/f64", "data": "synthetic",
         "config": {"workload": f"{w['name']} torus R=1 r=0.3 jitter 0.2, A=M+1e-2 L, 3 RHS b=M X, "
                                f"{n_levels} levels, mu 2/2, rtol 1e-8",
-                   "vertices": len(w["V"]), "levels": h.sizes, "rhs": 3, "graph": use_graph},
+                   "vertices": len(w["V"]), "levels": h.sizes, "rhs": 3, "graph": graph,
+                   "launch_mode": "chosen by timing eager and graph steps after the warmup" if args.graph < 0
+                   else "set by --graph", "launch_mode_ms_per_step": mode_ms},
         "fp64": {"value": args.steps / t_fp64, "ms_per_step": t_fp64 / args.steps * 1e3,
                  "cycles": infos_d[-1]["cycles"], "rel_res": infos_d[-1]["rel_res"],
                  "solve_only_per_s": 1.0 / so_d},
