@@ -27,6 +27,36 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// Sum over aligned groups of g adjacent lanes (g = 1, 2, 4 or 8, the same
+// in the whole wavefront) by DPP lane swaps: lane ^ 1 and lane ^ 2 inside each
+// quad, then the mirror of each 8-lane half-row (lane i <-> 7 - i), so every
+// lane of a group ends with the group's sum, ((a0 + a1) + (a2 + a3)) + the
+// other quad's.  All lanes of a group must be active.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_mov(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    } else {
+        const long long u = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+        return __hiloint2double(hi, lo);
+    }
+}
+template <int K, typename T>
+__device__ __forceinline__ void group_sum(T (&acc)[K], int g) {
+    constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141;   // quad_perm [1,0,3,2], [2,3,0,1]
+    if (g >= 2)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += dpp_mov<kXor1>(acc[q]);
+    if (g >= 4)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += dpp_mov<kXor2>(acc[q]);
+    if (g >= 8)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += dpp_mov<kHalfMirror>(acc[q]);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -89,9 +119,7 @@ __device__ __forceinline__ void row_gather(int o, int w, int lpr, const int32_t 
         else if (rem <= 4) gather_chunk<4, K, T>(o, e, w, cols, vals, x, acc);
         else gather_chunk<8, K, T>(o, e, w, cols, vals, x, acc);
     }
-    for (int m = lpr >> 1; m > 0; m >>= 1)
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+    group_sum<K>(acc, lpr);
 }
 
 // x_i <- (b_i - sum_{j != i} A_ij x_j) / A_ii for every row i of one color.
@@ -533,9 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, int lr, const int32
 #pragma unroll
             for (int q = 0; q < K; ++q) acc[q] += wt[u] * rv[u][q];
     }
-    for (int m = lr >> 1; m > 0; m >>= 1)
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+    group_sum<K>(acc, lr);
     if (a < nc && j == 0) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
@@ -1268,9 +1294,7 @@ __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool va
             for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)cc * K + q];
         }
     }
-    for (int m = G >> 1; m > 0; m >>= 1)
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+    group_sum<K>(acc, G);
 }
 
 template <int K, typename T>
@@ -1349,11 +1373,7 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
                         for (int q = 0; q < K; ++q) acc[q] += w * gld(L.r, (size_t)i * K + q);
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < K; ++q) {
-                    acc[q] += __shfl_xor(acc[q], 1, 64);
-                    acc[q] += __shfl_xor(acc[q], 2, 64);
-                }
+                group_sum<K>(acc, 4);
                 if (a < C.n && j == 0) {
 #pragma unroll
                     for (int q = 0; q < K; ++q) gst(C.b, (size_t)a * K + q, acc[q]);
@@ -1387,11 +1407,7 @@ __device__ void wg_vcycle(Team &tm, const TailLevel<T> *__restrict__ lv, int fir
                     for (int q = 0; q < K; ++q) acc[q] += a * (double)gld(C.b, (size_t)jj * K + q);
                 }
             }
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                acc[q] += __shfl_xor(acc[q], 1, 64);
-                acc[q] += __shfl_xor(acc[q], 2, 64);
-            }
+            group_sum<K>(acc, 4);
             if (i < C.n && j == 0) {
 #pragma unroll
                 for (int q = 0; q < K; ++q) gst(C.x, (size_t)i * K + q, (T)acc[q]);
@@ -1554,9 +1570,7 @@ __device__ __forceinline__ void tail_row(const LdsLevel<T> &L, const int2 *wv, i
 #pragma unroll
     for (int q = 0; q < K; ++q) { bq[q] = gld(L.b, (size_t)row * vs + vc + q); acc[q] = T(0); }
     tail_gather<K, KP, T>(L.rec + off + 2 * (tid & 63), kmax, xs, acc);
-    for (int m = G >> 1; m > 0; m >>= 1)
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+    group_sum<K>(acc, G);
 }
 
 // Multicolor Gauss-Seidel on one tail level (App. A): passes in color order
@@ -1673,11 +1687,7 @@ __device__ void tail_coarse(int n, const double *__restrict__ Ainv, const T *bl,
                 }
             }
         }
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-            acc[q] += __shfl_xor(acc[q], 1, 64);
-            acc[q] += __shfl_xor(acc[q], 2, 64);
-        }
+        group_sum<K>(acc, 4);
         if (i < n && j == 0)
 #pragma unroll
             for (int q = 0; q < K; ++q) xl[(size_t)i * KP + q] = (T)acc[q];
