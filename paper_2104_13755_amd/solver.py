@@ -390,9 +390,13 @@ class Solver:
         """V-cycles from x = 0 until every column's relative residual is at most
         rtol (or exactly fixed_cycles).  b: n or n x k (k <= 4) float64 on the
         device.  precision "fp32ir" runs FP32 cycles inside FP64 iterative
-        refinement.  Returns (x, info) with info cycles, rel_res, ms and
-        ms_phase (device ms per phase of Tab. "profile": prepare = the last
-        value refresh, and with timed=True relax, transfer, norm, other)."""
+        refinement.  use_graph replays each cycle from a captured hipGraph:
+        the same iterates bit for bit, one host call per cycle instead of one
+        per launch (faster wherever the host enqueues a launch more slowly
+        than the device runs it).  Returns (x, info) with info cycles,
+        rel_res, ms and ms_phase (device ms per phase of Tab. "profile":
+        prepare = the last value refresh, and with timed=True relax,
+        transfer, norm, other)."""
         b2 = b if b.dim() == 2 else b.unsqueeze(1)
         b2 = b2.contiguous()
         k = self._vecs(self.n, ("b", b2))
