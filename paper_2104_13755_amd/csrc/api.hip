@@ -1950,7 +1950,7 @@ extern "C" smg_status smg_launch_floor(smg_solver s, int32_t kind, int32_t level
     smg_status rc = SMG_OK;
     double dev_ms = 0.0, host_ms = 0.0;
     int iters = 2 * launches + 64;   // ~3.4 us per iteration
-    for (int rep = 0; rep < 4 && rc == SMG_OK; ++rep) {   // round 0 warms up
+    for (int rep = 0; rep < 4 && rc == SMG_OK; ++rep) {   // the first repetition warms up
         if (hipEventRecord(ed, st) != hipSuccess || launch_delay(iters, st) != hipSuccess ||
             hipEventRecord(s->ev_prep0, st) != hipSuccess) { rc = SMG_ERR_HIP; break; }
         const auto t0 = std::chrono::steady_clock::now();
