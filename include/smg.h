@@ -486,6 +486,9 @@ typedef struct {
     int32_t lanes_coarse;     /* lanes per row on the Galerkin levels: 1,2,4,8; 0 = tuned/default */
     int32_t team_max;         /* most workgroups per mesh (1..64); 0 = tuned/default */
     const char *cache_file;   /* autotune cache (read at create, written by autotune); may be NULL */
+    int32_t device_teams;     /* 0: each team's workgroups on one XCD, meeting at barriers in
+                                 that XCD's L2 (when the teams can be placed so); 1: teams
+                                 anywhere, barriers through device-scope atomics */
 } smg_batch_opts;
 
 /* Group solvers (same device, at least two levels each) for batched solves:
@@ -493,7 +496,10 @@ typedef struct {
  * by a team of workgroups (1..team_max, in proportion to its size, all
  * resident at once; largest meshes first) that loops over its own V-cycles
  * with barriers between dependent phases and the convergence test on the
- * device; converged meshes stop.  The solvers must outlive the batch.
+ * device; converged meshes stop.  Unless o->device_teams, whole teams are
+ * packed onto the 8 XCDs (workgroups i and i + 8 are dispatched to the same
+ * XCD) so that a team's barriers stay in its XCD's L2; a team found spread
+ * over XCDs fails the solve (HIP).  The solvers must outlive the batch.
  * Errors: INVALID_ARG, OOM. */
 smg_status smg_batch_create(const smg_solver *solvers, int32_t count, const smg_batch_opts *o,
                             smg_batch *out);

@@ -14,12 +14,16 @@ class BatchSolver:
     paper_2104_13755_amd.solver.Solver objects with values set; they must
     outlive the batch."""
 
-    def __init__(self, solvers, threads=0, lanes_level0=0, lanes_coarse=0, team_max=0, cache_file=None):
+    def __init__(self, solvers, threads=0, lanes_level0=0, lanes_coarse=0, team_max=0, cache_file=None,
+                 device_teams=False):
+        """device_teams: teams anywhere on the device with device-scope
+        barriers, instead of each team on one XCD with barriers in its L2."""
         self._lib = L.load()
         self.solvers = list(solvers)
         arr = (_c * len(self.solvers))(*[s._s for s in self.solvers])
         self._cache = cache_file.encode() if cache_file else None
-        o = L.BatchOpts(int(threads), int(lanes_level0), int(lanes_coarse), int(team_max), self._cache)
+        o = L.BatchOpts(int(threads), int(lanes_level0), int(lanes_coarse), int(team_max), self._cache,
+                        int(bool(device_teams)))
         h = _c()
         L.check(self._lib.smg_batch_create(arr, len(self.solvers), ctypes.byref(o), ctypes.byref(h)), "batch_create")
         self._b = h

@@ -27,11 +27,15 @@ using namespace smg;
             return fail(SMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+constexpr int kXcds = 8;   // accelerator complex dies: workgroup i runs on die i mod 8
+
 struct smg_batch_s {
     std::vector<smg_solver> solvers;
     int device = 0, count = 0;
     int threads = 1024, lanes0 = 1, lanes_c = 8, team_max = 8;   // launch shape
     int cus = 0, total_blocks = 0;
+    int device_teams = 0;                                  // 1: no XCD packing (device-scope barriers)
+    int local = 0;                                         // the current layout packs teams per XCD
     std::vector<int32_t> team;                             // workgroups per mesh
     int32_t *d_team_mesh = nullptr, *d_team_rank = nullptr;
     unsigned *d_ctr = nullptr;
@@ -112,8 +116,44 @@ static smg_status layout_teams(smg_batch_s *b) {
         return b->solvers[a]->lev[0].nnz_nat > b->solvers[c]->lev[0].nnz_nat;
     });
     std::vector<int32_t> tm, tr;
-    for (int i : order)
-        for (int r = 0; r < b->team[i]; ++r) { tm.push_back(i); tr.push_back(r); }
+    // Whole teams onto the XCDs: workgroups are dispatched to the 8 XCDs
+    // round robin, so workgroups x, x + 8, ... share one XCD; each team goes
+    // (largest first) to the least-loaded of these 8 classes that still has
+    // room for it, and its barriers then stay in that XCD's L2.  Slots left
+    // over are idle workgroups (mesh -1).
+    b->local = 0;
+    if (!b->device_teams && b->cus % kXcds == 0) {
+        const int per_xcd = capacity / kXcds;
+        std::vector<std::vector<int>> bins(kXcds);
+        std::vector<int> load(kXcds, 0);
+        bool fits = true;
+        for (int i : order) {
+            int best = -1;
+            for (int x = 0; x < kXcds; ++x)
+                if (load[x] + b->team[i] <= per_xcd && (best < 0 || load[x] < load[best])) best = x;
+            if (best < 0) { fits = false; break; }
+            bins[best].push_back(i);
+            load[best] += b->team[i];
+        }
+        const int rows = *std::max_element(load.begin(), load.end());
+        if (fits && kXcds * rows <= b->team_capacity) {
+            tm.assign((size_t)kXcds * rows, -1);
+            tr.assign((size_t)kXcds * rows, 0);
+            for (int x = 0; x < kXcds; ++x) {
+                int j = 0;
+                for (int i : bins[x])
+                    for (int r = 0; r < b->team[i]; ++r, ++j) {
+                        tm[(size_t)kXcds * j + x] = i;
+                        tr[(size_t)kXcds * j + x] = r;
+                    }
+            }
+            b->local = 1;
+            b->total_blocks = kXcds * rows;
+        }
+    }
+    if (!b->local)
+        for (int i : order)
+            for (int r = 0; r < b->team[i]; ++r) { tm.push_back(i); tr.push_back(r); }
     HIPCHK(hipMemcpy(b->d_team_mesh, tm.data(), tm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->d_team_rank, tr.data(), tr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     return SMG_OK;
@@ -186,6 +226,7 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
     if (o && o->lanes_level0) b->lanes0 = o->lanes_level0;
     if (o && o->lanes_coarse) b->lanes_c = o->lanes_coarse;
     if (o && o->team_max) b->team_max = o->team_max;
+    b->device_teams = o ? (o->device_teams != 0) : 0;
     if (b->team_max < 1 || b->team_max > 64) return fail(SMG_ERR_INVALID_ARG, "team_max must be 1..64");
     if (b->threads != 256 && b->threads != 512 && b->threads != 1024) return fail(SMG_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
     if (b->lanes0 != 1 && b->lanes0 != 2) return fail(SMG_ERR_INVALID_ARG, "lanes_level0 must be 1 or 2");
@@ -207,7 +248,7 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
     };
     if (!take(&b->d64, b->h64.size() * sizeof(TailLevel<double>)) ||
         !take(&b->d32, b->h32.size() * sizeof(TailLevel<float>)) || !take(&b->d_mesh, count * sizeof(BatchMesh)) ||
-        !take(&b->d_out, count * 8 * sizeof(double)) || !take(&b->d_ctr, count * sizeof(unsigned)) ||
+        !take(&b->d_out, count * 8 * sizeof(double)) || !take(&b->d_ctr, (size_t)count * kBatchCtrStride * sizeof(unsigned)) ||
         !take(&b->d_abort, count * sizeof(int)) || !take(&b->d_partial, (size_t)count * 8 * 64 * sizeof(double)) ||
         !take(&b->d_team_mesh, (size_t)b->team_capacity * sizeof(int32_t)) ||
         !take(&b->d_team_rank, (size_t)b->team_capacity * sizeof(int32_t)))
@@ -285,6 +326,7 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
         M.x_user = d_x[i];
         M.out = b->d_out + 8 * i;
         M.team = b->team[i];
+        M.local = b->local;
     }
     b->last_b.assign(d_b, d_b + b->count);
     b->last_x.assign(d_x, d_x + b->count);
@@ -305,7 +347,10 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     smg_status worst = SMG_OK;
     for (int i = 0; i < b->count; ++i)
-        if (b->h_abort[i]) return fail(SMG_ERR_HIP, "batched solve: a team barrier timed out (workgroups not co-resident?)");
+        if (b->h_abort[i])
+            return fail(SMG_ERR_HIP, b->h_abort[i] == 2
+                                         ? "batched solve: a workgroup of an XCD-local team ran on another XCD"
+                                         : "batched solve: a team barrier timed out (workgroups not co-resident?)");
     for (int i = 0; i < b->count; ++i) {
         const double *o = b->h_out + 8 * i;
         bool conv = true, finite = true;

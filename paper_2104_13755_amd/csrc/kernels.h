@@ -194,6 +194,7 @@ hipError_t launch_gather_records(const int32_t *src, const int32_t *cols, int64_
 struct BatchMesh {
     int k, nlev, mu_pre, mu_post, max_cycles, precision;   // precision: 0 FP64, 1 FP32 + FP64 IR
     int team;                         // workgroups cooperating on this mesh (<= 64)
+    int local;                        // 1: the team's workgroups sit on one XCD (same index mod 8)
     double rtol;
     TailLevel<double> l0;             // level 0 in FP64 (x, b, r, matrix)
     const TailLevel<float> *lv32;     // every level in FP32 (device array)
@@ -216,8 +217,12 @@ hipError_t launch_delay(int iters, hipStream_t st);
 template <typename T>
 hipError_t launch_team_vcycle(const TailLevel<T> *lv, int first, int nlev, int mu_pre, int mu_post,
                               const double *Ainv, unsigned *cb, int *flag, int m, int k, hipStream_t st);
-// team_mesh / team_rank: mesh and member index of every workgroup; ctrs and
-// aborts (count entries) are cleared by the launch; partials: count * 512.
+// team_mesh / team_rank: mesh and member index of every workgroup (mesh -1:
+// an idle workgroup that exits at once); ctrs (count * kBatchCtrStride: per
+// mesh a barrier counter and the XCD of an XCD-local team, 256 bytes apart)
+// and aborts (count entries) are cleared by the launch;
+// partials: count * 512.
+constexpr int kBatchCtrStride = 64;
 hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
                               const int32_t *team_rank, int nblocks_total, int threads,
                               unsigned *ctrs, int *aborts, double *partials, int count,

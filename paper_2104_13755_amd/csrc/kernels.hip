@@ -1948,16 +1948,30 @@ __global__ __launch_bounds__(BS) void k_batch_solve(const BatchMesh *__restrict_
                                                       int *__restrict__ aborts,
                                                       double *__restrict__ partials) {
     const int m = team_mesh[blockIdx.x];
+    if (m < 0) return;   // an idle slot of the XCD-packed grid
     const BatchMesh M = meshes[m];
     Team tm;
     tm.rank = team_rank[blockIdx.x];
     tm.nblk = M.team;
     tm.tid = tm.rank * (int)blockDim.x + (int)threadIdx.x;
     tm.nthreads = tm.nblk * (int)blockDim.x;
-    tm.ctr = ctrs + m;
+    tm.ctr = ctrs + (size_t)m * kBatchCtrStride;
     tm.abort = aborts + m;
     tm.target = 0u;
     tm.partial = partials + (size_t)m * 8 * 64;
+    tm.local = M.local;
+    // the team's L2-local barriers need every member on one XCD: the first
+    // member to arrive records its XCD (device-scope compare-and-swap on a
+    // word the launch cleared), the others check theirs against it
+    if (M.local && threadIdx.x == 0) {
+        unsigned expected = 0u;
+        const unsigned mine = xcc_id() + 1u;
+        unsigned *slot = tm.ctr + 1;
+        if (!__hip_atomic_compare_exchange_strong(slot, &expected, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) &&
+            expected != mine)
+            __hip_atomic_store(tm.abort, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     switch (M.k) {
     case 1: batch_mesh<1>(tm, M); break;
     case 2: batch_mesh<2>(tm, M); break;
@@ -1981,10 +1995,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_values(const double *__restr
     else diag[-1 - s] = v;
 }
 
-// T = A P, one thread per permuted fine row (owner of its T row): the row is
-// accumulated in the thread's own LDS slots (slot k of thread j at k * bs + j)
-// in a fixed order (diagonal term, then the off-diagonal entries), then
-// written out contiguously.
+// T = A P, G lanes per permuted fine row (the owners of its T row): lane g
+// takes the row's off-diagonal entries e = g, g + G, ... (lane 0 also the
+// diagonal term first) and accumulates them in its own LDS slots (slot k of
+// thread i at k * bs + i) in that fixed order; the row's G partial rows are
+// then added in lane order and written out contiguously, so the result does
+// not depend on timing.
+template <int G>
 __global__ __launch_bounds__(64) void k_galerkin_t(
     int n, const int32_t *__restrict__ tptr, const int32_t *__restrict__ plan1ptr,
     const uint16_t *__restrict__ plan1, const int32_t *__restrict__ row_slice,
@@ -1993,33 +2010,47 @@ __global__ __launch_bounds__(64) void k_galerkin_t(
     const double *__restrict__ vals, const double *__restrict__ diag,
     const double *__restrict__ pw, double *__restrict__ Tb) {
     extern __shared__ double acc_t[];
-    const int bs = blockDim.x, j = threadIdx.x;
-    const int r = blockIdx.x * bs + j;
-    if (r >= n) return;
-    double *acc = acc_t + j;
-    const int t0 = tptr[r], len = tptr[r + 1] - t0;
+    const int bs = blockDim.x, rows = bs / G;
+    const int jr = (int)threadIdx.x / G, g = (int)threadIdx.x % G;
+    const int r = blockIdx.x * rows + jr;
+    const bool act = r < n;
+    double *acc = acc_t + threadIdx.x;
+    const int t0 = act ? tptr[r] : 0, len = act ? tptr[r + 1] - t0 : 0;
     for (int k = 0; k < len; ++k) acc[k * bs] = 0.0;
-    const uint16_t *pl = plan1 + plan1ptr[r];
-    const double d = diag[r];
+    if (act) {
+        const uint16_t *pl = plan1 + plan1ptr[r];
+        if (g == 0) {
+            const double d = diag[r];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) acc[pl[m] * bs] += d * pw[(size_t)m * n + r];
-    const int s = row_slice[r];
-    const int base = slice_off[s] + (r - slice_row0[s]) * lpr;
-    const int rl = rowlen[r];
-#pragma unroll 4
-    for (int e = 0; e < rl; ++e) {
-        const int slot = base + (e / lpr) * 64 + (e % lpr);
-        const int c = cols[slot];
-        const double a = vals[slot];
+            for (int m = 0; m < 3; ++m) acc[pl[m] * bs] += d * pw[(size_t)m * n + r];
+        }
+        const int s = row_slice[r];
+        const int base = slice_off[s] + (r - slice_row0[s]) * lpr;
+        const int rl = rowlen[r];
+#pragma unroll 2
+        for (int e = g; e < rl; e += G) {
+            const int slot = base + (e / lpr) * 64 + (e % lpr);
+            const int c = cols[slot];
+            const double a = vals[slot];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) acc[pl[3 * (e + 1) + m] * bs] += a * pw[(size_t)m * n + c];
+            for (int m = 0; m < 3; ++m) acc[pl[3 * (e + 1) + m] * bs] += a * pw[(size_t)m * n + c];
+        }
     }
-    for (int k = 0; k < len; ++k) Tb[t0 + k] = acc[k * bs];
+    __syncthreads();
+    for (int k = g; k < len; k += G) {
+        double v = 0.0;
+#pragma unroll
+        for (int h = 0; h < G; ++h) v += acc_t[k * bs + jr * G + h];
+        Tb[t0 + k] = v;
+    }
 }
 
-// A_{l+1} = P^T T, one thread per permuted coarse row: contributions w T_rb
-// in (R entry, T entry) order into the row's local LDS slots, then each slot
-// stored to its position in level l+1.
+// A_{l+1} = P^T T, G lanes per permuted coarse row: lane g takes the row's R
+// entries p = g, g + G, ... (each contributing w T_rb for every entry of T row
+// r) into its own LDS slots, in (R entry, T entry) order; the G partial rows
+// are then added in lane order and each slot stored to its position in level
+// l+1.
+template <int G>
 __global__ __launch_bounds__(64) void k_galerkin_c(
     int nc, const int32_t *__restrict__ plan2ptr, const uint16_t *__restrict__ plan2,
     const int32_t *__restrict__ rptr, const int32_t *__restrict__ ridx,
@@ -2027,24 +2058,35 @@ __global__ __launch_bounds__(64) void k_galerkin_c(
     const double *__restrict__ Tb, const int32_t *__restrict__ optr,
     const int32_t *__restrict__ opos, double *__restrict__ vals, double *__restrict__ diag) {
     extern __shared__ double acc_c[];
-    const int bs = blockDim.x, j = threadIdx.x;
-    const int a = blockIdx.x * bs + j;
-    if (a >= nc) return;
-    double *acc = acc_c + j;
-    const int o0 = optr[a], len = optr[a + 1] - o0;
+    const int bs = blockDim.x, rows = bs / G;
+    const int jr = (int)threadIdx.x / G, g = (int)threadIdx.x % G;
+    const int a = blockIdx.x * rows + jr;
+    const bool act = a < nc;
+    double *acc = acc_c + threadIdx.x;
+    const int o0 = act ? optr[a] : 0, len = act ? optr[a + 1] - o0 : 0;
     for (int k = 0; k < len; ++k) acc[k * bs] = 0.0;
-    int idx = plan2ptr[a];
-    for (int p = rptr[a]; p < rptr[a + 1]; ++p) {
-        const int r = ridx[p];
-        const double w = rw[p];
-        const int t1 = tptr[r + 1];
+    if (act) {
+        int idx = plan2ptr[a];   // the plan lists the row's (p, t) pairs in order
+        const int p0 = rptr[a], p1 = rptr[a + 1];
+        for (int p = p0; p < p1; ++p) {
+            const int r = ridx[p];
+            const int tb = tptr[r], te = tptr[r + 1];
+            if ((p - p0) % G == g) {
+                const double w = rw[p];
 #pragma unroll 4
-        for (int t = tptr[r]; t < t1; ++t) acc[plan2[idx++] * bs] += w * Tb[t];
+                for (int t = tb; t < te; ++t) acc[plan2[idx + (t - tb)] * bs] += w * Tb[t];
+            }
+            idx += te - tb;
+        }
     }
-    for (int k = 0; k < len; ++k) {
+    __syncthreads();
+    for (int k = g; k < len; k += G) {
+        double v = 0.0;
+#pragma unroll
+        for (int h = 0; h < G; ++h) v += acc_c[k * bs + jr * G + h];
         const int32_t pos = opos[o0 + k];
-        if (pos >= 0) vals[pos] = acc[k * bs];
-        else diag[-1 - pos] = acc[k * bs];
+        if (pos >= 0) vals[pos] = v;
+        else diag[-1 - pos] = v;
     }
 }
 
@@ -2521,7 +2563,8 @@ hipError_t launch_batch_solve(const BatchMesh *meshes, const int32_t *team_mesh,
                               hipStream_t st) {
     if (nblocks_total <= 0) return hipSuccess;
     if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
-    k_fill<unsigned><<<nblocks(count), kBlock, 0, st>>>(ctrs, 0u, count);
+    k_fill<unsigned><<<nblocks((int64_t)count * kBatchCtrStride), kBlock, 0, st>>>(ctrs, 0u,
+                                                                                  (int64_t)count * kBatchCtrStride);
     k_fill<int><<<nblocks(count), kBlock, 0, st>>>(aborts, 0, count);
     if (threads == 256) k_batch_solve<256><<<nblocks_total, 256, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
     else if (threads == 512) k_batch_solve<512><<<nblocks_total, 512, 0, st>>>(meshes, team_mesh, team_rank, ctrs, aborts, partials);
@@ -2587,6 +2630,7 @@ hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_
 }
 
 // threads per block so that every thread has `slots` doubles of LDS
+constexpr int kGalerkinLanes = 4;   // lanes per output row of the Galerkin kernels
 static int galerkin_block(int slots) {
     int bs = 64;
     while (bs > 1 && (size_t)bs * slots * sizeof(double) > 160 * 1024) bs >>= 1;
@@ -2602,10 +2646,19 @@ hipError_t launch_galerkin_t(int n, int tmax, const int32_t *tptr, const int32_t
     const int slots = tmax > 0 ? tmax : 1, bs = galerkin_block(slots);
     const size_t lds = (size_t)bs * slots * sizeof(double);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)k_galerkin_t, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_galerkin_t<kGalerkinLanes>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_galerkin_t<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_galerkin_t<<<(n + bs - 1) / bs, bs, lds, st>>>(n, tptr, plan1ptr, plan1, row_slice, slice_row0,
-                                                     slice_off, lpr, rowlen, cols, vals, diag, pw, Tbuf);
+    if (bs >= kGalerkinLanes) {
+        const int rows = bs / kGalerkinLanes;
+        k_galerkin_t<kGalerkinLanes><<<(n + rows - 1) / rows, bs, lds, st>>>(
+            n, tptr, plan1ptr, plan1, row_slice, slice_row0, slice_off, lpr, rowlen, cols, vals, diag, pw, Tbuf);
+    } else {
+        k_galerkin_t<1><<<(n + bs - 1) / bs, bs, lds, st>>>(n, tptr, plan1ptr, plan1, row_slice, slice_row0,
+                                                            slice_off, lpr, rowlen, cols, vals, diag, pw, Tbuf);
+    }
     return hipGetLastError();
 }
 
@@ -2617,10 +2670,19 @@ hipError_t launch_galerkin_c(int nc, int cmax, const int32_t *plan2ptr, const ui
     const int slots = cmax > 0 ? cmax : 1, bs = galerkin_block(slots);
     const size_t lds = (size_t)bs * slots * sizeof(double);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)k_galerkin_c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_galerkin_c<kGalerkinLanes>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_galerkin_c<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_galerkin_c<<<(nc + bs - 1) / bs, bs, lds, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw, tptr, Tbuf,
-                                                      optr, opos, vals, diag);
+    if (bs >= kGalerkinLanes) {
+        const int rows = bs / kGalerkinLanes;
+        k_galerkin_c<kGalerkinLanes><<<(nc + rows - 1) / rows, bs, lds, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw,
+                                                                              tptr, Tbuf, optr, opos, vals, diag);
+    } else {
+        k_galerkin_c<1><<<(nc + bs - 1) / bs, bs, lds, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw, tptr, Tbuf,
+                                                             optr, opos, vals, diag);
+    }
     return hipGetLastError();
 }
 

@@ -20,7 +20,8 @@ STRUCTS = {
     "smg_opts": ("Opts", ["mu_pre", "mu_post", "tail_rows", "lanes_per_row", "team_level", "team_size"]),
     "smg_solve_params": ("SolveParams", ["rtol", "max_cycles", "precision", "fixed_cycles", "use_graph", "timed"]),
     "smg_solve_info": ("SolveInfo", ["cycles", "k", "rel_res", "ms", "ms_phase"]),
-    "smg_batch_opts": ("BatchOpts", ["threads", "lanes_level0", "lanes_coarse", "team_max", "cache_file"]),
+    "smg_batch_opts": ("BatchOpts", ["threads", "lanes_level0", "lanes_coarse", "team_max", "cache_file",
+                                     "device_teams"]),
 }
 CONSTANTS = ["SMG_OK", "SMG_FP64", "SMG_FP32_IR", "SMG_SMOOTH_GS", "SMG_SMOOTH_JACOBI",
              "SMG_COLLAPSE_ALL", "SMG_COLLAPSE_INTERIOR", "SMG_COLLAPSE_STRAIGHT",
