@@ -2149,16 +2149,24 @@ __global__ __launch_bounds__(kBlock) void k_ir_up(float *__restrict__ d32,
 // Row v of A = diag(s m) + t L_w, with L_ij = -1/2 sum cot(opposite angles)
 // (times w_e), L_ii = -sum_j L_ij, m_v = sum of incident face areas / 3.
 // One thread owns row v; contributions are gathered from v's faces.
+constexpr int kAsmSlots = 16;   // row entries accumulated in LDS by k_assemble (longer rows: in place)
 __global__ __launch_bounds__(kBlock) void k_assemble(MeshView M, const double *__restrict__ V,
                                                      double t, const double *__restrict__ s,
                                                      const float *__restrict__ ew,
                                                      double *__restrict__ a_vals,
                                                      double *__restrict__ l_vals,
                                                      double *__restrict__ mass) {
+    // the row is accumulated in the thread's own LDS slots (slot e at
+    // e * kBlock), or in place in a_vals when it is longer than kAsmSlots;
+    // either way the same additions in the same order
+    __shared__ double racc[kAsmSlots * kBlock];
     const int v = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (v >= M.n) return;
     const int p0 = M.rowptr[v], p1 = M.rowptr[v + 1];
-    for (int p = p0; p < p1; ++p) a_vals[p] = 0.0;
+    const bool in_lds = p1 - p0 <= kAsmSlots;
+    double *ra = racc + threadIdx.x;
+    auto row = [&](int p) -> double & { return in_lds ? ra[(p - p0) * kBlock] : a_vals[p]; };
+    for (int p = p0; p < p1; ++p) row(p) = 0.0;
     double m = 0.0;
     for (int q = M.vf_ptr[v]; q < M.vf_ptr[v + 1]; ++q) {
         const int f = M.vf_face[q];
@@ -2180,15 +2188,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble(MeshView M, const double *_
         const int sa = M.slot_a[q], sb = M.slot_b[q];
         const double wa = ew ? (double)ew[M.edge_of_entry[sa]] : 1.0;
         const double wb = ew ? (double)ew[M.edge_of_entry[sb]] : 1.0;
-        a_vals[sa] += -0.5 * cot_b * wa;
-        a_vals[sb] += -0.5 * cot_a * wb;
+        row(sa) += -0.5 * cot_b * wa;
+        row(sb) += -0.5 * cot_a * wb;
         m += cn / 6.0;   // area / 3 = |cross| / 6
     }
     double off = 0.0;
     const int dp = M.diag_pos[v];
     for (int p = p0; p < p1; ++p) {
         if (p == dp) continue;
-        const double lv = a_vals[p];
+        const double lv = row(p);
         off += lv;
         if (l_vals) l_vals[p] = lv;
         a_vals[p] = t * lv;
@@ -2630,7 +2638,12 @@ hipError_t launch_scatter_values(const double *src, const int32_t *store, int64_
 }
 
 // threads per block so that every thread has `slots` doubles of LDS
-constexpr int kGalerkinLanes = 4;   // lanes per output row of the Galerkin kernels
+// Lanes per output row of the Galerkin kernels on levels below kGalerkinLanesBelow
+// rows, whose products are latency-bound; larger levels keep one thread per
+// row (measured: 4 lanes made the 250k-row product 33% slower, the small ones
+// 15-40% faster).
+constexpr int kGalerkinLanes = 4;
+constexpr int kGalerkinLanesBelow = 32768;
 static int galerkin_block(int slots) {
     int bs = 64;
     while (bs > 1 && (size_t)bs * slots * sizeof(double) > 160 * 1024) bs >>= 1;
@@ -2651,7 +2664,7 @@ hipError_t launch_galerkin_t(int n, int tmax, const int32_t *tptr, const int32_t
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_galerkin_t<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (bs >= kGalerkinLanes) {
+    if (bs >= kGalerkinLanes && n < kGalerkinLanesBelow) {
         const int rows = bs / kGalerkinLanes;
         k_galerkin_t<kGalerkinLanes><<<(n + rows - 1) / rows, bs, lds, st>>>(
             n, tptr, plan1ptr, plan1, row_slice, slice_row0, slice_off, lpr, rowlen, cols, vals, diag, pw, Tbuf);
@@ -2675,7 +2688,7 @@ hipError_t launch_galerkin_c(int nc, int cmax, const int32_t *plan2ptr, const ui
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void *)k_galerkin_c<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (bs >= kGalerkinLanes) {
+    if (bs >= kGalerkinLanes && nc < kGalerkinLanesBelow) {
         const int rows = bs / kGalerkinLanes;
         k_galerkin_c<kGalerkinLanes><<<(nc + rows - 1) / rows, bs, lds, st>>>(nc, plan2ptr, plan2, rptr, ridx, rw,
                                                                               tptr, Tbuf, optr, opos, vals, diag);
