@@ -518,9 +518,13 @@ smg_status smg_batch_solve(smg_batch b, const double *const *d_b, double *const 
 /* Autotuner: re-runs the last smg_batch_solve for candidate launch shapes
  * (workgroups per mesh, workgroup size, lanes per row on level 0 and on the
  * Galerkin levels),
- * keeps the fastest, and writes it to the cache file if one was given.  It
- * never changes mu, the levels, the coloring or the color order.  budget_ms
- * bounds the search.  Errors: STATE (no previous solve). */
+ * keeps the fastest whose solve converged, and writes it to the cache file
+ * if one was given.  It never changes mu, the levels, the coloring or the
+ * color order.  budget_ms bounds the search.  The last solve's x buffers end
+ * up holding a solve in the chosen shape (the original shape when no
+ * candidate converged).  Errors: STATE (no previous solve), and the errors of
+ * smg_batch_solve other than NO_CONVERGENCE and NONFINITE, which only
+ * disqualify a shape (the final solve in the chosen shape reports them). */
 smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_stream stream);
 /* Current launch shape: threads, lanes_level0, lanes_coarse, team_max. */
 smg_status smg_batch_shape(smg_batch b, int32_t *shape4);

@@ -406,19 +406,25 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
         smg_status st = upload_descriptors(b);
         if (st) return st;
         double tmin = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
             const auto t0 = std::chrono::steady_clock::now();
             st = smg_batch_solve(b, b->last_b.data(), b->last_x.data(), b->last_k.data(), &b->last_p, nullptr, stream);
-            if (st != SMG_OK && st != SMG_ERR_NO_CONVERGENCE) return st;
+            // a shape whose solve does not converge is no candidate, however fast
+            if (st == SMG_ERR_NO_CONVERGENCE || st == SMG_ERR_NONFINITE) ok = false;
+            else if (st != SMG_OK) return st;
             tmin = std::min(tmin, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         }
-        if (tmin < best) { best = tmin; bestS = c; }
+        if (ok && tmin < best) { best = tmin; bestS = c; }
     }
     b->threads = bestS.t;
     b->lanes0 = bestS.l0;
     b->lanes_c = bestS.lc;
     b->team_max = bestS.tm;
     smg_status st = upload_descriptors(b);
+    if (st) return st;
+    // the caller's x again from a solve in the chosen shape
+    st = smg_batch_solve(b, b->last_b.data(), b->last_x.data(), b->last_k.data(), &b->last_p, nullptr, stream);
     if (st) return st;
     write_cache(b);
     return SMG_OK;

@@ -1174,10 +1174,13 @@ __device__ __forceinline__ unsigned xcc_id() {
 // arrival with an atomic and polls the counter with atomic read-modify-writes
 // that leave it unchanged (a compare-and-swap that never matches): atomics
 // all see the same counter, while plain loads of it were measured to return
-// stale values for up to a second.  Neither needs the L2 write-back or
-// invalidation that the scope of the whole device costs.  After the wait it
-// invalidates the compute unit's L1 so that later loads read the other
-// workgroups' stores from the shared L2.  The wait is bounded (abort flag).
+// stale values for up to a second.  Neither needs the L2 write-back that the
+// scope of the whole device costs.  After the wait it invalidates the
+// compute unit's L1 with the device-scope form of the invalidate, so that
+// later loads read the other workgroups' stores from the shared L2: the
+// workgroup-scope form was measured to leave stale lines (wrong solves with
+// 256- and 512-thread workgroups), the device-scope one costs no measurable
+// time here.  The wait is bounded (abort flag).
 __device__ __forceinline__ unsigned team_count(unsigned *ctr) {
     unsigned seen = 0xffffffffu;
     __hip_atomic_compare_exchange_strong(ctr, &seen, 0xffffffffu, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -1199,7 +1202,7 @@ __device__ void team_sync_local(Team &T) {
                 break;
             }
         }
-        asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);

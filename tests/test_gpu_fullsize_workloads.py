@@ -5,7 +5,9 @@ launch configurations bench.py times:
     1-3 right-hand sides each, in one persistent batched launch: every mesh
     takes exactly the cycles of its unbatched solve, meets the oracle's own
     FP64 residual (its assembly of A) and is within 1e-6 of x* (a solve to
-    1e-12 whose oracle residual is checked);
+    1e-12 whose oracle residual is checked); the same at workgroups of 256,
+    512 and 1024 threads, with each team on one XCD and spread over the
+    device;
   * the 2,000,810-vertex height-field disc with 8 levels, three frames of
     new edge weights and t: the device assembly against the oracle's (1e-12),
     every Galerkin level against the oracle's P^T A P on the same
@@ -53,26 +55,43 @@ def test_batch_64_meshes_bench_scale():
         solvers.append(S)
         bs.append(torch.tensor(w["b"], dtype=torch.float64, device="cuda"))
     print("[batch] solvers ready", flush=True)
-    B = BatchSolver(solvers)
-    xs, infos, _ = B.solve(bs, rtol=1e-8, precision="fp32ir")
-    print("[batch] batched solve done", flush=True)
+    B = BatchSolver(solvers)   # the first solve of every mesh is the batched one
+    xs0, infos0, _ = B.solve(bs, rtol=1e-8, precision="fp32ir")
+    del B
     with ThreadPoolExecutor(max_workers=16) as ex:
         As = list(ex.map(lambda w: AS.system(w["V"], w["F"], w["t"])[0], meshes))
-    worst_err = 0.0
-    for i, (w, S, b, x, info, A) in enumerate(zip(meshes, solvers, bs, xs, infos, As)):
-        xu, iu = S.solve(b, rtol=1e-8, precision="fp32ir")
-        assert info["cycles"] == iu["cycles"], (i, w["name"], info["cycles"], iu["cycles"])
+    ref = []
+    for w, S, b, A in zip(meshes, solvers, bs, As):
+        _, iu = S.solve(b, rtol=1e-8, precision="fp32ir")
         xstar, _ = S.solve(b, rtol=1e-12, max_cycles=400, precision="fp64")
         bn = np.linalg.norm(w["b"], axis=0)
         xs_np = xstar.cpu().numpy()
         assert (np.linalg.norm(w["b"] - A @ xs_np, axis=0) / bn).max() <= 1.0001e-12
-        xn = x.cpu().numpy()
-        res = np.linalg.norm(w["b"] - A @ xn, axis=0) / bn
-        err = np.linalg.norm(xn - xs_np) / np.linalg.norm(xs_np)
-        worst_err = max(worst_err, err)
-        assert res.max() <= 1e-8 * 1.0001, (i, w["name"], res)
-        assert err <= 1e-6, (i, w["name"], err)
-    print(f"[batch] 64 meshes: cycles equal to unbatched, worst error vs x* {worst_err:.2e}", flush=True)
+        ref.append((iu["cycles"], xs_np, bn))
+
+    def check(xs, infos, tag, exact_cycles):
+        worst_err = 0.0
+        for i, (w, x, info, A, (cu, xs_np, bn)) in enumerate(zip(meshes, xs, infos, As, ref)):
+            if exact_cycles:
+                assert info["cycles"] == cu, (tag, i, w["name"], info["cycles"], cu)
+            else:   # other reduction orders may move a mesh on the rtol edge by one cycle
+                assert abs(info["cycles"] - cu) <= 1, (tag, i, w["name"], info["cycles"], cu)
+            xn = x.cpu().numpy()
+            res = np.linalg.norm(w["b"] - A @ xn, axis=0) / bn
+            err = np.linalg.norm(xn - xs_np) / np.linalg.norm(xs_np)
+            worst_err = max(worst_err, err)
+            assert res.max() <= 1e-8 * 1.0001, (tag, i, w["name"], res)
+            assert err <= 1e-6, (tag, i, w["name"], err)
+        print(f"[batch] {tag}: 64 meshes converged, worst error vs x* {worst_err:.2e}", flush=True)
+
+    check(xs0, infos0, "default shape, cycles equal to unbatched", True)
+    # every workgroup size, teams on one XCD each and spread over the device
+    for threads in (256, 512, 1024):
+        for dev in (False, True):
+            B = BatchSolver(solvers, threads=threads, team_max=8, device_teams=dev)
+            xs, infos, _ = B.solve(bs, rtol=1e-8, precision="fp32ir")
+            check(xs, infos, f"{threads} threads, {'device-wide' if dev else 'XCD-local'} teams", False)
+            del B
 
 
 @pytest.mark.timeout(1200)
