@@ -69,28 +69,28 @@ def test_batch_64_meshes_bench_scale():
         assert (np.linalg.norm(w["b"] - A @ xs_np, axis=0) / bn).max() <= 1.0001e-12
         ref.append((iu["cycles"], xs_np, bn))
 
-    def check(xs, infos, tag, exact_cycles):
+    def check(xs, infos, tag):
+        # every launch shape sums the team norms in its own order, yet no mesh
+        # of this seeded workload lies close enough to rtol for that to move
+        # its stopping cycle: the counts must equal the unbatched ones exactly
         worst_err = 0.0
         for i, (w, x, info, A, (cu, xs_np, bn)) in enumerate(zip(meshes, xs, infos, As, ref)):
-            if exact_cycles:
-                assert info["cycles"] == cu, (tag, i, w["name"], info["cycles"], cu)
-            else:   # other reduction orders may move a mesh on the rtol edge by one cycle
-                assert abs(info["cycles"] - cu) <= 1, (tag, i, w["name"], info["cycles"], cu)
+            assert info["cycles"] == cu, (tag, i, w["name"], info["cycles"], cu)
             xn = x.cpu().numpy()
             res = np.linalg.norm(w["b"] - A @ xn, axis=0) / bn
             err = np.linalg.norm(xn - xs_np) / np.linalg.norm(xs_np)
             worst_err = max(worst_err, err)
             assert res.max() <= 1e-8 * 1.0001, (tag, i, w["name"], res)
             assert err <= 1e-6, (tag, i, w["name"], err)
-        print(f"[batch] {tag}: 64 meshes converged, worst error vs x* {worst_err:.2e}", flush=True)
+        print(f"[batch] {tag}: 64 meshes, cycles equal to unbatched, worst error vs x* {worst_err:.2e}", flush=True)
 
-    check(xs0, infos0, "default shape, cycles equal to unbatched", True)
+    check(xs0, infos0, "default shape")
     # every workgroup size, teams on one XCD each and spread over the device
     for threads in (256, 512, 1024):
         for dev in (False, True):
             B = BatchSolver(solvers, threads=threads, team_max=8, device_teams=dev)
             xs, infos, _ = B.solve(bs, rtol=1e-8, precision="fp32ir")
-            check(xs, infos, f"{threads} threads, {'device-wide' if dev else 'XCD-local'} teams", False)
+            check(xs, infos, f"{threads} threads, {'device-wide' if dev else 'XCD-local'} teams")
             del B
 
 
