@@ -91,3 +91,25 @@ def test_batch_rejects_single_level():
     S = Solver(Hierarchy.from_prolongations([len(V)], [], []), A.indptr, A.indices)
     with pytest.raises(SmgError):
         BatchSolver([S])
+
+
+def test_batch_every_launch_shape(batch_case):
+    """Every launch shape the autotuner may pick (workgroup size, lanes per
+    row on level 0 and on the Galerkin levels, team size, teams on one XCD or
+    spread over the device) gives an answer that meets the oracle's residual
+    and takes the unbatched solve's cycle counts."""
+    from paper_2104_13755_amd.batch import BatchSolver
+    bs = [c["b"] for c in batch_case]
+    cu = [c["S"].solve(c["b"], rtol=1e-8, precision="fp32ir")[1]["cycles"] for c in batch_case]
+    for threads in (256, 512, 1024):
+        for l0 in (1, 2):
+            for lc in (1, 2, 4, 8):
+                for tmax in (2, 8):
+                    for dev in (False, True):
+                        B = BatchSolver([c["S"] for c in batch_case], threads=threads, lanes_level0=l0,
+                                        lanes_coarse=lc, team_max=tmax, device_teams=dev)
+                        xs, infos, _ = B.solve(bs, rtol=1e-8)
+                        shape = (threads, l0, lc, tmax, dev)
+                        assert [i["cycles"] for i in infos] == cu, (shape, [i["cycles"] for i in infos], cu)
+                        _check(batch_case, xs, infos, 1e-8)
+                        del B
