@@ -32,6 +32,26 @@ static constexpr int kCoarsestMax = 16384;
 // independent solves): each holds one value per row in LDS and the columns
 // proceed on different compute units at once.
 constexpr bool kTailPerColumn = true;
+// Whole-level passes (residual, CG product, restriction) on levels with at
+// least this many rows take their slices region by region: workgroups are
+// dealt to the 8 XCDs in turn and each XCD runs a contiguous range of the
+// grid, so in color-major slice order one XCD would hold about one color
+// spread over the whole mesh and gather x from all of it.  The order below
+// gives XCD x the x-th eighth (a Morton range) of every color instead, and
+// its gathers stay in one region of the mesh.
+static constexpr int kRegionOrderRows = 65536;
+static std::vector<int32_t> region_order(const std::vector<int32_t> &bounds, int total) {
+    std::vector<int32_t> out;
+    if (bounds.size() < 2 || bounds.front() != 0 || bounds.back() != total) return out;
+    out.reserve((size_t)total);
+    for (int x = 0; x < 8; ++x)
+        for (size_t c = 0; c + 1 < bounds.size(); ++c) {
+            const int64_t b0 = bounds[c], len = (int64_t)bounds[c + 1] - b0;
+            for (int64_t i = b0 + len * x / 8; i < b0 + len * (x + 1) / 8; ++i) out.push_back((int32_t)i);
+        }
+    if ((int)out.size() != total) out.clear();   // bounds were not a partition
+    return out;
+}
 
 namespace smg {
 smg_status fail(smg_status st, const std::string &msg) {
@@ -519,6 +539,20 @@ static smg_status solver_create(const smg_ctx_s &ctx, smg_hier h, const int32_t 
             CHK(dupload(&D.rs_off, L.rs_off, S->owned));
             CHK(dupload(&D.rs_idx, L.rs_idx, S->owned));
             CHK(dupload(&D.rs_w, L.rs_w, S->owned));
+            if (L.n >= kRegionOrderRows) {
+                const std::vector<int32_t> ord = region_order(Sl.color_slice, Sl.nslices);
+                if (!ord.empty()) CHK(dupload(&D.slice_order, ord, S->owned));
+                const LevelHost &Lc = levels[l + 1];
+                if (!Lc.coarsest) {
+                    // restriction slices (rps coarse rows each) by the coarse color of their first row
+                    const int rps = 64 / L.rs_lanes, nrs = (Lc.n + rps - 1) / rps;
+                    std::vector<int32_t> bounds;
+                    for (int c = 0; c <= Lc.ncolors; ++c)
+                        bounds.push_back(std::min(nrs, (Lc.sell.color_row[c] + rps - 1) / rps));
+                    const std::vector<int32_t> rord = region_order(bounds, nrs);
+                    if (!rord.empty()) CHK(dupload(&D.rs_order, rord, S->owned));
+                }
+            }
             std::vector<float> rsw32(L.rs_w.begin(), L.rs_w.end());
             CHK(dupload(&D.rs_w32, rsw32, S->owned));
             CHK(dupload(&D.tptr, L.tptr, S->owned));
@@ -987,11 +1021,11 @@ template <typename T>
 static SellView<T> sell_view(const DevLevel &D);
 template <>
 SellView<double> sell_view<double>(const DevLevel &D) {
-    return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals, D.diag};
+    return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals, D.diag, D.slice_order};
 }
 template <>
 SellView<float> sell_view<float>(const DevLevel &D) {
-    return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32};
+    return {D.n, D.lpr, D.slice_row0, D.slice_off, D.cols, D.vals32, D.diag32, D.slice_order};
 }
 template <typename T> static const TailLevel<T> *team_desc(const smg_solver_s *s);
 template <> const TailLevel<double> *team_desc<double>(const smg_solver_s *s) { return s->team64; }
@@ -1000,7 +1034,7 @@ template <typename T> static const LdsLevel<T> *tail_desc(const smg_solver_s *s)
 template <> const LdsLevel<double> *tail_desc<double>(const smg_solver_s *s) { return s->lds64; }
 template <> const LdsLevel<float> *tail_desc<float>(const smg_solver_s *s) { return s->lds32; }
 static TransferView transfer_view(const DevLevel &D, const DevLevel &C) {
-    return {D.n, C.n, D.rs_lanes, D.pc, D.rs_off, D.rs_idx};
+    return {D.n, C.n, D.rs_lanes, D.pc, D.rs_off, D.rs_idx, D.rs_order};
 }
 template <typename T> static T *xbuf(DevLevel &D);
 template <> double *xbuf<double>(DevLevel &D) { return D.x; }

@@ -16,12 +16,17 @@ struct SellView {
     const int32_t *cols;
     const T *vals;
     const T *diag;
+    // order in which the wavefronts of a whole-level pass (residual, CG
+    // product) take the slices, so that each XCD works on one region of
+    // every color (nullptr: slice order)
+    const int32_t *order = nullptr;
 };
 
 struct TransferView {             // P_l (ELL-3, SoA) and R_l = P_l^T (sliced ELL, rs_lanes lanes per row)
     int n, nc, rs_lanes;
     const int32_t *pc;
     const int32_t *rs_off, *rs_idx;
+    const int32_t *rs_order = nullptr;   // as SellView::order, for the restriction's slices
 };
 
 // --- relaxation / residual / transfers (K right-hand sides, 1..4) ---

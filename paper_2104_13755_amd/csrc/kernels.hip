@@ -353,9 +353,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(int nslices, int lpr,
                                                      const T *__restrict__ diag,
                                                      const T *__restrict__ b,
                                                      const T *__restrict__ x, T *__restrict__ r,
-                                                     double *__restrict__ partial) {
+                                                     double *__restrict__ partial,
+                                                     const int32_t *__restrict__ order) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int w0 = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int s = (order != nullptr && w0 < nslices) ? order[w0] : w0;
     const int lane = threadIdx.x & 63;
     double sq[K], mx[K];
 #pragma unroll
@@ -416,9 +418,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int nslices, int lpr, const 
                                                     const double *__restrict__ vals,
                                                     const double *__restrict__ diag,
                                                     const double *__restrict__ p, double *__restrict__ ap,
-                                                    double *__restrict__ partial) {
+                                                    double *__restrict__ partial,
+                                                    const int32_t *__restrict__ order) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int s = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int w0 = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int s = (order != nullptr && w0 < nslices) ? order[w0] : w0;
     const int lane = threadIdx.x & 63;
     double pq[K], zero[K];
 #pragma unroll
@@ -532,11 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_restrict(int nc, int lr, const int32
                                                      const int32_t *__restrict__ rs_idx,
                                                      const T *__restrict__ rw,
                                                      const T *__restrict__ r, T *__restrict__ rc,
-                                                     T *__restrict__ xc) {
+                                                     T *__restrict__ xc, const int32_t *__restrict__ order) {
     constexpr int CH = 8;
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int s = t >> 6, lane = t & 63, rps = 64 / lr;
-    if (s * rps >= nc) return;   // whole wavefronts leave together
+    const int w0 = t >> 6, lane = t & 63, rps = 64 / lr;
+    if (w0 * rps >= nc) return;   // whole wavefronts leave together
+    const int s = order != nullptr ? order[w0] : w0;
     const int a = s * rps + lane / lr, j = lane & (lr - 1);
     const int o0 = rs_off[s] + lane, w = (rs_off[s + 1] - rs_off[s]) >> 6;
     T acc[K];
@@ -2357,18 +2362,18 @@ hipError_t launch_residual(const SellView<T> &A, int nslices, const T *b, const 
         if (partial) {
             SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_residual<KK, T, true>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
                                                    ns, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
-                                                   b, x, r, partial)));
+                                                   b, x, r, partial, A.order)));
         } else {
             SMG_K_SWITCH(k, (hipExtLaunchKernelGGL(k_residual<KK, T, false>, dim3(g), dim3(kBlock), 0, st, ev0, ev1, 0,
                                                    ns, A.lpr, A.slice_row0, A.slice_off, A.cols, A.vals, A.diag,
-                                                   b, x, r, (double *)nullptr)));
+                                                   b, x, r, (double *)nullptr, A.order)));
         }
     } else if (partial) {
         SMG_K_SWITCH(k, (k_residual<KK, T, true><<<g, kBlock, 0, st>>>(ns, A.lpr, A.slice_row0, A.slice_off, A.cols,
-                                                                       A.vals, A.diag, b, x, r, partial)));
+                                                                       A.vals, A.diag, b, x, r, partial, A.order)));
     } else {
         SMG_K_SWITCH(k, (k_residual<KK, T, false><<<g, kBlock, 0, st>>>(ns, A.lpr, A.slice_row0, A.slice_off, A.cols,
-                                                                        A.vals, A.diag, b, x, r, nullptr)));
+                                                                        A.vals, A.diag, b, x, r, nullptr, A.order)));
     }
     return hipGetLastError();
 }
@@ -2380,7 +2385,7 @@ hipError_t launch_restrict(const TransferView &P, const T *rw, const T *r, T *rc
     const int lr = P.rs_lanes, rps = 64 / lr;
     const int64_t threads = (int64_t)((P.nc + rps - 1) / rps) * 64;
     SMG_K_SWITCH(k, (k_restrict<KK, T><<<nblocks(threads), kBlock, 0, st>>>(P.nc, lr, P.rs_off, P.rs_idx, rw, r,
-                                                                            rc, xc)));
+                                                                            rc, xc, P.rs_order)));
     return hipGetLastError();
 }
 
@@ -2492,7 +2497,7 @@ hipError_t launch_cg_spmv(const SellView<double> &A, int nslices, const double *
     *nblk = g;
     if (nslices <= 0) return hipSuccess;
     SMG_K_SWITCH(k, (k_cg_spmv<KK><<<g, kBlock, 0, st>>>(nslices, A.lpr, A.slice_row0, A.slice_off, A.cols,
-                                                         A.vals, A.diag, p, ap, partial)));
+                                                         A.vals, A.diag, p, ap, partial, A.order)));
     return hipGetLastError();
 }
 

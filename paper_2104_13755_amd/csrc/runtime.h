@@ -67,6 +67,8 @@ struct DevLevel {
     double *dense = nullptr, *dense_a = nullptr, *dense_w = nullptr, *dense_inv = nullptr;
     // transfers to the next level and the Galerkin plan
     int32_t *pc = nullptr, *rptr = nullptr, *ridx = nullptr, *rs_off = nullptr, *rs_idx = nullptr;
+    // slice orders of the whole-level passes on large levels (nullptr: slice order)
+    int32_t *slice_order = nullptr, *rs_order = nullptr;
     double *rs_w = nullptr;
     float *rs_w32 = nullptr;
     int rs_lanes = 4;
