@@ -33,12 +33,13 @@ static constexpr int kCoarsestMax = 16384;
 // proceed on different compute units at once.
 constexpr bool kTailPerColumn = true;
 // Whole-level passes (residual, CG product, restriction) on levels with at
-// least this many rows take their slices region by region: workgroups are
-// dealt to the 8 XCDs in turn and each XCD runs a contiguous range of the
-// grid, so in color-major slice order one XCD would hold about one color
-// spread over the whole mesh and gather x from all of it.  The order below
-// gives XCD x the x-th eighth (a Morton range) of every color instead, and
-// its gathers stay in one region of the mesh.
+// least this many rows take their slices region by region.  Workgroups are
+// dealt to the 8 XCDs in turn and the kernels renumber them (xcd_block) so
+// that each XCD works through a contiguous eighth of the wavefront indices;
+// in color-major slice order that eighth is about one color spread over the
+// whole mesh, whose gathers reach all of x.  The order below lists, for
+// x = 0..7, the x-th eighth (a Morton range) of every color, so the eighth
+// an XCD takes is one region of the mesh in every color.
 static constexpr int kRegionOrderRows = 65536;
 static std::vector<int32_t> region_order(const std::vector<int32_t> &bounds, int total) {
     std::vector<int32_t> out;
