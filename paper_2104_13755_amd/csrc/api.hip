@@ -523,6 +523,14 @@ static smg_status solver_create(const smg_ctx_s &ctx, smg_hier h, const int32_t 
             CHK(dupload(&D.cols, Sl.cols, S->owned));
             CHK(dupload(&D.rowlen, Sl.rowlen, S->owned));
             CHK(dupload(&D.row_slice, Sl.row_slice, S->owned));
+            {   // first slot of every row, for the one-workgroup and team kernels
+                std::vector<int32_t> rb((size_t)L.n);
+                for (int r = 0; r < L.n; ++r) {
+                    const int sl = Sl.row_slice[r];
+                    rb[r] = Sl.slice_off[sl] + (r - Sl.slice_row0[sl]) * Sl.lpr;
+                }
+                CHK(dupload(&D.row_base, rb, S->owned));
+            }
             CHK(dalloc(&D.vals, (size_t)D.slots, S->owned));
             CHK(dalloc(&D.diag, (size_t)L.n, S->owned));
             CHK(dalloc(&D.vals32, (size_t)D.slots, S->owned));
@@ -666,9 +674,9 @@ static smg_status solver_create(const smg_ctx_s &ctx, smg_hier h, const int32_t 
             const DevLevel &D = S->lev[l];
             const int grp = l == 0 ? 1 : 8;
             h64[l] = {D.n, D.ncolors, D.lpr, grp, D.color_row, D.slice_row0, D.slice_off, D.row_slice, D.rowlen,
-                      D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw, D.rptr, D.ridx, D.rw};
+                      D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw, D.rptr, D.ridx, D.rw, D.row_base};
             h32[l] = {D.n, D.ncolors, D.lpr, grp, D.color_row, D.slice_row0, D.slice_off, D.row_slice, D.rowlen,
-                      D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32, D.pc, D.pw32, D.rptr, D.ridx, D.rw32};
+                      D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32, D.pc, D.pw32, D.rptr, D.ridx, D.rw32, D.row_base};
         }
         CHK(dupload(&S->team64, h64, S->owned));
         CHK(dupload(&S->team32, h32, S->owned));

@@ -211,10 +211,10 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
             const DevLevel &D = s->lev[l];
             b->h64.push_back({D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off,
                               D.row_slice, D.rowlen, D.cols, D.vals, D.diag, D.x, D.b, D.r, D.pc, D.pw,
-                              D.rptr, D.ridx, D.rw});
+                              D.rptr, D.ridx, D.rw, D.row_base});
             b->h32.push_back({D.n, D.ncolors, D.lpr, D.lpr, D.color_row, D.slice_row0, D.slice_off,
                               D.row_slice, D.rowlen, D.cols, D.vals32, D.diag32, D.x32, D.b32, D.r32,
-                              D.pc, D.pw32, D.rptr, D.ridx, D.rw32});
+                              D.pc, D.pw32, D.rptr, D.ridx, D.rw32, D.row_base});
             mix((uint64_t)D.n);
             mix((uint64_t)D.nnz_nat);
         }

@@ -127,6 +127,7 @@ struct TailLevel {
     const T *pw;
     const int32_t *rptr, *ridx;   // restriction into the next level
     const T *rw;
+    const int32_t *row_base;      // first slot of every row (slice_off + row offset in its slice * lpr)
 };
 
 // --- one-workgroup tail with every iterate in LDS ---

@@ -1268,15 +1268,20 @@ __device__ void team_reduce(Team &T, double (&v)[K], bool take_max) {
     }
 }
 
-// off-diagonal sum of row r (valid) over its lane group; all lanes call it
+// off-diagonal sum of row r (valid) over its lane group; all lanes call it.
+// The row's first slot comes from a per-row table (one load beside its
+// length), the lane's entries are taken four at a time with all loads in
+// flight, and its last (fewer than four) entries as one more such chunk whose
+// loads are clamped to the row's last entry and whose products are added only
+// for entries that exist: one round trip for the row's place, then two per
+// chunk.  Products are added in entry order.
 template <int K, typename T>
 __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool valid, int j, int G,
                                            const T *__restrict__ x, T (&acc)[K]) {
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = T(0);
     if (valid) {
-        const int s = gld(L.row_slice, r);
-        const int base = gld(L.slice_off, s) + (r - gld(L.slice_row0, s)) * L.lpr;
+        const int base = gld(L.row_base, r);
         const int len = gld(L.rowlen, r);
         int e = j;
         for (; e + 3 * G < len; e += 4 * G) {   // four independent gathers in flight
@@ -1294,12 +1299,21 @@ __device__ __forceinline__ void wg_row_sum(const TailLevel<T> &L, int r, bool va
 #pragma unroll
                 for (int q = 0; q < K; ++q) acc[q] += a[u] * x[(size_t)c[u] * K + q];
         }
-        for (; e < len; e += G) {
-            const int slot = base + (e / L.lpr) * 64 + (e % L.lpr);
-            const int cc = gld(L.cols, slot);
-            const T a = gld(L.vals, slot);
+        if (e < len) {
+            int c[4];
+            T a[4];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] += a * x[(size_t)cc * K + q];
+            for (int u = 0; u < 4; ++u) {
+                const int ee = min(e + u * G, len - 1);
+                const int slot = base + (ee / L.lpr) * 64 + (ee % L.lpr);
+                c[u] = gld(L.cols, slot);
+                a[u] = gld(L.vals, slot);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e + u * G < len)
+#pragma unroll
+                    for (int q = 0; q < K; ++q) acc[q] += a[u] * x[(size_t)c[u] * K + q];
         }
     }
     group_sum<K>(acc, G);
@@ -1315,12 +1329,19 @@ __device__ void wg_relax(Team &tm, const TailLevel<T> &L, int sweeps) {
             for (int rb = r0; rb < r1; rb += per) {
                 const int r = rb + g;
                 const bool valid = r < r1;
+                T d = T(1), bq[K];   // loaded beside the row's place, ahead of the sum
+#pragma unroll
+                for (int q = 0; q < K; ++q) bq[q] = T(0);
+                if (valid && j == 0) {
+                    d = gld(L.diag, r);
+#pragma unroll
+                    for (int q = 0; q < K; ++q) bq[q] = gld(L.b, (size_t)r * K + q);
+                }
                 T acc[K];
                 wg_row_sum<K, T>(L, r, valid, j, G, L.x, acc);
                 if (valid && j == 0) {
-                    const T d = gld(L.diag, r);
 #pragma unroll
-                    for (int q = 0; q < K; ++q) gst(L.x, (size_t)r * K + q, (gld(L.b, (size_t)r * K + q) - acc[q]) / d);
+                    for (int q = 0; q < K; ++q) gst(L.x, (size_t)r * K + q, (bq[q] - acc[q]) / d);
                 }
             }
             team_sync(tm);
@@ -1336,13 +1357,20 @@ __device__ void wg_residual(Team &tm, const TailLevel<T> &L, double (*sq)[K] = n
     for (int rb = 0; rb < L.n; rb += per) {
         const int r = rb + g;
         const bool valid = r < L.n;
+        T d = T(1), bq[K], xo[K];   // loaded beside the row's place, ahead of the sum
+#pragma unroll
+        for (int q = 0; q < K; ++q) { bq[q] = T(0); xo[q] = T(0); }
+        if (valid && j == 0) {
+            d = gld(L.diag, r);
+#pragma unroll
+            for (int q = 0; q < K; ++q) { bq[q] = gld(L.b, (size_t)r * K + q); xo[q] = gld(L.x, (size_t)r * K + q); }
+        }
         T acc[K];
         wg_row_sum<K, T>(L, r, valid, j, G, L.x, acc);
         if (valid && j == 0) {
-            const T d = gld(L.diag, r);
 #pragma unroll
             for (int q = 0; q < K; ++q) {
-                const T rv = gld(L.b, (size_t)r * K + q) - (acc[q] + d * gld(L.x, (size_t)r * K + q));
+                const T rv = bq[q] - (acc[q] + d * xo[q]);
                 gst(L.r, (size_t)r * K + q, rv);
                 if (sq) { (*sq)[q] += (double)rv * (double)rv; (*mx)[q] = fmax((*mx)[q], fabs((double)rv)); }
             }

@@ -59,7 +59,7 @@ struct DevLevel {
     int32_t *perm = nullptr, *store = nullptr;
     // sliced ELL (smoothed levels)
     int32_t *slice_row0 = nullptr, *slice_off = nullptr, *cols = nullptr, *rowlen = nullptr,
-            *row_slice = nullptr;
+            *row_slice = nullptr, *row_base = nullptr;
     double *vals = nullptr, *diag = nullptr;
     float *vals32 = nullptr, *diag32 = nullptr;
     // coarsest: A_H (dense_a), its Cholesky factor (dense), G^{-1} (dense_w)
