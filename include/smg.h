@@ -489,6 +489,8 @@ typedef struct {
     int32_t device_teams;     /* 0: each team's workgroups on one XCD, meeting at barriers in
                                  that XCD's L2 (when the teams can be placed so); 1: teams
                                  anywhere, barriers through device-scope atomics */
+    int32_t balance;          /* 1: workgroups per mesh by level-0 entries x the last solve's
+                                 cycles (from the second solve on); 0: by entries (or tuned) */
 } smg_batch_opts;
 
 /* Group solvers (same device, at least two levels each) for batched solves:
@@ -517,7 +519,9 @@ smg_status smg_batch_solve(smg_batch b, const double *const *d_b, double *const 
                            smg_stream stream);
 /* Autotuner: re-runs the last smg_batch_solve for candidate launch shapes
  * (workgroups per mesh, workgroup size, lanes per row on level 0 and on the
- * Galerkin levels),
+ * Galerkin levels; teams sized by level-0 entries or, with the last solve's
+ * cycle counts, by entries x cycles, so the meshes that take longest get the
+ * larger teams; a cached work-sized shape takes effect from the second solve),
  * keeps the fastest whose solve converged, and writes it to the cache file
  * if one was given.  It never changes mu, the levels, the coloring or the
  * color order.  budget_ms bounds the search.  The last solve's x buffers end
@@ -526,8 +530,9 @@ smg_status smg_batch_solve(smg_batch b, const double *const *d_b, double *const 
  * smg_batch_solve other than NO_CONVERGENCE and NONFINITE, which only
  * disqualify a shape (the final solve in the chosen shape reports them). */
 smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_stream stream);
-/* Current launch shape: threads, lanes_level0, lanes_coarse, team_max. */
-smg_status smg_batch_shape(smg_batch b, int32_t *shape4);
+/* Current launch shape into shape5: threads, lanes_level0, lanes_coarse,
+ * team_max, balance (1: teams sized by entries x cycles). */
+smg_status smg_batch_shape(smg_batch b, int32_t *shape5);
 
 const char *smg_status_string(smg_status st);
 const char *smg_last_error(void);

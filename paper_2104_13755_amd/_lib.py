@@ -38,7 +38,8 @@ class SolveInfo(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("threads", c_int32), ("lanes_level0", c_int32), ("lanes_coarse", c_int32),
-                ("team_max", c_int32), ("cache_file", ctypes.c_char_p), ("device_teams", c_int32)]
+                ("team_max", c_int32), ("cache_file", ctypes.c_char_p), ("device_teams", c_int32),
+                ("balance", c_int32)]
 
 
 SMG_OK = 0

@@ -15,15 +15,17 @@ class BatchSolver:
     outlive the batch."""
 
     def __init__(self, solvers, threads=0, lanes_level0=0, lanes_coarse=0, team_max=0, cache_file=None,
-                 device_teams=False):
+                 device_teams=False, balance=False):
         """device_teams: teams anywhere on the device with device-scope
-        barriers, instead of each team on one XCD with barriers in its L2."""
+        barriers, instead of each team on one XCD with barriers in its L2.
+        balance: workgroups per mesh by level-0 entries x the last solve's
+        cycles (from the second solve on) instead of by entries."""
         self._lib = L.load()
         self.solvers = list(solvers)
         arr = (_c * len(self.solvers))(*[s._s for s in self.solvers])
         self._cache = cache_file.encode() if cache_file else None
         o = L.BatchOpts(int(threads), int(lanes_level0), int(lanes_coarse), int(team_max), self._cache,
-                        int(bool(device_teams)))
+                        int(bool(device_teams)), int(bool(balance)))
         h = _c()
         L.check(self._lib.smg_batch_create(arr, len(self.solvers), ctypes.byref(o), ctypes.byref(h)), "batch_create")
         self._b = h
@@ -53,6 +55,6 @@ class BatchSolver:
         return self.shape()
 
     def shape(self):
-        s = (ctypes.c_int32 * 4)()
+        s = (ctypes.c_int32 * 5)()
         L.check(self._lib.smg_batch_shape(self._b, s), "batch_shape")
-        return dict(threads=s[0], lanes_level0=s[1], lanes_coarse=s[2], team_max=s[3])
+        return dict(threads=s[0], lanes_level0=s[1], lanes_coarse=s[2], team_max=s[3], balance=s[4])

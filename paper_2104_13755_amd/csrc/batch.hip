@@ -37,6 +37,12 @@ struct smg_batch_s {
     int device_teams = 0;                                  // 1: no XCD packing (device-scope barriers)
     int local = 0;                                         // the current layout packs teams per XCD
     std::vector<int32_t> team;                             // workgroups per mesh
+    // 1: workgroups per mesh in proportion to level-0 entries x the last
+    // solve's cycles (the estimated work), once cycle counts are known; 0: to
+    // entries alone (set by the autotuner)
+    int balance = 0;
+    bool balanced = false;                                 // the current layout used cycle counts
+    std::vector<int32_t> last_cycles;                      // per mesh, from the last solve (empty: none yet)
     int32_t *d_team_mesh = nullptr, *d_team_rank = nullptr;
     unsigned *d_ctr = nullptr;
     int *d_abort = nullptr;
@@ -86,22 +92,29 @@ static void apply_shape(smg_batch_s *b) {
     }
 }
 
-// Workgroups per mesh: proportional to the mesh's level-0 entries, between 1
-// and team_max, scaled down until every workgroup of the launch can be
+// Workgroups per mesh: proportional to the mesh's level-0 entries (times its
+// last cycle count when balancing), between 1 and team_max, scaled down until
+// every workgroup of the launch can be
 // resident at once (the team barriers need co-residency).  Blocks of the
-// largest meshes come first.
+// largest teams come first.
 static smg_status layout_teams(smg_batch_s *b) {
     const int per_cu = batch_blocks_per_cu(b->threads);
     if (per_cu < 1) return fail(SMG_ERR_HIP, "batched kernel cannot be resident");
     const int capacity = per_cu * b->cus;
-    int64_t zmax = 1;
-    for (smg_solver s : b->solvers) zmax = std::max<int64_t>(zmax, s->lev[0].nnz_nat);
+    const bool use_cycles = b->balance && (int)b->last_cycles.size() == b->count;
+    auto weight = [&](int i) {
+        const double z = (double)b->solvers[i]->lev[0].nnz_nat;
+        return use_cycles ? z * std::max(1, b->last_cycles[i]) : z;
+    };
+    double wmax = 1.0;
+    for (int i = 0; i < b->count; ++i) wmax = std::max(wmax, weight(i));
+    b->balanced = use_cycles;
     int tmax = b->team_max;
     for (;;) {
         int total = 0;
         b->team.assign(b->count, 1);
         for (int i = 0; i < b->count; ++i) {
-            const double share = (double)b->solvers[i]->lev[0].nnz_nat / (double)zmax;
+            const double share = weight(i) / wmax;
             b->team[i] = std::max(1, std::min(tmax, (int)std::lround(share * tmax)));
             total += b->team[i];
         }
@@ -113,6 +126,7 @@ static smg_status layout_teams(smg_batch_s *b) {
     std::vector<int32_t> order(b->count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        if (b->team[a] != b->team[c]) return b->team[a] > b->team[c];
         return b->solvers[a]->lev[0].nnz_nat > b->solvers[c]->lev[0].nnz_nat;
     });
     std::vector<int32_t> tm, tr;
@@ -172,12 +186,17 @@ static bool read_cache(smg_batch_s *b) {
     if (b->cache_file.empty()) return false;
     FILE *f = std::fopen(b->cache_file.c_str(), "r");
     if (!f) return false;
-    unsigned long long key;
-    int t, l0, lc;
     bool found = false;
-    int tmx;
-    while (std::fscanf(f, "%llx %d %d %d %d", &key, &t, &l0, &lc, &tmx) == 5)
-        if (key == b->key) { b->threads = t; b->lanes0 = l0; b->lanes_c = lc; b->team_max = tmx; found = true; }
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long key;
+        int t, l0, lc, tmx, bal = 0;
+        const int got = std::sscanf(line, "%llx %d %d %d %d %d", &key, &t, &l0, &lc, &tmx, &bal);
+        if (got >= 5 && key == b->key) {
+            b->threads = t; b->lanes0 = l0; b->lanes_c = lc; b->team_max = tmx; b->balance = bal;
+            found = true;
+        }
+    }
     std::fclose(f);
     return found;
 }
@@ -186,8 +205,8 @@ static void write_cache(smg_batch_s *b) {
     if (b->cache_file.empty()) return;
     FILE *f = std::fopen(b->cache_file.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%llx %d %d %d %d\n", (unsigned long long)b->key, b->threads, b->lanes0, b->lanes_c,
-                 b->team_max);
+    std::fprintf(f, "%llx %d %d %d %d %d\n", (unsigned long long)b->key, b->threads, b->lanes0, b->lanes_c,
+                 b->team_max, b->balance);
     std::fclose(f);
 }
 
@@ -227,6 +246,7 @@ extern "C" smg_status smg_batch_create(const smg_solver *solvers, int32_t count,
     if (o && o->lanes_coarse) b->lanes_c = o->lanes_coarse;
     if (o && o->team_max) b->team_max = o->team_max;
     b->device_teams = o ? (o->device_teams != 0) : 0;
+    if (o && o->balance) b->balance = 1;
     if (b->team_max < 1 || b->team_max > 64) return fail(SMG_ERR_INVALID_ARG, "team_max must be 1..64");
     if (b->threads != 256 && b->threads != 512 && b->threads != 1024) return fail(SMG_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
     if (b->lanes0 != 1 && b->lanes0 != 2) return fail(SMG_ERR_INVALID_ARG, "lanes_level0 must be 1 or 2");
@@ -351,8 +371,10 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
             return fail(SMG_ERR_HIP, b->h_abort[i] == 2
                                          ? "batched solve: a workgroup of an XCD-local team ran on another XCD"
                                          : "batched solve: a team barrier timed out (workgroups not co-resident?)");
+    b->last_cycles.resize(b->count);
     for (int i = 0; i < b->count; ++i) {
         const double *o = b->h_out + 8 * i;
+        b->last_cycles[i] = (int32_t)o[0];
         bool conv = true, finite = true;
         for (int q = 0; q < k[i]; ++q) {
             if (!std::isfinite(o[1 + q])) finite = false;
@@ -368,17 +390,24 @@ extern "C" smg_status smg_batch_solve(smg_batch b, const double *const *d_b, dou
             for (int q = 0; q < 5; ++q) infos[i].ms_phase[q] = q == SMG_PHASE_PREPARE ? b->solvers[i]->ms_prepare : 0.0;
         }
     }
+    // a balanced shape (read from the cache) needs cycle counts: lay the teams
+    // out again for the next solve now that they are known
+    if (b->balance && !b->balanced) {
+        const smg_status st2 = upload_descriptors(b);
+        if (st2) return st2;
+    }
     if (worst == SMG_ERR_NONFINITE) return fail(worst, "non-finite residual in a batch member");
     if (worst == SMG_ERR_NO_CONVERGENCE) return fail(worst, "a batch member hit the cycle cap");
     return SMG_OK;
 }
 
-extern "C" smg_status smg_batch_shape(smg_batch b, int32_t *shape3) {
-    if (!b || !shape3) return fail(SMG_ERR_INVALID_ARG, "null argument");
-    shape3[0] = b->threads;
-    shape3[1] = b->lanes0;
-    shape3[2] = b->lanes_c;
-    shape3[3] = b->team_max;
+extern "C" smg_status smg_batch_shape(smg_batch b, int32_t *shape5) {
+    if (!b || !shape5) return fail(SMG_ERR_INVALID_ARG, "null argument");
+    shape5[0] = b->threads;
+    shape5[1] = b->lanes0;
+    shape5[2] = b->lanes_c;
+    shape5[3] = b->team_max;
+    shape5[4] = b->balance;
     return SMG_OK;
 }
 
@@ -386,13 +415,18 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
     if (!b) return fail(SMG_ERR_INVALID_ARG, "null batch");
     if (!b->have_last) return fail(SMG_ERR_STATE, "autotune needs a previous smg_batch_solve");
     HIPCHK(hipSetDevice(b->device));
-    struct Shape { int t, l0, lc, tm; };
+    struct Shape { int t, l0, lc, tm, bal; };
     std::vector<Shape> cands;
-    for (int tm : {8, 16, 4, 32, 2})
-        for (int t : {1024, 512, 256})
-            for (int lc : {8, 4})
-                for (int l0 : {1, 2}) cands.push_back({t, l0, lc, tm});
-    const Shape orig{b->threads, b->lanes0, b->lanes_c, b->team_max};
+    // each shape with teams by entries and, once cycle counts are known, by work
+    const bool cyc = (int)b->last_cycles.size() == b->count;
+    // (most promising first: the search stops at the budget)
+    for (int tm : {32, 16, 8, 64, 4, 2})
+        for (int bal : {1, 0})
+            for (int t : {1024, 512, 256})
+                for (int lc : {4, 8})
+                    for (int l0 : {1, 2})
+                        if (bal == 0 || cyc) cands.push_back({t, l0, lc, tm, bal});
+    const Shape orig{b->threads, b->lanes0, b->lanes_c, b->team_max, b->balance};
     Shape bestS = orig;
     double best = 1e300;
     const auto start = std::chrono::steady_clock::now();
@@ -403,6 +437,7 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
         b->lanes0 = c.l0;
         b->lanes_c = c.lc;
         b->team_max = c.tm;
+        b->balance = c.bal;
         smg_status st = upload_descriptors(b);
         if (st) return st;
         double tmin = 1e300;
@@ -421,6 +456,7 @@ extern "C" smg_status smg_batch_autotune(smg_batch b, int32_t budget_ms, smg_str
     b->lanes0 = bestS.l0;
     b->lanes_c = bestS.lc;
     b->team_max = bestS.tm;
+    b->balance = bestS.bal;
     smg_status st = upload_descriptors(b);
     if (st) return st;
     // the caller's x again from a solve in the chosen shape

@@ -21,7 +21,7 @@ STRUCTS = {
     "smg_solve_params": ("SolveParams", ["rtol", "max_cycles", "precision", "fixed_cycles", "use_graph", "timed"]),
     "smg_solve_info": ("SolveInfo", ["cycles", "k", "rel_res", "ms", "ms_phase"]),
     "smg_batch_opts": ("BatchOpts", ["threads", "lanes_level0", "lanes_coarse", "team_max", "cache_file",
-                                     "device_teams"]),
+                                     "device_teams", "balance"]),
 }
 CONSTANTS = ["SMG_OK", "SMG_FP64", "SMG_FP32_IR", "SMG_SMOOTH_GS", "SMG_SMOOTH_JACOBI",
              "SMG_COLLAPSE_ALL", "SMG_COLLAPSE_INTERIOR", "SMG_COLLAPSE_STRAIGHT",

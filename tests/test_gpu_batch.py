@@ -113,3 +113,20 @@ def test_batch_every_launch_shape(batch_case):
                         assert [i["cycles"] for i in infos] == cu, (shape, [i["cycles"] for i in infos], cu)
                         _check(batch_case, xs, infos, 1e-8)
                         del B
+
+
+def test_batch_balanced_teams(batch_case):
+    """Teams sized by level-0 entries x the last solve's cycles: the first
+    solve lays the teams out by entries, the second by work; both meet the
+    oracle's residual and take the unbatched cycle counts."""
+    from paper_2104_13755_amd.batch import BatchSolver
+    bs = [c["b"] for c in batch_case]
+    cu = [c["S"].solve(c["b"], rtol=1e-8, precision="fp32ir")[1]["cycles"] for c in batch_case]
+    for threads, tmax in ((1024, 16), (512, 32)):
+        B = BatchSolver([c["S"] for c in batch_case], threads=threads, team_max=tmax, balance=True)
+        assert B.shape()["balance"] == 1
+        for _ in range(2):
+            xs, infos, _ = B.solve(bs, rtol=1e-8)
+            assert [i["cycles"] for i in infos] == cu, (threads, tmax, [i["cycles"] for i in infos], cu)
+            _check(batch_case, xs, infos, 1e-8)
+        del B

@@ -5,9 +5,9 @@ launch configurations bench.py times:
     1-3 right-hand sides each, in one persistent batched launch: every mesh
     takes exactly the cycles of its unbatched solve, meets the oracle's own
     FP64 residual (its assembly of A) and is within 1e-6 of x* (a solve to
-    1e-12 whose oracle residual is checked); the same at workgroups of 256,
-    512 and 1024 threads, with each team on one XCD and spread over the
-    device;
+    1e-12 whose oracle residual is checked); the same with teams sized by
+    work (entries x cycles) and at workgroups of 256, 512 and 1024 threads,
+    with each team on one XCD and spread over the device;
   * the 2,000,810-vertex height-field disc with 8 levels, three frames of
     new edge weights and t: the device assembly against the oracle's (1e-12),
     every Galerkin level against the oracle's P^T A P on the same
@@ -85,6 +85,12 @@ def test_batch_64_meshes_bench_scale():
         print(f"[batch] {tag}: 64 meshes, cycles equal to unbatched, worst error vs x* {worst_err:.2e}", flush=True)
 
     check(xs0, infos0, "default shape")
+    # teams sized by work (entries x the first solve's cycles) from the second solve on
+    B = BatchSolver(solvers, threads=1024, team_max=32, balance=True)
+    for i in range(2):
+        xs, infos, _ = B.solve(bs, rtol=1e-8, precision="fp32ir")
+        check(xs, infos, f"work-balanced teams, solve {i + 1}")
+    del B
     # every workgroup size, teams on one XCD each and spread over the device
     for threads in (256, 512, 1024):
         for dev in (False, True):
